@@ -1,0 +1,309 @@
+"""Plain FP64 CPU oracle for model-based multi-parameter mapping (arXiv 2102.01604).
+
+TEST INFRASTRUCTURE ONLY.  This package is the slow, obviously correct
+reference that the GPU library is checked against.  Only ``tests/``, the smoke
+check in ``__graft_entry__`` and the CPU-baseline leg of ``bench.py`` may import
+it; the GPU library never does, and the two share no code.
+
+The arithmetic lives in ``mpm_oracle.c`` (plain C, double precision); this
+module only marshals numpy arrays into it.  Protocols are plain dicts::
+
+    {"n_echoes": [8, 8, 6], "tr": [0.025]*3, "flip": [rad, ...], "mt": [0, 0, 1],
+     "te": [s, ...] (contrast-major, one per image), "sigma": [...] (one per image)}
+
+Arrays are C-contiguous float64: maps ``[4][N]``, echoes ``[I][N]``, with voxel
+index ``n = x + nx*(y + ny*z)``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "mpm_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "libmpm_oracle.so")
+
+MAX_CONTRASTS = 8
+MAX_IMAGES = 64
+ML, MAP = 0, 1
+INIT_DEFAULT, INIT_CONST, INIT_FROM_MAPS = 0, 1, 2
+LOAD_PROPOSED, LOAD_GN = 0, 1
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (-O2, OpenMP, IEEE arithmetic)."""
+    if force or not os.path.exists(_LIB_PATH):
+        cmd = ["gcc", "-O2", "-std=c99", "-fopenmp", "-fPIC", "-shared", "-Wall",
+               "-o", _LIB_PATH + ".tmp", _SRC, "-lm"]
+        subprocess.check_call(cmd, cwd=_HERE)
+        os.replace(_LIB_PATH + ".tmp", _LIB_PATH)
+    return _LIB_PATH
+
+
+class Protocol(C.Structure):
+    _fields_ = [("n_contrasts", C.c_int32), ("n_echoes", C.c_int32 * MAX_CONTRASTS),
+                ("tr", C.c_double * MAX_CONTRASTS), ("flip", C.c_double * MAX_CONTRASTS),
+                ("mt", C.c_int32 * MAX_CONTRASTS), ("te", C.c_double * MAX_IMAGES),
+                ("sigma", C.c_double * MAX_IMAGES)]
+
+
+class Options(C.Structure):
+    _fields_ = [("mode", C.c_int32), ("n_outer", C.c_int32), ("n_gn", C.c_int32),
+                ("n_cg", C.c_int32), ("max_halvings", C.c_int32), ("loading", C.c_int32),
+                ("init_kind", C.c_int32), ("pad_", C.c_int32), ("lam", C.c_double * 4),
+                ("jtv_eps", C.c_double), ("cg_stop", C.c_double),
+                ("init_const", C.c_double * 4)]
+
+
+class Report(C.Structure):
+    _fields_ = [("objective", C.c_double), ("nll", C.c_double), ("jtv", C.c_double),
+                ("outer_done", C.c_int32), ("gn_done", C.c_int32), ("cg_done", C.c_int32),
+                ("rejected", C.c_int32), ("degenerate_voxels", C.c_int64),
+                ("nonfinite_voxels", C.c_int64), ("nll_increases", C.c_int64)]
+
+
+_lib = None
+_dp = C.POINTER(C.c_double)
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build(force=True)
+        lib = C.CDLL(_LIB_PATH)
+        lib.orc_spgr_derivs.argtypes = [_dp, C.c_double, C.c_double, C.c_double, C.c_int,
+                                        _dp, _dp, _dp]
+        lib.orc_simulate.argtypes = [C.POINTER(Protocol), C.c_int64, _dp, _dp, _dp]
+        lib.orc_lik_voxel.argtypes = [C.POINTER(Protocol), _dp, C.c_int64, _dp, C.c_double,
+                                      C.c_int, _dp, _dp, _dp]
+        lib.orc_solve4.argtypes = [_dp, _dp, _dp]
+        lib.orc_solve4.restype = C.c_int
+        lib.orc_jtv_weights.argtypes = [C.POINTER(C.c_int64), _dp, _dp, C.c_double, _dp, _dp]
+        lib.orc_jtv_weights.restype = C.c_double
+        lib.orc_apply_L.argtypes = [C.POINTER(C.c_int64), _dp, _dp, _dp, _dp]
+        lib.orc_pcg.argtypes = [C.POINTER(C.c_int64), _dp, _dp, _dp, _dp, _dp, C.c_int,
+                                C.c_double, _dp]
+        lib.orc_pcg.restype = C.c_int
+        lib.orc_default_init.argtypes = [C.POINTER(Protocol), C.c_int64, _dp, _dp, _dp]
+        lib.orc_default_init.restype = C.c_int
+        lib.orc_fit.argtypes = [C.POINTER(Protocol), C.POINTER(C.c_int64), _dp, _dp,
+                                C.POINTER(Options), _dp, C.POINTER(Report), _dp, C.c_int32]
+        lib.orc_fit.restype = C.c_int
+        lib.orc_uncertainty.argtypes = [C.POINTER(Protocol), C.POINTER(C.c_int64), _dp, _dp,
+                                        C.POINTER(Options), _dp, _dp, _dp]
+        lib.orc_uncertainty.restype = C.c_int
+        lib.orc_num_threads.restype = C.c_int
+        _lib = lib
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(_dp)
+
+
+def _f64(a):
+    return None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+
+
+def n_images(proto) -> int:
+    return int(sum(proto["n_echoes"]))
+
+
+def make_protocol(proto) -> Protocol:
+    p = Protocol()
+    C_ = len(proto["n_echoes"])
+    p.n_contrasts = C_
+    for c in range(C_):
+        p.n_echoes[c] = int(proto["n_echoes"][c])
+        p.tr[c] = float(proto["tr"][c])
+        p.flip[c] = float(proto["flip"][c])
+        p.mt[c] = int(proto["mt"][c])
+    for i in range(n_images(proto)):
+        p.te[i] = float(proto["te"][i])
+        p.sigma[i] = float(proto["sigma"][i])
+    return p
+
+
+def make_options(opts: dict) -> Options:
+    o = Options()
+    o.mode = {"ml": ML, "map": MAP}[opts.get("mode", "ml")]
+    o.n_outer = int(opts.get("n_outer", 1))
+    o.n_gn = int(opts.get("n_gn", 20))
+    o.n_cg = int(opts.get("n_cg", 32))
+    o.max_halvings = int(opts.get("max_halvings", 4))
+    o.loading = {"proposed": LOAD_PROPOSED, "gn": LOAD_GN}[opts.get("loading", "proposed")]
+    kind = opts.get("init", "default")
+    o.init_kind = {"default": INIT_DEFAULT, "const": INIT_CONST, "maps": INIT_FROM_MAPS}[kind]
+    lam = opts.get("lam", (0.0, 0.0, 0.0, 0.0))
+    for k in range(4):
+        o.lam[k] = float(lam[k])
+    o.jtv_eps = float(opts.get("jtv_eps", 0.0))
+    o.cg_stop = float(opts.get("cg_stop", 0.0))
+    ic = opts.get("init_const", (0.0, 0.0, 0.0, 0.0))
+    for k in range(4):
+        o.init_const[k] = float(ic[k])
+    return o
+
+
+def _dims(dims):
+    d = (C.c_int64 * 3)(*[int(v) for v in dims])
+    return d
+
+
+def num_threads() -> int:
+    return int(_load().orc_num_threads())
+
+
+def spgr_derivs(y, alpha, tr, te, mt):
+    """Signal, gradient and diagonal second derivatives for one image."""
+    lib = _load()
+    yv = _f64(np.asarray(y))
+    s = np.zeros(1)
+    ds = np.zeros(4)
+    d2s = np.zeros(4)
+    lib.orc_spgr_derivs(_ptr(yv), alpha, tr, te, int(mt), _ptr(s), _ptr(ds), _ptr(d2s))
+    return float(s[0]), ds, d2s
+
+
+def simulate(proto, maps, b1=None):
+    """Noise-free echoes [I][N] from maps [4][N]."""
+    lib = _load()
+    maps = _f64(maps).reshape(4, -1)
+    n = maps.shape[1]
+    b1 = None if b1 is None else _f64(b1).reshape(-1)
+    out = np.empty((n_images(proto), n))
+    p = make_protocol(proto)
+    lib.orc_simulate(C.byref(p), n, _ptr(maps), _ptr(b1), _ptr(out))
+    return out
+
+
+def lik_voxel(proto, x, y, b1=1.0, loading="proposed"):
+    """(nll, g[4], P[4,4]) of one voxel; x holds its I observations."""
+    lib = _load()
+    xv = _f64(np.asarray(x).reshape(-1))
+    yv = _f64(np.asarray(y).reshape(-1))
+    nll = np.zeros(1)
+    g = np.zeros(4)
+    P = np.zeros(16)
+    p = make_protocol(proto)
+    lib.orc_lik_voxel(C.byref(p), _ptr(xv), 1, _ptr(yv), float(b1),
+                      {"proposed": LOAD_PROPOSED, "gn": LOAD_GN}[loading],
+                      _ptr(nll), _ptr(g), _ptr(P))
+    return float(nll[0]), g, P.reshape(4, 4)
+
+
+def solve4(P, g):
+    """(P^{-1} g with the degenerate rule, status) for one symmetric 4x4 P."""
+    lib = _load()
+    Pv = _f64(np.asarray(P).reshape(16))
+    gv = _f64(np.asarray(g).reshape(4))
+    out = np.zeros(4)
+    st = lib.orc_solve4(_ptr(Pv), _ptr(gv), _ptr(out))
+    return out, int(st)
+
+
+def jtv_weights(dims, maps, lam, eps):
+    """(w[N], d[N], sum sqrt(q+eps^2)) of maps [4][N] on a grid (nx, ny, nz)."""
+    lib = _load()
+    maps = _f64(maps).reshape(4, -1)
+    n = maps.shape[1]
+    w = np.empty(n)
+    d = np.empty(n)
+    lv = _f64(np.asarray(lam, dtype=np.float64))
+    jt = lib.orc_jtv_weights(_dims(dims), _ptr(maps), _ptr(lv), float(eps), _ptr(w), _ptr(d))
+    return w, d, float(jt)
+
+
+def apply_L(dims, w, lam, v):
+    """(L v) for v [4][N] with L = G^T W G (x) diag(lambda)."""
+    lib = _load()
+    v = _f64(v).reshape(4, -1)
+    w = _f64(w).reshape(-1)
+    lv = _f64(np.asarray(lam, dtype=np.float64))
+    out = np.empty_like(v)
+    lib.orc_apply_L(_dims(dims), _ptr(w), _ptr(lv), _ptr(v), _ptr(out))
+    return out
+
+
+def pcg(dims, P, w, d, lam, b, n_cg, cg_stop=1e-10):
+    """PCG solve of (P + L) delta = b; P is [N][4][4].  Returns (delta, iterations)."""
+    lib = _load()
+    P = _f64(P).reshape(-1, 16)
+    b = _f64(b).reshape(4, -1)
+    w = _f64(w).reshape(-1)
+    d = _f64(d).reshape(-1)
+    lv = _f64(np.asarray(lam, dtype=np.float64))
+    delta = np.empty_like(b)
+    it = lib.orc_pcg(_dims(dims), _ptr(P), _ptr(w), _ptr(d), _ptr(lv), _ptr(b), int(n_cg),
+                     float(cg_stop), _ptr(delta))
+    return delta, int(it)
+
+
+def default_init(proto, x, b1=None):
+    """Constant initial log-parameters (4,) from per-image volume means."""
+    lib = _load()
+    x = _f64(x).reshape(n_images(proto), -1)
+    b1 = None if b1 is None else _f64(b1).reshape(-1)
+    y0 = np.zeros(4)
+    p = make_protocol(proto)
+    st = lib.orc_default_init(C.byref(p), x.shape[1], _ptr(x), _ptr(b1), _ptr(y0))
+    if st:
+        raise ValueError("protocol has no usable PDw/T1w/MTw contrasts for the default init")
+    return y0
+
+
+def trace_len(opts: dict) -> int:
+    if opts.get("mode", "ml") == "ml":
+        return int(opts.get("n_gn", 20)) + 1
+    return int(opts.get("n_outer", 1)) * (int(opts.get("n_gn", 20)) + 2)
+
+
+def fit(proto, dims, x, b1, opts: dict, maps0=None):
+    """Run the fit.  Returns (maps [4][N], report dict, trace array)."""
+    lib = _load()
+    N = int(np.prod(dims))
+    x = _f64(x).reshape(n_images(proto), N)
+    b1 = None if b1 is None else _f64(b1).reshape(N)
+    o = make_options(opts)
+    if maps0 is not None:
+        maps = _f64(maps0).reshape(4, N).copy()
+        o.init_kind = INIT_FROM_MAPS
+    else:
+        maps = np.zeros((4, N))
+        if o.init_kind == INIT_FROM_MAPS:
+            raise ValueError("init='maps' needs maps0")
+    tl = trace_len(opts)
+    trace = np.empty(tl)
+    rep = Report()
+    p = make_protocol(proto)
+    st = lib.orc_fit(C.byref(p), _dims(dims), _ptr(x), _ptr(b1), C.byref(o), _ptr(maps),
+                     C.byref(rep), _ptr(trace), tl)
+    if st:
+        raise ValueError("default initialisation failed")
+    report = {f[0]: getattr(rep, f[0]) for f in Report._fields_}
+    return maps, report, trace
+
+
+def uncertainty(proto, dims, x, b1, opts: dict, maps, moments=False):
+    """Laplace posterior variance [4][N] (and optional moments [4][N])."""
+    lib = _load()
+    N = int(np.prod(dims))
+    x = _f64(x).reshape(n_images(proto), N)
+    b1 = None if b1 is None else _f64(b1).reshape(N)
+    maps = _f64(maps).reshape(4, N)
+    o = make_options(opts)
+    var = np.empty((4, N))
+    mom = np.empty((4, N)) if moments else None
+    p = make_protocol(proto)
+    lib.orc_uncertainty(C.byref(p), _dims(dims), _ptr(x), _ptr(b1), C.byref(o), _ptr(maps),
+                        _ptr(var), _ptr(mom))
+    return (var, mom) if moments else var
+
+
+def default_eps(lam) -> float:
+    return 1e-3 * math.sqrt(float(sum(lam)))

@@ -1,0 +1,771 @@
+/*
+ * mpm_oracle.c -- plain FP64 CPU oracle for model-based multi-parameter
+ * mapping (Balbastre et al., arXiv 2102.01604).
+ *
+ * TEST INFRASTRUCTURE ONLY: the reference the GPU library is checked against.
+ * Only the test suite, the smoke check and the CPU-baseline leg of the
+ * benchmark may load it.  It shares no code with the GPU library.
+ *
+ * Style: every quantity is computed the way the paper writes it, in double
+ * precision, one voxel at a time.  Loops over voxels carry an OpenMP pragma so
+ * the oracle finishes moderate volumes in seconds; every sum over voxels is
+ * taken afterwards in index order by a plain serial loop, so results do not
+ * depend on the thread count.
+ *
+ * Readings of points the paper leaves open (each one is marked where used):
+ *   R-sigma  : each image's squared residual is weighted by 1/sigma_i^2 in the
+ *              gradient and in the approximate Hessian (Sec. 2.4 objective).
+ *   R-degen  : 4x4 solves are Jacobi-scaled; a parameter whose diagonal entry
+ *              is <= 1e-30 * (largest diagonal entry) is frozen (step 0); if a
+ *              Cholesky pivot of the scaled matrix falls below 1e-6 the whole
+ *              voxel takes step 0 and is counted as degenerate.
+ *   R-border : JTV finite differences use unit voxel spacing and a Neumann
+ *              border (differences across the border are zero).
+ *   R-eps    : the JTV weight is (q + eps^2)^(-1/2); the objective uses the
+ *              matching smoothed norm sum_n sqrt(q_n + eps^2).
+ *   R-w0     : IRLS starts from w = 0 (the first outer loop is an ML warm
+ *              start); weights are recomputed at the start of every later
+ *              outer loop and once after the last one.
+ *   R-cg     : CG starts from 0 and stops early only when p.q <= 0 or when
+ *              r.z <= cg_stop * r0.z0 (cg_stop = 0 by default: the fixed
+ *              iteration count of the configured schedule).
+ *   R-accept : a MAP Newton step y - 2^-h * delta is accepted for the first
+ *              h = 0..max_halvings that does not increase F_w; if none does,
+ *              y is kept and the remaining Newton steps of that outer loop are
+ *              skipped.
+ *   R-init   : default initial maps from per-image volume means (see
+ *              orc_default_init).
+ */
+#include "mpm_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define FROZEN_REL 1e-30
+#define PIVOT_MIN 1e-6
+/* a voxel NLL "rises" only beyond rounding level (changes near convergence are ~1e-15) */
+#define NLL_RISE_REL 1e-12
+
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* Index of the contrast that image i belongs to (images are contrast-major). */
+static int contrast_of(const orc_protocol *p, int i)
+{
+    int c = 0, first = 0;
+    while (c < p->n_contrasts && i >= first + p->n_echoes[c]) {
+        first += p->n_echoes[c];
+        c++;
+    }
+    return c;
+}
+
+static int n_images(const orc_protocol *p)
+{
+    int I = 0;
+    for (int c = 0; c < p->n_contrasts; c++) I += p->n_echoes[c];
+    return I;
+}
+
+/* ------------------------------------------------------------------------
+ * Forward model.
+ *
+ * Signal of a spoiled gradient echo with an optional MT pulse (TR2 = 0),
+ * written in the log / logit parameters (Sec. 2.1 eqs. 1-3; Sec. 2.4 eq.
+ * spgr_signal with a = exp(y0), r1 = exp(y1), r2 = exp(y2),
+ * delta = 1/(1+exp(-y3))).  For contrasts without an MT pulse delta is 0 and
+ * every derivative with respect to y3 is 0 (Sec. 2.4).
+ *
+ * ds and d2s are the first derivatives and the diagonal second derivatives
+ * with respect to (y0..y3), in the form Sec. 2.4 prints them.
+ * ------------------------------------------------------------------------ */
+void orc_spgr_derivs(const double y[4], double alpha, double tr, double te, int mt,
+                     double *s, double ds[4], double d2s[4])
+{
+    double a = exp(y[0]);
+    double r1 = exp(y[1]);
+    double r2 = exp(y[2]);
+    double delta = mt ? 1.0 / (1.0 + exp(-y[3])) : 0.0;
+    double e1 = exp(-r1 * tr);
+    double ca = cos(alpha), sa = sin(alpha);
+    double den = 1.0 - (1.0 - delta) * ca * e1;
+
+    double sig = a * sa * (1.0 - delta) * (1.0 - e1) / den * exp(-r2 * te);
+    *s = sig;
+
+    ds[0] = sig;
+    ds[1] = -tr * r1 * (((1.0 - delta) * ca - 1.0) * e1) / (den * (1.0 - e1)) * sig;
+    ds[2] = -te * r2 * sig;
+    ds[3] = mt ? delta / ((1.0 - delta) * ca * e1 - 1.0) * sig : 0.0;
+
+    d2s[0] = ds[0];
+    d2s[1] = (1.0 - tr * r1 * (1.0 + (1.0 - delta) * ca * e1) / den) * ds[1];
+    d2s[2] = (1.0 - te * r2) * ds[2];
+    d2s[3] = mt ? (2.0 * (1.0 - delta) * (1.0 - ca * e1) / den - 1.0) * ds[3] : 0.0;
+}
+
+/* Noise-free echoes of every image at every voxel.  The flip angle of a voxel
+ * is the nominal one times the transmit-field efficiency b1 (Sec. 2.4,
+ * footnote on B1).  maps: [4][n]; b1: [n] or NULL (= 1); out: [I][n]. */
+void orc_simulate(const orc_protocol *p, int64_t n, const double *maps,
+                  const double *b1, double *out)
+{
+    int I = n_images(p);
+#pragma omp parallel for schedule(static)
+    for (int64_t v = 0; v < n; v++) {
+        double y[4] = {maps[v], maps[n + v], maps[2 * n + v], maps[3 * n + v]};
+        double b = b1 ? b1[v] : 1.0;
+        for (int i = 0; i < I; i++) {
+            int c = contrast_of(p, i);
+            double s, ds[4], d2s[4];
+            orc_spgr_derivs(y, p->flip[c] * b, p->tr[c], p->te[i], p->mt[c], &s, ds, d2s);
+            out[(int64_t)i * n + v] = s;
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------
+ * Per-voxel likelihood block (Sec. 2.3 eq. chainrule and eq. precond;
+ * Sec. 2.4, summed over every echo of every contrast).
+ *
+ *   nll = sum_i (s_i - x_i)^2 / (2 sigma_i^2)
+ *   g   = sum_i (s_i - x_i) / sigma_i^2 * grad s_i
+ *   P   = sum_i [ grad s_i grad s_i^T + |s_i - x_i| diag|d2 s_i| ] / sigma_i^2
+ *
+ * (R-sigma.)  With loading == ORC_LOAD_GN the |.| term is dropped, giving
+ * the Gauss-Newton / Fisher-scoring matrix of Sec. 2.3.
+ * x points at image 0 of this voxel; image i is at x[i*stride].
+ * P is the full 4x4 matrix, row-major.
+ * ------------------------------------------------------------------------ */
+void orc_lik_voxel(const orc_protocol *p, const double *x, int64_t stride,
+                   const double y[4], double b1, int loading,
+                   double *nll, double g[4], double P[16])
+{
+    int I = n_images(p);
+    double l = 0.0;
+    for (int k = 0; k < 4; k++) g[k] = 0.0;
+    for (int k = 0; k < 16; k++) P[k] = 0.0;
+    for (int i = 0; i < I; i++) {
+        int c = contrast_of(p, i);
+        double s, ds[4], d2s[4];
+        orc_spgr_derivs(y, p->flip[c] * b1, p->tr[c], p->te[i], p->mt[c], &s, ds, d2s);
+        double res = s - x[(int64_t)i * stride];
+        double wgt = 1.0 / (p->sigma[i] * p->sigma[i]);
+        l += 0.5 * wgt * res * res;
+        for (int k = 0; k < 4; k++) {
+            g[k] += wgt * res * ds[k];
+            for (int j = 0; j < 4; j++) P[4 * k + j] += wgt * ds[k] * ds[j];
+            if (loading == ORC_LOAD_PROPOSED) P[4 * k + k] += wgt * fabs(res) * fabs(d2s[k]);
+        }
+    }
+    *nll = l;
+}
+
+/* ------------------------------------------------------------------------
+ * out = P^{-1} g for a symmetric 4x4 P, with the degenerate rule R-degen.
+ * Returns 0 on success, 1 if the voxel was degenerate (out = 0).
+ * ------------------------------------------------------------------------ */
+int orc_solve4(const double P[16], const double g[4], double out[4])
+{
+    double maxd = 0.0;
+    int ok = 1;
+    for (int k = 0; k < 4; k++) {
+        out[k] = 0.0;
+        if (!isfinite(P[4 * k + k]) || !isfinite(g[k])) ok = 0;
+        if (P[4 * k + k] > maxd) maxd = P[4 * k + k];
+    }
+    if (!ok || !(maxd > 0.0)) return 1;
+
+    int frozen[4];
+    double D[4], S[4][4], rhs[4], L[4][4], u[4];
+    for (int k = 0; k < 4; k++) {
+        frozen[k] = !(P[4 * k + k] > FROZEN_REL * maxd);
+        D[k] = frozen[k] ? 0.0 : 1.0 / sqrt(P[4 * k + k]);
+    }
+    for (int k = 0; k < 4; k++) {
+        for (int j = 0; j < 4; j++) {
+            if (frozen[k] || frozen[j]) S[k][j] = (k == j) ? 1.0 : 0.0;
+            else S[k][j] = D[k] * P[4 * k + j] * D[j];
+        }
+        rhs[k] = frozen[k] ? 0.0 : D[k] * g[k];
+    }
+    /* Cholesky S = L L^T */
+    for (int j = 0; j < 4; j++) {
+        double piv = S[j][j];
+        for (int m = 0; m < j; m++) piv -= L[j][m] * L[j][m];
+        if (!(piv >= PIVOT_MIN)) return 1;
+        L[j][j] = sqrt(piv);
+        for (int i = j + 1; i < 4; i++) {
+            double v = S[i][j];
+            for (int m = 0; m < j; m++) v -= L[i][m] * L[j][m];
+            L[i][j] = v / L[j][j];
+        }
+    }
+    /* L t = rhs, then L^T u = t */
+    double t[4];
+    for (int i = 0; i < 4; i++) {
+        double v = rhs[i];
+        for (int m = 0; m < i; m++) v -= L[i][m] * t[m];
+        t[i] = v / L[i][i];
+    }
+    for (int i = 3; i >= 0; i--) {
+        double v = t[i];
+        for (int m = i + 1; m < 4; m++) v -= L[m][i] * u[m];
+        u[i] = v / L[i][i];
+    }
+    for (int k = 0; k < 4; k++) out[k] = D[k] * u[k];
+    return 0;
+}
+
+/* ------------------------------------------------------------------------
+ * Joint total variation (Sec. 2.5).
+ *
+ * G_n holds the 6 forward and backward finite differences about voxel n
+ * (R-border), so ||G_n y_k||^2 = sum over in-bounds neighbours m of
+ * (y_k[m] - y_k[n])^2 and
+ *     q_n = sum_k lambda_k ||G_n y_k||^2 .
+ * The IRLS weights are the minimisers of the bound eq. bound,
+ *     w_n = (q_n + eps^2)^(-1/2)             (R-eps),
+ * and d_n = diag(G^T W G)_n = sum over in-bounds neighbours m of (w_n + w_m)
+ * (the "cross kernel" of Sec. 2.5).  Returns sum_n sqrt(q_n + eps^2).
+ * ------------------------------------------------------------------------ */
+static int neighbours(const int64_t dims[3], int64_t n, int64_t nb[6])
+{
+    int64_t nx = dims[0], ny = dims[1], nz = dims[2];
+    int64_t x = n % nx, y = (n / nx) % ny, z = n / (nx * ny);
+    int cnt = 0;
+    if (x > 0) nb[cnt++] = n - 1;
+    if (x < nx - 1) nb[cnt++] = n + 1;
+    if (y > 0) nb[cnt++] = n - nx;
+    if (y < ny - 1) nb[cnt++] = n + nx;
+    if (z > 0) nb[cnt++] = n - nx * ny;
+    if (z < nz - 1) nb[cnt++] = n + nx * ny;
+    return cnt;
+}
+
+double orc_jtv_weights(const int64_t dims[3], const double *maps, const double lambda[4],
+                       double eps, double *w, double *d)
+{
+    int64_t N = dims[0] * dims[1] * dims[2];
+    double *root = (double *)malloc(sizeof(double) * (size_t)N);
+#pragma omp parallel for schedule(static)
+    for (int64_t n = 0; n < N; n++) {
+        int64_t nb[6];
+        int cnt = neighbours(dims, n, nb);
+        double q = 0.0;
+        for (int k = 0; k < 4; k++) {
+            double gk = 0.0;
+            for (int j = 0; j < cnt; j++) {
+                double diff = maps[k * N + nb[j]] - maps[k * N + n];
+                gk += diff * diff;
+            }
+            q += lambda[k] * gk;
+        }
+        root[n] = sqrt(q + eps * eps);
+        w[n] = root[n] > 0.0 ? 1.0 / root[n] : 0.0;
+    }
+    if (d) {
+#pragma omp parallel for schedule(static)
+        for (int64_t n = 0; n < N; n++) {
+            int64_t nb[6];
+            int cnt = neighbours(dims, n, nb);
+            double s = 0.0;
+            for (int j = 0; j < cnt; j++) s += w[n] + w[nb[j]];
+            d[n] = s;
+        }
+    }
+    double jtv = 0.0;
+    for (int64_t n = 0; n < N; n++) jtv += root[n];
+    free(root);
+    return jtv;
+}
+
+/* out = L v with L = G^T W G (x) diag(lambda), W = diag(w) (x) I_6 (Sec. 2.5):
+ *   (L v)_k[n] = lambda_k * sum over in-bounds neighbours m of
+ *                (w_n + w_m) (v_k[n] - v_k[m]).
+ * v and out are [4][N]. */
+void orc_apply_L(const int64_t dims[3], const double *w, const double lambda[4],
+                 const double *v, double *out)
+{
+    int64_t N = dims[0] * dims[1] * dims[2];
+#pragma omp parallel for schedule(static)
+    for (int64_t n = 0; n < N; n++) {
+        int64_t nb[6];
+        int cnt = neighbours(dims, n, nb);
+        for (int k = 0; k < 4; k++) {
+            double s = 0.0;
+            for (int j = 0; j < cnt; j++) s += (w[n] + w[nb[j]]) * (v[k * N + n] - v[k * N + nb[j]]);
+            out[k * N + n] = lambda[k] * s;
+        }
+    }
+}
+
+static double dot(const double *a, const double *b, int64_t n)
+{
+    double s = 0.0;
+    for (int64_t i = 0; i < n; i++) s += a[i] * b[i];
+    return s;
+}
+
+/* z = M^{-1} r with the block-diagonal preconditioner of Sec. 2.6,
+ * M_n = P_n + diag(lambda_k d_n), solved per voxel with R-degen. */
+static void precond(int64_t N, const double *P, const double *d, const double lambda[4],
+                    const double *r, double *z)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t n = 0; n < N; n++) {
+        double M[16], rv[4], zv[4];
+        memcpy(M, P + 16 * n, sizeof(M));
+        for (int k = 0; k < 4; k++) {
+            M[4 * k + k] += lambda[k] * d[n];
+            rv[k] = r[k * N + n];
+        }
+        orc_solve4(M, rv, zv);
+        for (int k = 0; k < 4; k++) z[k * N + n] = zv[k];
+    }
+}
+
+/* q = (P + L) p */
+static void apply_A(const int64_t dims[3], const double *P, const double *w,
+                    const double lambda[4], const double *p, double *q)
+{
+    int64_t N = dims[0] * dims[1] * dims[2];
+    orc_apply_L(dims, w, lambda, p, q);
+#pragma omp parallel for schedule(static)
+    for (int64_t n = 0; n < N; n++)
+        for (int k = 0; k < 4; k++) {
+            double s = 0.0;
+            for (int j = 0; j < 4; j++) s += P[16 * n + 4 * k + j] * p[j * N + n];
+            q[k * N + n] += s;
+        }
+}
+
+/* ------------------------------------------------------------------------
+ * Preconditioned conjugate gradient for (P + L) delta = b (Sec. 2.6), with
+ * the block-Jacobi preconditioner P + (G^T W G o I) (x) diag(lambda)
+ * (R-cg).  P: [N][16]; w, d, b, delta: [N] / [4][N].  Returns the number of
+ * iterations executed.
+ * ------------------------------------------------------------------------ */
+int orc_pcg(const int64_t dims[3], const double *P, const double *w, const double *d,
+            const double lambda[4], const double *b, int n_cg, double cg_stop, double *delta)
+{
+    int64_t N = dims[0] * dims[1] * dims[2];
+    int64_t V = 4 * N;
+    double *r = (double *)malloc(sizeof(double) * (size_t)V);
+    double *z = (double *)malloc(sizeof(double) * (size_t)V);
+    double *p = (double *)malloc(sizeof(double) * (size_t)V);
+    double *q = (double *)malloc(sizeof(double) * (size_t)V);
+    int it_done = 0;
+
+    for (int64_t i = 0; i < V; i++) {
+        delta[i] = 0.0;
+        r[i] = b[i];
+    }
+    precond(N, P, d, lambda, r, z);
+    memcpy(p, z, sizeof(double) * (size_t)V);
+    double gamma = dot(r, z, V);
+    double gamma0 = gamma;
+    if (gamma0 > 0.0) {
+        for (int it = 0; it < n_cg; it++) {
+            apply_A(dims, P, w, lambda, p, q);
+            double pq = dot(p, q, V);
+            if (!(pq > 0.0)) break;
+            double alpha = gamma / pq;
+            for (int64_t i = 0; i < V; i++) {
+                delta[i] += alpha * p[i];
+                r[i] -= alpha * q[i];
+            }
+            precond(N, P, d, lambda, r, z);
+            double gamma_new = dot(r, z, V);
+            it_done++;
+            if (gamma_new <= cg_stop * gamma0) break;
+            double beta = gamma_new / gamma;
+            gamma = gamma_new;
+            for (int64_t i = 0; i < V; i++) p[i] = z[i] + beta * p[i];
+        }
+    }
+    free(r);
+    free(z);
+    free(p);
+    free(q);
+    return it_done;
+}
+
+/* ------------------------------------------------------------------------
+ * Likelihood blocks of every voxel.  maps: [4][N]; nll: [N]; g: [4][N] or
+ * NULL; P: [N][16] or NULL.
+ * ------------------------------------------------------------------------ */
+static void lik_all(const orc_protocol *p, int64_t N, const double *x, const double *b1,
+                    int loading, const double *maps, double *nll, double *g, double *P)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t n = 0; n < N; n++) {
+        double y[4] = {maps[n], maps[N + n], maps[2 * N + n], maps[3 * N + n]};
+        double gl[4], Pl[16], l;
+        orc_lik_voxel(p, x + n, N, y, b1 ? b1[n] : 1.0, loading, &l, gl, Pl);
+        nll[n] = l;
+        if (g)
+            for (int k = 0; k < 4; k++) g[k * N + n] = gl[k];
+        if (P) memcpy(P + 16 * n, Pl, sizeof(Pl));
+    }
+}
+
+static double sum(const double *v, int64_t n)
+{
+    double s = 0.0;
+    for (int64_t i = 0; i < n; i++) s += v[i];
+    return s;
+}
+
+/* F_w(y) = sum_n nll_n + 1/2 y^T L y  (Sec. 2.6 objective at fixed weights). */
+static double objective_w(const orc_protocol *p, const int64_t dims[3], const double *x,
+                          const double *b1, int loading, const double *w,
+                          const double lambda[4], const double *maps, double *nll_buf,
+                          double *Ly_buf)
+{
+    int64_t N = dims[0] * dims[1] * dims[2];
+    lik_all(p, N, x, b1, loading, maps, nll_buf, NULL, NULL);
+    orc_apply_L(dims, w, lambda, maps, Ly_buf);
+    return sum(nll_buf, N) + 0.5 * dot(maps, Ly_buf, 4 * N);
+}
+
+static double logit(double v) { return log(v / (1.0 - v)); }
+
+static double clampd(double v, double lo, double hi)
+{
+    if (!(v >= lo)) return lo;  /* also maps NaN to lo */
+    if (v > hi) return hi;
+    return v;
+}
+
+/* ------------------------------------------------------------------------
+ * Default constant initial maps (R-init; the paper starts from constant maps
+ * derived from per-volume means, Sec. 2.7, without saying how).
+ *   1. m_i = mean over voxels of image i.
+ *   2. log m_i = beta_c(i) - r2 * TE_i, least squares with one shared r2,
+ *      giving TE = 0 intercepts S_c = exp(beta_c).
+ *   3. Small-angle closed forms (the approximation of Helms et al. 2008 that
+ *      the paper builds its MT model on, Sec. 2.1) for R1 and A from the two
+ *      non-MT contrasts with the smallest (P) and largest (T) flip angle, and
+ *      for delta from the first MT contrast (M); flip angles are scaled by the
+ *      mean of b1.
+ *   4. Clamp R1 to [0.05, 20], R2* to [0.5, 500], delta to [1e-4, 0.2].
+ * Returns 0, or 1 when the protocol lacks the contrasts above.
+ * ------------------------------------------------------------------------ */
+int orc_default_init(const orc_protocol *p, int64_t n, const double *x, const double *b1,
+                     double y0[4])
+{
+    int I = n_images(p), C = p->n_contrasts;
+    double m[ORC_MAX_IMAGES];
+    for (int i = 0; i < I; i++) {
+        double s = 0.0;
+        for (int64_t v = 0; v < n; v++) s += x[(int64_t)i * n + v];
+        m[i] = s / (double)n;
+    }
+    double b1m = 1.0;
+    if (b1) {
+        double s = 0.0;
+        for (int64_t v = 0; v < n; v++) s += b1[v];
+        b1m = s / (double)n;
+    }
+    /* normal equations of the (C+1)-unknown linear least squares */
+    int U = C + 1;
+    double A[ORC_MAX_CONTRASTS + 1][ORC_MAX_CONTRASTS + 2];
+    memset(A, 0, sizeof(A));
+    for (int i = 0; i < I; i++) {
+        int c = contrast_of(p, i);
+        double row[ORC_MAX_CONTRASTS + 1];
+        memset(row, 0, sizeof(row));
+        row[c] = 1.0;
+        row[C] = -p->te[i];
+        double rhs = log(m[i] > 1e-12 ? m[i] : 1e-12);
+        for (int a = 0; a < U; a++) {
+            for (int b = 0; b < U; b++) A[a][b] += row[a] * row[b];
+            A[a][U] += row[a] * rhs;
+        }
+    }
+    /* Gaussian elimination with partial pivoting */
+    for (int col = 0; col < U; col++) {
+        int piv = col;
+        for (int r = col + 1; r < U; r++)
+            if (fabs(A[r][col]) > fabs(A[piv][col])) piv = r;
+        if (fabs(A[piv][col]) < 1e-300) return 1;
+        if (piv != col)
+            for (int k = 0; k <= U; k++) {
+                double t = A[col][k];
+                A[col][k] = A[piv][k];
+                A[piv][k] = t;
+            }
+        for (int r = 0; r < U; r++) {
+            if (r == col) continue;
+            double f = A[r][col] / A[col][col];
+            for (int k = col; k <= U; k++) A[r][k] -= f * A[col][k];
+        }
+    }
+    double beta[ORC_MAX_CONTRASTS + 1];
+    for (int a = 0; a < U; a++) beta[a] = A[a][U] / A[a][a];
+    double r2 = beta[C];
+
+    int cP = -1, cT = -1, cM = -1;
+    for (int c = 0; c < C; c++) {
+        if (p->mt[c]) {
+            if (cM < 0) cM = c;
+            continue;
+        }
+        if (cP < 0 || p->flip[c] < p->flip[cP]) cP = c;
+        if (cT < 0 || p->flip[c] > p->flip[cT]) cT = c;
+    }
+    if (cP < 0 || cT < 0 || cP == cT || cM < 0) return 1;
+    double SP = exp(beta[cP]), ST = exp(beta[cT]), SM = exp(beta[cM]);
+    double aP = p->flip[cP] * b1m, aT = p->flip[cT] * b1m, aM = p->flip[cM] * b1m;
+    double tP = p->tr[cP], tT = p->tr[cT], tM = p->tr[cM];
+
+    double R1 = 0.5 * (ST * aT / tT - SP * aP / tP) / (SP / aP - ST / aT);
+    double Aa = SP * ST * (tP * aT / aP - tT * aP / aT) / (ST * tP * aT - SP * tT * aP);
+    R1 = clampd(R1, 0.05, 20.0);
+    if (!(Aa > 0.0) || !isfinite(Aa)) Aa = SP / sin(aP);
+    double dl = (Aa * aM / SM - 1.0) * R1 * tM - 0.5 * aM * aM;
+    dl = clampd(dl, 1e-4, 0.2);
+    r2 = clampd(r2, 0.5, 500.0);
+
+    y0[0] = log(Aa);
+    y0[1] = log(R1);
+    y0[2] = log(r2);
+    y0[3] = logit(dl);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------
+ * Full fit.
+ *
+ * ML (SPGR-ML, Sec. 3.3): n_gn Newton-like steps y <- y - P~^{-1} g taken
+ * independently in every voxel (Sec. 2.3, Newton step with the approximate
+ * Hessian of eq. precond); every step is taken, as the paper's method uses no
+ * line search.
+ *
+ * MAP (SPGR+JTV, Sec. 2.5-2.7): IRLS.  For each outer loop t the weights are
+ * refreshed (t >= 1; R-w0), then n_gn Newton-like steps solve
+ * (P~ + L) delta = g + L y by PCG (Sec. 2.6) and take y - 2^-h delta
+ * (R-accept).
+ *
+ * maps: [4][N], initial values on entry when init_kind = FROM_MAPS, the
+ * result on return.  trace (optional):
+ *   ML : trace[j] = total NLL before step j, trace[n_gn] = final NLL;
+ *   MAP: per outer loop t, slots t*(n_gn+2) + j: F_w before step 0 (j = 0)
+ *        and after step j-1 (j = 1..n_gn), then the true objective
+ *        NLL + sum sqrt(q + eps^2) at the end of the loop; skipped steps NaN.
+ * Returns 0, or 1 on an unusable default initialisation.
+ * ------------------------------------------------------------------------ */
+int orc_fit(const orc_protocol *p, const int64_t dims[3], const double *x, const double *b1,
+            const orc_options *opt, double *maps, orc_report *rep, double *trace,
+            int32_t trace_len)
+{
+    int64_t N = dims[0] * dims[1] * dims[2];
+    int64_t V = 4 * N;
+    orc_report R;
+    memset(&R, 0, sizeof(R));
+    for (int32_t i = 0; i < trace_len; i++) trace[i] = NAN;
+
+    if (opt->init_kind == ORC_INIT_CONST || opt->init_kind == ORC_INIT_DEFAULT) {
+        double y0[4];
+        if (opt->init_kind == ORC_INIT_CONST) {
+            for (int k = 0; k < 4; k++) y0[k] = opt->init_const[k];
+        } else if (orc_default_init(p, N, x, b1, y0)) {
+            return 1;
+        }
+        for (int k = 0; k < 4; k++)
+            for (int64_t n = 0; n < N; n++) maps[k * N + n] = y0[k];
+    }
+
+    double *nll = (double *)malloc(sizeof(double) * (size_t)N);
+    double *g = (double *)malloc(sizeof(double) * (size_t)V);
+    double *P = (double *)malloc(sizeof(double) * (size_t)N * 16);
+    unsigned char *degen = (unsigned char *)calloc((size_t)N, 1);
+
+    if (opt->mode == ORC_ML) {
+        double *prev = (double *)malloc(sizeof(double) * (size_t)N);
+        for (int it = 0; it < opt->n_gn; it++) {
+            lik_all(p, N, x, b1, opt->loading, maps, nll, g, P);
+            if (trace && it < trace_len) trace[it] = sum(nll, N);
+            if (it > 0)
+                for (int64_t n = 0; n < N; n++)
+                    if (nll[n] > prev[n] * (1.0 + NLL_RISE_REL)) R.nll_increases++;
+            memcpy(prev, nll, sizeof(double) * (size_t)N);
+#pragma omp parallel for schedule(static)
+            for (int64_t n = 0; n < N; n++) {
+                double gv[4] = {g[n], g[N + n], g[2 * N + n], g[3 * N + n]};
+                double step[4];
+                degen[n] = (unsigned char)orc_solve4(P + 16 * n, gv, step);
+                for (int k = 0; k < 4; k++) maps[k * N + n] -= step[k];
+            }
+            R.gn_done++;
+        }
+        lik_all(p, N, x, b1, opt->loading, maps, nll, NULL, NULL);
+        if (opt->n_gn > 0)
+            for (int64_t n = 0; n < N; n++)
+                if (nll[n] > prev[n] * (1.0 + NLL_RISE_REL)) R.nll_increases++;
+        R.nll = sum(nll, N);
+        R.objective = R.nll;
+        if (trace && opt->n_gn < trace_len) trace[opt->n_gn] = R.nll;
+        for (int64_t n = 0; n < N; n++) R.degenerate_voxels += degen[n];
+        free(prev);
+    } else {
+        double lam_sum = opt->lambda[0] + opt->lambda[1] + opt->lambda[2] + opt->lambda[3];
+        double eps = opt->jtv_eps > 0.0 ? opt->jtv_eps : 1e-3 * sqrt(lam_sum);
+        double cg_stop = opt->cg_stop > 0.0 ? opt->cg_stop : 0.0;
+        double *w = (double *)calloc((size_t)N, sizeof(double));
+        double *d = (double *)calloc((size_t)N, sizeof(double));
+        double *Ly = (double *)malloc(sizeof(double) * (size_t)V);
+        double *b = (double *)malloc(sizeof(double) * (size_t)V);
+        double *delta = (double *)malloc(sizeof(double) * (size_t)V);
+        double *trial = (double *)malloc(sizeof(double) * (size_t)V);
+        int slots = opt->n_gn + 2;
+
+        for (int t = 0; t < opt->n_outer; t++) {
+            if (t >= 1 && lam_sum > 0.0) orc_jtv_weights(dims, maps, opt->lambda, eps, w, d);
+            for (int j = 0; j < opt->n_gn; j++) {
+                lik_all(p, N, x, b1, opt->loading, maps, nll, g, P);
+                orc_apply_L(dims, w, opt->lambda, maps, Ly);
+                double F = sum(nll, N) + 0.5 * dot(maps, Ly, V);
+                if (trace && j == 0 && t * slots < trace_len) trace[t * slots] = F;
+                for (int64_t i = 0; i < V; i++) b[i] = g[i] + Ly[i];
+                R.cg_done += orc_pcg(dims, P, w, d, opt->lambda, b, opt->n_cg, cg_stop, delta);
+
+                int accepted = 0;
+                double Fnew = F;
+                if (opt->max_halvings < 0) {
+                    for (int64_t i = 0; i < V; i++) maps[i] -= delta[i];
+                    Fnew = objective_w(p, dims, x, b1, opt->loading, w, opt->lambda, maps, nll, Ly);
+                    accepted = 1;
+                } else {
+                    double step = 1.0;
+                    for (int h = 0; h <= opt->max_halvings; h++) {
+                        for (int64_t i = 0; i < V; i++) trial[i] = maps[i] - step * delta[i];
+                        double Ft = objective_w(p, dims, x, b1, opt->loading, w, opt->lambda,
+                                                trial, nll, Ly);
+                        if (Ft <= F) {
+                            memcpy(maps, trial, sizeof(double) * (size_t)V);
+                            Fnew = Ft;
+                            accepted = 1;
+                            break;
+                        }
+                        step *= 0.5;
+                    }
+                }
+                if (!accepted) {
+                    R.rejected++;
+                    break;
+                }
+                R.gn_done++;
+                if (trace && t * slots + j + 1 < trace_len) trace[t * slots + j + 1] = Fnew;
+            }
+            R.outer_done++;
+            if (trace && t * slots + opt->n_gn + 1 < trace_len) {
+                double jt = lam_sum > 0.0 ? orc_jtv_weights(dims, maps, opt->lambda, eps, Ly, NULL) : 0.0;
+                lik_all(p, N, x, b1, opt->loading, maps, nll, NULL, NULL);
+                trace[t * slots + opt->n_gn + 1] = sum(nll, N) + jt;
+            }
+        }
+        /* final weights, objective and degenerate count (R-w0) */
+        double jt = 0.0;
+        if (lam_sum > 0.0) jt = orc_jtv_weights(dims, maps, opt->lambda, eps, w, d);
+        else
+            for (int64_t n = 0; n < N; n++) w[n] = d[n] = 0.0;
+        lik_all(p, N, x, b1, opt->loading, maps, nll, NULL, P);
+        R.nll = sum(nll, N);
+        R.jtv = jt;
+        R.objective = R.nll + jt;
+        for (int64_t n = 0; n < N; n++) {
+            double M[16], e[4] = {1.0, 0.0, 0.0, 0.0}, o[4];
+            memcpy(M, P + 16 * n, sizeof(M));
+            for (int k = 0; k < 4; k++) M[4 * k + k] += opt->lambda[k] * d[n];
+            R.degenerate_voxels += orc_solve4(M, e, o);
+        }
+        free(w);
+        free(d);
+        free(Ly);
+        free(b);
+        free(delta);
+        free(trial);
+    }
+    for (int64_t n = 0; n < N; n++) {
+        int bad = 0;
+        for (int k = 0; k < 4; k++)
+            if (!isfinite(maps[k * N + n])) bad = 1;
+        R.nonfinite_voxels += bad;
+    }
+    free(nll);
+    free(g);
+    free(P);
+    free(degen);
+    if (rep) *rep = R;
+    return 0;
+}
+
+/* ------------------------------------------------------------------------
+ * Laplace posterior variance (Sec. 3.6): the diagonal of
+ * (P~ + diag(G^T W G) (x) diag(lambda))^{-1} at the fitted maps, with W from
+ * the fitted maps (lambda = 0 / ML mode: the diagonal of P~^{-1}).  Frozen
+ * parameters and degenerate voxels (R-degen) get +inf.
+ * moments (optional, [4][N]): E[r1], V[r1], E[t1], V[t1] of the log-normal
+ * posterior of r1 = exp(y1) and t1 = exp(-y1) (Sec. 3.6).
+ * ------------------------------------------------------------------------ */
+int orc_uncertainty(const orc_protocol *p, const int64_t dims[3], const double *x,
+                    const double *b1, const orc_options *opt, const double *maps,
+                    double *var, double *moments)
+{
+    int64_t N = dims[0] * dims[1] * dims[2];
+    double lam[4] = {0.0, 0.0, 0.0, 0.0};
+    double *d = (double *)calloc((size_t)N, sizeof(double));
+    double *nll = (double *)malloc(sizeof(double) * (size_t)N);
+    double *P = (double *)malloc(sizeof(double) * (size_t)N * 16);
+    if (opt->mode == ORC_MAP) {
+        double lam_sum = opt->lambda[0] + opt->lambda[1] + opt->lambda[2] + opt->lambda[3];
+        if (lam_sum > 0.0) {
+            double eps = opt->jtv_eps > 0.0 ? opt->jtv_eps : 1e-3 * sqrt(lam_sum);
+            double *w = (double *)malloc(sizeof(double) * (size_t)N);
+            orc_jtv_weights(dims, maps, opt->lambda, eps, w, d);
+            free(w);
+            for (int k = 0; k < 4; k++) lam[k] = opt->lambda[k];
+        }
+    }
+    lik_all(p, N, x, b1, opt->loading, maps, nll, NULL, P);
+#pragma omp parallel for schedule(static)
+    for (int64_t n = 0; n < N; n++) {
+        double M[16];
+        memcpy(M, P + 16 * n, sizeof(M));
+        for (int k = 0; k < 4; k++) M[4 * k + k] += lam[k] * d[n];
+        double maxd = 0.0;
+        for (int k = 0; k < 4; k++)
+            if (M[4 * k + k] > maxd) maxd = M[4 * k + k];
+        for (int k = 0; k < 4; k++) {
+            double e[4] = {0.0, 0.0, 0.0, 0.0}, col[4];
+            e[k] = 1.0;
+            int frozen = !(M[4 * k + k] > FROZEN_REL * maxd);
+            if (frozen || orc_solve4(M, e, col)) var[k * N + n] = INFINITY;
+            else var[k * N + n] = col[k];
+        }
+        if (moments) {
+            double v = var[N + n], r1t = maps[N + n];
+            double ev = exp(v);
+            moments[n] = sqrt(ev) * exp(r1t);
+            moments[N + n] = (ev - 1.0) * ev * exp(r1t) * exp(r1t);
+            moments[2 * N + n] = sqrt(ev) * exp(-r1t);
+            moments[3 * N + n] = (ev - 1.0) * ev * exp(-r1t) * exp(-r1t);
+        }
+    }
+    free(d);
+    free(nll);
+    free(P);
+    return 0;
+}

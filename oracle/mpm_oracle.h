@@ -1,0 +1,107 @@
+/*
+ * mpm_oracle.h -- plain FP64 CPU oracle for model-based multi-parameter
+ * mapping (Balbastre et al., "Model-Based Multi-Parameter Mapping",
+ * arXiv 2102.01604).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library is the slow, obviously correct
+ * reference that the GPU library is checked against.  Only the test suite,
+ * the smoke check and the CPU-baseline leg of the benchmark may load it.  It
+ * shares no code, header, table or helper with the GPU library.
+ *
+ * Conventions (all host memory, all FP64):
+ *   - voxel index n = x + nx*(y + ny*z), x fastest;
+ *   - images are numbered contrast-major: all echoes of contrast 0, then
+ *     contrast 1, ...; echoes X are laid out [I][N];
+ *   - log-parameter maps Y are laid out [4][N] in the order
+ *     (log A, log R1, log R2*, logit MTsat)   (paper Sec. 2.4).
+ */
+#ifndef MPM_ORACLE_H
+#define MPM_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ORC_MAX_CONTRASTS 8
+#define ORC_MAX_IMAGES 64
+
+typedef struct {
+    int32_t n_contrasts;
+    int32_t n_echoes[ORC_MAX_CONTRASTS];
+    double  tr[ORC_MAX_CONTRASTS];      /* repetition time, s            */
+    double  flip[ORC_MAX_CONTRASTS];    /* nominal flip angle, rad       */
+    int32_t mt[ORC_MAX_CONTRASTS];      /* 1 if the contrast has an MT pulse */
+    double  te[ORC_MAX_IMAGES];         /* echo time per image, s        */
+    double  sigma[ORC_MAX_IMAGES];      /* noise standard deviation per image */
+} orc_protocol;
+
+enum { ORC_ML = 0, ORC_MAP = 1 };
+enum { ORC_INIT_DEFAULT = 0, ORC_INIT_CONST = 1, ORC_INIT_FROM_MAPS = 2 };
+enum { ORC_LOAD_PROPOSED = 0, ORC_LOAD_GN = 1 };
+
+typedef struct {
+    int32_t mode;           /* ORC_ML or ORC_MAP                                  */
+    int32_t n_outer;        /* IRLS re-weighting loops (MAP)                      */
+    int32_t n_gn;           /* Newton-like steps (per outer loop for MAP)         */
+    int32_t n_cg;           /* conjugate-gradient iterations per Newton step      */
+    int32_t max_halvings;   /* MAP step acceptance: halvings tried; <0 = no test  */
+    int32_t loading;        /* ORC_LOAD_PROPOSED (paper) or ORC_LOAD_GN           */
+    int32_t init_kind;      /* ORC_INIT_*                                         */
+    int32_t pad_;
+    double  lambda[4];      /* JTV regularisation per map                         */
+    double  jtv_eps;        /* smoothing of the JTV norm; 0 -> 1e-3*sqrt(sum lambda) */
+    double  cg_stop;        /* CG stops when r.z <= cg_stop * r0.z0 (0: fixed count) */
+    double  init_const[4];  /* ORC_INIT_CONST values                              */
+} orc_options;
+
+typedef struct {
+    double  objective;        /* final objective (ML: NLL; MAP: NLL + smoothed JTV) */
+    double  nll;              /* final negative log-likelihood                      */
+    double  jtv;              /* final smoothed JTV value (MAP), 0 for ML           */
+    int32_t outer_done;
+    int32_t gn_done;          /* accepted Newton-like steps                         */
+    int32_t cg_done;          /* CG iterations executed in total                    */
+    int32_t rejected;         /* MAP steps whose every halving increased F          */
+    int64_t degenerate_voxels;/* voxels whose last 4x4 solve hit the degenerate rule */
+    int64_t nonfinite_voxels; /* voxels with a non-finite final map value           */
+    int64_t nll_increases;    /* ML: (voxel, step) pairs where the voxel NLL rose   */
+} orc_report;
+
+/* ---- forward model ---- */
+void orc_spgr_derivs(const double y[4], double alpha, double tr, double te, int mt,
+                     double *s, double ds[4], double d2s[4]);
+void orc_simulate(const orc_protocol *p, int64_t n, const double *maps,
+                  const double *b1, double *out);
+
+/* ---- per-voxel likelihood block ---- */
+void orc_lik_voxel(const orc_protocol *p, const double *x, int64_t stride,
+                   const double y[4], double b1, int loading,
+                   double *nll, double g[4], double P[16]);
+int  orc_solve4(const double P[16], const double g[4], double out[4]);
+
+/* ---- JTV prior ---- */
+double orc_jtv_weights(const int64_t dims[3], const double *maps, const double lambda[4],
+                       double eps, double *w, double *d);
+void   orc_apply_L(const int64_t dims[3], const double *w, const double lambda[4],
+                   const double *v, double *out);
+int    orc_pcg(const int64_t dims[3], const double *P, const double *w, const double *d,
+               const double lambda[4], const double *b, int n_cg, double cg_stop,
+               double *delta);
+
+/* ---- full fit and uncertainty ---- */
+int  orc_default_init(const orc_protocol *p, int64_t n, const double *x, const double *b1,
+                      double y0[4]);
+int  orc_fit(const orc_protocol *p, const int64_t dims[3], const double *x, const double *b1,
+             const orc_options *opt, double *maps, orc_report *rep, double *trace,
+             int32_t trace_len);
+int  orc_uncertainty(const orc_protocol *p, const int64_t dims[3], const double *x,
+                     const double *b1, const orc_options *opt, const double *maps,
+                     double *var, double *moments);
+int  orc_num_threads(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

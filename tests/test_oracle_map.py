@@ -1,0 +1,147 @@
+"""Pins for the oracle's MAP fit (SPGR+JTV, Sec. 2.5-2.7) and its Laplace
+uncertainty (Sec. 3.6).
+
+* MAP with lambda = 0 is exactly the ML fit (no prior, so each PCG solve is
+  exact in one iteration);
+* the objective gradient g + L_w y equals finite differences of
+  NLL + sum sqrt(q + eps^2) at w = w(y);
+* with the acceptance test the objective never increases; without it the MM
+  bound still makes the true objective decrease across outer loops (reported);
+* fewer echoes: MAP is closer to the truth than ML (Sec. 4.4);
+* the posterior variance matches the spread of ML estimates over noise draws
+  (Laplace / Cramer-Rao, Sec. 3.6) and the log-normal moments match sampling.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from conftest import observations
+from paper_2102_01604_amd import synth
+
+
+def _brain(dims=(16, 16, 12), seed=3, echoes=(8, 8, 6)):
+    c = synth.make_case("map_brain", dims=dims, seed=seed, echoes=echoes)
+    x = observations(__import__("oracle"), c).astype(np.float64)
+    return c, x
+
+
+def test_map_without_prior_equals_ml(orc):
+    c, x = _brain()
+    y0 = orc.fit(c["proto"], c["dims"], x, c["b1"], {"mode": "ml", "n_gn": 0})[0]
+    ml, rml, _ = orc.fit(c["proto"], c["dims"], x, c["b1"], {"mode": "ml", "n_gn": 12}, maps0=y0)
+    mp, rmp, _ = orc.fit(c["proto"], c["dims"], x, c["b1"],
+                         {"mode": "map", "n_outer": 3, "n_gn": 4, "n_cg": 5, "lam": [0, 0, 0, 0],
+                          "max_halvings": -1}, maps0=y0)
+    assert np.abs(ml - mp).max() <= 1e-10
+    assert rmp["nll"] == pytest.approx(rml["nll"], rel=1e-12)
+
+
+def _total_objective(orc, c, x, maps, eps):
+    nll = orc.fit(c["proto"], c["dims"], x, c["b1"], {"mode": "ml", "n_gn": 0}, maps0=maps)[1]["nll"]
+    return nll + orc.jtv_weights(c["dims"], maps, c["lam"], eps)[2]
+
+
+def test_map_gradient_matches_fd(orc):
+    c, x = _brain(dims=(6, 5, 4))
+    rng = np.random.default_rng(0)
+    y = c["truth"] + 0.05 * rng.normal(size=c["truth"].shape)
+    lam = np.array(c["lam"]) * 50
+    c["lam"] = lam
+    eps = orc.default_eps(lam)
+    w, _, _ = orc.jtv_weights(c["dims"], y, lam, eps)
+    N = y.shape[1]
+    g = np.zeros((4, N))
+    for n in range(N):
+        g[:, n] = orc.lik_voxel(c["proto"], x[:, n], y[:, n], c["b1"][n])[1]
+    grad = g + orc.apply_L(c["dims"], w, lam, y)
+    h = 1e-6
+    for k, n in [(0, 3), (1, 17), (2, 40), (3, 99), (1, 119)]:
+        yp, ym = y.copy(), y.copy()
+        yp[k, n] += h
+        ym[k, n] -= h
+        fd = (_total_objective(orc, c, x, yp, eps) - _total_objective(orc, c, x, ym, eps)) / (2 * h)
+        assert grad[k, n] == pytest.approx(fd, rel=1e-5, abs=1e-6 * np.abs(grad).max())
+
+
+def _check_monotone(trace, n_outer, n_gn):
+    t = trace.reshape(n_outer, n_gn + 2)
+    inner_bad = 0
+    for row in t:
+        fw = row[: n_gn + 1]
+        fw = fw[np.isfinite(fw)]
+        inner_bad += int(np.sum(np.diff(fw) > 1e-12 * np.abs(fw[:-1])))
+    ftrue = t[:, -1]
+    outer_bad = int(np.sum(np.diff(ftrue) > 1e-12 * np.abs(ftrue[:-1])))
+    return inner_bad, outer_bad
+
+
+def test_map_objective_monotone(orc):
+    c, x = _brain(seed=4)
+    opts = dict(c["opts"], n_outer=5, n_gn=4, n_cg=16)
+    _, rep, trace = orc.fit(c["proto"], c["dims"], x, c["b1"], opts)
+    inner_bad, outer_bad = _check_monotone(trace, 5, 4)
+    assert inner_bad == 0 and outer_bad == 0
+    assert rep["nonfinite_voxels"] == 0
+    # acceptance off: report (the paper claims monotone steps, Sec. 4.1)
+    _, rep2, trace2 = orc.fit(c["proto"], c["dims"], x, c["b1"], dict(opts, max_halvings=-1))
+    ib, ob = _check_monotone(trace2, 5, 4)
+    print(f"acceptance off: {ib} inner and {ob} outer objective increases")
+    assert ob == 0
+
+
+@pytest.mark.parametrize("n_echo", [2, 4, 6])
+def test_fewer_echoes_map_beats_ml(orc, n_echo):
+    """Synthetic analogue of the echo-decimation experiment (Sec. 3.5, 4.4)."""
+    c, x = _brain(dims=(20, 20, 12), seed=7, echoes=(n_echo,) * 3)
+    opts = dict(c["opts"], n_outer=4, n_gn=6, n_cg=16)
+    mp, _, _ = orc.fit(c["proto"], c["dims"], x, c["b1"], opts)
+    ml, _, _ = orc.fit(c["proto"], c["dims"], x, c["b1"], {"mode": "ml", "n_gn": 24})
+    rmse = lambda m: np.sqrt(((m - c["truth"]) ** 2).mean(1))
+    print(n_echo, "MAP", rmse(mp), "ML", rmse(ml))
+    assert (rmse(mp) <= rmse(ml)).all()
+
+
+def test_laplace_variance_matches_monte_carlo(orc):
+    """2000 noise draws of one voxel: the spread of the ML estimates matches
+    the diagonal of P~^{-1} (Laplace approximation / Cramer-Rao bound)."""
+    n = 2000
+    rng = np.random.default_rng(21)
+    proto = synth.protocol()
+    sigma = 0.5  # high SNR so the Laplace approximation is accurate
+    proto["sigma"] = [sigma] * 22
+    y_true = synth.encode([800.0], [0.9], [22.0], [0.015])[:, 0]
+    truth = np.repeat(y_true[:, None], n, axis=1)
+    s = orc.simulate(proto, truth)
+    x = s + sigma * rng.normal(size=s.shape)
+    maps, rep, _ = orc.fit(proto, (n, 1, 1), x, None,
+                           {"mode": "ml", "n_gn": 30, "init": "const", "init_const": y_true})
+    emp = maps.var(axis=1, ddof=1)
+    var = orc.uncertainty(proto, (1, 1, 1), s[:, :1], None, {"mode": "ml"}, y_true.reshape(4, 1))[:, 0]
+    print("empirical", emp, "laplace", var)
+    assert np.allclose(emp, var, rtol=0.1)
+
+
+def test_lognormal_moments_match_sampling(orc):
+    rng = np.random.default_rng(22)
+    proto = synth.protocol()
+    proto["sigma"] = [20.0] * 22  # low SNR: a visibly wide posterior
+    y = synth.encode([700.0], [1.2], [30.0], [0.01])
+    x = orc.simulate(proto, y)
+    var, mom = orc.uncertainty(proto, (1, 1, 1), x, None, {"mode": "ml"}, y, moments=True)
+    v, m = var[1, 0], y[1, 0]
+    samp = rng.normal(m, math.sqrt(v), 2_000_000)
+    assert mom[0, 0] == pytest.approx(np.exp(samp).mean(), rel=2e-3)
+    assert mom[1, 0] == pytest.approx(np.exp(samp).var(), rel=2e-2)
+    assert mom[2, 0] == pytest.approx(np.exp(-samp).mean(), rel=2e-3)
+    assert mom[3, 0] == pytest.approx(np.exp(-samp).var(), rel=2e-2)
+
+
+def test_map_uncertainty_below_ml(orc):
+    """The prior adds curvature, so posterior variances shrink (Sec. 3.6)."""
+    c, x = _brain(seed=8)
+    mp, _, _ = orc.fit(c["proto"], c["dims"], x, c["b1"], dict(c["opts"], n_outer=3, n_gn=4, n_cg=8))
+    v_map = orc.uncertainty(c["proto"], c["dims"], x, c["b1"], c["opts"], mp)
+    v_ml = orc.uncertainty(c["proto"], c["dims"], x, c["b1"], {"mode": "ml"}, mp)
+    assert (v_map <= v_ml * (1 + 1e-12)).all()
+    assert (v_map < v_ml).mean() > 0.99
