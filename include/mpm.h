@@ -1,0 +1,194 @@
+/*
+ * mpm.h -- C ABI of libmpm, a gfx950 (MI355X) implementation of the
+ * voxel-parallel second-order fit of model-based multi-parameter mapping
+ * (Balbastre et al., "Model-Based Multi-Parameter Mapping",
+ * arXiv 2102.01604).
+ *
+ * The library fits log-parameter maps (log A, log R1, log R2*, logit MTsat)
+ * to multi-echo spoiled-gradient-echo (SPGR) magnitude images, by the paper's
+ * Newton-like iteration with its loaded approximate Hessian, either voxelwise
+ * (maximum likelihood, "SPGR-ML") or with the joint-total-variation prior
+ * solved by IRLS + preconditioned conjugate gradient ("SPGR+JTV").
+ *
+ * Conventions shared by every entry point
+ *   - Voxel index n = x + nx*(y + ny*z) (x fastest); N = nx*ny*nz.
+ *   - Images are numbered contrast-major: all echoes of contrast 0, then of
+ *     contrast 1, ...  I = sum of n_echoes.
+ *   - echoes: device array [I][N] of the storage dtype (mpm_dtype);
+ *     maps / var: device float arrays [4][N] in the order
+ *     (log A, log R1, log R2*, logit MTsat); b1: device float [N] or NULL
+ *     (NULL means a transmit efficiency of 1 everywhere).
+ *   - Device pointers belong to the caller and must stay valid until the call
+ *     returns.  The library allocates its own workspace on the given stream
+ *     and frees it before returning.  Calls block until their device work is
+ *     done.  `stream` is a hipStream_t (NULL: the default stream).
+ *   - All arguments are validated on the host before any device work.  On an
+ *     error nothing is written and mpm_last_error() describes the problem.
+ *     Numerical degeneracy (an ill-posed voxel) is not an error: it is
+ *     counted in mpm_report.
+ *   - Arithmetic is FP32 per voxel; objective sums, CG inner products and the
+ *     step-acceptance test are accumulated in FP64.
+ */
+#ifndef MPM_H
+#define MPM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MPM_OK = 0,
+    MPM_ERR_INVALID_ARG = 1,   /* a value or pointer failed validation          */
+    MPM_ERR_UNSUPPORTED = 2,   /* a valid request this build does not handle    */
+    MPM_ERR_OUT_OF_MEMORY = 3, /* workspace allocation failed                   */
+    MPM_ERR_DEVICE = 4,        /* a HIP call failed                             */
+    MPM_ERR_BUSY = 5,          /* server: request not finished yet              */
+    MPM_ERR_NOT_FOUND = 6      /* server: unknown ticket                        */
+} mpm_status;
+
+typedef enum { MPM_F32 = 0, MPM_F16 = 1, MPM_BF16 = 2 } mpm_dtype; /* echo storage only */
+typedef enum { MPM_ML = 0, MPM_MAP_JTV = 1 } mpm_mode;
+typedef enum { MPM_INIT_DEFAULT = 0, MPM_INIT_CONST = 1, MPM_INIT_FROM_MAPS = 2 } mpm_init_kind;
+typedef enum { MPM_LOAD_PROPOSED = 0, MPM_LOAD_GN = 1 } mpm_loading;
+
+#define MPM_MAX_CONTRASTS 8
+#define MPM_MAX_IMAGES 64
+
+/* Acquisition protocol: the fixed parameters theta_i = (alpha_i, TR_i, TE_i,
+ * sigma_i^2) of every image (paper Sec. 2.4).  An MT contrast carries the
+ * off-resonance pulse of the Sec. 2.1 MT signal model (TR2 = 0). */
+typedef struct {
+    int32_t n_contrasts;                  /* 1..MPM_MAX_CONTRASTS              */
+    int32_t n_echoes[MPM_MAX_CONTRASTS];  /* >= 1 each, sum <= MPM_MAX_IMAGES  */
+    double tr_s[MPM_MAX_CONTRASTS];       /* repetition time (s), > 0          */
+    double flip_rad[MPM_MAX_CONTRASTS];   /* nominal flip angle, (0, pi)       */
+    int32_t mt[MPM_MAX_CONTRASTS];        /* 1 = MT-weighted contrast          */
+    double te_s[MPM_MAX_IMAGES];          /* echo time per image (s), >= 0     */
+    double sigma[MPM_MAX_IMAGES];         /* noise std per image, > 0          */
+} mpm_protocol;
+
+typedef struct {
+    int64_t nx, ny, nz; /* each >= 1 */
+} mpm_grid;
+
+typedef struct {
+    int32_t mode;          /* mpm_mode                                               */
+    int32_t n_outer;       /* MAP: IRLS re-weighting loops (paper Sec. 2.7)          */
+    int32_t n_gn;          /* ML: Newton-like steps; MAP: steps per outer loop       */
+    int32_t n_cg;          /* MAP: CG iterations per Newton-like step                */
+    int32_t max_halvings;  /* MAP: step halvings tried by the acceptance test (<= 7); <0 off */
+    int32_t loading;       /* mpm_loading: the paper's loaded Hessian or plain GN    */
+    int32_t init_kind;     /* mpm_init_kind                                          */
+    int32_t flags;         /* reserved, must be 0                                    */
+    double lambda[4];      /* MAP: JTV weight per map, >= 0 (paper Sec. 2.5)         */
+    double jtv_eps;        /* MAP: JTV smoothing; 0 -> 1e-3*sqrt(sum lambda)         */
+    double cg_stop;        /* MAP: stop CG when r.z <= cg_stop*r0.z0; 0 -> fixed n_cg */
+    double init_const[4];  /* MPM_INIT_CONST: the constant initial log-parameters    */
+} mpm_options;
+
+typedef struct {
+    double objective;          /* final NLL (ML) or NLL + smoothed JTV (MAP)          */
+    double nll;                /* final negative log-likelihood                       */
+    double jtv;                /* final smoothed JTV (MAP), 0 for ML                  */
+    int32_t outer_done;        /* MAP outer loops executed                            */
+    int32_t gn_done;           /* Newton-like steps taken (accepted, for MAP)         */
+    int32_t cg_done;           /* CG iterations executed in total                     */
+    int32_t rejected;          /* MAP steps whose every halving increased F_w         */
+    int64_t degenerate_voxels; /* voxels whose last 4x4 solve was degenerate          */
+    int64_t nonfinite_voxels;  /* voxels with a non-finite final map value            */
+    int64_t nll_increases;     /* ML: (voxel, step) pairs whose NLL rose (> 1e-5 rel) */
+} mpm_report;
+
+/*
+ * mpm_fit -- fit the maps (paper Sec. 2.3-2.4 for ML; Sec. 2.5-2.7 for MAP).
+ *
+ * ML: n_gn steps y <- y - P~^{-1} g in every voxel, P~ the loaded approximate
+ * Hessian of eq. precond summed over every echo (Sec. 2.4), g the NLL
+ * gradient.  MAP: for each of n_outer loops, refresh the JTV weights (from
+ * the second loop on; the first loop starts from zero weights), then take
+ * n_gn steps solving (P~ + L) delta = g + L y by n_cg iterations of PCG with
+ * the block-diagonal preconditioner P~ + diag(G^T W G) (x) diag(lambda)
+ * (Sec. 2.6), accepting y - 2^-h delta for the first h <= max_halvings that
+ * does not increase F_w = NLL + 1/2 y^T L y.
+ *
+ * maps: in/out device float [4][N]; read as the initial values when
+ * init_kind = MPM_INIT_FROM_MAPS, overwritten with the result.
+ * report: host, may be NULL.  trace: host double array or NULL; if given it
+ * receives trace_len values (NaN where not reached):
+ *   ML : trace[j] = NLL before step j, trace[n_gn] = final NLL;
+ *   MAP: for outer loop t, slots t*(n_gn+2)+j hold F_w before step 0 (j=0)
+ *        and after step j-1 (j=1..n_gn), then NLL + smoothed JTV at the end
+ *        of the loop.
+ * Errors: MPM_ERR_INVALID_ARG (bad protocol, grid, options or NULL pointer;
+ * |FP16 echo| is not checked), MPM_ERR_UNSUPPORTED (no MT contrast, fewer
+ * than two distinct non-MT flip angles with MPM_INIT_DEFAULT, MAP with N < 2),
+ * MPM_ERR_OUT_OF_MEMORY, MPM_ERR_DEVICE.
+ */
+mpm_status mpm_fit(const mpm_protocol *protocol, const mpm_grid *grid, mpm_dtype dtype,
+                   const void *echoes, const float *b1, const mpm_options *options,
+                   float *maps, mpm_report *report, double *trace, int32_t trace_len,
+                   void *stream);
+
+/*
+ * mpm_uncertainty -- Laplace posterior variance of the log-parameters at
+ * `maps` (paper Sec. 3.6): the diagonal of
+ * (P~ + diag(G^T W G) (x) diag(lambda))^{-1}, W from `maps`; lambda is 0 in
+ * ML mode.  var: device float [4][N]; +inf marks a frozen parameter or a
+ * degenerate voxel.  moments: device float [4][N] or NULL; receives the
+ * log-normal posterior mean and variance of r1 = exp(y1) and of
+ * t1 = exp(-y1): E[r1], V[r1], E[t1], V[t1] (Sec. 3.6).
+ * options: mode, loading, lambda and jtv_eps are used.  Errors as mpm_fit.
+ */
+mpm_status mpm_uncertainty(const mpm_protocol *protocol, const mpm_grid *grid, mpm_dtype dtype,
+                           const void *echoes, const float *b1, const mpm_options *options,
+                           const float *maps, float *var, float *moments, void *stream);
+
+/*
+ * mpm_simulate -- the forward model: SPGR echoes of every image at every
+ * voxel from log-parameter maps (paper Sec. 2.1 eqs. 1-3 with TR2 = 0, in the
+ * log/logit encoding of Sec. 2.4; flip angle alpha_c * b1_n).
+ * maps: device float [4][N]; b1: device float [N] or NULL; noise: device
+ * float [I][N] or NULL, added as sigma_i * noise; out: device [I][N] of
+ * out_dtype (round-to-nearest-even for FP16/BF16).  Errors as mpm_fit.
+ */
+mpm_status mpm_simulate(const mpm_protocol *protocol, const mpm_grid *grid, const float *maps,
+                        const float *b1, const float *noise, mpm_dtype out_dtype, void *out,
+                        void *stream);
+
+/* Device bytes a fit of this size needs: inputs, maps and the library's
+ * workspace.  Returns 0 for invalid arguments. */
+size_t mpm_footprint_bytes(const mpm_protocol *protocol, const mpm_grid *grid, mpm_dtype dtype,
+                           int32_t mode);
+
+/* Text of the last error raised on the calling thread ("" if none). */
+const char *mpm_last_error(void);
+
+/* Library version string. */
+const char *mpm_version(void);
+
+/*
+ * Kernel timing for measurement tools.  mpm_profile_enable(k) with k >= 1
+ * brackets one in every k launches of each kernel with HIP events on the
+ * launch stream (k = 0 turns timing off and is the default); the elapsed
+ * times are collected when each call finishes.  mpm_profile_read copies up to
+ * `max` records and returns how many kernels have records.
+ */
+typedef struct {
+    char name[40];
+    int64_t launches;   /* launches since the last reset              */
+    int64_t timed;      /* launches that were bracketed by events     */
+    double timed_ms;    /* summed event time of the timed launches    */
+    double bytes;       /* algorithmic HBM bytes of all launches      */
+} mpm_kernel_stat;
+
+void mpm_profile_enable(int32_t every);
+void mpm_profile_reset(void);
+int32_t mpm_profile_read(mpm_kernel_stat *out, int32_t max);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

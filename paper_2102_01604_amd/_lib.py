@@ -1,0 +1,221 @@
+"""ctypes binding of libmpm (include/mpm.h): argument marshalling only.
+
+Every step of the fit runs in the HIP library; torch is used for device memory
+and streams.  Importing this module does not load the library; the first call
+does, and raises if ``libmpm.so`` has not been built (there is no fallback).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmpm.so")
+
+MPM_MAX_CONTRASTS = 8
+MPM_MAX_IMAGES = 64
+MPM_F32, MPM_F16, MPM_BF16 = 0, 1, 2
+MPM_ML, MPM_MAP_JTV = 0, 1
+MPM_INIT_DEFAULT, MPM_INIT_CONST, MPM_INIT_FROM_MAPS = 0, 1, 2
+MPM_LOAD_PROPOSED, MPM_LOAD_GN = 0, 1
+STATUS = {0: "MPM_OK", 1: "MPM_ERR_INVALID_ARG", 2: "MPM_ERR_UNSUPPORTED", 3: "MPM_ERR_OUT_OF_MEMORY",
+          4: "MPM_ERR_DEVICE", 5: "MPM_ERR_BUSY", 6: "MPM_ERR_NOT_FOUND"}
+
+
+class mpm_protocol(C.Structure):
+    _fields_ = [("n_contrasts", C.c_int32), ("n_echoes", C.c_int32 * MPM_MAX_CONTRASTS),
+                ("tr_s", C.c_double * MPM_MAX_CONTRASTS), ("flip_rad", C.c_double * MPM_MAX_CONTRASTS),
+                ("mt", C.c_int32 * MPM_MAX_CONTRASTS), ("te_s", C.c_double * MPM_MAX_IMAGES),
+                ("sigma", C.c_double * MPM_MAX_IMAGES)]
+
+
+class mpm_grid(C.Structure):
+    _fields_ = [("nx", C.c_int64), ("ny", C.c_int64), ("nz", C.c_int64)]
+
+
+class mpm_options(C.Structure):
+    _fields_ = [("mode", C.c_int32), ("n_outer", C.c_int32), ("n_gn", C.c_int32), ("n_cg", C.c_int32),
+                ("max_halvings", C.c_int32), ("loading", C.c_int32), ("init_kind", C.c_int32),
+                ("flags", C.c_int32), ("lam", C.c_double * 4), ("jtv_eps", C.c_double),
+                ("cg_stop", C.c_double), ("init_const", C.c_double * 4)]
+
+
+class mpm_report(C.Structure):
+    _fields_ = [("objective", C.c_double), ("nll", C.c_double), ("jtv", C.c_double),
+                ("outer_done", C.c_int32), ("gn_done", C.c_int32), ("cg_done", C.c_int32),
+                ("rejected", C.c_int32), ("degenerate_voxels", C.c_int64),
+                ("nonfinite_voxels", C.c_int64), ("nll_increases", C.c_int64)]
+
+
+class mpm_kernel_stat(C.Structure):
+    _fields_ = [("name", C.c_char * 40), ("launches", C.c_int64), ("timed", C.c_int64),
+                ("timed_ms", C.c_double), ("bytes", C.c_double)]
+
+
+class MpmError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+# every function declared in include/mpm.h, with its ctypes signature
+_P, _G, _O, _R = C.POINTER(mpm_protocol), C.POINTER(mpm_grid), C.POINTER(mpm_options), C.POINTER(mpm_report)
+SIGNATURES = {
+    "mpm_fit": (C.c_int, [_P, _G, C.c_int, C.c_void_p, C.c_void_p, _O, C.c_void_p, _R,
+                          C.POINTER(C.c_double), C.c_int32, C.c_void_p]),
+    "mpm_uncertainty": (C.c_int, [_P, _G, C.c_int, C.c_void_p, C.c_void_p, _O, C.c_void_p, C.c_void_p,
+                                  C.c_void_p, C.c_void_p]),
+    "mpm_simulate": (C.c_int, [_P, _G, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]),
+    "mpm_footprint_bytes": (C.c_size_t, [_P, _G, C.c_int, C.c_int32]),
+    "mpm_last_error": (C.c_char_p, []),
+    "mpm_version": (C.c_char_p, []),
+    "mpm_profile_enable": (None, [C.c_int32]),
+    "mpm_profile_reset": (None, []),
+    "mpm_profile_read": (C.c_int32, [C.POINTER(mpm_kernel_stat), C.c_int32]),
+}
+
+
+def load():
+    """Load libmpm.so (raises if it is missing: there is no CPU fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() or "
+                               "python paper_2102_01604_amd/build.py")
+        lib = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _check(st):
+    if st != 0:
+        raise MpmError(st, load().mpm_last_error().decode())
+
+
+def make_protocol(proto: dict) -> mpm_protocol:
+    p = mpm_protocol()
+    nc = len(proto["n_echoes"])
+    p.n_contrasts = nc
+    for c in range(min(nc, MPM_MAX_CONTRASTS)):
+        p.n_echoes[c] = int(proto["n_echoes"][c])
+        p.tr_s[c] = float(proto["tr"][c])
+        p.flip_rad[c] = float(proto["flip"][c])
+        p.mt[c] = int(proto["mt"][c])
+    for i in range(min(len(proto["te"]), MPM_MAX_IMAGES)):
+        p.te_s[i] = float(proto["te"][i])
+        p.sigma[i] = float(proto["sigma"][i])
+    return p
+
+
+def make_grid(dims) -> mpm_grid:
+    g = mpm_grid()
+    g.nx, g.ny, g.nz = (int(v) for v in dims)
+    return g
+
+
+def make_options(opts: dict) -> mpm_options:
+    o = mpm_options()
+    o.mode = {"ml": MPM_ML, "map": MPM_MAP_JTV}[opts.get("mode", "ml")]
+    o.n_outer = int(opts.get("n_outer", 1))
+    o.n_gn = int(opts.get("n_gn", 20))
+    o.n_cg = int(opts.get("n_cg", 32))
+    o.max_halvings = int(opts.get("max_halvings", 4))
+    o.loading = {"proposed": MPM_LOAD_PROPOSED, "gn": MPM_LOAD_GN}[opts.get("loading", "proposed")]
+    o.init_kind = {"default": MPM_INIT_DEFAULT, "const": MPM_INIT_CONST,
+                   "maps": MPM_INIT_FROM_MAPS}[opts.get("init", "default")]
+    o.flags = int(opts.get("flags", 0))
+    lam = opts.get("lam", (0.0, 0.0, 0.0, 0.0))
+    for k in range(4):
+        o.lam[k] = float(lam[k])
+    o.jtv_eps = float(opts.get("jtv_eps", 0.0))
+    o.cg_stop = float(opts.get("cg_stop", 0.0))
+    ic = opts.get("init_const", (0.0, 0.0, 0.0, 0.0))
+    for k in range(4):
+        o.init_const[k] = float(ic[k])
+    return o
+
+
+def trace_len(opts: dict) -> int:
+    if opts.get("mode", "ml") == "ml":
+        return int(opts.get("n_gn", 20)) + 1
+    return int(opts.get("n_outer", 1)) * (int(opts.get("n_gn", 20)) + 2)
+
+
+def _dtype_code(t):
+    import torch
+    return {torch.float32: MPM_F32, torch.float16: MPM_F16, torch.bfloat16: MPM_BF16}[t.dtype]
+
+
+def _stream(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def mpm_fit(protocol: dict, dims, echoes, b1, options: dict, maps, stream=None):
+    """Run mpm_fit on device tensors.  ``maps`` (float32 [4][N]) is updated in
+    place.  Returns (report dict, trace numpy array)."""
+    lib = load()
+    tl = trace_len(options)
+    trace = (C.c_double * tl)()
+    rep = mpm_report()
+    _check(lib.mpm_fit(C.byref(make_protocol(protocol)), C.byref(make_grid(dims)), _dtype_code(echoes),
+                       _ptr(echoes), _ptr(b1), C.byref(make_options(options)), _ptr(maps), C.byref(rep),
+                       trace, tl, _stream(stream)))
+    report = {f[0]: getattr(rep, f[0]) for f in mpm_report._fields_}
+    return report, np.array(trace[:], dtype=np.float64)
+
+
+def mpm_uncertainty(protocol: dict, dims, echoes, b1, options: dict, maps, var, moments=None, stream=None):
+    lib = load()
+    _check(lib.mpm_uncertainty(C.byref(make_protocol(protocol)), C.byref(make_grid(dims)), _dtype_code(echoes),
+                               _ptr(echoes), _ptr(b1), C.byref(make_options(options)), _ptr(maps), _ptr(var),
+                               _ptr(moments), _stream(stream)))
+
+
+def mpm_simulate(protocol: dict, dims, maps, b1, noise, out, stream=None):
+    lib = load()
+    _check(lib.mpm_simulate(C.byref(make_protocol(protocol)), C.byref(make_grid(dims)), _ptr(maps), _ptr(b1),
+                            _ptr(noise), _dtype_code(out), _ptr(out), _stream(stream)))
+
+
+def mpm_footprint_bytes(protocol: dict, dims, dtype: int, mode: int) -> int:
+    return int(load().mpm_footprint_bytes(C.byref(make_protocol(protocol)), C.byref(make_grid(dims)), dtype, mode))
+
+
+def mpm_version() -> str:
+    return load().mpm_version().decode()
+
+
+def mpm_profile_enable(every: int):
+    load().mpm_profile_enable(int(every))
+
+
+def mpm_profile_reset():
+    load().mpm_profile_reset()
+
+
+def mpm_profile_read():
+    lib = load()
+    arr = (mpm_kernel_stat * 64)()
+    n = lib.mpm_profile_read(arr, 64)
+    return {arr[i].name.decode(): {"launches": arr[i].launches, "timed": arr[i].timed,
+                                   "timed_ms": arr[i].timed_ms, "bytes": arr[i].bytes}
+            for i in range(min(n, 64))}
+
+
+def nan_trace_ok(trace) -> bool:
+    return all(math.isnan(v) or math.isfinite(v) for v in trace)

@@ -1,0 +1,268 @@
+// k_voxel.hip -- voxelwise kernels of libmpm: forward model, per-image means,
+// the maximum-likelihood fit (SPGR-ML) and a fixed-order row reduction.
+#include "mpm_kernels.h"
+
+namespace mpm {
+
+// ---------------------------------------------------------------------------
+// fills
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(BLOCK) void k_fill_maps(float *maps, int64_t N, float y0, float y1,
+                                                     float y2, float y3)
+{
+    int64_t n = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (n >= N) return;
+    maps[n] = y0;
+    maps[N + n] = y1;
+    maps[2 * N + n] = y2;
+    maps[3 * N + n] = y3;
+}
+
+hipError_t launch_fill_maps(const LaunchCtx &c, float *maps, int64_t N, const float y0[4])
+{
+    int nb = (int)((N + BLOCK - 1) / BLOCK);
+    hipLaunchKernelGGL(k_fill_maps, dim3(nb), dim3(BLOCK), 0, c.stream, maps, N, y0[0], y0[1], y0[2],
+                       y0[3]);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(BLOCK) void k_fill(float *p, int64_t n, float v)
+{
+    int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+hipError_t launch_fill(const LaunchCtx &c, float *p, int64_t n, float v)
+{
+    if (n <= 0) return hipSuccess;
+    int nb = (int)((n + BLOCK - 1) / BLOCK);
+    hipLaunchKernelGGL(k_fill, dim3(nb), dim3(BLOCK), 0, c.stream, p, n, v);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// forward model: out[i][n] = s_i(y_n) + sigma_i * noise[i][n]
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_simulate(DevProto P, const float *__restrict__ maps,
+                                                    const float *__restrict__ b1,
+                                                    const float *__restrict__ noise, T *__restrict__ out,
+                                                    int64_t N)
+{
+    int64_t n = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (n >= N) return;
+    float y[4] = {maps[n], maps[N + n], maps[2 * N + n], maps[3 * N + n]};
+    float b = b1 ? b1[n] : 1.0f;
+    Params p = decode(y);
+    for (int c = 0; c < P.C; c++) {
+        ContrastK K = contrast_factors(p, P.tr[c], make_angle(P.flip[c] * b), P.mt[c]);
+        for (int i = P.first[c]; i < P.first[c + 1]; i++) {
+            float s = K.s0 * __expf(-p.r2 * P.te[i]);
+            if (noise) s += rsqrtf(P.wgt[i]) * noise[(int64_t)i * N + n];
+            store_echo(out + (int64_t)i * N + n, s);
+        }
+    }
+}
+
+hipError_t launch_simulate(const LaunchCtx &c, const DevProto &P, const float *maps, const float *b1,
+                           const float *noise, int dtype, void *out, int64_t N)
+{
+    int nb = (int)((N + BLOCK - 1) / BLOCK);
+    if (dtype == DT_F32)
+        hipLaunchKernelGGL(k_simulate<float>, dim3(nb), dim3(BLOCK), 0, c.stream, P, maps, b1, noise,
+                           (float *)out, N);
+    else if (dtype == DT_F16)
+        hipLaunchKernelGGL(k_simulate<F16>, dim3(nb), dim3(BLOCK), 0, c.stream, P, maps, b1, noise,
+                           (F16 *)out, N);
+    else
+        hipLaunchKernelGGL(k_simulate<BF16>, dim3(nb), dim3(BLOCK), 0, c.stream, P, maps, b1, noise,
+                           (BF16 *)out, N);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// per-image sums (for the default initialisation): grid (nblk, I + 1)
+// ---------------------------------------------------------------------------
+constexpr int SUM_ITEMS = 16;  // voxels per thread
+
+int echo_sums_blocks(int64_t N)
+{
+    int64_t per = (int64_t)BLOCK * SUM_ITEMS;
+    return (int)((N + per - 1) / per);
+}
+
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_echo_sums(int I, const T *__restrict__ X,
+                                                     const float *__restrict__ b1, int64_t N,
+                                                     double *__restrict__ partials)
+{
+    __shared__ double lds[1][NWAVE];
+    int row = blockIdx.y;
+    int64_t base = (int64_t)blockIdx.x * BLOCK * SUM_ITEMS + threadIdx.x;
+    double v[1] = {0.0};
+    for (int j = 0; j < SUM_ITEMS; j++) {
+        int64_t n = base + (int64_t)j * BLOCK;
+        if (n >= N) break;
+        if (row < I) v[0] += (double)load_echo(X + (int64_t)row * N + n);
+        else v[0] += b1 ? (double)b1[n] : 1.0;
+    }
+    block_sum<1>(v, lds);
+    if (threadIdx.x == 0) partials[(int64_t)row * gridDim.x + blockIdx.x] = v[0];
+}
+
+hipError_t launch_echo_sums(const LaunchCtx &c, const DevProto &P, int dtype, const void *X,
+                            const float *b1, int64_t N, double *partials, int nblk)
+{
+    dim3 g(nblk, P.I + 1);
+    if (dtype == DT_F32)
+        hipLaunchKernelGGL(k_echo_sums<float>, g, dim3(BLOCK), 0, c.stream, P.I, (const float *)X, b1, N,
+                           partials);
+    else if (dtype == DT_F16)
+        hipLaunchKernelGGL(k_echo_sums<F16>, g, dim3(BLOCK), 0, c.stream, P.I, (const F16 *)X, b1, N,
+                           partials);
+    else
+        hipLaunchKernelGGL(k_echo_sums<BF16>, g, dim3(BLOCK), 0, c.stream, P.I, (const BF16 *)X, b1, N,
+                           partials);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// fixed-order reduction of rows: one workgroup per row
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(BLOCK) void k_reduce_rows(const double *__restrict__ in, int ncols,
+                                                       double *__restrict__ out)
+{
+    __shared__ double lds[1][NWAVE];
+    const double *row = in + (int64_t)blockIdx.x * ncols;
+    double v[1] = {0.0};
+    for (int b = threadIdx.x; b < ncols; b += BLOCK) v[0] += row[b];
+    block_sum<1>(v, lds);
+    if (threadIdx.x == 0) out[blockIdx.x] = v[0];
+}
+
+hipError_t launch_reduce_rows(const LaunchCtx &c, const double *in, int nrows, int ncols, double *out)
+{
+    hipLaunchKernelGGL(k_reduce_rows, dim3(nrows), dim3(BLOCK), 0, c.stream, in, ncols, out);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// ML fit (paper Sec. 2.3-2.4): each thread owns one voxel, keeps its echoes in
+// registers and runs all n_gn Newton-like steps y <- y - P~^{-1} g.
+// CM x EM bounds the echoes held in registers (contrasts x echoes each).
+// ---------------------------------------------------------------------------
+int ml_fit_blocks(int64_t N) { return (int)((N + BLOCK - 1) / BLOCK); }
+
+template <typename T, int CM, int EM>
+__global__ __launch_bounds__(BLOCK) void k_ml_fit(DevProto P, const T *__restrict__ X,
+                                                  const float *__restrict__ b1, float *__restrict__ maps,
+                                                  int64_t N, int n_gn, int loading,
+                                                  double *__restrict__ partials)
+{
+    __shared__ double lds[1][NWAVE];
+    const int nblk = gridDim.x;
+    int64_t n = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    const bool active = n < N;
+    const int64_t nn = active ? n : 0;
+
+    float x[CM][EM];
+    Angle an[CM];
+    float b = b1 ? b1[nn] : 1.0f;
+#pragma unroll
+    for (int c = 0; c < CM; c++) {
+        if (c < P.C) {
+            an[c] = make_angle(P.flip[c] * b);
+            int i0 = P.first[c], ne = P.first[c + 1] - i0;
+#pragma unroll
+            for (int e = 0; e < EM; e++)
+                x[c][e] = (e < ne) ? load_echo(X + (int64_t)(i0 + e) * N + nn) : 0.0f;
+        }
+    }
+    float y[4] = {maps[nn], maps[N + nn], maps[2 * N + nn], maps[3 * N + nn]};
+
+    float prev_nll = 0.0f;
+    double cnt_inc = 0.0, degen = 0.0;
+    for (int it = 0; it <= n_gn; it++) {
+        const bool last = (it == n_gn);
+        Params p = decode(y);
+        float g[4] = {0.f, 0.f, 0.f, 0.f};
+        float H[10] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        float nll = 0.0f;
+#pragma unroll
+        for (int c = 0; c < CM; c++) {
+            if (c < P.C) {
+                ContrastK K = contrast_factors(p, P.tr[c], an[c], P.mt[c]);
+                int i0 = P.first[c], ne = P.first[c + 1] - i0;
+                EchoAcc acc;
+#pragma unroll
+                for (int e = 0; e < EM; e++) {
+                    if (e < ne) {
+                        float te = P.te[i0 + e];
+                        float s = K.s0 * __expf(-p.r2 * te);
+                        acc.add(s, x[c][e], te, P.wgt[i0 + e], p.r2);
+                    }
+                }
+                nll += 0.5f * acc.L;
+                if (!last) accumulate_contrast(acc, K, p.r2, loading, g, H);
+            }
+        }
+        if (it > 0 && nll > prev_nll * (1.0f + 1e-5f)) cnt_inc += 1.0;
+        prev_nll = nll;
+        double v[1] = {active ? (double)nll : 0.0};
+        block_sum<1>(v, lds);
+        if (threadIdx.x == 0) partials[(int64_t)it * nblk + blockIdx.x] = v[0];
+        __syncthreads();
+        if (last) break;
+        float step[4];
+        bool bad = solve_sym4(H, g, step);
+        degen = bad ? 1.0 : 0.0;
+#pragma unroll
+        for (int k = 0; k < 4; k++) y[k] -= step[k];
+    }
+    double fin = 0.0;
+#pragma unroll
+    for (int k = 0; k < 4; k++) fin += (fabsf(y[k]) < INFINITY) ? 0.0 : 1.0;
+    double st[3] = {active ? (n_gn > 0 ? degen : 0.0) : 0.0, (active && fin > 0.0) ? 1.0 : 0.0,
+                    active ? cnt_inc : 0.0};
+    __shared__ double lds3[3][NWAVE];
+    block_sum<3>(st, lds3);
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 3; k++) partials[(int64_t)(n_gn + 1 + k) * nblk + blockIdx.x] = st[k];
+    if (active) {
+        maps[n] = y[0];
+        maps[N + n] = y[1];
+        maps[2 * N + n] = y[2];
+        maps[3 * N + n] = y[3];
+    }
+}
+
+template <typename T>
+static hipError_t ml_dispatch(const LaunchCtx &c, const DevProto &P, const T *X, const float *b1,
+                              float *maps, int64_t N, int n_gn, int loading, double *partials, int nblk)
+{
+    int emax = 0;
+    for (int k = 0; k < P.C; k++) emax = max(emax, P.first[k + 1] - P.first[k]);
+    dim3 g(nblk), b(BLOCK);
+    if (P.C <= 4 && emax <= 8)
+        hipLaunchKernelGGL((k_ml_fit<T, 4, 8>), g, b, 0, c.stream, P, X, b1, maps, N, n_gn, loading, partials);
+    else if (P.C <= 4 && emax <= 16)
+        hipLaunchKernelGGL((k_ml_fit<T, 4, 16>), g, b, 0, c.stream, P, X, b1, maps, N, n_gn, loading, partials);
+    else if (emax <= 8)
+        hipLaunchKernelGGL((k_ml_fit<T, 8, 8>), g, b, 0, c.stream, P, X, b1, maps, N, n_gn, loading, partials);
+    else
+        return hipErrorInvalidValue;  // rejected on the host before launch
+    return hipGetLastError();
+}
+
+hipError_t launch_ml_fit(const LaunchCtx &c, const DevProto &P, int dtype, const void *X,
+                         const float *b1, float *maps, int64_t N, int n_gn, int loading,
+                         double *partials, int nblk)
+{
+    if (dtype == DT_F32)
+        return ml_dispatch(c, P, (const float *)X, b1, maps, N, n_gn, loading, partials, nblk);
+    if (dtype == DT_F16)
+        return ml_dispatch(c, P, (const F16 *)X, b1, maps, N, n_gn, loading, partials, nblk);
+    return ml_dispatch(c, P, (const BF16 *)X, b1, maps, N, n_gn, loading, partials, nblk);
+}
+
+}  // namespace mpm

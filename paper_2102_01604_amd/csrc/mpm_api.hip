@@ -1,0 +1,433 @@
+// mpm_api.hip -- the C ABI of libmpm (declared in include/mpm.h): argument
+// validation, workspace management, kernel orchestration and kernel timing.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/mpm.h"
+#include "mpm_api_internal.h"
+#include "mpm_kernels.h"
+
+using namespace mpm;
+
+namespace mpm {
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+static thread_local std::string t_last_error;
+
+mpm_status fail(mpm_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    t_last_error = buf;
+    return st;
+}
+
+void clear_error() { t_last_error.clear(); }
+
+// ---------------------------------------------------------------------------
+// kernel timing registry
+// ---------------------------------------------------------------------------
+static std::mutex g_prof_mu;
+static std::vector<mpm_kernel_stat> g_stats;
+static int g_every = 0;
+
+static int stat_id(const char *name)
+{
+    for (size_t i = 0; i < g_stats.size(); i++)
+        if (!strcmp(g_stats[i].name, name)) return (int)i;
+    mpm_kernel_stat s;
+    memset(&s, 0, sizeof(s));
+    snprintf(s.name, sizeof(s.name), "%s", name);
+    g_stats.push_back(s);
+    return (int)g_stats.size() - 1;
+}
+
+hipError_t Prof::launch(const char *name, double bytes, const std::function<hipError_t()> &fn)
+{
+    int every, id;
+    int64_t count;
+    {
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        every = g_every;
+        id = stat_id(name);
+        count = g_stats[id].launches++;
+        g_stats[id].bytes += bytes;
+    }
+    bool timed = every > 0 && (count % every) == 0;
+    hipEvent_t a = nullptr, b = nullptr;
+    if (timed) {
+        if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) timed = false;
+        else hipEventRecord(a, stream);
+    }
+    hipError_t e = fn();
+    if (timed) {
+        hipEventRecord(b, stream);
+        pend.push_back({id, a, b});
+    }
+    return e;
+}
+
+void Prof::collect()
+{
+    for (auto &p : pend) {
+        float ms = 0.f;
+        hipEventSynchronize(p.b);
+        hipEventElapsedTime(&ms, p.a, p.b);
+        hipEventDestroy(p.a);
+        hipEventDestroy(p.b);
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        g_stats[p.id].timed++;
+        g_stats[p.id].timed_ms += ms;
+    }
+    pend.clear();
+}
+
+Prof::~Prof()
+{
+    for (auto &p : pend) {
+        hipEventDestroy(p.a);
+        hipEventDestroy(p.b);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// validation
+// ---------------------------------------------------------------------------
+int n_images(const mpm_protocol *p)
+{
+    int I = 0;
+    for (int c = 0; c < p->n_contrasts; c++) I += p->n_echoes[c];
+    return I;
+}
+
+mpm_status check_protocol(const mpm_protocol *p)
+{
+    if (!p) return fail(MPM_ERR_INVALID_ARG, "protocol is NULL");
+    if (p->n_contrasts < 1 || p->n_contrasts > MPM_MAX_CONTRASTS)
+        return fail(MPM_ERR_INVALID_ARG, "n_contrasts=%d outside [1, %d]", p->n_contrasts, MPM_MAX_CONTRASTS);
+    int I = 0;
+    for (int c = 0; c < p->n_contrasts; c++) {
+        if (p->n_echoes[c] < 1) return fail(MPM_ERR_INVALID_ARG, "contrast %d has %d echoes", c, p->n_echoes[c]);
+        I += p->n_echoes[c];
+        if (I > MPM_MAX_IMAGES) return fail(MPM_ERR_INVALID_ARG, "more than %d images", MPM_MAX_IMAGES);
+        if (!(p->tr_s[c] > 0.0) || !std::isfinite(p->tr_s[c]))
+            return fail(MPM_ERR_INVALID_ARG, "contrast %d: TR must be > 0", c);
+        if (!(p->flip_rad[c] > 0.0) || !(p->flip_rad[c] < M_PI))
+            return fail(MPM_ERR_INVALID_ARG, "contrast %d: flip angle must be in (0, pi)", c);
+        if (p->mt[c] != 0 && p->mt[c] != 1) return fail(MPM_ERR_INVALID_ARG, "contrast %d: mt must be 0 or 1", c);
+    }
+    for (int i = 0; i < I; i++) {
+        if (!(p->te_s[i] >= 0.0) || !std::isfinite(p->te_s[i]))
+            return fail(MPM_ERR_INVALID_ARG, "image %d: TE must be >= 0", i);
+        if (!(p->sigma[i] > 0.0) || !std::isfinite(p->sigma[i]))
+            return fail(MPM_ERR_INVALID_ARG, "image %d: sigma must be > 0", i);
+    }
+    return MPM_OK;
+}
+
+mpm_status check_grid(const mpm_grid *g, int64_t *N)
+{
+    if (!g) return fail(MPM_ERR_INVALID_ARG, "grid is NULL");
+    if (g->nx < 1 || g->ny < 1 || g->nz < 1)
+        return fail(MPM_ERR_INVALID_ARG, "grid %lld x %lld x %lld has an empty axis", (long long)g->nx,
+                    (long long)g->ny, (long long)g->nz);
+    if (g->nx > (1 << 20) || g->ny > (1 << 20) || g->nz > (1 << 20))
+        return fail(MPM_ERR_INVALID_ARG, "grid axis longer than 2^20");
+    int64_t n = g->nx * g->ny * g->nz;
+    if (n > ((int64_t)1 << 31) - 1) return fail(MPM_ERR_INVALID_ARG, "grid has more than 2^31-1 voxels");
+    *N = n;
+    return MPM_OK;
+}
+
+mpm_status check_dtype(int dtype)
+{
+    if (dtype != MPM_F32 && dtype != MPM_F16 && dtype != MPM_BF16)
+        return fail(MPM_ERR_INVALID_ARG, "unknown echo dtype %d", dtype);
+    return MPM_OK;
+}
+
+bool has_mt(const mpm_protocol *p)
+{
+    for (int c = 0; c < p->n_contrasts; c++)
+        if (p->mt[c]) return true;
+    return false;
+}
+
+DevProto to_dev(const mpm_protocol *p)
+{
+    DevProto d;
+    memset(&d, 0, sizeof(d));
+    d.C = p->n_contrasts;
+    int i = 0;
+    for (int c = 0; c < p->n_contrasts; c++) {
+        d.first[c] = i;
+        d.tr[c] = (float)p->tr_s[c];
+        d.flip[c] = (float)p->flip_rad[c];
+        d.mt[c] = p->mt[c];
+        i += p->n_echoes[c];
+    }
+    d.first[p->n_contrasts] = i;
+    d.I = i;
+    for (int k = 0; k < i; k++) {
+        d.te[k] = (float)p->te_s[k];
+        d.wgt[k] = (float)(1.0 / (p->sigma[k] * p->sigma[k]));
+    }
+    return d;
+}
+
+size_t dtype_size(int dtype) { return dtype == MPM_F32 ? 4 : 2; }
+
+// ---------------------------------------------------------------------------
+// default initialisation from per-image volume means: a log-linear fit with
+// one shared R2* gives the TE = 0 intercept of each contrast; small-angle
+// closed forms (Helms et al. 2008, the approximation the paper's MT model
+// comes from) give A and R1 from the two non-MT contrasts with the smallest
+// and largest flip angle and MTsat from the first MT contrast.
+// ---------------------------------------------------------------------------
+static double clampd(double v, double lo, double hi) { return v >= lo ? (v <= hi ? v : hi) : lo; }
+
+mpm_status default_init_from_means(const mpm_protocol *p, const double *mean, double b1_mean, float y0[4])
+{
+    const int C = p->n_contrasts, U = C + 1;
+    // normal equations of  log m_i = beta_c(i) - r2 * TE_i
+    double A[MPM_MAX_CONTRASTS + 1][MPM_MAX_CONTRASTS + 2] = {};
+    int i = 0;
+    for (int c = 0; c < C; c++)
+        for (int e = 0; e < p->n_echoes[c]; e++, i++) {
+            double lm = std::log(std::max(mean[i], 1e-12));
+            double te = p->te_s[i];
+            A[c][c] += 1.0;
+            A[c][C] -= te;
+            A[C][c] -= te;
+            A[C][C] += te * te;
+            A[c][U] += lm;
+            A[C][U] -= te * lm;
+        }
+    for (int col = 0; col < U; col++) {
+        int piv = col;
+        for (int r = col + 1; r < U; r++)
+            if (std::fabs(A[r][col]) > std::fabs(A[piv][col])) piv = r;
+        if (std::fabs(A[piv][col]) < 1e-300)
+            return fail(MPM_ERR_UNSUPPORTED, "default init: echo times do not determine R2*");
+        for (int k = 0; k <= U; k++) std::swap(A[col][k], A[piv][k]);
+        for (int r = 0; r < U; r++) {
+            if (r == col) continue;
+            double f = A[r][col] / A[col][col];
+            for (int k = col; k <= U; k++) A[r][k] -= f * A[col][k];
+        }
+    }
+    double beta[MPM_MAX_CONTRASTS + 1];
+    for (int u = 0; u < U; u++) beta[u] = A[u][U] / A[u][u];
+    int cP = -1, cT = -1, cM = -1;
+    for (int c = 0; c < C; c++) {
+        if (p->mt[c]) {
+            if (cM < 0) cM = c;
+        } else {
+            if (cP < 0 || p->flip_rad[c] < p->flip_rad[cP]) cP = c;
+            if (cT < 0 || p->flip_rad[c] > p->flip_rad[cT]) cT = c;
+        }
+    }
+    if (cM < 0 || cP < 0 || cT < 0 || p->flip_rad[cP] == p->flip_rad[cT])
+        return fail(MPM_ERR_UNSUPPORTED,
+                    "default init needs an MT contrast and two non-MT contrasts with distinct flip angles");
+    double SP = std::exp(beta[cP]), ST = std::exp(beta[cT]), SM = std::exp(beta[cM]);
+    double aP = p->flip_rad[cP] * b1_mean, aT = p->flip_rad[cT] * b1_mean, aM = p->flip_rad[cM] * b1_mean;
+    double tP = p->tr_s[cP], tT = p->tr_s[cT], tM = p->tr_s[cM];
+    double R1 = 0.5 * (ST * aT / tT - SP * aP / tP) / (SP / aP - ST / aT);
+    double Aa = SP * ST * (tP * aT / aP - tT * aP / aT) / (ST * tP * aT - SP * tT * aP);
+    R1 = clampd(R1, 0.05, 20.0);
+    if (!(Aa > 0.0) || !std::isfinite(Aa)) Aa = SP / std::sin(aP);
+    double dl = clampd((Aa * aM / SM - 1.0) * R1 * tM - 0.5 * aM * aM, 1e-4, 0.2);
+    double r2 = clampd(beta[C], 0.5, 500.0);
+    y0[0] = (float)std::log(Aa);
+    y0[1] = (float)std::log(R1);
+    y0[2] = (float)std::log(r2);
+    y0[3] = (float)std::log(dl / (1.0 - dl));
+    return MPM_OK;
+}
+
+// device buffer helper (stream-ordered)
+hipError_t Workspace::alloc(void **p, size_t bytes)
+{
+    if (bytes == 0) bytes = 256;
+    hipError_t e = hipMallocAsync(p, bytes, stream);
+    if (e == hipSuccess) bufs.push_back(*p);
+    return e;
+}
+
+Workspace::~Workspace()
+{
+    for (void *p : bufs) hipFreeAsync(p, stream);
+    hipStreamSynchronize(stream);
+}
+
+// Per-image means and the mean b1, reduced on the device in FP64.
+mpm_status image_means(Workspace &ws, Prof &prof, const DevProto &P, int dtype, const void *X,
+                       const float *b1, int64_t N, std::vector<double> &mean, double &b1m)
+{
+    LaunchCtx c{ws.stream};
+    int nblk = echo_sums_blocks(N);
+    double *part = nullptr, *sums = nullptr;
+    if (ws.alloc((void **)&part, sizeof(double) * (size_t)nblk * (P.I + 1)) != hipSuccess ||
+        ws.alloc((void **)&sums, sizeof(double) * (P.I + 1)) != hipSuccess)
+        return fail(MPM_ERR_OUT_OF_MEMORY, "workspace allocation failed");
+    hipError_t e = prof.launch("echo_sums", (double)N * ((double)P.I * dtype_size(dtype) + (b1 ? 4 : 0)),
+                               [&] { return launch_echo_sums(c, P, dtype, X, b1, N, part, nblk); });
+    if (e == hipSuccess) e = launch_reduce_rows(c, part, P.I + 1, nblk, sums);
+    std::vector<double> host(P.I + 1);
+    if (e == hipSuccess) e = hipMemcpyAsync(host.data(), sums, sizeof(double) * (P.I + 1), hipMemcpyDeviceToHost, ws.stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ws.stream);
+    if (e != hipSuccess) return fail(MPM_ERR_DEVICE, "image means: %s", hipGetErrorString(e));
+    mean.resize(P.I);
+    for (int i = 0; i < P.I; i++) mean[i] = host[i] / (double)N;
+    b1m = host[P.I] / (double)N;
+    return MPM_OK;
+}
+
+}  // namespace mpm
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char *mpm_last_error(void) { return t_last_error.c_str(); }
+
+const char *mpm_version(void) { return "libmpm 0.1 (gfx950)"; }
+
+void mpm_profile_enable(int32_t every)
+{
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_every = every > 0 ? every : 0;
+}
+
+void mpm_profile_reset(void)
+{
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_stats.clear();
+}
+
+int32_t mpm_profile_read(mpm_kernel_stat *out, int32_t max)
+{
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    int32_t n = (int32_t)g_stats.size();
+    for (int32_t i = 0; i < n && i < max; i++) out[i] = g_stats[i];
+    return n;
+}
+
+mpm_status mpm_simulate(const mpm_protocol *protocol, const mpm_grid *grid, const float *maps, const float *b1,
+                        const float *noise, mpm_dtype out_dtype, void *out, void *stream)
+{
+    clear_error();
+    int64_t N;
+    mpm_status st;
+    if ((st = check_protocol(protocol)) || (st = check_grid(grid, &N)) || (st = check_dtype(out_dtype))) return st;
+    if (!maps || !out) return fail(MPM_ERR_INVALID_ARG, "maps and out must be device pointers");
+    DevProto P = to_dev(protocol);
+    hipStream_t s = (hipStream_t)stream;
+    Prof prof(s);
+    LaunchCtx c{s};
+    double bytes = (double)N * (16.0 + (b1 ? 4 : 0) + P.I * (dtype_size(out_dtype) + (noise ? 4.0 : 0.0)));
+    hipError_t e = prof.launch("simulate", bytes,
+                               [&] { return launch_simulate(c, P, maps, b1, noise, out_dtype, out, N); });
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    prof.collect();
+    if (e != hipSuccess) return fail(MPM_ERR_DEVICE, "simulate: %s", hipGetErrorString(e));
+    return MPM_OK;
+}
+
+size_t mpm_footprint_bytes(const mpm_protocol *protocol, const mpm_grid *grid, mpm_dtype dtype, int32_t mode)
+{
+    int64_t N;
+    if (check_protocol(protocol) || check_grid(grid, &N) || check_dtype(dtype)) return 0;
+    size_t I = (size_t)n_images(protocol);
+    size_t inputs = (size_t)N * (I * dtype_size(dtype) + 4 /* b1 */ + 16 /* maps */);
+    size_t ws = (size_t)N * (mode == MPM_ML ? 0 : map_workspace_floats_per_voxel() * 4) + ((size_t)1 << 20);
+    return inputs + ws;
+}
+
+mpm_status mpm_fit(const mpm_protocol *protocol, const mpm_grid *grid, mpm_dtype dtype, const void *echoes,
+                   const float *b1, const mpm_options *opt, float *maps, mpm_report *report, double *trace,
+                   int32_t trace_len, void *stream)
+{
+    clear_error();
+    int64_t N;
+    mpm_status st;
+    if ((st = check_protocol(protocol)) || (st = check_grid(grid, &N)) || (st = check_dtype(dtype))) return st;
+    if (!opt) return fail(MPM_ERR_INVALID_ARG, "options is NULL");
+    if (!echoes || !maps) return fail(MPM_ERR_INVALID_ARG, "echoes and maps must be device pointers");
+    if (opt->mode != MPM_ML && opt->mode != MPM_MAP_JTV) return fail(MPM_ERR_INVALID_ARG, "unknown mode %d", opt->mode);
+    if (opt->n_gn < 0 || opt->n_outer < 0 || opt->n_cg < 0 || opt->n_gn > 100000 || opt->n_outer > 100000 ||
+        opt->n_cg > 100000)
+        return fail(MPM_ERR_INVALID_ARG, "iteration counts must be in [0, 100000]");
+    if (opt->max_halvings > 7) return fail(MPM_ERR_INVALID_ARG, "max_halvings must be <= 7");
+    if (opt->loading != MPM_LOAD_PROPOSED && opt->loading != MPM_LOAD_GN)
+        return fail(MPM_ERR_INVALID_ARG, "unknown loading %d", opt->loading);
+    if (opt->init_kind < MPM_INIT_DEFAULT || opt->init_kind > MPM_INIT_FROM_MAPS)
+        return fail(MPM_ERR_INVALID_ARG, "unknown init_kind %d", opt->init_kind);
+    if (opt->flags != 0) return fail(MPM_ERR_INVALID_ARG, "flags must be 0");
+    if (trace_len < 0 || (trace_len > 0 && !trace)) return fail(MPM_ERR_INVALID_ARG, "trace is NULL");
+    for (int k = 0; k < 4; k++) {
+        if (!(opt->lambda[k] >= 0.0) || !std::isfinite(opt->lambda[k]))
+            return fail(MPM_ERR_INVALID_ARG, "lambda[%d] must be finite and >= 0", k);
+        if (opt->init_kind == MPM_INIT_CONST && !std::isfinite(opt->init_const[k]))
+            return fail(MPM_ERR_INVALID_ARG, "init_const[%d] is not finite", k);
+    }
+    if (!(opt->jtv_eps >= 0.0) || !(opt->cg_stop >= 0.0)) return fail(MPM_ERR_INVALID_ARG, "jtv_eps and cg_stop must be >= 0");
+    if (!has_mt(protocol))
+        return fail(MPM_ERR_UNSUPPORTED, "the four-parameter model needs at least one MT contrast");
+    if (opt->mode == MPM_MAP_JTV && N < 2) return fail(MPM_ERR_UNSUPPORTED, "MAP needs at least 2 voxels");
+    if (opt->mode == MPM_ML) {
+        int emax = 0;
+        for (int c = 0; c < protocol->n_contrasts; c++) emax = std::max(emax, (int)protocol->n_echoes[c]);
+        if (!((protocol->n_contrasts <= 4 && emax <= 16) || emax <= 8))
+            return fail(MPM_ERR_UNSUPPORTED, "ML fit keeps echoes in registers: at most 4 contrasts x 16 echoes or 8 x 8");
+    }
+    for (int i = 0; i < trace_len; i++) trace[i] = NAN;
+
+    hipStream_t s = (hipStream_t)stream;
+    DevProto P = to_dev(protocol);
+    FitArgs a{protocol, P, dtype, echoes, b1, opt, maps, N, grid->nx, grid->ny, grid->nz, s};
+    mpm_report rep;
+    memset(&rep, 0, sizeof(rep));
+    {
+        Workspace ws(s);
+        Prof prof(s);
+        if (opt->init_kind != MPM_INIT_FROM_MAPS) {
+            float y0[4];
+            if (opt->init_kind == MPM_INIT_CONST) {
+                for (int k = 0; k < 4; k++) y0[k] = (float)opt->init_const[k];
+            } else {
+                std::vector<double> mean;
+                double b1m;
+                if ((st = image_means(ws, prof, P, dtype, echoes, b1, N, mean, b1m))) return st;
+                if ((st = default_init_from_means(protocol, mean.data(), b1m, y0))) return st;
+            }
+            LaunchCtx c{s};
+            hipError_t e = launch_fill_maps(c, maps, N, y0);
+            if (e != hipSuccess) return fail(MPM_ERR_DEVICE, "init: %s", hipGetErrorString(e));
+        }
+        st = opt->mode == MPM_ML ? fit_ml(a, ws, prof, rep, trace, trace_len)
+                                 : fit_map(a, ws, prof, rep, trace, trace_len);
+        hipError_t e = hipStreamSynchronize(s);
+        prof.collect();
+        if (st) return st;
+        if (e != hipSuccess) return fail(MPM_ERR_DEVICE, "fit: %s", hipGetErrorString(e));
+    }
+    if (report) *report = rep;
+    return MPM_OK;
+}
+
+}  // extern "C"

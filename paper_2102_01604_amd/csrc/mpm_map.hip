@@ -1,0 +1,182 @@
+// mpm_map.hip -- host driver of the JTV-regularised (MAP) fit and of the
+// Laplace uncertainty (paper Sec. 2.5-2.7, Sec. 3.6).
+#include <cmath>
+#include <cstring>
+
+#include "mpm_api_internal.h"
+#include "mpm_map.h"
+
+namespace mpm {
+
+// H (10) + R, Z, P0, P1, D (4 each) + w (1)
+size_t map_workspace_floats_per_voxel() { return 31; }
+
+struct MapBuffers {
+    MapArgs m;
+    int nblk;
+};
+
+static mpm_status alloc_map(const FitArgs &a, Workspace &ws, MapArgs &m, int trace_len)
+{
+    const int64_t N = a.N;
+    m.g = make_grid3(a.nx, a.ny, a.nz);
+    m.P = a.P;
+    m.dtype = a.dtype;
+    m.X = a.X;
+    m.b1 = a.b1;
+    m.Y = a.maps;
+    const int nblk = (int)((int64_t)m.g.gx * m.g.gy * m.g.nz);
+    float *big = nullptr;
+    const size_t nf = map_workspace_floats_per_voxel() * (size_t)N;
+    if (ws.alloc((void **)&big, nf * sizeof(float)) != hipSuccess ||
+        ws.alloc((void **)&m.partials, sizeof(double) * (size_t)(MAX_TRIALS + 2) * nblk) != hipSuccess ||
+        ws.alloc((void **)&m.ctl, sizeof(MapCtl)) != hipSuccess ||
+        ws.alloc((void **)&m.trace, sizeof(double) * (size_t)(trace_len > 0 ? trace_len : 1)) != hipSuccess)
+        return fail(MPM_ERR_OUT_OF_MEMORY, "MAP workspace allocation failed (%zu bytes)", nf * sizeof(float));
+    m.H = big;
+    m.R = m.H + 10 * N;
+    m.Z = m.R + 4 * N;
+    m.P0 = m.Z + 4 * N;
+    m.P1 = m.P0 + 4 * N;
+    m.D = m.P1 + 4 * N;
+    m.w = m.D + 4 * N;
+    return MPM_OK;
+}
+
+static void set_prior(const mpm_options *o, MapArgs &m, bool use_lambda, int &prior_on)
+{
+    double ls = 0.0;
+    for (int k = 0; k < 4; k++) {
+        m.lam[k] = use_lambda ? (float)o->lambda[k] : 0.0f;
+        ls += use_lambda ? o->lambda[k] : 0.0;
+    }
+    m.eps = (float)(o->jtv_eps > 0.0 ? o->jtv_eps : 1e-3 * std::sqrt(ls));
+    prior_on = ls > 0.0 ? 1 : 0;
+    m.loading = o->loading;
+}
+
+mpm_status fit_map(const FitArgs &a, Workspace &ws, Prof &prof, mpm_report &rep, double *trace, int trace_len)
+{
+    const mpm_options *o = a.opt;
+    const int T = o->n_outer, J = o->n_gn, K = o->n_cg, S = J + 2;
+    const int tl = T * S;
+    MapArgs m;
+    memset(&m, 0, sizeof(m));
+    mpm_status st = alloc_map(a, ws, m, tl);
+    if (st) return st;
+    int prior_on;
+    set_prior(o, m, true, prior_on);
+    const int ntrial = o->max_halvings < 0 ? 1 : o->max_halvings + 1;
+    const int accept_off = o->max_halvings < 0;
+    const double cg_rel = o->cg_stop;
+    const hipStream_t s = a.stream;
+    const double N = (double)a.N, I = a.P.I, xb = I * dtype_size(a.dtype), bb = a.b1 ? 4.0 : 0.0;
+
+    hipError_t e = launch_ctl_init(s, m.ctl, m.trace, tl);
+    LaunchCtx c{s};
+    if (e == hipSuccess) e = launch_fill(c, m.w, a.N, 0.0f);
+    auto fin = [&](int stage, int arg) { return launch_fin(s, m, stage, arg, cg_rel, ntrial, accept_off); };
+#define RUN(name, bytes, call)                                                    \
+    do {                                                                          \
+        if (e == hipSuccess) e = prof.launch(name, bytes, [&] { return call; }); \
+    } while (0)
+    for (int t = 0; t < T && e == hipSuccess; t++) {
+        if (t >= 1) {
+            RUN("jtv_weights", N * 20.0, launch_weights(s, m, prior_on));
+            RUN("fin", 0.0, fin(FIN_W, (t - 1) * S + J + 1));
+        }
+        for (int j = 0; j < J && e == hipSuccess; j++) {
+            RUN("map_lik", N * (xb + bb + 16 + 4 + 40 + 16 + 16), launch_lik(s, m));
+            RUN("fin", 0.0, fin(FIN_LIK, j == 0 ? t * S : -1));
+            for (int i = 0; i < K && e == hipSuccess; i++) {
+                double ab = 16 + (i > 0 ? 16 : 0) + 40 + 4 + 16 + (i == 1 ? 16 : i >= 2 ? 32 : 0);
+                RUN("cg_a", N * ab, launch_cg_a(s, m, i));
+                RUN("fin", 0.0, fin(FIN_A, i));
+                RUN("cg_b", N * (16 + 4 + 40 + 32 + 16), launch_cg_b(s, m, i));
+                RUN("fin", 0.0, fin(FIN_B, i));
+            }
+            RUN("map_accept", N * (xb + bb + 16 + 16 + 16 + 4), launch_accept(s, m, ntrial));
+            RUN("fin", 0.0, fin(FIN_ACCEPT, t * S + j + 1));
+            RUN("map_update", N * 64.0, launch_update(s, m));
+        }
+    }
+    // final weights (objective and report), then statistics at the final maps
+    RUN("jtv_weights", N * 20.0, launch_weights(s, m, prior_on));
+    RUN("fin", 0.0, fin(FIN_W, T >= 1 ? (T - 1) * S + J + 1 : -1));
+    RUN("map_final", N * (xb + bb + 16 + 4), launch_final(s, m, nullptr, nullptr));
+    RUN("fin", 0.0, fin(FIN_STATS, 0));
+#undef RUN
+    MapCtl h;
+    std::vector<double> ht(tl > 0 ? tl : 1);
+    if (e == hipSuccess) e = hipMemcpyAsync(&h, m.ctl, sizeof(h), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess && tl > 0)
+        e = hipMemcpyAsync(ht.data(), m.trace, sizeof(double) * tl, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail(MPM_ERR_DEVICE, "MAP fit: %s", hipGetErrorString(e));
+    for (int i = 0; i < tl && i < trace_len; i++) trace[i] = ht[i];
+    rep.nll = h.nll_final;
+    rep.jtv = prior_on ? h.jtv : 0.0;
+    rep.objective = rep.nll + rep.jtv;
+    rep.outer_done = T;
+    rep.gn_done = h.gn_done;
+    rep.cg_done = h.cg_done;
+    rep.rejected = h.rejected;
+    rep.degenerate_voxels = (int64_t)llround(h.degenerate);
+    rep.nonfinite_voxels = (int64_t)llround(h.nonfinite);
+    rep.nll_increases = 0;
+    return MPM_OK;
+}
+
+}  // namespace mpm
+
+using namespace mpm;
+
+extern "C" mpm_status mpm_uncertainty(const mpm_protocol *protocol, const mpm_grid *grid, mpm_dtype dtype,
+                                      const void *echoes, const float *b1, const mpm_options *opt,
+                                      const float *maps, float *var, float *moments, void *stream)
+{
+    clear_error();
+    int64_t N;
+    mpm_status st;
+    if ((st = check_protocol(protocol)) || (st = check_grid(grid, &N)) || (st = check_dtype(dtype))) return st;
+    if (!opt) return fail(MPM_ERR_INVALID_ARG, "options is NULL");
+    if (!echoes || !maps || !var) return fail(MPM_ERR_INVALID_ARG, "echoes, maps and var must be device pointers");
+    if (opt->mode != MPM_ML && opt->mode != MPM_MAP_JTV) return fail(MPM_ERR_INVALID_ARG, "unknown mode %d", opt->mode);
+    if (opt->loading != MPM_LOAD_PROPOSED && opt->loading != MPM_LOAD_GN)
+        return fail(MPM_ERR_INVALID_ARG, "unknown loading %d", opt->loading);
+    for (int k = 0; k < 4; k++)
+        if (!(opt->lambda[k] >= 0.0) || !std::isfinite(opt->lambda[k]))
+            return fail(MPM_ERR_INVALID_ARG, "lambda[%d] must be finite and >= 0", k);
+    if (!(opt->jtv_eps >= 0.0)) return fail(MPM_ERR_INVALID_ARG, "jtv_eps must be >= 0");
+    if (!has_mt(protocol)) return fail(MPM_ERR_UNSUPPORTED, "the four-parameter model needs at least one MT contrast");
+    hipStream_t s = (hipStream_t)stream;
+    FitArgs a{protocol, to_dev(protocol), dtype, echoes, b1, opt, const_cast<float *>(maps), N,
+              grid->nx, grid->ny, grid->nz, s};
+    {
+        Workspace ws(s);
+        Prof prof(s);
+        MapArgs m;
+        memset(&m, 0, sizeof(m));
+        m.g = make_grid3(a.nx, a.ny, a.nz);
+        m.P = a.P;
+        m.dtype = dtype;
+        m.X = echoes;
+        m.b1 = b1;
+        m.Y = a.maps;  // only read
+        const int nblk = (int)((int64_t)m.g.gx * m.g.gy * m.g.nz);
+        if (ws.alloc((void **)&m.w, sizeof(float) * (size_t)N) != hipSuccess ||
+            ws.alloc((void **)&m.partials, sizeof(double) * 3 * (size_t)nblk) != hipSuccess)
+            return fail(MPM_ERR_OUT_OF_MEMORY, "uncertainty workspace allocation failed");
+        int prior_on;
+        set_prior(opt, m, opt->mode == MPM_MAP_JTV, prior_on);
+        const double xb = (double)a.P.I * dtype_size(dtype), bb = b1 ? 4.0 : 0.0;
+        hipError_t e = prof.launch("jtv_weights", (double)N * 20.0, [&] { return launch_weights(s, m, prior_on); });
+        if (e == hipSuccess)
+            e = prof.launch("uncertainty", (double)N * (xb + bb + 16 + 4 + 16 + (moments ? 16 : 0)),
+                            [&] { return launch_final(s, m, var, moments); });
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        prof.collect();
+        if (e != hipSuccess) return fail(MPM_ERR_DEVICE, "uncertainty: %s", hipGetErrorString(e));
+    }
+    return MPM_OK;
+}

@@ -1,0 +1,116 @@
+"""CPU checks of the C ABI: libmpm.so loads, exports every function that
+include/mpm.h declares, and rejects bad arguments on the host before any
+device work (no compute call is made here)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2102_01604_amd import _lib, synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mpm.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b(mpm_[a-z_0-9]+)\s*\(", text)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.fail("libmpm.so is not built (run __graft_entry__.build())")
+    return _lib.load()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert "mpm_fit" in names and "mpm_uncertainty" in names and "mpm_simulate" in names
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) <= set(_lib.SIGNATURES)
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """Every ctypes struct mirrors the header: size and each field offset, as
+    gcc lays the C structs out."""
+    import subprocess
+    structs = {"mpm_protocol": _lib.mpm_protocol, "mpm_grid": _lib.mpm_grid, "mpm_options": _lib.mpm_options,
+               "mpm_report": _lib.mpm_report, "mpm_kernel_stat": _lib.mpm_kernel_stat}
+    rename = {"lam": "lambda"}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "mpm.h"', "int main(void){"]
+    for name, cls in structs.items():
+        lines.append(f'printf("{name} size %zu\\n", sizeof({name}));')
+        for f in cls._fields_:
+            cf = rename.get(f[0], f[0])
+            lines.append(f'printf("{name} {f[0]} %zu\\n", offsetof({name}, {cf}));')
+    lines.append("return 0;}")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)])
+    out = subprocess.check_output([str(exe)]).decode().split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for name, cls in structs.items():
+        assert got[(name, "size")] == C.sizeof(cls), name
+        for f in cls._fields_:
+            assert got[(name, f[0])] == getattr(cls, f[0]).offset, (name, f[0])
+
+
+def _fit_raw(lib, proto, dims, opts):
+    rep = _lib.mpm_report()
+    return lib.mpm_fit(C.byref(_lib.make_protocol(proto)), C.byref(_lib.make_grid(dims)), 0,
+                       C.c_void_p(16), None, C.byref(_lib.make_options(opts)), C.c_void_p(16),
+                       C.byref(rep), None, 0, None)
+
+
+@pytest.mark.parametrize("mutate,status", [
+    (lambda p, d, o: p.update(tr=[0.0, 0.025, 0.025]), 1),
+    (lambda p, d, o: p.update(flip=[0.1, 3.5, 0.1]), 1),
+    (lambda p, d, o: p.update(sigma=[0.0] * 22), 1),
+    (lambda p, d, o: p.update(te=[-1.0] + p["te"][1:]), 1),
+    (lambda p, d, o: p.update(n_echoes=[0, 8, 6]), 1),
+    (lambda p, d, o: p.update(mt=[0, 0, 0]), 2),
+    (lambda p, d, o: d.__setitem__(0, 0), 1),
+    (lambda p, d, o: o.update(n_gn=-1), 1),
+    (lambda p, d, o: o.update(lam=[-1.0, 0, 0, 0]), 1),
+    (lambda p, d, o: o.update(flags=3), 1),
+    (lambda p, d, o: (d.__setitem__(0, 1), d.__setitem__(1, 1), d.__setitem__(2, 1), o.update(mode="map")), 2),
+])
+def test_host_validation(lib, mutate, status):
+    proto = synth.protocol()
+    proto["sigma"] = [1.0] * 22
+    dims = [8, 8, 8]
+    opts = {"mode": "ml", "n_gn": 5}
+    mutate(proto, dims, opts)
+    st = _fit_raw(lib, proto, dims, opts)
+    assert st == status, lib.mpm_last_error()
+    assert lib.mpm_last_error()
+
+
+def test_null_pointers_rejected(lib):
+    proto = synth.protocol()
+    proto["sigma"] = [1.0] * 22
+    rep = _lib.mpm_report()
+    st = lib.mpm_fit(C.byref(_lib.make_protocol(proto)), C.byref(_lib.make_grid((4, 4, 4))), 0, None, None,
+                     C.byref(_lib.make_options({})), None, C.byref(rep), None, 0, None)
+    assert st == 1
+    st = lib.mpm_simulate(C.byref(_lib.make_protocol(proto)), C.byref(_lib.make_grid((4, 4, 4))), None, None,
+                          None, 0, None, None)
+    assert st == 1
+
+
+def test_footprint_is_host_only(lib):
+    proto = synth.protocol()
+    proto["sigma"] = [1.0] * 22
+    ml = _lib.mpm_footprint_bytes(proto, (192, 240, 256), 0, 0)
+    mp = _lib.mpm_footprint_bytes(proto, (192, 240, 256), 0, 1)
+    N = 192 * 240 * 256
+    assert ml >= N * (22 * 4 + 16)
+    assert mp > ml
+    assert _lib.mpm_footprint_bytes(proto, (192, 240, 256), 1, 1) < mp
+    assert _lib.mpm_version().startswith("libmpm")

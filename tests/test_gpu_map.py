@@ -1,0 +1,147 @@
+"""GPU parity of the JTV-MAP fit (SPGR+JTV) and of the Laplace uncertainty
+against the FP64 oracle, through the C ABI."""
+import numpy as np
+import pytest
+
+from conftest import cuda, f32, map_errors, observations, well_posed
+from paper_2102_01604_amd import _lib, synth
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    _lib.load()
+    return torch
+
+
+def _inputs(orc, name, dims, seed=None, **over):
+    c = synth.make_case(name, dims=dims, seed=seed, **over)
+    if c["b1"] is not None:
+        c["b1"] = f32(c["b1"])
+    x = observations(orc, c)
+    return c, x
+
+
+def _gpu(torch, c, x, opts, dtype=None, maps0=None):
+    X = cuda(x.astype(np.float32))
+    if dtype is not None:
+        X = X.to(dtype)
+    b1 = None if c["b1"] is None else cuda(c["b1"].astype(np.float32))
+    maps = cuda(np.zeros((4, x.shape[1]), np.float32) if maps0 is None else maps0.astype(np.float32))
+    rep, trace = _lib.mpm_fit(c["proto"], c["dims"], X, b1, opts, maps)
+    torch.cuda.synchronize()
+    return maps.cpu().numpy().astype(np.float64), rep, trace
+
+
+def _const_opts(orc, c, x, **kw):
+    y0 = f32(orc.default_init(c["proto"], x.astype(np.float64), c["b1"]))
+    o = dict(c["opts"], init="const", init_const=[float(v) for v in y0])
+    o.update(kw)
+    return o
+
+
+def _compare(orc, torch, c, x, opts, tol=TOL, trace_rtol=1e-5):
+    y_gpu, rep, tr = _gpu(torch, c, x, opts)
+    y_orc, rep_o, tr_o = orc.fit(c["proto"], c["dims"], x.astype(np.float64), c["b1"], opts)
+    good = well_posed(y_orc, c["truth"])
+    rel, ab, rms = map_errors(y_gpu, y_orc, good)
+    rel_all, ab_all, _ = map_errors(y_gpu, y_orc)
+    print(c["dims"], "well-posed", good.mean(), "rel", rel, "abs", ab, "rms", rms, "| all voxels rel", rel_all)
+    print("gpu report", rep)
+    print("orc report", rep_o)
+    assert (rel <= tol).all()
+    fin = np.isfinite(tr_o)
+    assert np.array_equal(np.isfinite(tr), fin)
+    assert np.allclose(tr[fin], tr_o[fin], rtol=trace_rtol)
+    assert rep["gn_done"] == rep_o["gn_done"] and rep["rejected"] == rep_o["rejected"]
+    assert rep["nonfinite_voxels"] == 0
+    assert rep["objective"] == pytest.approx(rep_o["objective"], rel=trace_rtol)
+    return y_gpu, y_orc, rep, rep_o
+
+
+@pytest.mark.parametrize("dims,sched", [((24, 20, 12), (4, 4, 16)), ((70, 9, 5), (3, 3, 8)),
+                                        ((2, 1, 1), (2, 2, 4)), ((1, 1, 5), (2, 3, 4))])
+def test_map_parity_small(torch_cuda, orc, dims, sched):
+    c, x = _inputs(orc, "map_brain", dims, seed=31)
+    T, J, K = sched
+    opts = _const_opts(orc, c, x, n_outer=T, n_gn=J, n_cg=K)
+    _compare(orc, torch_cuda, c, x, opts)
+
+
+def test_map_parity_crop_full_schedule(torch_cuda, orc):
+    """A 64^3 volume drawn with the high-resolution recipe (B1 in [0.7, 1.3],
+    sigma 2% of mean PD) fitted with the full 10 x 8 x 32 schedule on both
+    sides."""
+    c, x = _inputs(orc, "map_hires", (64, 64, 64))
+    opts = _const_opts(orc, c, x)
+    _compare(orc, torch_cuda, c, x, opts)
+
+
+def test_map_without_prior_equals_ml_on_gpu(torch_cuda, orc):
+    c, x = _inputs(orc, "map_brain", (40, 24, 8), seed=32)
+    ml = _const_opts(orc, c, x, mode="ml", n_gn=9)
+    mp = _const_opts(orc, c, x, mode="map", n_outer=3, n_gn=3, n_cg=6, lam=[0, 0, 0, 0])
+    y_ml, _, _ = _gpu(torch_cuda, c, x, ml)
+    y_mp, rep, _ = _gpu(torch_cuda, c, x, mp)
+    good = well_posed(y_ml, c["truth"])
+    rel, _, _ = map_errors(y_mp, y_ml, good)
+    print("MAP(lambda=0) vs ML", rel)
+    assert (rel <= TOL).all()
+
+
+def test_map_objective_monotone_on_gpu(torch_cuda, orc):
+    c, x = _inputs(orc, "map_brain", (48, 40, 24), seed=33)
+    opts = _const_opts(orc, c, x, n_outer=5, n_gn=4, n_cg=16)
+    _, rep, tr = _gpu(torch_cuda, c, x, opts)
+    t = tr.reshape(5, 6)
+    for row in t:
+        fw = row[:5][np.isfinite(row[:5])]
+        assert np.all(np.diff(fw) <= 0)
+    assert np.all(np.diff(t[:, -1]) <= 1e-9 * np.abs(t[:-1, -1]))
+
+
+@pytest.mark.parametrize("dtype", ["f16", "bf16"])
+def test_map_reduced_precision_storage(torch_cuda, orc, dtype):
+    torch = torch_cuda
+    dt = {"f16": torch.float16, "bf16": torch.bfloat16}[dtype]
+    c, x = _inputs(orc, "map_brain", (32, 24, 16), seed=34)
+    opts = _const_opts(orc, c, x, n_outer=4, n_gn=4, n_cg=16)
+    xq = torch.from_numpy(x).to(dt).float().numpy()
+    y_gpu, rep, tr = _gpu(torch, c, x, opts, dtype=dt)
+    y_orc, _, tr_o = orc.fit(c["proto"], c["dims"], xq.astype(np.float64), c["b1"], opts)
+    rel, ab, rms = map_errors(y_gpu, y_orc, well_posed(y_orc, c["truth"]))
+    print(dtype, "vs dequantised oracle", rel, ab, rms)
+    assert (rel <= TOL).all()
+    y_orc_u, _, _ = orc.fit(c["proto"], c["dims"], x.astype(np.float64), c["b1"], opts)
+    good = well_posed(y_orc_u, c["truth"])
+    rel_u, ab_u, rms_u = map_errors(y_gpu, y_orc_u, good)
+    print(dtype, "vs unquantised oracle", rel_u, ab_u, rms_u / np.abs(y_orc_u[:, good]).max(axis=1))
+
+
+@pytest.mark.parametrize("mode", ["ml", "map"])
+def test_uncertainty_parity(torch_cuda, orc, mode):
+    torch = torch_cuda
+    c, x = _inputs(orc, "map_brain", (30, 20, 10), seed=35)
+    opts = _const_opts(orc, c, x, n_outer=3, n_gn=4, n_cg=8, mode=mode)
+    if mode == "ml":
+        opts["n_gn"] = 12
+    y_orc, _, _ = orc.fit(c["proto"], c["dims"], x.astype(np.float64), c["b1"], opts)
+    maps = f32(y_orc)
+    var_o, mom_o = orc.uncertainty(c["proto"], c["dims"], x.astype(np.float64), c["b1"], opts, maps, moments=True)
+    N = x.shape[1]
+    var = torch.empty((4, N), dtype=torch.float32, device="cuda")
+    mom = torch.empty((4, N), dtype=torch.float32, device="cuda")
+    _lib.mpm_uncertainty(c["proto"], c["dims"], cuda(x.astype(np.float32)), cuda(c["b1"].astype(np.float32)),
+                         opts, cuda(maps.astype(np.float32)), var, mom)
+    v = var.cpu().numpy().astype(np.float64)
+    m = mom.cpu().numpy().astype(np.float64)
+    good = well_posed(y_orc, c["truth"]) & np.all(np.isfinite(var_o), axis=0)
+    assert np.array_equal(np.isfinite(v), np.isfinite(var_o))
+    rv = np.abs(v[:, good] - var_o[:, good]) / var_o[:, good]
+    rm = np.abs(m[:, good] - mom_o[:, good]) / np.abs(mom_o[:, good])
+    print(mode, "variance rel err max", rv.max(axis=1), "moments", rm.max(axis=1))
+    assert rv.max() <= 2e-3 and rm.max() <= 2e-3
