@@ -67,6 +67,11 @@ def main():
     ap.add_argument("--profile-every", type=int, default=7,
                     help="bracket one in this many launches of each kernel with HIP events")
     ap.add_argument("--dims", default="192,240,256")
+    ap.add_argument("--counters", action="store_true",
+                    help="for hardware-counter runs: two outer loops of one Newton step each of the MAP fit "
+                         "(2 x 1 x 32; the second loop has JTV weights, so its 32 CG iterations all run, as in "
+                         "the timed fit) on the same volume and a plain 1 GiB device copy as the byte-count "
+                         "calibration, then exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU z-slab design is "
@@ -101,6 +106,16 @@ def main():
     log("echoes simulated on the GPU")
 
     lam = case["lam"]
+    if args.counters:
+        maps = torch.empty((4, N), dtype=torch.float32, device=dev)
+        _lib.mpm_fit(case["proto"], dims, X, b1, {"mode": "map", "n_outer": 2, "n_gn": 1, "n_cg": 32,
+                                                   "max_halvings": 4, "lam": lam}, maps)
+        a = torch.ones(1 << 28, dtype=torch.float32, device=dev)  # 1 GiB
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log("counter workload done: MAP 2x1x32 + one 1 GiB copy")
+        return
     ml_opts = {"mode": "ml", "n_gn": 20, "init": "default"}
     map_opts = {"mode": "map", "n_outer": 10, "n_gn": 8, "n_cg": 32, "max_halvings": 4, "lam": lam,
                 "init": "default"}

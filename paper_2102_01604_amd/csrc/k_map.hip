@@ -10,50 +10,58 @@
 // z-plane; the 1-D workgroup index is remapped so that each of the 8 XCDs
 // receives a contiguous run of tiles (consecutive tiles share stencil halos
 // in that XCD's L2).
+#include <cstdlib>
+
 #include "mpm_map.h"
 
 namespace mpm {
 
 // ---------------------------------------------------------------------------
-// voxel location and the 6-neighbour stencil (unit spacing, zero difference
-// across the border)
+// Column walk.  A workgroup owns a TILE_X x TILE_Y tile of the x-y plane and
+// the planes [z0, z1); each thread walks its own (x, y) column.  The values
+// at z - 1, z, z + 1 of the thread's own column rotate through registers; the
+// four in-plane neighbours are loaded (they are L2-resident: adjacent tiles of
+// the same z-run are processed by the same XCD at the same time).
 // ---------------------------------------------------------------------------
-struct Vox {
-    int x, y, z;
-    int64_t n;
+struct Col {
+    int x, y, z0, z1;
     bool act;
+    bool xm, xp, ym, yp;  // in-plane neighbours inside the grid
+    int64_t base;         // voxel index of (x, y, 0)
+    int64_t sxy;          // plane stride
 };
 
-__device__ __forceinline__ Vox locate(const Grid3 &g)
+__device__ __forceinline__ Col locate_col(const Grid3 &g)
 {
     const int L = blockIdx.x, T = gridDim.x;
     const int q = T >> 3, r = T & 7, j = L & 7;
-    const int lid = j * q + min(j, r) + (L >> 3);  // XCD-contiguous tile index
+    const int lid = j * q + min(j, r) + (L >> 3);  // XCD-contiguous workgroup index
     const int bx = lid % g.gx;
     const int t2 = lid / g.gx;
     const int by = t2 % g.gy;
     const int bz = t2 / g.gy;
-    Vox v;
-    v.x = bx * TILE_X + (threadIdx.x & (TILE_X - 1));
-    v.y = by * TILE_Y + (threadIdx.x / TILE_X);
-    v.z = bz;
-    v.act = v.x < g.nx && v.y < g.ny;
-    v.n = v.act ? (int64_t)v.x + (int64_t)g.nx * ((int64_t)v.y + (int64_t)g.ny * v.z) : 0;
-    return v;
+    Col c;
+    c.x = bx * TILE_X + (threadIdx.x & (TILE_X - 1));
+    c.y = by * g.ty + (threadIdx.x / TILE_X);
+    c.z0 = bz * g.zc;
+    c.z1 = min(c.z0 + g.zc, g.nz);
+    c.act = c.x < g.nx && c.y < g.ny;
+    c.xm = c.x > 0;
+    c.xp = c.x < g.nx - 1;
+    c.ym = c.y > 0;
+    c.yp = c.y < g.ny - 1;
+    c.sxy = (int64_t)g.nx * g.ny;
+    c.base = c.act ? (int64_t)c.x + (int64_t)g.nx * c.y : 0;
+    return c;
 }
 
-// The in-bounds neighbour offsets of a voxel (count in *cnt).
-__device__ __forceinline__ int neighbours(const Grid3 &g, const Vox &v, int64_t off[6])
+template <class Visit>
+__device__ __forceinline__ void for_inplane(const Col &c, int64_t n, int nx, Visit visit)
 {
-    int c = 0;
-    const int64_t sy = g.nx, sz = (int64_t)g.nx * g.ny;
-    if (v.x > 0) off[c++] = -1;
-    if (v.x < g.nx - 1) off[c++] = 1;
-    if (v.y > 0) off[c++] = -sy;
-    if (v.y < g.ny - 1) off[c++] = sy;
-    if (v.z > 0) off[c++] = -sz;
-    if (v.z < g.nz - 1) off[c++] = sz;
-    return c;
+    if (c.xm) visit(n - 1);
+    if (c.xp) visit(n + 1);
+    if (c.ym) visit(n - nx);
+    if (c.yp) visit(n + nx);
 }
 
 __device__ __forceinline__ void load4(const float *__restrict__ a, int64_t N, int64_t n, float v[4])
@@ -68,28 +76,25 @@ __device__ __forceinline__ void store4(float *__restrict__ a, int64_t N, int64_t
     for (int k = 0; k < 4; k++) a[k * N + n] = v[k];
 }
 
-// (L v)_k[n] = lam_k * sum_m (w_n + w_m)(v_k[n] - v_k[m]) and
-// d_n = sum_m (w_n + w_m) = diag(G^T W G)_n   (paper Sec. 2.5).
-// get(m, vm) fetches the field at voxel m.
-template <class Get>
-__device__ __forceinline__ void apply_L(const int64_t off[6], int cnt, int64_t n, const float *__restrict__ w,
-                                        float wn, const float own[4], const float lam[4], Get get,
-                                        float out[4], float &d)
+__device__ __forceinline__ void copy4(float d[4], const float s[4])
 {
-    float acc[4] = {0.f, 0.f, 0.f, 0.f};
-    float dd = 0.f;
-    for (int j = 0; j < cnt; j++) {
-        const int64_t m = n + off[j];
-        const float f = wn + w[m];
-        float vm[4];
-        get(m, vm);
-        dd += f;
 #pragma unroll
-        for (int k = 0; k < 4; k++) acc[k] += f * (own[k] - vm[k]);
-    }
+    for (int k = 0; k < 4; k++) d[k] = s[k];
+}
+
+// One edge of the L stencil (paper Sec. 2.5): adds (w_n + w_m)(v_n - v_m) to
+// acc and (w_n + w_m) to d = diag(G^T W G)_n.
+__device__ __forceinline__ void edge(float wn, float wm, const float vn[4], const float vm[4], float acc[4], float &d)
+{
+    const float f = wn + wm;
+    d += f;
 #pragma unroll
-    for (int k = 0; k < 4; k++) out[k] = lam[k] * acc[k];
-    d = dd;
+    for (int k = 0; k < 4; k++) acc[k] += f * (vn[k] - vm[k]);
+}
+
+__device__ __forceinline__ double dot4(const float a[4], const float b[4])
+{
+    return (double)a[0] * b[0] + (double)a[1] * b[1] + (double)a[2] * b[2] + (double)a[3] * b[3];
 }
 
 __device__ __forceinline__ void symv4(const float H[10], const float p[4], float q[4])
@@ -129,9 +134,70 @@ __device__ __forceinline__ void write_partials(double (&v)[NV], double *__restri
     }
 }
 
+// Non-temporal access for arrays that a kernel streams exactly once (no
+// stencil reuse), so they do not evict the stencil operands' halos from L2.
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef float v2f __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ void vload_nt(const float4 *__restrict__ a, int64_t n, float v[4])
+{
+    const v4f t = __builtin_nontemporal_load((const v4f *)(a + n));
+    v[0] = t.x;
+    v[1] = t.y;
+    v[2] = t.z;
+    v[3] = t.w;
+}
+
+__device__ __forceinline__ void vstore_nt(float4 *__restrict__ a, int64_t n, const float v[4])
+{
+    const v4f t = {v[0], v[1], v[2], v[3]};
+    __builtin_nontemporal_store(t, (v4f *)(a + n));
+}
+
+__device__ __forceinline__ void vload(const float4 *__restrict__ a, int64_t n, float v[4])
+{
+    const float4 t = a[n];
+    v[0] = t.x;
+    v[1] = t.y;
+    v[2] = t.z;
+    v[3] = t.w;
+}
+
+__device__ __forceinline__ void vstore(float4 *__restrict__ a, int64_t n, const float v[4])
+{
+    a[n] = make_float4(v[0], v[1], v[2], v[3]);
+}
+
+// packed symmetric index: 0:00 1:01 2:02 3:03 4:11 5:12 6:13 7:22 8:23 9:33
+__device__ __forceinline__ void load_H(const HessArrays &h, int64_t n, float H[10])
+{
+    const v4f d = __builtin_nontemporal_load((const v4f *)(h.d + n));
+    const v4f o = __builtin_nontemporal_load((const v4f *)(h.o + n));
+    const v2f r = __builtin_nontemporal_load((const v2f *)(h.r + n));
+    H[0] = d.x;
+    H[4] = d.y;
+    H[7] = d.z;
+    H[9] = d.w;
+    H[1] = o.x;
+    H[2] = o.y;
+    H[3] = o.z;
+    H[5] = o.w;
+    H[6] = r.x;
+    H[8] = r.y;
+}
+
+__device__ __forceinline__ void store_H(const HessArrays &h, int64_t n, const float H[10])
+{
+    const v4f d = {H[0], H[4], H[7], H[9]};
+    const v4f o = {H[1], H[2], H[3], H[5]};
+    const v2f r = {H[6], H[8]};
+    __builtin_nontemporal_store(d, (v4f *)(h.d + n));
+    __builtin_nontemporal_store(o, (v4f *)(h.o + n));
+    __builtin_nontemporal_store(r, (v2f *)(h.r + n));
+}
+
 // Likelihood block of one voxel: NLL, gradient and loaded Hessian summed over
-// all echoes (paper eq. precond with the Sec. 2.4 derivatives).  X is read
-// once per call.
+// all echoes (paper eq. precond with the Sec. 2.4 derivatives).
 template <typename T>
 __device__ __forceinline__ float lik_block(const DevProto &P, const T *__restrict__ X, int64_t N, int64_t n,
                                            float b, const float y[4], int loading, float g[4], float H[10])
@@ -152,6 +218,23 @@ __device__ __forceinline__ float lik_block(const DevProto &P, const T *__restric
         }
         nll += 0.5f * acc.L;
         accumulate_contrast(acc, K, p.r2, loading, g, H);
+    }
+    return nll;
+}
+
+// NLL of one voxel at maps y (value only).
+template <typename T>
+__device__ __forceinline__ float nll_only(const DevProto &P, const T *__restrict__ X, int64_t N, int64_t n,
+                                          float b, const float y[4])
+{
+    Params p = decode(y);
+    float nll = 0.f;
+    for (int c = 0; c < P.C; c++) {
+        const float s0 = contrast_factors(p, P.tr[c], make_angle(P.flip[c] * b), P.mt[c]).s0;
+        for (int i = P.first[c]; i < P.first[c + 1]; i++) {
+            const float res = s0 * __expf(-p.r2 * P.te[i]) - load_echo(X + (int64_t)i * N + n);
+            nll += 0.5f * P.wgt[i] * res * res;
+        }
     }
     return nll;
 }
@@ -177,231 +260,439 @@ template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_lik(Grid3 g, DevProto P, const T *__restrict__ X,
                                                const float *__restrict__ b1, const float *__restrict__ Y,
                                                const float *__restrict__ w, float l0, float l1, float l2,
-                                               float l3, int loading, float *__restrict__ Hs,
-                                               float *__restrict__ R, float *__restrict__ Z,
+                                               float l3, int loading, HessArrays Hs,
+                                               float4 *__restrict__ R, float4 *__restrict__ Z,
                                                const MapCtl *__restrict__ ctl, double *__restrict__ partials)
 {
     if (ctl->gn_stop) return;
     const int64_t N = g.N;
     const float lam[4] = {l0, l1, l2, l3};
-    Vox v = locate(g);
+    const Col c = locate_col(g);
     double part[3] = {0.0, 0.0, 0.0};
-    if (v.act) {
-        int64_t off[6];
-        int cnt = neighbours(g, v, off);
-        float y[4], Ly[4], d;
-        load4(Y, N, v.n, y);
-        const float wn = w[v.n];
-        apply_L(off, cnt, v.n, w, wn, y, lam, [&](int64_t m, float vm[4]) { load4(Y, N, m, vm); }, Ly, d);
-        float gr[4], H[10];
-        float nll = lik_block(P, X, N, v.n, b1 ? b1[v.n] : 1.0f, y, loading, gr, H);
-        float r[4], z[4];
+    if (c.act) {
+        int64_t n = c.base + (int64_t)c.z0 * c.sxy;
+        float ym[4], y0[4], yp[4], wm = 0.f, w0, wp = 0.f;
+        if (c.z0 > 0) {
+            load4(Y, N, n - c.sxy, ym);
+            wm = w[n - c.sxy];
+        }
+        load4(Y, N, n, y0);
+        w0 = w[n];
+        for (int z = c.z0; z < c.z1; z++, n += c.sxy) {
+            const bool hzp = z < g.nz - 1;
+            if (hzp) {
+                load4(Y, N, n + c.sxy, yp);
+                wp = w[n + c.sxy];
+            }
+            float acc[4] = {0.f, 0.f, 0.f, 0.f}, d = 0.f;
+            for_inplane(c, n, g.nx, [&](int64_t m) {
+                float vm[4];
+                load4(Y, N, m, vm);
+                edge(w0, w[m], y0, vm, acc, d);
+            });
+            if (z > 0) edge(w0, wm, y0, ym, acc, d);
+            if (hzp) edge(w0, wp, y0, yp, acc, d);
+            float gr[4], H[10], r[4], zz[4];
+            const float nll = lik_block(P, X, N, n, b1 ? b1[n] : 1.0f, y0, loading, gr, H);
 #pragma unroll
-        for (int k = 0; k < 4; k++) r[k] = gr[k] + Ly[k];
-        precond(H, lam, d, r, z);
-#pragma unroll
-        for (int k = 0; k < 10; k++) Hs[k * N + v.n] = H[k];
-        store4(R, N, v.n, r);
-        store4(Z, N, v.n, z);
-        part[0] = nll;
-        part[1] = (double)y[0] * Ly[0] + (double)y[1] * Ly[1] + (double)y[2] * Ly[2] + (double)y[3] * Ly[3];
-        part[2] = (double)r[0] * z[0] + (double)r[1] * z[1] + (double)r[2] * z[2] + (double)r[3] * z[3];
+            for (int k = 0; k < 4; k++) {
+                acc[k] *= lam[k];  // (L y)_k
+                r[k] = gr[k] + acc[k];
+            }
+            precond(H, lam, d, r, zz);
+            store_H(Hs, n, H);
+            vstore_nt(R, n, r);
+            vstore_nt(Z, n, zz);
+            part[0] += nll;
+            part[1] += dot4(y0, acc);
+            part[2] += dot4(r, zz);
+            copy4(ym, y0);
+            copy4(y0, yp);
+            wm = w0;
+            w0 = wp;
+        }
     }
     write_partials<3>(part, partials);
 }
 
 // ---------------------------------------------------------------------------
-// CG sweep A (iteration i): p = z + beta p_old, q = (H + L) p, partial p.q;
-// the deferred update delta += alpha_{i-1} p_old.
+// CG sweeps (paper Sec. 2.6, preconditioned CG on (H + L) delta = g + L y).
+//   sweep A (iteration it): p = z + beta p_old, q = (H + L) p, partial p.q,
+//                           and the deferred update delta += alpha_{it-1} p_old;
+//   sweep B (iteration it): q = (H + L) p recomputed, r -= alpha q,
+//                           z = M^{-1} r, partial r.z.
+// A workgroup of TILE_X x TALL_Y threads owns a TILE_X x TALL_Y tile and walks
+// its z-run; each plane of the stencil operand (p and w) is staged in LDS
+// (double-buffered, one barrier per plane), so in-plane neighbours inside the
+// tile come from LDS and only the tile's rim reads neighbours from memory
+// (those reads mostly hit L2: arrays streamed once use non-temporal accesses
+// and leave L2 to the stencil operands).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(BLOCK) void k_cg_a(Grid3 g, int it, const float *__restrict__ Hs,
-                                                const float *__restrict__ w, float l0, float l1, float l2,
-                                                float l3, const float *__restrict__ Z,
-                                                const float *__restrict__ Pold, float *__restrict__ Pnew,
-                                                float *__restrict__ D, const MapCtl *__restrict__ ctl,
-                                                double *__restrict__ partials)
+constexpr int TALL_THREADS = TILE_X * TALL_Y;
+
+struct TallLds {
+    float4 p[2][TALL_Y][TILE_X];
+    float w[2][TALL_Y][TILE_X];
+};
+
+// Neighbours of (tx, ty) at plane buffer `buf`: inside the tile from LDS,
+// across the tile rim from memory through get(m, v, wm).
+template <class GetMem>
+__device__ __forceinline__ void tall_neighbours(const Col &c, const Grid3 &g, int64_t n, int tx, int ty,
+                                                const TallLds &L, int buf, float w0, const float p0[4],
+                                                GetMem get, float acc[4], float &d)
+{
+    auto from_lds = [&](int yy, int xx) {
+        const float4 v = L.p[buf][yy][xx];
+        const float vm[4] = {v.x, v.y, v.z, v.w};
+        edge(w0, L.w[buf][yy][xx], p0, vm, acc, d);
+    };
+    auto from_mem = [&](int64_t m) {
+        float vm[4], wm;
+        get(m, vm, wm);
+        edge(w0, wm, p0, vm, acc, d);
+    };
+    if (c.xm) {
+        if (tx > 0) from_lds(ty, tx - 1);
+        else from_mem(n - 1);
+    }
+    if (c.xp) {
+        if (tx < TILE_X - 1) from_lds(ty, tx + 1);
+        else from_mem(n + 1);
+    }
+    if (c.ym) {
+        if (ty > 0) from_lds(ty - 1, tx);
+        else from_mem(n - g.nx);
+    }
+    if (c.yp) {
+        if (ty < TALL_Y - 1) from_lds(ty + 1, tx);
+        else from_mem(n + g.nx);
+    }
+}
+
+__global__ __launch_bounds__(TALL_THREADS) void k_cg_a(Grid3 g, int it, HessArrays Hs,
+                                                            const float *__restrict__ w, float l0, float l1, float l2,
+                                                            float l3, const float4 *__restrict__ Z,
+                                                            const float4 *__restrict__ Pold, float4 *__restrict__ Pnew,
+                                                            float4 *__restrict__ D, const MapCtl *__restrict__ ctl,
+                                                            double *__restrict__ partials)
 {
     if (ctl->gn_stop || ctl->cg_stop) return;
+    __shared__ TallLds L;
     const int64_t N = g.N;
     const float lam[4] = {l0, l1, l2, l3};
     const float beta = it > 0 ? (float)ctl->beta : 0.0f;
     const float alpha_prev = (float)ctl->alpha_pend;
-    Vox v = locate(g);
-    double part[1] = {0.0};
-    if (v.act) {
-        int64_t off[6];
-        int cnt = neighbours(g, v, off);
-        auto getp = [&](int64_t m, float pm[4]) {
-            load4(Z, N, m, pm);
-            if (it > 0) {
-#pragma unroll
-                for (int k = 0; k < 4; k++) pm[k] += beta * Pold[k * N + m];
-            }
-        };
-        float p[4], po[4] = {0.f, 0.f, 0.f, 0.f};
-        load4(Z, N, v.n, p);
+    const Col c = locate_col(g);
+    const int tx = threadIdx.x & (TILE_X - 1), ty = threadIdx.x / TILE_X;
+    auto getp = [&](int64_t m, float p[4], float po[4]) {
+        vload(Z, m, p);
         if (it > 0) {
-            load4(Pold, N, v.n, po);
+            vload(Pold, m, po);
 #pragma unroll
             for (int k = 0; k < 4; k++) p[k] += beta * po[k];
         }
-        float Lp[4], d, H[10], q[4];
-        apply_L(off, cnt, v.n, w, w[v.n], p, lam, getp, Lp, d);
-#pragma unroll
-        for (int k = 0; k < 10; k++) H[k] = Hs[k * N + v.n];
-        symv4(H, p, q);
-#pragma unroll
-        for (int k = 0; k < 4; k++) q[k] += Lp[k];
-        store4(Pnew, N, v.n, p);
-        if (it == 1) {
-            float dl[4];
-#pragma unroll
-            for (int k = 0; k < 4; k++) dl[k] = alpha_prev * po[k];
-            store4(D, N, v.n, dl);
-        } else if (it >= 2) {
-            float dl[4];
-            load4(D, N, v.n, dl);
-#pragma unroll
-            for (int k = 0; k < 4; k++) dl[k] += alpha_prev * po[k];
-            store4(D, N, v.n, dl);
+    };
+    auto getmem = [&](int64_t m, float p[4], float &wm) {
+        float po[4];
+        getp(m, p, po);
+        wm = w[m];
+    };
+    double part[1] = {0.0};
+    int64_t n = c.base + (int64_t)c.z0 * c.sxy;
+    float pm[4] = {0.f, 0.f, 0.f, 0.f}, p0[4] = {0.f, 0.f, 0.f, 0.f}, pp[4] = {0.f, 0.f, 0.f, 0.f};
+    float po0[4] = {0.f, 0.f, 0.f, 0.f}, pop[4] = {0.f, 0.f, 0.f, 0.f}, tmp[4];
+    float wm = 0.f, w0 = 0.f, wp = 0.f;
+    if (c.act) {
+        if (c.z0 > 0) {
+            getp(n - c.sxy, pm, tmp);
+            wm = w[n - c.sxy];
         }
-        part[0] = (double)p[0] * q[0] + (double)p[1] * q[1] + (double)p[2] * q[2] + (double)p[3] * q[3];
+        getp(n, p0, po0);
+        w0 = w[n];
     }
-    write_partials<1>(part, partials);
+    for (int z = c.z0; z < c.z1; z++, n += c.sxy) {
+        const int buf = (z - c.z0) & 1;
+        const bool hzp = z < g.nz - 1;
+        if (c.act && hzp) {
+            getp(n + c.sxy, pp, pop);
+            wp = w[n + c.sxy];
+        }
+        L.p[buf][ty][tx] = make_float4(p0[0], p0[1], p0[2], p0[3]);
+        L.w[buf][ty][tx] = w0;
+        __syncthreads();
+        if (c.act) {
+            float acc[4] = {0.f, 0.f, 0.f, 0.f}, d = 0.f;
+            tall_neighbours(c, g, n, tx, ty, L, buf, w0, p0, getmem, acc, d);
+            if (z > 0) edge(w0, wm, p0, pm, acc, d);
+            if (hzp) edge(w0, wp, p0, pp, acc, d);
+            float H[10], q[4];
+            load_H(Hs, n, H);
+            symv4(H, p0, q);
+#pragma unroll
+            for (int k = 0; k < 4; k++) q[k] += lam[k] * acc[k];
+            vstore_nt(Pnew, n, p0);
+            if (it == 1) {
+                float dl[4];
+#pragma unroll
+                for (int k = 0; k < 4; k++) dl[k] = alpha_prev * po0[k];
+                vstore_nt(D, n, dl);
+            } else if (it >= 2) {
+                float dl[4];
+                vload_nt(D, n, dl);
+#pragma unroll
+                for (int k = 0; k < 4; k++) dl[k] += alpha_prev * po0[k];
+                vstore_nt(D, n, dl);
+            }
+            part[0] += dot4(p0, q);
+        }
+        copy4(pm, p0);
+        copy4(p0, pp);
+        copy4(po0, pop);
+        wm = w0;
+        w0 = wp;
+    }
+    __shared__ double lds_part[1][TALL_THREADS / 64];
+    {
+        const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+        double s = wave_sum(part[0]);
+        if (lane == 0) lds_part[0][wid] = s;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double t = 0.0;
+            for (int i = 0; i < TALL_THREADS / 64; i++) t += lds_part[0][i];
+            partials[blockIdx.x] = t;
+        }
+    }
 }
 
-// ---------------------------------------------------------------------------
-// CG sweep B (iteration i): q = (H + L) p recomputed, r -= alpha q,
-// z = M^{-1} r, partial r.z
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(BLOCK) void k_cg_b(Grid3 g, const float *__restrict__ Hs,
-                                                const float *__restrict__ w, float l0, float l1, float l2,
-                                                float l3, const float *__restrict__ Pc, float *__restrict__ R,
-                                                float *__restrict__ Z, const MapCtl *__restrict__ ctl,
-                                                double *__restrict__ partials)
+__global__ __launch_bounds__(TALL_THREADS) void k_cg_b(Grid3 g, HessArrays Hs, const float *__restrict__ w,
+                                                            float l0, float l1, float l2, float l3,
+                                                            const float4 *__restrict__ Pc, float4 *__restrict__ R,
+                                                            float4 *__restrict__ Z, const MapCtl *__restrict__ ctl,
+                                                            double *__restrict__ partials)
 {
     if (ctl->gn_stop || ctl->cg_stop) return;
+    __shared__ TallLds L;
     const int64_t N = g.N;
     const float lam[4] = {l0, l1, l2, l3};
     const float alpha = (float)ctl->alpha_pend;
-    Vox v = locate(g);
+    const Col c = locate_col(g);
+    const int tx = threadIdx.x & (TILE_X - 1), ty = threadIdx.x / TILE_X;
+    auto getmem = [&](int64_t m, float p[4], float &wm) {
+        vload(Pc, m, p);
+        wm = w[m];
+    };
     double part[1] = {0.0};
-    if (v.act) {
-        int64_t off[6];
-        int cnt = neighbours(g, v, off);
-        float p[4], Lp[4], d, H[10], q[4], r[4], z[4];
-        load4(Pc, N, v.n, p);
-        apply_L(off, cnt, v.n, w, w[v.n], p, lam, [&](int64_t m, float pm[4]) { load4(Pc, N, m, pm); }, Lp, d);
-#pragma unroll
-        for (int k = 0; k < 10; k++) H[k] = Hs[k * N + v.n];
-        symv4(H, p, q);
-        load4(R, N, v.n, r);
-#pragma unroll
-        for (int k = 0; k < 4; k++) r[k] -= alpha * (q[k] + Lp[k]);
-        precond(H, lam, d, r, z);
-        store4(R, N, v.n, r);
-        store4(Z, N, v.n, z);
-        part[0] = (double)r[0] * z[0] + (double)r[1] * z[1] + (double)r[2] * z[2] + (double)r[3] * z[3];
+    int64_t n = c.base + (int64_t)c.z0 * c.sxy;
+    float pm[4] = {0.f, 0.f, 0.f, 0.f}, p0[4] = {0.f, 0.f, 0.f, 0.f}, pp[4] = {0.f, 0.f, 0.f, 0.f};
+    float wm = 0.f, w0 = 0.f, wp = 0.f;
+    if (c.act) {
+        if (c.z0 > 0) {
+            vload(Pc, n - c.sxy, pm);
+            wm = w[n - c.sxy];
+        }
+        vload(Pc, n, p0);
+        w0 = w[n];
     }
-    write_partials<1>(part, partials);
+    for (int z = c.z0; z < c.z1; z++, n += c.sxy) {
+        const int buf = (z - c.z0) & 1;
+        const bool hzp = z < g.nz - 1;
+        if (c.act && hzp) {
+            vload(Pc, n + c.sxy, pp);
+            wp = w[n + c.sxy];
+        }
+        L.p[buf][ty][tx] = make_float4(p0[0], p0[1], p0[2], p0[3]);
+        L.w[buf][ty][tx] = w0;
+        __syncthreads();
+        if (c.act) {
+            float acc[4] = {0.f, 0.f, 0.f, 0.f}, d = 0.f;
+            tall_neighbours(c, g, n, tx, ty, L, buf, w0, p0, getmem, acc, d);
+            if (z > 0) edge(w0, wm, p0, pm, acc, d);
+            if (hzp) edge(w0, wp, p0, pp, acc, d);
+            float H[10], q[4], r[4], zz[4];
+            load_H(Hs, n, H);
+            symv4(H, p0, q);
+            vload_nt(R, n, r);
+#pragma unroll
+            for (int k = 0; k < 4; k++) r[k] -= alpha * (q[k] + lam[k] * acc[k]);
+            precond(H, lam, d, r, zz);
+            vstore_nt(R, n, r);
+            vstore_nt(Z, n, zz);
+            part[0] += dot4(r, zz);
+        }
+        copy4(pm, p0);
+        copy4(p0, pp);
+        wm = w0;
+        w0 = wp;
+    }
+    __shared__ double lds_part[1][TALL_THREADS / 64];
+    {
+        const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+        double s = wave_sum(part[0]);
+        if (lane == 0) lds_part[0][wid] = s;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double t = 0.0;
+            for (int i = 0; i < TALL_THREADS / 64; i++) t += lds_part[0][i];
+            partials[blockIdx.x] = t;
+        }
+    }
 }
 
+// delta_f = delta + alpha_pend p_last at voxel m
+struct DeltaF {
+    const float4 *__restrict__ D;
+    const float4 *__restrict__ Pl;
+    float alpha;
+    bool dvalid;
+    __device__ __forceinline__ void operator()(int64_t m, float v[4]) const
+    {
+        float4 t = dvalid ? D[m] : make_float4(0.f, 0.f, 0.f, 0.f);
+        if (alpha != 0.0f) {
+            const float4 p = Pl[m];
+            t.x += alpha * p.x;
+            t.y += alpha * p.y;
+            t.z += alpha * p.z;
+            t.w += alpha * p.w;
+        }
+        v[0] = t.x;
+        v[1] = t.y;
+        v[2] = t.z;
+        v[3] = t.w;
+    }
+};
+
 // ---------------------------------------------------------------------------
-// accept: with delta_f = delta + alpha_pend p_last, the NLL at every trial
-// y - 2^-h delta_f (h < ntrial) and the quadratic pieces delta_f.(L y),
-// delta_f.(L delta_f) of the prior.  Partials: NLL_0..NLL_{ntrial-1}, c1, c2
+// accept, pass 1: the NLL at the full step y - delta_f and the prior pieces
+// c1 = delta_f.(L y), c2 = delta_f.(L delta_f), so that
+// F_w(y - t delta_f) = NLL(y - t delta_f) + (y.Ly - 2 t c1 + t^2 c2) / 2.
+// Partials: NLL_0, c1, c2
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_accept(Grid3 g, DevProto P, const T *__restrict__ X,
                                                   const float *__restrict__ b1, const float *__restrict__ Y,
                                                   const float *__restrict__ w, float l0, float l1, float l2,
-                                                  float l3, const float *__restrict__ D,
-                                                  const float *__restrict__ P0, const float *__restrict__ P1,
-                                                  int ntrial, const MapCtl *__restrict__ ctl,
-                                                  double *__restrict__ partials)
+                                                  float l3, const float4 *__restrict__ D,
+                                                  const float4 *__restrict__ P0, const float4 *__restrict__ P1,
+                                                  const MapCtl *__restrict__ ctl, double *__restrict__ partials)
 {
     if (ctl->gn_stop) return;
     const int64_t N = g.N;
     const float lam[4] = {l0, l1, l2, l3};
-    const float alpha = (float)ctl->alpha_pend;
-    const bool dvalid = ctl->delta_valid;
-    const float *__restrict__ Pl = ctl->p_buf ? P1 : P0;
-    Vox v = locate(g);
-    double part[MAX_TRIALS + 2];
+    const DeltaF getd{D, ctl->p_buf ? P1 : P0, (float)ctl->alpha_pend, ctl->delta_valid != 0};
+    const Col c = locate_col(g);
+    double part[3] = {0.0, 0.0, 0.0};
+    if (c.act) {
+        int64_t n = c.base + (int64_t)c.z0 * c.sxy;
+        float ym[4], y0[4], yp[4], dm[4], d0[4], dp[4], wm = 0.f, w0, wp = 0.f;
+        if (c.z0 > 0) {
+            load4(Y, N, n - c.sxy, ym);
+            getd(n - c.sxy, dm);
+            wm = w[n - c.sxy];
+        }
+        load4(Y, N, n, y0);
+        getd(n, d0);
+        w0 = w[n];
+        for (int z = c.z0; z < c.z1; z++, n += c.sxy) {
+            const bool hzp = z < g.nz - 1;
+            if (hzp) {
+                load4(Y, N, n + c.sxy, yp);
+                getd(n + c.sxy, dp);
+                wp = w[n + c.sxy];
+            }
+            float ay[4] = {0.f, 0.f, 0.f, 0.f}, ad[4] = {0.f, 0.f, 0.f, 0.f}, d = 0.f, d2 = 0.f;
+            for_inplane(c, n, g.nx, [&](int64_t m) {
+                float vm[4], um[4];
+                load4(Y, N, m, vm);
+                getd(m, um);
+                const float wmm = w[m];
+                edge(w0, wmm, y0, vm, ay, d);
+                edge(w0, wmm, d0, um, ad, d2);
+            });
+            if (z > 0) {
+                edge(w0, wm, y0, ym, ay, d);
+                edge(w0, wm, d0, dm, ad, d2);
+            }
+            if (hzp) {
+                edge(w0, wp, y0, yp, ay, d);
+                edge(w0, wp, d0, dp, ad, d2);
+            }
 #pragma unroll
-    for (int h = 0; h < MAX_TRIALS + 2; h++) part[h] = 0.0;
-    if (v.act) {
-        int64_t off[6];
-        int cnt = neighbours(g, v, off);
-        auto getd = [&](int64_t m, float dm[4]) {
-#pragma unroll
-            for (int k = 0; k < 4; k++)
-                dm[k] = (dvalid ? D[k * N + m] : 0.0f) + (alpha != 0.0f ? alpha * Pl[k * N + m] : 0.0f);
-        };
-        float y[4], df[4], Ly[4], Ld[4], d;
-        load4(Y, N, v.n, y);
-        getd(v.n, df);
-        const float wn = w[v.n];
-        apply_L(off, cnt, v.n, w, wn, y, lam, [&](int64_t m, float vm[4]) { load4(Y, N, m, vm); }, Ly, d);
-        apply_L(off, cnt, v.n, w, wn, df, lam, getd, Ld, d);
-        part[MAX_TRIALS] = (double)df[0] * Ly[0] + (double)df[1] * Ly[1] + (double)df[2] * Ly[2] + (double)df[3] * Ly[3];
-        part[MAX_TRIALS + 1] =
-            (double)df[0] * Ld[0] + (double)df[1] * Ld[1] + (double)df[2] * Ld[2] + (double)df[3] * Ld[3];
-        const float b = b1 ? b1[v.n] : 1.0f;
-        Params pt[MAX_TRIALS];
-        float step = 1.0f;
-#pragma unroll
-        for (int h = 0; h < MAX_TRIALS; h++) {
+            for (int k = 0; k < 4; k++) {
+                ay[k] *= lam[k];
+                ad[k] *= lam[k];
+            }
             float yt[4];
 #pragma unroll
-            for (int k = 0; k < 4; k++) yt[k] = y[k] - step * df[k];
-            pt[h] = decode(yt);
-            step *= 0.5f;
+            for (int k = 0; k < 4; k++) yt[k] = y0[k] - d0[k];
+            part[0] += nll_only(P, X, N, n, b1 ? b1[n] : 1.0f, yt);
+            part[1] += dot4(d0, ay);
+            part[2] += dot4(d0, ad);
+            copy4(ym, y0);
+            copy4(y0, yp);
+            copy4(dm, d0);
+            copy4(d0, dp);
+            wm = w0;
+            w0 = wp;
         }
-        float nll[MAX_TRIALS];
-#pragma unroll
-        for (int h = 0; h < MAX_TRIALS; h++) nll[h] = 0.f;
-        for (int c = 0; c < P.C; c++) {
-            const Angle an = make_angle(P.flip[c] * b);
-            float s0[MAX_TRIALS];
-#pragma unroll
-            for (int h = 0; h < MAX_TRIALS; h++)
-                if (h < ntrial) s0[h] = contrast_factors(pt[h], P.tr[c], an, P.mt[c]).s0;
-            for (int i = P.first[c]; i < P.first[c + 1]; i++) {
-                const float x = load_echo(X + (int64_t)i * N + v.n);
-                const float te = P.te[i], wi = P.wgt[i];
-#pragma unroll
-                for (int h = 0; h < MAX_TRIALS; h++) {
-                    if (h < ntrial) {
-                        const float res = s0[h] * __expf(-pt[h].r2 * te) - x;
-                        nll[h] += 0.5f * wi * res * res;
-                    }
-                }
-            }
-        }
-#pragma unroll
-        for (int h = 0; h < MAX_TRIALS; h++) part[h] = nll[h];
     }
-    write_partials<MAX_TRIALS + 2>(part, partials);
+    write_partials<3>(part, partials);
 }
 
-// y -= step * (delta + alpha_pend p_last)
-__global__ __launch_bounds__(BLOCK) void k_update(int64_t N, float *__restrict__ Y, const float *__restrict__ D,
-                                                  const float *__restrict__ P0, const float *__restrict__ P1,
+// accept, pass 2 (only after the full step was rejected): the NLL at the
+// halved steps y - 2^-h delta_f, h = 1 .. ntrial-1.  Partial row h.
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_accept2(Grid3 g, DevProto P, const T *__restrict__ X,
+                                                   const float *__restrict__ b1, const float *__restrict__ Y,
+                                                   const float4 *__restrict__ D, const float4 *__restrict__ P0,
+                                                   const float4 *__restrict__ P1, int ntrial,
+                                                   const MapCtl *__restrict__ ctl, double *__restrict__ partials)
+{
+    if (ctl->gn_stop || !ctl->accept_more) return;
+    const int64_t N = g.N;
+    const DeltaF getd{D, ctl->p_buf ? P1 : P0, (float)ctl->alpha_pend, ctl->delta_valid != 0};
+    const Col c = locate_col(g);
+    double part[MAX_TRIALS];
+#pragma unroll
+    for (int h = 0; h < MAX_TRIALS; h++) part[h] = 0.0;
+    if (c.act) {
+        for (int z = c.z0; z < c.z1; z++) {
+            const int64_t n = c.base + (int64_t)z * c.sxy;
+            float y[4], df[4];
+            load4(Y, N, n, y);
+            getd(n, df);
+            const float b = b1 ? b1[n] : 1.0f;
+            float step = 0.5f;
+#pragma unroll
+            for (int h = 1; h < MAX_TRIALS; h++) {
+                if (h < ntrial) {
+                    float yt[4];
+#pragma unroll
+                    for (int k = 0; k < 4; k++) yt[k] = y[k] - step * df[k];
+                    part[h] += nll_only(P, X, N, n, b, yt);
+                }
+                step *= 0.5f;
+            }
+        }
+    }
+    write_partials<MAX_TRIALS>(part, partials);
+}
+
+// y -= step * delta_f
+__global__ __launch_bounds__(BLOCK) void k_update(int64_t N, float *__restrict__ Y, const float4 *__restrict__ D,
+                                                  const float4 *__restrict__ P0, const float4 *__restrict__ P1,
                                                   const MapCtl *__restrict__ ctl)
 {
     if (ctl->gn_stop || ctl->step == 0.0) return;
     const float step = (float)ctl->step;
-    const float alpha = (float)ctl->alpha_pend;
-    const bool dvalid = ctl->delta_valid;
-    const float *__restrict__ Pl = ctl->p_buf ? P1 : P0;
+    const DeltaF getd{D, ctl->p_buf ? P1 : P0, (float)ctl->alpha_pend, ctl->delta_valid != 0};
     int64_t n = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
     if (n >= N) return;
+    float df[4];
+    getd(n, df);
 #pragma unroll
-    for (int k = 0; k < 4; k++) {
-        float df = (dvalid ? D[k * N + n] : 0.0f) + (alpha != 0.0f ? alpha * Pl[k * N + n] : 0.0f);
-        Y[k * N + n] -= step * df;
-    }
+    for (int k = 0; k < 4; k++) Y[k * N + n] -= step * df[k];
 }
 
 // ---------------------------------------------------------------------------
@@ -414,37 +705,52 @@ __global__ __launch_bounds__(BLOCK) void k_weights(Grid3 g, const float *__restr
 {
     const int64_t N = g.N;
     const float lam[4] = {l0, l1, l2, l3};
-    Vox v = locate(g);
+    const Col c = locate_col(g);
     double part[1] = {0.0};
-    if (v.act) {
-        float wn = 0.0f;
-        if (prior_on) {
-            int64_t off[6];
-            int cnt = neighbours(g, v, off);
-            float y[4], q = 0.f;
-            load4(Y, N, v.n, y);
-            float acc[4] = {0.f, 0.f, 0.f, 0.f};
-            for (int j = 0; j < cnt; j++) {
+    if (c.act) {
+        int64_t n = c.base + (int64_t)c.z0 * c.sxy;
+        if (!prior_on) {
+            for (int z = c.z0; z < c.z1; z++, n += c.sxy) w[n] = 0.0f;
+        } else {
+            float ym[4], y0[4], yp[4];
+            if (c.z0 > 0) load4(Y, N, n - c.sxy, ym);
+            load4(Y, N, n, y0);
+            for (int z = c.z0; z < c.z1; z++, n += c.sxy) {
+                const bool hzp = z < g.nz - 1;
+                if (hzp) load4(Y, N, n + c.sxy, yp);
+                float acc[4] = {0.f, 0.f, 0.f, 0.f};
+                auto sq = [&](const float vm[4]) {
 #pragma unroll
-                for (int k = 0; k < 4; k++) {
-                    const float dk = Y[k * N + v.n + off[j]] - y[k];
-                    acc[k] += dk * dk;
-                }
+                    for (int k = 0; k < 4; k++) {
+                        const float dk = vm[k] - y0[k];
+                        acc[k] += dk * dk;
+                    }
+                };
+                for_inplane(c, n, g.nx, [&](int64_t m) {
+                    float vm[4];
+                    load4(Y, N, m, vm);
+                    sq(vm);
+                });
+                if (z > 0) sq(ym);
+                if (hzp) sq(yp);
+                float q = 0.f;
+#pragma unroll
+                for (int k = 0; k < 4; k++) q += lam[k] * acc[k];
+                const float root = sqrtf(q + eps * eps);
+                w[n] = root > 0.f ? 1.0f / root : 0.0f;
+                part[0] += root;
+                copy4(ym, y0);
+                copy4(y0, yp);
             }
-#pragma unroll
-            for (int k = 0; k < 4; k++) q += lam[k] * acc[k];
-            const float root = sqrtf(q + eps * eps);
-            wn = root > 0.f ? 1.0f / root : 0.0f;
-            part[0] = root;
         }
-        w[v.n] = wn;
     }
     write_partials<1>(part, partials);
 }
 
 // ---------------------------------------------------------------------------
 // final statistics at the fitted maps: NLL, degenerate M blocks, non-finite
-// voxels.  Also used (with var != NULL) for the Laplace variance of Sec. 3.6.
+// voxels.  With var != NULL also the Laplace variance of paper Sec. 3.6 (and
+// with mom != NULL the log-normal moments of r1 and t1).
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_final(Grid3 g, DevProto P, const T *__restrict__ X,
@@ -455,55 +761,61 @@ __global__ __launch_bounds__(BLOCK) void k_final(Grid3 g, DevProto P, const T *_
 {
     const int64_t N = g.N;
     const float lam[4] = {l0, l1, l2, l3};
-    Vox v = locate(g);
+    const Col c = locate_col(g);
     double part[3] = {0.0, 0.0, 0.0};
-    if (v.act) {
-        int64_t off[6];
-        int cnt = neighbours(g, v, off);
-        float y[4];
-        load4(Y, N, v.n, y);
-        const float wn = w[v.n];
-        float d = 0.f;
-        for (int j = 0; j < cnt; j++) d += wn + w[v.n + off[j]];
-        float gr[4], H[10];
-        float nll = lik_block(P, X, N, v.n, b1 ? b1[v.n] : 1.0f, y, loading, gr, H);
-        float M[10];
+    if (c.act) {
+        int64_t n = c.base + (int64_t)c.z0 * c.sxy;
+        float wm = c.z0 > 0 ? w[n - c.sxy] : 0.f, w0 = w[n], wp = 0.f;
+        for (int z = c.z0; z < c.z1; z++, n += c.sxy) {
+            const bool hzp = z < g.nz - 1;
+            if (hzp) wp = w[n + c.sxy];
+            float d = 0.f;
+            for_inplane(c, n, g.nx, [&](int64_t m) { d += w0 + w[m]; });
+            if (z > 0) d += w0 + wm;
+            if (hzp) d += w0 + wp;
+            float y[4], gr[4], H[10];
+            load4(Y, N, n, y);
+            const float nll = lik_block(P, X, N, n, b1 ? b1[n] : 1.0f, y, loading, gr, H);
+            float M[10];
 #pragma unroll
-        for (int k = 0; k < 10; k++) M[k] = H[k];
-        M[0] += lam[0] * d;
-        M[4] += lam[1] * d;
-        M[7] += lam[2] * d;
-        M[9] += lam[3] * d;
-        const float e0[4] = {1.f, 0.f, 0.f, 0.f};
-        float tmp[4];
-        bool degen = solve_sym4(M, e0, tmp);
-        bool bad = false;
+            for (int k = 0; k < 10; k++) M[k] = H[k];
+            M[0] += lam[0] * d;
+            M[4] += lam[1] * d;
+            M[7] += lam[2] * d;
+            M[9] += lam[3] * d;
+            const float e0[4] = {1.f, 0.f, 0.f, 0.f};
+            float tmp[4];
+            const bool degen = solve_sym4(M, e0, tmp);
+            bool bad = false;
 #pragma unroll
-        for (int k = 0; k < 4; k++) bad |= !(fabsf(y[k]) < INFINITY);
-        part[0] = nll;
-        part[1] = degen ? 1.0 : 0.0;
-        part[2] = bad ? 1.0 : 0.0;
-        if (var) {
-            const float dg[4] = {M[0], M[4], M[7], M[9]};
-            const float maxd = fmaxf(fmaxf(dg[0], dg[1]), fmaxf(dg[2], dg[3]));
-            float vv[4];
+            for (int k = 0; k < 4; k++) bad |= !(fabsf(y[k]) < INFINITY);
+            part[0] += nll;
+            part[1] += degen ? 1.0 : 0.0;
+            part[2] += bad ? 1.0 : 0.0;
+            if (var) {
+                const float dg[4] = {M[0], M[4], M[7], M[9]};
+                const float maxd = fmaxf(fmaxf(dg[0], dg[1]), fmaxf(dg[2], dg[3]));
+                float vv[4];
 #pragma unroll
-            for (int k = 0; k < 4; k++) {
-                float e[4] = {0.f, 0.f, 0.f, 0.f}, col[4];
-                e[k] = 1.0f;
-                const bool frozen = !(dg[k] > FROZEN_REL * maxd);
-                const bool dk = solve_sym4(M, e, col);
-                vv[k] = (frozen || dk) ? INFINITY : col[k];
-                var[k * N + v.n] = vv[k];
+                for (int k = 0; k < 4; k++) {
+                    float e[4] = {0.f, 0.f, 0.f, 0.f}, col[4];
+                    e[k] = 1.0f;
+                    const bool frozen = !(dg[k] > FROZEN_REL * maxd);
+                    const bool dk = solve_sym4(M, e, col);
+                    vv[k] = (frozen || dk) ? INFINITY : col[k];
+                    var[k * N + n] = vv[k];
+                }
+                if (mom) {
+                    const float ev = expf(vv[1]);
+                    const float er = expf(y[1]), et = expf(-y[1]);
+                    mom[n] = sqrtf(ev) * er;
+                    mom[N + n] = (ev - 1.0f) * ev * er * er;
+                    mom[2 * N + n] = sqrtf(ev) * et;
+                    mom[3 * N + n] = (ev - 1.0f) * ev * et * et;
+                }
             }
-            if (mom) {
-                const float ev = expf(vv[1]);
-                const float er = expf(y[1]), et = expf(-y[1]);
-                mom[v.n] = sqrtf(ev) * er;
-                mom[N + v.n] = (ev - 1.0f) * ev * er * er;
-                mom[2 * N + v.n] = sqrtf(ev) * et;
-                mom[3 * N + v.n] = (ev - 1.0f) * ev * et * et;
-            }
+            wm = w0;
+            w0 = wp;
         }
     }
     write_partials<3>(part, partials);
@@ -513,30 +825,46 @@ __global__ __launch_bounds__(BLOCK) void k_final(Grid3 g, DevProto P, const T *_
 // one-workgroup finalisers: fixed-order reduction of the partials, then the
 // scalar logic of the step
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double reduce_row(const double *__restrict__ row, int ncols, double *lds_tmp)
+constexpr int FIN_THREADS = 1024;
+
+// Sum of row[0..ncols) in a fixed order; four independent accumulators per
+// thread keep several loads in flight.  The result is valid in every thread.
+__device__ __forceinline__ double reduce_row(const double *__restrict__ row, int ncols, double *lds)
 {
-    double v[1] = {0.0};
-    for (int b = threadIdx.x; b < ncols; b += BLOCK) v[0] += row[b];
-    __shared__ double lds[1][NWAVE];
-    block_sum<1>(v, lds);
-    if (threadIdx.x == 0) *lds_tmp = v[0];
+    const int t = threadIdx.x;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int b = t;
+    for (; b + 3 * FIN_THREADS < ncols; b += 4 * FIN_THREADS) {
+        a0 += row[b];
+        a1 += row[b + FIN_THREADS];
+        a2 += row[b + 2 * FIN_THREADS];
+        a3 += row[b + 3 * FIN_THREADS];
+    }
+    for (; b < ncols; b += FIN_THREADS) a0 += row[b];
+    double v = wave_sum((a0 + a1) + (a2 + a3));
+    if ((t & 63) == 0) lds[t >> 6] = v;
     __syncthreads();
-    double r = *lds_tmp;
+    double r = 0.0;
+    for (int i = 0; i < FIN_THREADS / 64; i++) r += lds[i];
     __syncthreads();
     return r;
 }
 
-__global__ __launch_bounds__(BLOCK) void k_fin(int stage, int arg, int nblk, const double *__restrict__ partials,
-                                               MapCtl *__restrict__ ctl, double *__restrict__ trace,
-                                               double cg_stop_rel, int ntrial, int accept_off)
+__global__ __launch_bounds__(FIN_THREADS) void k_fin(int stage, int arg, int nblk,
+                                                     const double *__restrict__ partials, MapCtl *__restrict__ ctl,
+                                                     double *__restrict__ trace, double cg_stop_rel, int ntrial,
+                                                     int accept_off)
 {
-    __shared__ double tmp;
+    __shared__ double lds[FIN_THREADS / 64];
     const bool gated = (stage == FIN_W || stage == FIN_STATS) ? false : (ctl->gn_stop != 0);
     if (gated) return;
     if ((stage == FIN_A || stage == FIN_B) && ctl->cg_stop) return;
-    double s[MAX_TRIALS + 2];
-    int rows = stage == FIN_LIK ? 3 : stage == FIN_ACCEPT ? MAX_TRIALS + 2 : stage == FIN_STATS ? 3 : 1;
-    for (int k = 0; k < rows; k++) s[k] = reduce_row(partials + (int64_t)k * nblk, nblk, &tmp);
+    if (stage == FIN_ACCEPT2 && !ctl->accept_more) return;
+    double s[MAX_TRIALS];
+    const int rows = (stage == FIN_LIK || stage == FIN_ACCEPT || stage == FIN_STATS) ? 3
+                     : stage == FIN_ACCEPT2                                          ? MAX_TRIALS
+                                                                                     : 1;
+    for (int k = 0; k < rows; k++) s[k] = reduce_row(partials + (int64_t)k * nblk, nblk, lds);
     if (threadIdx.x != 0) return;
     MapCtl &c = *ctl;
     switch (stage) {
@@ -550,6 +878,7 @@ __global__ __launch_bounds__(BLOCK) void k_fin(int stage, int arg, int nblk, con
         c.step = 0.0;
         c.delta_valid = 0;
         c.p_buf = 0;
+        c.accept_more = 0;
         c.cg_stop = !(s[2] > 0.0);
         if (arg >= 0) trace[arg] = c.F;
         break;
@@ -573,20 +902,39 @@ __global__ __launch_bounds__(BLOCK) void k_fin(int stage, int arg, int nblk, con
         c.gamma = gn;
         break;
     }
-    case FIN_ACCEPT: {  // arg: trace slot for "F after this step"
-        const double c1 = s[MAX_TRIALS], c2 = s[MAX_TRIALS + 1];
-        double t = 1.0;
+    case FIN_ACCEPT: {  // full step; arg: trace slot for "F after this step"
+        c.c1 = s[1];
+        c.c2 = s[2];
+        const double F0 = s[0] + 0.5 * (c.yLy - 2.0 * c.c1 + c.c2);
+        if (accept_off || F0 <= c.F) {
+            c.step = 1.0;
+            c.nll_cur = s[0];
+            c.F = F0;
+            c.gn_done++;
+            if (arg >= 0) trace[arg] = F0;
+        } else if (ntrial > 1) {
+            c.accept_more = 1;
+        } else {
+            c.step = 0.0;
+            c.gn_stop = 1;
+            c.rejected++;
+        }
+        break;
+    }
+    case FIN_ACCEPT2: {  // halved steps
+        double t = 0.5;
         int chosen = -1;
         double Fc = 0.0;
-        for (int h = 0; h < ntrial; h++) {
-            const double Fh = s[h] + 0.5 * (c.yLy - 2.0 * t * c1 + t * t * c2);
-            if (accept_off || Fh <= c.F) {
+        for (int h = 1; h < ntrial; h++) {
+            const double Fh = s[h] + 0.5 * (c.yLy - 2.0 * t * c.c1 + t * t * c.c2);
+            if (Fh <= c.F) {
                 chosen = h;
                 Fc = Fh;
                 break;
             }
             t *= 0.5;
         }
+        c.accept_more = 0;
         if (chosen >= 0) {
             c.step = t;
             c.nll_cur = s[chosen];
@@ -616,7 +964,7 @@ __global__ __launch_bounds__(BLOCK) void k_fin(int stage, int arg, int nblk, con
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-static dim3 tiles(const Grid3 &g) { return dim3((unsigned)((int64_t)g.gx * g.gy * g.nz)); }
+static dim3 cols(const Grid3 &g) { return dim3((unsigned)grid_blocks(g)); }
 
 hipError_t launch_ctl_init(hipStream_t s, MapCtl *ctl, double *trace, int trace_len)
 {
@@ -624,30 +972,48 @@ hipError_t launch_ctl_init(hipStream_t s, MapCtl *ctl, double *trace, int trace_
     return hipGetLastError();
 }
 
+#define DISPATCH_T(KERNEL, ...)                                                         \
+    do {                                                                                \
+        if (a.dtype == DT_F32) {                                                        \
+            using T = float;                                                            \
+            hipLaunchKernelGGL(KERNEL<T>, cols(a.gp), dim3(BLOCK), 0, s, __VA_ARGS__); \
+        } else if (a.dtype == DT_F16) {                                                 \
+            using T = F16;                                                              \
+            hipLaunchKernelGGL(KERNEL<T>, cols(a.gp), dim3(BLOCK), 0, s, __VA_ARGS__); \
+        } else {                                                                        \
+            using T = BF16;                                                             \
+            hipLaunchKernelGGL(KERNEL<T>, cols(a.gp), dim3(BLOCK), 0, s, __VA_ARGS__); \
+        }                                                                               \
+    } while (0)
+
+#define DISPATCH_COL_T(KERNEL, ...)                                                    \
+    do {                                                                               \
+        if (a.dtype == DT_F32) {                                                       \
+            using T = float;                                                           \
+            hipLaunchKernelGGL(KERNEL<T>, cols(a.g), dim3(BLOCK), 0, s, __VA_ARGS__); \
+        } else if (a.dtype == DT_F16) {                                                \
+            using T = F16;                                                             \
+            hipLaunchKernelGGL(KERNEL<T>, cols(a.g), dim3(BLOCK), 0, s, __VA_ARGS__); \
+        } else {                                                                       \
+            using T = BF16;                                                            \
+            hipLaunchKernelGGL(KERNEL<T>, cols(a.g), dim3(BLOCK), 0, s, __VA_ARGS__); \
+        }                                                                              \
+    } while (0)
+
 hipError_t launch_lik(hipStream_t s, const MapArgs &a)
 {
     const float *l = a.lam;
-#define LIK_ARGS a.g, a.P, (const T *)a.X, a.b1, a.Y, a.w, l[0], l[1], l[2], l[3], a.loading, a.H, a.R, a.Z, a.ctl, a.partials
-    if (a.dtype == DT_F32) {
-        using T = float;
-        hipLaunchKernelGGL(k_lik<T>, tiles(a.g), dim3(BLOCK), 0, s, LIK_ARGS);
-    } else if (a.dtype == DT_F16) {
-        using T = F16;
-        hipLaunchKernelGGL(k_lik<T>, tiles(a.g), dim3(BLOCK), 0, s, LIK_ARGS);
-    } else {
-        using T = BF16;
-        hipLaunchKernelGGL(k_lik<T>, tiles(a.g), dim3(BLOCK), 0, s, LIK_ARGS);
-    }
-#undef LIK_ARGS
+    DISPATCH_T(k_lik, a.gp, a.P, (const T *)a.X, a.b1, a.Y, a.w, l[0], l[1], l[2], l[3], a.loading, a.H, a.R, a.Z,
+               a.ctl, a.partials);
     return hipGetLastError();
 }
 
 hipError_t launch_cg_a(hipStream_t s, const MapArgs &a, int it)
 {
     const float *l = a.lam;
-    const float *pold = (it & 1) ? a.P0 : a.P1;
-    float *pnew = (it & 1) ? a.P1 : a.P0;
-    hipLaunchKernelGGL(k_cg_a, tiles(a.g), dim3(BLOCK), 0, s, a.g, it, a.H, a.w, l[0], l[1], l[2], l[3], a.Z,
+    const float4 *pold = (it & 1) ? a.P0 : a.P1;
+    float4 *pnew = (it & 1) ? a.P1 : a.P0;
+    hipLaunchKernelGGL(k_cg_a, cols(a.gt), dim3(TALL_THREADS), 0, s, a.gt, it, a.H, a.w, l[0], l[1], l[2], l[3], a.Z,
                        pold, pnew, a.D, a.ctl, a.partials);
     return hipGetLastError();
 }
@@ -655,27 +1021,25 @@ hipError_t launch_cg_a(hipStream_t s, const MapArgs &a, int it)
 hipError_t launch_cg_b(hipStream_t s, const MapArgs &a, int it)
 {
     const float *l = a.lam;
-    const float *pc = (it & 1) ? a.P1 : a.P0;
-    hipLaunchKernelGGL(k_cg_b, tiles(a.g), dim3(BLOCK), 0, s, a.g, a.H, a.w, l[0], l[1], l[2], l[3], pc, a.R,
+    const float4 *pc = (it & 1) ? a.P1 : a.P0;
+    hipLaunchKernelGGL(k_cg_b, cols(a.gt), dim3(TALL_THREADS), 0, s, a.gt, a.H, a.w, l[0], l[1], l[2], l[3], pc, a.R,
                        a.Z, a.ctl, a.partials);
     return hipGetLastError();
 }
 
-hipError_t launch_accept(hipStream_t s, const MapArgs &a, int ntrial)
+int cg_blocks(const MapArgs &a) { return grid_blocks(a.gt); }
+
+hipError_t launch_accept(hipStream_t s, const MapArgs &a)
 {
     const float *l = a.lam;
-#define ACC_ARGS a.g, a.P, (const T *)a.X, a.b1, a.Y, a.w, l[0], l[1], l[2], l[3], a.D, a.P0, a.P1, ntrial, a.ctl, a.partials
-    if (a.dtype == DT_F32) {
-        using T = float;
-        hipLaunchKernelGGL(k_accept<T>, tiles(a.g), dim3(BLOCK), 0, s, ACC_ARGS);
-    } else if (a.dtype == DT_F16) {
-        using T = F16;
-        hipLaunchKernelGGL(k_accept<T>, tiles(a.g), dim3(BLOCK), 0, s, ACC_ARGS);
-    } else {
-        using T = BF16;
-        hipLaunchKernelGGL(k_accept<T>, tiles(a.g), dim3(BLOCK), 0, s, ACC_ARGS);
-    }
-#undef ACC_ARGS
+    DISPATCH_COL_T(k_accept, a.g, a.P, (const T *)a.X, a.b1, a.Y, a.w, l[0], l[1], l[2], l[3], a.D, a.P0, a.P1, a.ctl,
+               a.partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_accept2(hipStream_t s, const MapArgs &a, int ntrial)
+{
+    DISPATCH_T(k_accept2, a.gp, a.P, (const T *)a.X, a.b1, a.Y, a.D, a.P0, a.P1, ntrial, a.ctl, a.partials);
     return hipGetLastError();
 }
 
@@ -689,34 +1053,23 @@ hipError_t launch_update(hipStream_t s, const MapArgs &a)
 hipError_t launch_weights(hipStream_t s, const MapArgs &a, int prior_on)
 {
     const float *l = a.lam;
-    hipLaunchKernelGGL(k_weights, tiles(a.g), dim3(BLOCK), 0, s, a.g, a.Y, l[0], l[1], l[2], l[3], a.eps,
-                       prior_on, a.w, a.partials);
+    hipLaunchKernelGGL(k_weights, cols(a.g), dim3(BLOCK), 0, s, a.g, a.Y, l[0], l[1], l[2], l[3], a.eps, prior_on,
+                       a.w, a.partials);
     return hipGetLastError();
 }
 
 hipError_t launch_final(hipStream_t s, const MapArgs &a, float *var, float *mom)
 {
     const float *l = a.lam;
-#define FIN_ARGS a.g, a.P, (const T *)a.X, a.b1, a.Y, a.w, l[0], l[1], l[2], l[3], a.loading, var, mom, a.partials
-    if (a.dtype == DT_F32) {
-        using T = float;
-        hipLaunchKernelGGL(k_final<T>, tiles(a.g), dim3(BLOCK), 0, s, FIN_ARGS);
-    } else if (a.dtype == DT_F16) {
-        using T = F16;
-        hipLaunchKernelGGL(k_final<T>, tiles(a.g), dim3(BLOCK), 0, s, FIN_ARGS);
-    } else {
-        using T = BF16;
-        hipLaunchKernelGGL(k_final<T>, tiles(a.g), dim3(BLOCK), 0, s, FIN_ARGS);
-    }
-#undef FIN_ARGS
+    DISPATCH_T(k_final, a.gp, a.P, (const T *)a.X, a.b1, a.Y, a.w, l[0], l[1], l[2], l[3], a.loading, var, mom,
+               a.partials);
     return hipGetLastError();
 }
 
-hipError_t launch_fin(hipStream_t s, const MapArgs &a, int stage, int arg, double cg_stop_rel, int ntrial,
-                      int accept_off)
+hipError_t launch_fin(hipStream_t s, const MapArgs &a, int stage, int arg, int nblk, double cg_stop_rel,
+                      int ntrial, int accept_off)
 {
-    int nblk = (int)((int64_t)a.g.gx * a.g.gy * a.g.nz);
-    hipLaunchKernelGGL(k_fin, dim3(1), dim3(BLOCK), 0, s, stage, arg, nblk, a.partials, a.ctl, a.trace,
+    hipLaunchKernelGGL(k_fin, dim3(1), dim3(FIN_THREADS), 0, s, stage, arg, nblk, a.partials, a.ctl, a.trace,
                        cg_stop_rel, ntrial, accept_off);
     return hipGetLastError();
 }

@@ -1,6 +1,7 @@
 // mpm_map.hip -- host driver of the JTV-regularised (MAP) fit and of the
 // Laplace uncertainty (paper Sec. 2.5-2.7, Sec. 3.6).
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 
 #include "mpm_api_internal.h"
@@ -8,13 +9,29 @@
 
 namespace mpm {
 
-// H (10) + R, Z, P0, P1, D (4 each) + w (1)
+int stencil_workgroups()
+{
+    static int v = [] {
+        const char *e = std::getenv("MPM_STENCIL_WORKGROUPS");
+        int x = e ? std::atoi(e) : 0;
+        return (x >= 64 && x <= (1 << 20)) ? x : TARGET_WORKGROUPS;
+    }();
+    return v;
+}
+
+int tall_workgroups()
+{
+    static int v = [] {
+        const char *e = std::getenv("MPM_TALL_WORKGROUPS");
+        int x = e ? std::atoi(e) : 0;
+        return (x >= 16 && x <= (1 << 20)) ? x : TALL_WORKGROUPS;
+    }();
+    return v;
+}
+
+// Hessian d, o (4 each), R, Z, P0, P1, D (4 each), Hessian r (2), w (1)
 size_t map_workspace_floats_per_voxel() { return 31; }
 
-struct MapBuffers {
-    MapArgs m;
-    int nblk;
-};
 
 static mpm_status alloc_map(const FitArgs &a, Workspace &ws, MapArgs &m, int trace_len)
 {
@@ -25,7 +42,9 @@ static mpm_status alloc_map(const FitArgs &a, Workspace &ws, MapArgs &m, int tra
     m.X = a.X;
     m.b1 = a.b1;
     m.Y = a.maps;
-    const int nblk = (int)((int64_t)m.g.gx * m.g.gy * m.g.nz);
+    m.gp = plane_grid(m.g);
+    m.gt = make_grid3(a.nx, a.ny, a.nz, TALL_Y, tall_workgroups());
+    const int nblk = std::max(std::max(grid_blocks(m.g), grid_blocks(m.gp)), grid_blocks(m.gt));
     float *big = nullptr;
     const size_t nf = map_workspace_floats_per_voxel() * (size_t)N;
     if (ws.alloc((void **)&big, nf * sizeof(float)) != hipSuccess ||
@@ -33,13 +52,16 @@ static mpm_status alloc_map(const FitArgs &a, Workspace &ws, MapArgs &m, int tra
         ws.alloc((void **)&m.ctl, sizeof(MapCtl)) != hipSuccess ||
         ws.alloc((void **)&m.trace, sizeof(double) * (size_t)(trace_len > 0 ? trace_len : 1)) != hipSuccess)
         return fail(MPM_ERR_OUT_OF_MEMORY, "MAP workspace allocation failed (%zu bytes)", nf * sizeof(float));
-    m.H = big;
-    m.R = m.H + 10 * N;
-    m.Z = m.R + 4 * N;
-    m.P0 = m.Z + 4 * N;
-    m.P1 = m.P0 + 4 * N;
-    m.D = m.P1 + 4 * N;
-    m.w = m.D + 4 * N;
+    float4 *v4 = (float4 *)big;  // 16-byte aligned (hipMallocAsync)
+    m.H.d = v4;
+    m.H.o = v4 + N;
+    m.R = v4 + 2 * N;
+    m.Z = v4 + 3 * N;
+    m.P0 = v4 + 4 * N;
+    m.P1 = v4 + 5 * N;
+    m.D = v4 + 6 * N;
+    m.H.r = (float2 *)(v4 + 7 * N);
+    m.w = (float *)(m.H.r + N);
     return MPM_OK;
 }
 
@@ -75,7 +97,10 @@ mpm_status fit_map(const FitArgs &a, Workspace &ws, Prof &prof, mpm_report &rep,
     hipError_t e = launch_ctl_init(s, m.ctl, m.trace, tl);
     LaunchCtx c{s};
     if (e == hipSuccess) e = launch_fill(c, m.w, a.N, 0.0f);
-    auto fin = [&](int stage, int arg) { return launch_fin(s, m, stage, arg, cg_rel, ntrial, accept_off); };
+    const int nb_col = grid_blocks(m.g), nb_pl = grid_blocks(m.gp), nb_cg = cg_blocks(m);
+    auto fin = [&](int stage, int arg, int nblk) {
+        return launch_fin(s, m, stage, arg, nblk, cg_rel, ntrial, accept_off);
+    };
 #define RUN(name, bytes, call)                                                    \
     do {                                                                          \
         if (e == hipSuccess) e = prof.launch(name, bytes, [&] { return call; }); \
@@ -83,28 +108,33 @@ mpm_status fit_map(const FitArgs &a, Workspace &ws, Prof &prof, mpm_report &rep,
     for (int t = 0; t < T && e == hipSuccess; t++) {
         if (t >= 1) {
             RUN("jtv_weights", N * 20.0, launch_weights(s, m, prior_on));
-            RUN("fin", 0.0, fin(FIN_W, (t - 1) * S + J + 1));
+            RUN("fin", 0.0, fin(FIN_W, (t - 1) * S + J + 1, nb_col));
         }
         for (int j = 0; j < J && e == hipSuccess; j++) {
             RUN("map_lik", N * (xb + bb + 16 + 4 + 40 + 16 + 16), launch_lik(s, m));
-            RUN("fin", 0.0, fin(FIN_LIK, j == 0 ? t * S : -1));
+            RUN("fin", 0.0, fin(FIN_LIK, j == 0 ? t * S : -1, nb_pl));
             for (int i = 0; i < K && e == hipSuccess; i++) {
                 double ab = 16 + (i > 0 ? 16 : 0) + 40 + 4 + 16 + (i == 1 ? 16 : i >= 2 ? 32 : 0);
                 RUN("cg_a", N * ab, launch_cg_a(s, m, i));
-                RUN("fin", 0.0, fin(FIN_A, i));
+                RUN("fin", 0.0, fin(FIN_A, i, nb_cg));
                 RUN("cg_b", N * (16 + 4 + 40 + 32 + 16), launch_cg_b(s, m, i));
-                RUN("fin", 0.0, fin(FIN_B, i));
+                RUN("fin", 0.0, fin(FIN_B, i, nb_cg));
             }
-            RUN("map_accept", N * (xb + bb + 16 + 16 + 16 + 4), launch_accept(s, m, ntrial));
-            RUN("fin", 0.0, fin(FIN_ACCEPT, t * S + j + 1));
+            RUN("map_accept", N * (xb + bb + 16 + 16 + 16 + 4), launch_accept(s, m));
+            RUN("fin", 0.0, fin(FIN_ACCEPT, t * S + j + 1, nb_col));
+            if (ntrial > 1) {
+                // runs only when the full step was rejected (device flag)
+                RUN("map_accept2", 0.0, launch_accept2(s, m, ntrial));
+                RUN("fin", 0.0, fin(FIN_ACCEPT2, t * S + j + 1, nb_pl));
+            }
             RUN("map_update", N * 64.0, launch_update(s, m));
         }
     }
     // final weights (objective and report), then statistics at the final maps
     RUN("jtv_weights", N * 20.0, launch_weights(s, m, prior_on));
-    RUN("fin", 0.0, fin(FIN_W, T >= 1 ? (T - 1) * S + J + 1 : -1));
+    RUN("fin", 0.0, fin(FIN_W, T >= 1 ? (T - 1) * S + J + 1 : -1, nb_col));
     RUN("map_final", N * (xb + bb + 16 + 4), launch_final(s, m, nullptr, nullptr));
-    RUN("fin", 0.0, fin(FIN_STATS, 0));
+    RUN("fin", 0.0, fin(FIN_STATS, 0, nb_pl));
 #undef RUN
     MapCtl h;
     std::vector<double> ht(tl > 0 ? tl : 1);
@@ -163,7 +193,8 @@ extern "C" mpm_status mpm_uncertainty(const mpm_protocol *protocol, const mpm_gr
         m.X = echoes;
         m.b1 = b1;
         m.Y = a.maps;  // only read
-        const int nblk = (int)((int64_t)m.g.gx * m.g.gy * m.g.nz);
+        m.gp = plane_grid(m.g);
+        const int nblk = std::max(grid_blocks(m.g), grid_blocks(m.gp));
         if (ws.alloc((void **)&m.w, sizeof(float) * (size_t)N) != hipSuccess ||
             ws.alloc((void **)&m.partials, sizeof(double) * 3 * (size_t)nblk) != hipSuccess)
             return fail(MPM_ERR_OUT_OF_MEMORY, "uncertainty workspace allocation failed");

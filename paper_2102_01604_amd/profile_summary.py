@@ -1,0 +1,78 @@
+"""Summaries of rocprofv3 output for the profiles/ folder.
+
+    python -m paper_2102_01604_amd.profile_summary trace <run_kernel_stats.csv>
+    python -m paper_2102_01604_amd.profile_summary traffic <FETCH run_counter_collection.csv>
+                                                   <WRITE run_counter_collection.csv> <kernel> <voxels> [last]
+
+`trace` prints a markdown table of per-kernel call counts and durations.
+`traffic` prints the HBM bytes per dispatch of one kernel (averaged over its
+last `last` dispatches, default all): FETCH_SIZE and WRITE_SIZE (KiB per
+dispatch) scaled by what the same counters read for a
+plain device-to-device copy of 1 GiB in the same run (the copy kernel whose
+name contains "copyBuffer" with the largest FETCH_SIZE), in the key: value
+format bench.py reads, tagged with the hash of the MAP kernel source.
+"""
+from __future__ import annotations
+
+import csv
+import hashlib
+import os
+import statistics
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SOURCE = os.path.join(HERE, "csrc", "k_map.hip")
+
+
+def _short(name):
+    return name.split("(")[0].replace("void ", "")
+
+
+def trace(path):
+    rows = list(csv.DictReader(open(path)))
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    print("| kernel | calls | total ms | avg us | % |")
+    print("|---|---:|---:|---:|---:|")
+    for r in rows:
+        print(f"| {_short(r['Name'])} | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.2f} | "
+              f"{float(r['AverageNs']) / 1e3:.2f} | {float(r['Percentage']):.2f} |")
+
+
+def _counter(path):
+    out = {}
+    for r in csv.DictReader(open(path)):
+        out.setdefault(_short(r["Kernel_Name"]), []).append(float(r["Counter_Value"]))
+    return out
+
+
+def traffic(fetch_csv, write_csv, kernel, voxels, last=0):
+    f, w = _counter(fetch_csv), _counter(write_csv)
+    copy = [k for k in f if "copyBuffer" in k]
+    cf = max((v for k in copy for v in f[k]))
+    cw = max((v for k in copy for v in w[k]))
+    gib_kib = 1024.0 * 1024.0
+    fs, ws = gib_kib / cf, gib_kib / cw
+    name = [k for k in f if k.endswith(kernel) or k.split("<")[0].endswith(kernel)][0]
+    fv, wv = f[name][-last:] if last else f[name], w[name][-last:] if last else w[name]
+    fk, wk = statistics.mean(fv), statistics.mean(wv)
+    b = (fk * fs + wk * ws) * 1024.0
+    src = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()[:16]
+    print(f"kernel: {kernel}")
+    print(f"dispatches: {len(fv)} (of {len(f[name])})")
+    print(f"fetch_kib_min_max: {min(fv):.1f} {max(fv):.1f}")
+    print(f"fetch_kib_per_dispatch: {fk:.1f}")
+    print(f"write_kib_per_dispatch: {wk:.1f}")
+    print(f"copy_calibration_fetch_kib_for_1gib: {cf:.1f}")
+    print(f"copy_calibration_write_kib_for_1gib: {cw:.1f}")
+    print(f"fetch_scale: {fs:.4f}")
+    print(f"write_scale: {ws:.4f}")
+    print(f"bytes_per_launch: {b:.0f}")
+    print(f"bytes_per_voxel: {b / voxels:.1f}")
+    print(f"source_sha256_16: {src}")
+
+
+if __name__ == "__main__":
+    if sys.argv[1] == "trace":
+        trace(sys.argv[2])
+    else:
+        traffic(sys.argv[2], sys.argv[3], sys.argv[4], int(sys.argv[5]), int(sys.argv[6]) if len(sys.argv) > 6 else 0)
