@@ -67,6 +67,11 @@ def main():
     ap.add_argument("--profile-every", type=int, default=7,
                     help="bracket one in this many launches of each kernel with HIP events")
     ap.add_argument("--dims", default="192,240,256")
+    ap.add_argument("--serving", action="store_true",
+                    help="serving benchmark instead: 64 fit requests of uneven sizes (ML or MAP), Poisson "
+                         "arrivals, continuous-batching server against serial plain fits; one JSON line")
+    ap.add_argument("--requests", type=int, default=64)
+    ap.add_argument("--rate", type=float, default=2.0, help="serving: arrivals per second")
     ap.add_argument("--counters", action="store_true",
                     help="for hardware-counter runs: two outer loops of one Newton step each of the MAP fit "
                          "(2 x 1 x 32; the second loop has JTV weights, so its 32 CG iterations all run, as in "
@@ -88,6 +93,9 @@ def main():
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream()
 
+    if args.serving:
+        serving(args, torch, _lib, synth, dev)
+        return
     dims = tuple(int(v) for v in args.dims.split(","))
     t0 = time.time()
     case = synth.make_case("map_brain", dims=dims)
@@ -219,6 +227,119 @@ def main():
                                           "nonfinite_voxels")},
         "kernels": kernels,
     }
+    print(json.dumps(out), flush=True)
+
+
+SERVE_SIZES = [(64, 64, 64), (96, 128, 128), (128, 160, 160), (192, 240, 256)]
+
+
+def serving(args, torch, _lib, synth, dev):
+    """Continuous batching against serial plain fits on the same arrival
+    schedule.  Each size class has one seeded tissue volume; each request
+    draws its own noise (seeded) on the GPU; all inputs are resident in HBM
+    before the clock starts."""
+    rng = np.random.default_rng(4000)
+    n = args.requests
+    cls = rng.integers(0, len(SERVE_SIZES), n)
+    is_map = rng.random(n) < 0.5
+    gaps = rng.exponential(1.0 / args.rate, n)
+    arrive = np.cumsum(gaps) - gaps[0]
+    vols = {}
+    for k, dims in enumerate(SERVE_SIZES):
+        if k in set(cls.tolist()):
+            c = synth.make_case("map_brain", dims=dims, seed=4100 + k)
+            vols[k] = {"case": c, "truth": torch.from_numpy(c["truth"].astype(np.float32)).to(dev),
+                       "b1": torch.from_numpy(c["b1"].astype(np.float32)).to(dev)}
+    log(f"serving: generated {len(vols)} volume classes")
+    reqs = []
+    for r in range(n):
+        v = vols[int(cls[r])]
+        c = v["case"]
+        dims = c["dims"]
+        N = int(np.prod(dims))
+        g = torch.Generator(device=dev).manual_seed(4100 + r)
+        eps = torch.randn((22, N), generator=g, device=dev)
+        X = torch.empty((22, N), dtype=torch.float32, device=dev)
+        _lib.mpm_simulate(c["proto"], dims, v["truth"], v["b1"], eps, X)
+        del eps
+        opts = ({"mode": "map", "n_outer": 10, "n_gn": 8, "n_cg": 32, "max_halvings": 4, "lam": c["lam"]}
+                if is_map[r] else {"mode": "ml", "n_gn": 20})
+        reqs.append({"proto": c["proto"], "dims": dims, "X": X, "b1": v["b1"], "opts": opts, "N": N,
+                     "iters": N * (80 if is_map[r] else 20)})
+    torch.cuda.synchronize()
+    log(f"serving: {n} requests resident ({sum(r['N'] for r in reqs) / 1e6:.1f} M voxels)")
+    # warm-up: one small fit of each mode
+    small = min(range(n), key=lambda i: reqs[i]["N"])
+    for mode in ("ml", "map"):
+        r = reqs[small]
+        o = torch.empty((4, r["N"]), device=dev)
+        _lib.mpm_fit(r["proto"], r["dims"], r["X"], r["b1"], dict(r["opts"], mode=mode, lam=r["opts"].get("lam", [1e-3] * 4),
+                                                                  n_outer=1, n_gn=1, n_cg=2), o)
+    torch.cuda.synchronize()
+
+    def run_serial(times):
+        outs, done = [], np.zeros(n)
+        t0 = time.perf_counter()
+        for i, r in enumerate(reqs):
+            now = time.perf_counter() - t0
+            if now < times[i]:
+                time.sleep(times[i] - now)
+            o = torch.empty((4, r["N"]), device=dev)
+            _lib.mpm_fit(r["proto"], r["dims"], r["X"], r["b1"], r["opts"], o)
+            done[i] = time.perf_counter() - t0
+            outs.append(o)
+        return outs, done
+
+    def run_batched(times):
+        outs = [torch.empty((4, r["N"]), device=dev) for r in reqs]
+        done = np.full(n, np.nan)
+        tickets = [None] * n
+        srv = _lib.MpmServer(hbm_budget=int(args_budget), max_active=4)
+        t0 = time.perf_counter()
+        nxt = 0
+        while np.isnan(done).any():
+            now = time.perf_counter() - t0
+            while nxt < n and times[nxt] <= now:
+                r = reqs[nxt]
+                tickets[nxt] = srv.submit(r["proto"], r["dims"], r["X"], r["b1"], r["opts"], outs[nxt])
+                nxt += 1
+            srv.step()
+            now = time.perf_counter() - t0
+            for i in range(nxt):
+                if np.isnan(done[i]) and srv.poll(tickets[i]) is not None:
+                    done[i] = now
+            time.sleep(0.0002)
+        srv.close()
+        return outs, done
+
+    args_budget = 64 << 30
+    res = {}
+    for label, times in (("poisson", arrive), ("burst", np.zeros(n))):
+        so, sd = run_serial(times)
+        torch.cuda.synchronize()
+        bo, bd = run_batched(times)
+        torch.cuda.synchronize()
+        lat_s, lat_b = sd - times, bd - times
+        diff = max(float((a - b).abs().max()) for a, b in zip(so, bo))
+        nr = lambda v, q: float(np.sort(v)[max(0, int(np.ceil(q * len(v))) - 1)])
+        iters = sum(r["iters"] for r in reqs)
+        res[label] = {
+            "serial": {"p50_s": round(nr(lat_s, 0.5), 3), "p99_s": round(nr(lat_s, 0.99), 3),
+                       "makespan_s": round(float(sd.max()), 3),
+                       "voxel_iters_per_s": round(iters / float(sd.max()), 1)},
+            "batched": {"p50_s": round(nr(lat_b, 0.5), 3), "p99_s": round(nr(lat_b, 0.99), 3),
+                        "makespan_s": round(float(bd.max()), 3),
+                        "voxel_iters_per_s": round(iters / float(bd.max()), 1)},
+            "max_abs_map_diff_batched_vs_serial": diff,
+        }
+        log(f"serving {label}: {res[label]}")
+    out = {"metric": "p50/p99 fit latency, batched vs plain (serving)", "value": res["poisson"]["batched"]["p99_s"],
+           "unit": "s (p99 latency, batched)", "n_gpus": 1, "higher_is_better": False, "data": "synthetic",
+           "config": {"workload": f"{n} fit requests, sizes uniform over {SERVE_SIZES}, 22 echoes, ML (20 GN) or "
+                                  f"JTV-MAP (10x8x32) with p=0.5, Poisson arrivals {args.rate}/s; burst = all at t=0",
+                      "max_active": 4, "hbm_budget_bytes": args_budget,
+                      "n_map": int(is_map.sum()), "n_ml": int((~is_map).sum())},
+           "serving": res}
     print(json.dumps(out), flush=True)
 
 

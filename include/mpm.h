@@ -166,6 +166,56 @@ size_t mpm_footprint_bytes(const mpm_protocol *protocol, const mpm_grid *grid, m
 /* Text of the last error raised on the calling thread ("" if none). */
 const char *mpm_last_error(void);
 
+/*
+ * Serving: a request queue with continuous batching.
+ *
+ * A server owns `max_active` HIP streams (default-priority).  Submitted fits
+ * wait in FIFO order; mpm_server_step() admits the head of the queue when a
+ * stream is free and the sum of mpm_footprint_bytes() of the admitted fits
+ * stays within `hbm_budget`, then enqueues the next piece of work of every
+ * admitted fit (the whole ML fit, or one Newton-like step of a MAP fit) on
+ * its stream, so fits admitted at different times run concurrently on the
+ * device and new arrivals join while others are in flight.  Each fit runs
+ * the same kernels with the same launch shapes as mpm_fit(), so its result is
+ * the same as when it is run alone.
+ *
+ * mpm_request: the arguments of mpm_fit() (report and trace excepted).  The
+ * caller's device buffers must hold their inputs before submit and stay valid
+ * until poll reports done; maps receives the result.
+ * flags: MPM_SERVER_THREAD starts a host thread that calls mpm_server_step()
+ * continuously; otherwise the caller drives it.
+ * mpm_server_submit validates like mpm_fit (same errors) and returns a ticket.
+ * mpm_server_step: non-blocking apart from the brief synchronisation of a
+ * default initialisation; *pending (may be NULL) receives the number of fits
+ * queued or running.
+ * mpm_server_poll: *done = 1 and the report once the fit finished (returning
+ * that fit's status), *done = 0 while queued or running; MPM_ERR_NOT_FOUND for
+ * an unknown ticket.  A fit whose footprint exceeds the budget finishes with
+ * MPM_ERR_OUT_OF_MEMORY.
+ * mpm_server_destroy waits for running fits and frees the server.
+ * Calls on one server are serialised by an internal lock.
+ */
+typedef struct {
+    mpm_protocol protocol;
+    mpm_grid grid;
+    int32_t dtype;      /* mpm_dtype */
+    int32_t reserved;   /* must be 0 */
+    const void *echoes;
+    const float *b1;
+    mpm_options options;
+    float *maps;
+} mpm_request;
+
+typedef struct mpm_server mpm_server;
+
+#define MPM_SERVER_THREAD 1
+
+mpm_status mpm_server_create(size_t hbm_budget, int32_t max_active, int32_t flags, mpm_server **out);
+mpm_status mpm_server_submit(mpm_server *server, const mpm_request *request, uint64_t *ticket);
+mpm_status mpm_server_step(mpm_server *server, int32_t *pending);
+mpm_status mpm_server_poll(mpm_server *server, uint64_t ticket, int32_t *done, mpm_report *report);
+mpm_status mpm_server_destroy(mpm_server *server);
+
 /* Library version string. */
 const char *mpm_version(void);
 

@@ -55,6 +55,14 @@ class mpm_kernel_stat(C.Structure):
                 ("timed_ms", C.c_double), ("bytes", C.c_double)]
 
 
+class mpm_request(C.Structure):
+    _fields_ = [("protocol", mpm_protocol), ("grid", mpm_grid), ("dtype", C.c_int32), ("reserved", C.c_int32),
+                ("echoes", C.c_void_p), ("b1", C.c_void_p), ("options", mpm_options), ("maps", C.c_void_p)]
+
+
+MPM_SERVER_THREAD = 1
+
+
 class MpmError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"{STATUS.get(status, status)}: {msg}")
@@ -77,6 +85,11 @@ SIGNATURES = {
     "mpm_profile_enable": (None, [C.c_int32]),
     "mpm_profile_reset": (None, []),
     "mpm_profile_read": (C.c_int32, [C.POINTER(mpm_kernel_stat), C.c_int32]),
+    "mpm_server_create": (C.c_int, [C.c_size_t, C.c_int32, C.c_int32, C.POINTER(C.c_void_p)]),
+    "mpm_server_submit": (C.c_int, [C.c_void_p, C.POINTER(mpm_request), C.POINTER(C.c_uint64)]),
+    "mpm_server_step": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32)]),
+    "mpm_server_poll": (C.c_int, [C.c_void_p, C.c_uint64, C.POINTER(C.c_int32), _R]),
+    "mpm_server_destroy": (C.c_int, [C.c_void_p]),
 }
 
 
@@ -215,6 +228,65 @@ def mpm_profile_read():
     return {arr[i].name.decode(): {"launches": arr[i].launches, "timed": arr[i].timed,
                                    "timed_ms": arr[i].timed_ms, "bytes": arr[i].bytes}
             for i in range(min(n, 64))}
+
+
+class MpmServer:
+    """Thin wrapper of the mpm_server_* calls (continuous batching of fits)."""
+
+    def __init__(self, hbm_budget: int, max_active: int = 4, thread: bool = False):
+        lib = load()
+        h = C.c_void_p()
+        _check(lib.mpm_server_create(int(hbm_budget), int(max_active), MPM_SERVER_THREAD if thread else 0,
+                                     C.byref(h)))
+        self._h = h
+        self._keep = {}
+
+    def submit(self, protocol: dict, dims, echoes, b1, options: dict, maps) -> int:
+        """Queue a fit; device buffers must already hold their inputs and stay
+        alive until poll() reports it done."""
+        r = mpm_request()
+        r.protocol = make_protocol(protocol)
+        r.grid = make_grid(dims)
+        r.dtype = _dtype_code(echoes)
+        r.echoes = echoes.data_ptr()
+        r.b1 = None if b1 is None else b1.data_ptr()
+        r.options = make_options(options)
+        r.maps = maps.data_ptr()
+        t = C.c_uint64()
+        _check(load().mpm_server_submit(self._h, C.byref(r), C.byref(t)))
+        self._keep[t.value] = (echoes, b1, maps)
+        return t.value
+
+    def step(self) -> int:
+        p = C.c_int32()
+        _check(load().mpm_server_step(self._h, C.byref(p)))
+        return p.value
+
+    def poll(self, ticket: int):
+        """None while the fit is queued or running, else its report (raises on a failed fit)."""
+        d = C.c_int32()
+        rep = mpm_report()
+        st = load().mpm_server_poll(self._h, C.c_uint64(ticket), C.byref(d), C.byref(rep))
+        if st != 0:
+            if d.value:
+                self._keep.pop(ticket, None)
+            _check(st)
+        if not d.value:
+            return None
+        self._keep.pop(ticket, None)
+        return {f[0]: getattr(rep, f[0]) for f in mpm_report._fields_}
+
+    def close(self):
+        if self._h:
+            _check(load().mpm_server_destroy(self._h))
+            self._h = None
+            self._keep.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
 
 
 def nan_trace_ok(trace) -> bool:

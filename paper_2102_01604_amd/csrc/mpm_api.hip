@@ -6,6 +6,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -258,6 +259,42 @@ mpm_status default_init_from_means(const mpm_protocol *p, const double *mean, do
     return MPM_OK;
 }
 
+mpm_status check_fit_args(const mpm_protocol *protocol, const mpm_grid *grid, int dtype, const void *echoes,
+                          const mpm_options *opt, const float *maps, int64_t *N)
+{
+    mpm_status st;
+    if ((st = check_protocol(protocol)) || (st = check_grid(grid, N)) || (st = check_dtype(dtype))) return st;
+    if (!opt) return fail(MPM_ERR_INVALID_ARG, "options is NULL");
+    if (!echoes || !maps) return fail(MPM_ERR_INVALID_ARG, "echoes and maps must be device pointers");
+    if (opt->mode != MPM_ML && opt->mode != MPM_MAP_JTV) return fail(MPM_ERR_INVALID_ARG, "unknown mode %d", opt->mode);
+    if (opt->n_gn < 0 || opt->n_outer < 0 || opt->n_cg < 0 || opt->n_gn > 100000 || opt->n_outer > 100000 ||
+        opt->n_cg > 100000)
+        return fail(MPM_ERR_INVALID_ARG, "iteration counts must be in [0, 100000]");
+    if (opt->max_halvings > 7) return fail(MPM_ERR_INVALID_ARG, "max_halvings must be <= 7");
+    if (opt->loading != MPM_LOAD_PROPOSED && opt->loading != MPM_LOAD_GN)
+        return fail(MPM_ERR_INVALID_ARG, "unknown loading %d", opt->loading);
+    if (opt->init_kind < MPM_INIT_DEFAULT || opt->init_kind > MPM_INIT_FROM_MAPS)
+        return fail(MPM_ERR_INVALID_ARG, "unknown init_kind %d", opt->init_kind);
+    if (opt->flags != 0) return fail(MPM_ERR_INVALID_ARG, "flags must be 0");
+    for (int k = 0; k < 4; k++) {
+        if (!(opt->lambda[k] >= 0.0) || !std::isfinite(opt->lambda[k]))
+            return fail(MPM_ERR_INVALID_ARG, "lambda[%d] must be finite and >= 0", k);
+        if (opt->init_kind == MPM_INIT_CONST && !std::isfinite(opt->init_const[k]))
+            return fail(MPM_ERR_INVALID_ARG, "init_const[%d] is not finite", k);
+    }
+    if (!(opt->jtv_eps >= 0.0) || !(opt->cg_stop >= 0.0)) return fail(MPM_ERR_INVALID_ARG, "jtv_eps and cg_stop must be >= 0");
+    if (!has_mt(protocol))
+        return fail(MPM_ERR_UNSUPPORTED, "the four-parameter model needs at least one MT contrast");
+    if (opt->mode == MPM_MAP_JTV && *N < 2) return fail(MPM_ERR_UNSUPPORTED, "MAP needs at least 2 voxels");
+    if (opt->mode == MPM_ML) {
+        int emax = 0;
+        for (int c = 0; c < protocol->n_contrasts; c++) emax = std::max(emax, (int)protocol->n_echoes[c]);
+        if (!((protocol->n_contrasts <= 4 && emax <= 16) || emax <= 8))
+            return fail(MPM_ERR_UNSUPPORTED, "ML fit keeps echoes in registers: at most 4 contrasts x 16 echoes or 8 x 8");
+    }
+    return MPM_OK;
+}
+
 // device buffer helper (stream-ordered)
 hipError_t Workspace::alloc(void **p, size_t bytes)
 {
@@ -364,67 +401,28 @@ mpm_status mpm_fit(const mpm_protocol *protocol, const mpm_grid *grid, mpm_dtype
 {
     clear_error();
     int64_t N;
-    mpm_status st;
-    if ((st = check_protocol(protocol)) || (st = check_grid(grid, &N)) || (st = check_dtype(dtype))) return st;
-    if (!opt) return fail(MPM_ERR_INVALID_ARG, "options is NULL");
-    if (!echoes || !maps) return fail(MPM_ERR_INVALID_ARG, "echoes and maps must be device pointers");
-    if (opt->mode != MPM_ML && opt->mode != MPM_MAP_JTV) return fail(MPM_ERR_INVALID_ARG, "unknown mode %d", opt->mode);
-    if (opt->n_gn < 0 || opt->n_outer < 0 || opt->n_cg < 0 || opt->n_gn > 100000 || opt->n_outer > 100000 ||
-        opt->n_cg > 100000)
-        return fail(MPM_ERR_INVALID_ARG, "iteration counts must be in [0, 100000]");
-    if (opt->max_halvings > 7) return fail(MPM_ERR_INVALID_ARG, "max_halvings must be <= 7");
-    if (opt->loading != MPM_LOAD_PROPOSED && opt->loading != MPM_LOAD_GN)
-        return fail(MPM_ERR_INVALID_ARG, "unknown loading %d", opt->loading);
-    if (opt->init_kind < MPM_INIT_DEFAULT || opt->init_kind > MPM_INIT_FROM_MAPS)
-        return fail(MPM_ERR_INVALID_ARG, "unknown init_kind %d", opt->init_kind);
-    if (opt->flags != 0) return fail(MPM_ERR_INVALID_ARG, "flags must be 0");
+    mpm_status st = check_fit_args(protocol, grid, dtype, echoes, opt, maps, &N);
+    if (st) return st;
     if (trace_len < 0 || (trace_len > 0 && !trace)) return fail(MPM_ERR_INVALID_ARG, "trace is NULL");
-    for (int k = 0; k < 4; k++) {
-        if (!(opt->lambda[k] >= 0.0) || !std::isfinite(opt->lambda[k]))
-            return fail(MPM_ERR_INVALID_ARG, "lambda[%d] must be finite and >= 0", k);
-        if (opt->init_kind == MPM_INIT_CONST && !std::isfinite(opt->init_const[k]))
-            return fail(MPM_ERR_INVALID_ARG, "init_const[%d] is not finite", k);
-    }
-    if (!(opt->jtv_eps >= 0.0) || !(opt->cg_stop >= 0.0)) return fail(MPM_ERR_INVALID_ARG, "jtv_eps and cg_stop must be >= 0");
-    if (!has_mt(protocol))
-        return fail(MPM_ERR_UNSUPPORTED, "the four-parameter model needs at least one MT contrast");
-    if (opt->mode == MPM_MAP_JTV && N < 2) return fail(MPM_ERR_UNSUPPORTED, "MAP needs at least 2 voxels");
-    if (opt->mode == MPM_ML) {
-        int emax = 0;
-        for (int c = 0; c < protocol->n_contrasts; c++) emax = std::max(emax, (int)protocol->n_echoes[c]);
-        if (!((protocol->n_contrasts <= 4 && emax <= 16) || emax <= 8))
-            return fail(MPM_ERR_UNSUPPORTED, "ML fit keeps echoes in registers: at most 4 contrasts x 16 echoes or 8 x 8");
-    }
     for (int i = 0; i < trace_len; i++) trace[i] = NAN;
 
     hipStream_t s = (hipStream_t)stream;
-    DevProto P = to_dev(protocol);
-    FitArgs a{protocol, P, dtype, echoes, b1, opt, maps, N, grid->nx, grid->ny, grid->nz, s};
+    FitArgs a{protocol, to_dev(protocol), dtype, echoes, b1, opt, maps, N, grid->nx, grid->ny, grid->nz, s};
     mpm_report rep;
     memset(&rep, 0, sizeof(rep));
     {
         Workspace ws(s);
         Prof prof(s);
-        if (opt->init_kind != MPM_INIT_FROM_MAPS) {
-            float y0[4];
-            if (opt->init_kind == MPM_INIT_CONST) {
-                for (int k = 0; k < 4; k++) y0[k] = (float)opt->init_const[k];
-            } else {
-                std::vector<double> mean;
-                double b1m;
-                if ((st = image_means(ws, prof, P, dtype, echoes, b1, N, mean, b1m))) return st;
-                if ((st = default_init_from_means(protocol, mean.data(), b1m, y0))) return st;
-            }
-            LaunchCtx c{s};
-            hipError_t e = launch_fill_maps(c, maps, N, y0);
-            if (e != hipSuccess) return fail(MPM_ERR_DEVICE, "init: %s", hipGetErrorString(e));
-        }
-        st = opt->mode == MPM_ML ? fit_ml(a, ws, prof, rep, trace, trace_len)
-                                 : fit_map(a, ws, prof, rep, trace, trace_len);
+        std::unique_ptr<FitJob> job =
+            opt->mode == MPM_ML ? make_ml_job(a, ws, prof, &st) : make_map_job(a, ws, prof, &st);
+        if (st) return st;
+        bool more = true;
+        while (more)
+            if ((st = job->enqueue_next(&more))) return st;
         hipError_t e = hipStreamSynchronize(s);
         prof.collect();
-        if (st) return st;
         if (e != hipSuccess) return fail(MPM_ERR_DEVICE, "fit: %s", hipGetErrorString(e));
+        if ((st = job->collect(rep, trace, trace_len))) return st;
     }
     if (report) *report = rep;
     return MPM_OK;

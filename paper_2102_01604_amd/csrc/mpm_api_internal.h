@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <functional>
+#include <memory>
 #include <vector>
 
 #include "../../include/mpm.h"
@@ -60,10 +61,31 @@ struct FitArgs {
 
 mpm_status image_means(Workspace &ws, Prof &prof, const DevProto &P, int dtype, const void *X,
                        const float *b1, int64_t N, std::vector<double> &mean, double &b1m);
-mpm_status fit_ml(const FitArgs &a, Workspace &ws, Prof &prof, mpm_report &rep, double *trace,
-                  int trace_len);
-mpm_status fit_map(const FitArgs &a, Workspace &ws, Prof &prof, mpm_report &rep, double *trace,
-                   int trace_len);
+// Writes the initial maps (constant, or the default initialisation from the
+// image means, which synchronises the stream once) unless they are given.
+mpm_status enqueue_init(const FitArgs &a, Workspace &ws, Prof &prof);
 size_t map_workspace_floats_per_voxel();
+
+// A fit enqueued piece by piece on one stream (a piece is the whole ML fit,
+// or the initialisation, one Newton-like step or the finalisation of a MAP
+// fit).  collect() reads the results once all enqueued work has completed.
+struct FitJob {
+    virtual ~FitJob() {}
+    virtual mpm_status enqueue_next(bool *more) = 0;
+    virtual mpm_status collect(mpm_report &rep, double *trace, int trace_len) = 0;
+};
+std::unique_ptr<FitJob> make_ml_job(const FitArgs &a, Workspace &ws, Prof &prof, mpm_status *st);
+std::unique_ptr<FitJob> make_map_job(const FitArgs &a, Workspace &ws, Prof &prof, mpm_status *st);
+
+// Host-side validation shared by mpm_fit and the server.
+mpm_status check_fit_args(const mpm_protocol *protocol, const mpm_grid *grid, int dtype, const void *echoes,
+                          const mpm_options *opt, const float *maps, int64_t *N);
+
+// Pinned host buffer (freed with the owner).
+struct PinnedBuf {
+    void *p = nullptr;
+    ~PinnedBuf();
+    hipError_t alloc(size_t bytes);
+};
 
 }  // namespace mpm

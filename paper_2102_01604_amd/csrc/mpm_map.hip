@@ -77,40 +77,75 @@ static void set_prior(const mpm_options *o, MapArgs &m, bool use_lambda, int &pr
     m.loading = o->loading;
 }
 
-mpm_status fit_map(const FitArgs &a, Workspace &ws, Prof &prof, mpm_report &rep, double *trace, int trace_len)
-{
-    const mpm_options *o = a.opt;
-    const int T = o->n_outer, J = o->n_gn, K = o->n_cg, S = J + 2;
-    const int tl = T * S;
+// ---------------------------------------------------------------------------
+// MAP fit as a job: piece 0 initialises (maps, control block, w = 0); then
+// one piece per Newton-like step (preceded by the weight refresh at the start
+// of each outer loop after the first); the last piece refreshes the weights
+// from the final maps, computes the final statistics and copies the control
+// block and the objective trace to pinned host memory.
+// ---------------------------------------------------------------------------
+struct MapJob : FitJob {
+    FitArgs a;
+    Workspace &ws;
+    Prof &prof;
     MapArgs m;
-    memset(&m, 0, sizeof(m));
-    mpm_status st = alloc_map(a, ws, m, tl);
-    if (st) return st;
-    int prior_on;
-    set_prior(o, m, true, prior_on);
-    const int ntrial = o->max_halvings < 0 ? 1 : o->max_halvings + 1;
-    const int accept_off = o->max_halvings < 0;
-    const double cg_rel = o->cg_stop;
-    const hipStream_t s = a.stream;
-    const double N = (double)a.N, I = a.P.I, xb = I * dtype_size(a.dtype), bb = a.b1 ? 4.0 : 0.0;
+    int prior_on = 0, ntrial = 1, accept_off = 0;
+    int T = 0, J = 0, K = 0, S = 0, tl = 0;
+    int nb_col = 0, nb_pl = 0, nb_cg = 0;
+    int t = 0, j = 0;  // next Newton-like step
+    bool started = false, finished = false;
+    PinnedBuf host;    // MapCtl followed by the trace
 
-    hipError_t e = launch_ctl_init(s, m.ctl, m.trace, tl);
-    LaunchCtx c{s};
-    if (e == hipSuccess) e = launch_fill(c, m.w, a.N, 0.0f);
-    const int nb_col = grid_blocks(m.g), nb_pl = grid_blocks(m.gp), nb_cg = cg_blocks(m);
-    auto fin = [&](int stage, int arg, int nblk) {
-        return launch_fin(s, m, stage, arg, nblk, cg_rel, ntrial, accept_off);
-    };
+    MapJob(const FitArgs &a_, Workspace &ws_, Prof &prof_) : a(a_), ws(ws_), prof(prof_) { memset(&m, 0, sizeof(m)); }
+
+    mpm_status setup()
+    {
+        const mpm_options *o = a.opt;
+        T = o->n_outer;
+        J = o->n_gn;
+        K = o->n_cg;
+        S = J + 2;
+        tl = T * S;
+        mpm_status st = alloc_map(a, ws, m, tl);
+        if (st) return st;
+        if (host.alloc(sizeof(MapCtl) + sizeof(double) * (size_t)(tl > 0 ? tl : 1)) != hipSuccess)
+            return fail(MPM_ERR_OUT_OF_MEMORY, "pinned host allocation failed");
+        set_prior(o, m, true, prior_on);
+        ntrial = o->max_halvings < 0 ? 1 : o->max_halvings + 1;
+        accept_off = o->max_halvings < 0;
+        nb_col = grid_blocks(m.g);
+        nb_pl = grid_blocks(m.gp);
+        nb_cg = cg_blocks(m);
+        return MPM_OK;
+    }
+
+    hipError_t fin(int stage, int arg, int nblk)
+    {
+        return launch_fin(a.stream, m, stage, arg, nblk, a.opt->cg_stop, ntrial, accept_off);
+    }
+
+    mpm_status enqueue_next(bool *more) override
+    {
+        const hipStream_t s = a.stream;
+        const double N = (double)a.N, xb = (double)a.P.I * dtype_size(a.dtype), bb = a.b1 ? 4.0 : 0.0;
+        hipError_t e = hipSuccess;
 #define RUN(name, bytes, call)                                                    \
     do {                                                                          \
         if (e == hipSuccess) e = prof.launch(name, bytes, [&] { return call; }); \
     } while (0)
-    for (int t = 0; t < T && e == hipSuccess; t++) {
-        if (t >= 1) {
-            RUN("jtv_weights", N * 20.0, launch_weights(s, m, prior_on));
-            RUN("fin", 0.0, fin(FIN_W, (t - 1) * S + J + 1, nb_col));
-        }
-        for (int j = 0; j < J && e == hipSuccess; j++) {
+        *more = true;
+        if (!started) {
+            started = true;
+            mpm_status st = enqueue_init(a, ws, prof);
+            if (st) return st;
+            e = launch_ctl_init(s, m.ctl, m.trace, tl);
+            LaunchCtx c{s};
+            if (e == hipSuccess) e = launch_fill(c, m.w, a.N, 0.0f);
+        } else if (t < T && J > 0) {
+            if (j == 0 && t >= 1) {
+                RUN("jtv_weights", N * 20.0, launch_weights(s, m, prior_on));
+                RUN("fin", 0.0, fin(FIN_W, (t - 1) * S + J + 1, nb_col));
+            }
             RUN("map_lik", N * (xb + bb + 16 + 4 + 40 + 16 + 16), launch_lik(s, m));
             RUN("fin", 0.0, fin(FIN_LIK, j == 0 ? t * S : -1, nb_pl));
             for (int i = 0; i < K && e == hipSuccess; i++) {
@@ -128,33 +163,59 @@ mpm_status fit_map(const FitArgs &a, Workspace &ws, Prof &prof, mpm_report &rep,
                 RUN("fin", 0.0, fin(FIN_ACCEPT2, t * S + j + 1, nb_pl));
             }
             RUN("map_update", N * 64.0, launch_update(s, m));
+            if (++j == J) {
+                j = 0;
+                t++;
+            }
+        } else {
+            // outer loops without Newton steps only refresh the weights
+            for (int tt = (J > 0 ? T : 1); tt < T && e == hipSuccess; tt++) {
+                RUN("jtv_weights", N * 20.0, launch_weights(s, m, prior_on));
+                RUN("fin", 0.0, fin(FIN_W, (tt - 1) * S + J + 1, nb_col));
+            }
+            // final weights (objective and report), then statistics at the final maps
+            RUN("jtv_weights", N * 20.0, launch_weights(s, m, prior_on));
+            RUN("fin", 0.0, fin(FIN_W, T >= 1 ? (T - 1) * S + J + 1 : -1, nb_col));
+            RUN("map_final", N * (xb + bb + 16 + 4), launch_final(s, m, nullptr, nullptr));
+            RUN("fin", 0.0, fin(FIN_STATS, 0, nb_pl));
+            if (e == hipSuccess) e = hipMemcpyAsync(host.p, m.ctl, sizeof(MapCtl), hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess && tl > 0)
+                e = hipMemcpyAsync((char *)host.p + sizeof(MapCtl), m.trace, sizeof(double) * tl,
+                                   hipMemcpyDeviceToHost, s);
+            finished = true;
+            *more = false;
         }
-    }
-    // final weights (objective and report), then statistics at the final maps
-    RUN("jtv_weights", N * 20.0, launch_weights(s, m, prior_on));
-    RUN("fin", 0.0, fin(FIN_W, T >= 1 ? (T - 1) * S + J + 1 : -1, nb_col));
-    RUN("map_final", N * (xb + bb + 16 + 4), launch_final(s, m, nullptr, nullptr));
-    RUN("fin", 0.0, fin(FIN_STATS, 0, nb_pl));
 #undef RUN
-    MapCtl h;
-    std::vector<double> ht(tl > 0 ? tl : 1);
-    if (e == hipSuccess) e = hipMemcpyAsync(&h, m.ctl, sizeof(h), hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess && tl > 0)
-        e = hipMemcpyAsync(ht.data(), m.trace, sizeof(double) * tl, hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) return fail(MPM_ERR_DEVICE, "MAP fit: %s", hipGetErrorString(e));
-    for (int i = 0; i < tl && i < trace_len; i++) trace[i] = ht[i];
-    rep.nll = h.nll_final;
-    rep.jtv = prior_on ? h.jtv : 0.0;
-    rep.objective = rep.nll + rep.jtv;
-    rep.outer_done = T;
-    rep.gn_done = h.gn_done;
-    rep.cg_done = h.cg_done;
-    rep.rejected = h.rejected;
-    rep.degenerate_voxels = (int64_t)llround(h.degenerate);
-    rep.nonfinite_voxels = (int64_t)llround(h.nonfinite);
-    rep.nll_increases = 0;
-    return MPM_OK;
+        if (e != hipSuccess) return fail(MPM_ERR_DEVICE, "MAP fit: %s", hipGetErrorString(e));
+        return MPM_OK;
+    }
+
+    mpm_status collect(mpm_report &rep, double *trace, int trace_len) override
+    {
+        MapCtl h;
+        memcpy(&h, host.p, sizeof(h));
+        const double *ht = (const double *)((const char *)host.p + sizeof(MapCtl));
+        for (int i = 0; i < tl && i < trace_len; i++) trace[i] = ht[i];
+        memset(&rep, 0, sizeof(rep));
+        rep.nll = h.nll_final;
+        rep.jtv = prior_on ? h.jtv : 0.0;
+        rep.objective = rep.nll + rep.jtv;
+        rep.outer_done = T;
+        rep.gn_done = h.gn_done;
+        rep.cg_done = h.cg_done;
+        rep.rejected = h.rejected;
+        rep.degenerate_voxels = (int64_t)llround(h.degenerate);
+        rep.nonfinite_voxels = (int64_t)llround(h.nonfinite);
+        return MPM_OK;
+    }
+};
+
+std::unique_ptr<FitJob> make_map_job(const FitArgs &a, Workspace &ws, Prof &prof, mpm_status *st)
+{
+    std::unique_ptr<MapJob> j(new MapJob(a, ws, prof));
+    *st = j->setup();
+    if (*st) return nullptr;
+    return std::unique_ptr<FitJob>(j.release());
 }
 
 }  // namespace mpm

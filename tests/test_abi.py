@@ -40,7 +40,8 @@ def test_struct_layouts_match_header(tmp_path):
     gcc lays the C structs out."""
     import subprocess
     structs = {"mpm_protocol": _lib.mpm_protocol, "mpm_grid": _lib.mpm_grid, "mpm_options": _lib.mpm_options,
-               "mpm_report": _lib.mpm_report, "mpm_kernel_stat": _lib.mpm_kernel_stat}
+               "mpm_report": _lib.mpm_report, "mpm_kernel_stat": _lib.mpm_kernel_stat,
+               "mpm_request": _lib.mpm_request}
     rename = {"lam": "lambda"}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "mpm.h"', "int main(void){"]
     for name, cls in structs.items():
