@@ -70,6 +70,9 @@ def main():
     ap.add_argument("--serving", action="store_true",
                     help="serving benchmark instead: 64 fit requests of uneven sizes (ML or MAP), Poisson "
                          "arrivals, continuous-batching server against serial plain fits; one JSON line")
+    ap.add_argument("--hires", action="store_true",
+                    help="high-resolution workload instead: 416 x 384 x 320 voxels, FP16 echo storage, B1 in "
+                         "[0.7, 1.3], sigma 2%% of mean PD, JTV-MAP 10 x 8 x 32 then the Laplace variance")
     ap.add_argument("--requests", type=int, default=64)
     ap.add_argument("--rate", type=float, default=2.0, help="serving: arrivals per second")
     ap.add_argument("--counters", action="store_true",
@@ -95,6 +98,9 @@ def main():
 
     if args.serving:
         serving(args, torch, _lib, synth, dev)
+        return
+    if args.hires:
+        hires(torch, _lib, synth, dev)
         return
     dims = tuple(int(v) for v in args.dims.split(","))
     t0 = time.time()
@@ -164,6 +170,25 @@ def main():
     t_end = time.perf_counter()
     _lib.mpm_profile_enable(0)
     stats = _lib.mpm_profile_read()
+    # the same MAP fit with FP16 echo storage (outside the timed steps)
+    f16 = None
+    if args.dtype == "f32":
+        X16 = X.half()
+        m16 = torch.empty((4, N), dtype=torch.float32, device=dev)
+        _lib.mpm_fit(case["proto"], dims, X16, b1, dict(map_opts, n_outer=1, n_gn=1, n_cg=1), m16, stream=stream)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        rep16 = _lib.mpm_fit(case["proto"], dims, X16, b1, map_opts, m16, stream=stream)[0]
+        e1.record(stream)
+        e1.synchronize()
+        ms16 = e0.elapsed_time(e1)
+        d16 = (m16 - maps_map).abs().amax(dim=1) / maps_map.abs().amax(dim=1)
+        f16 = {"map_fit_ms": round(ms16, 3), "map_voxel_gn_iters_per_s": round(N * 80 / (ms16 * 1e-3), 1),
+               "max_rel_diff_vs_f32_storage": [float(v) for v in d16.cpu()],
+               "objective": rep16["objective"]}
+        del X16, m16
+        log(f"f16 storage MAP fit {ms16:.1f} ms")
 
     ms_per_step = (t_end - t_start) * 1e3 / args.steps
     ml_ms, map_ms, unc_ms = (float(np.median(parts[k])) for k in ("ml", "map", "unc"))
@@ -225,8 +250,54 @@ def main():
         "map_voxel_cg_iters_per_s": round(N * rm["cg_done"] / (map_ms * 1e-3), 1),
         "map_report": {k: rm[k] for k in ("objective", "gn_done", "cg_done", "rejected", "degenerate_voxels",
                                           "nonfinite_voxels")},
+        "map_f16_storage": f16,
         "kernels": kernels,
     }
+    print(json.dumps(out), flush=True)
+
+
+def hires(torch, _lib, synth, dev):
+    """High-resolution JTV-MAP fit + Laplace variance on 51 M voxels (FP16 echoes)."""
+    t0 = time.time()
+    case = synth.make_case("map_hires")
+    dims = case["dims"]
+    N = int(np.prod(dims))
+    log(f"generated {dims} in {time.time() - t0:.1f}s")
+    truth = torch.from_numpy(case["truth"].astype(np.float32)).to(dev)
+    b1 = torch.from_numpy(case["b1"].astype(np.float32)).to(dev)
+    eps = torch.from_numpy(case["eps"]).to(dev)
+    del case["eps"]
+    X = torch.empty((22, N), dtype=torch.float16, device=dev)
+    _lib.mpm_simulate(case["proto"], dims, truth, b1, eps, X)
+    del eps
+    opts = {"mode": "map", "n_outer": 10, "n_gn": 8, "n_cg": 32, "max_halvings": 4, "lam": case["lam"]}
+    maps = torch.empty((4, N), dtype=torch.float32, device=dev)
+    var = torch.empty((4, N), dtype=torch.float32, device=dev)
+    mom = torch.empty((4, N), dtype=torch.float32, device=dev)
+    _lib.mpm_fit(case["proto"], dims, X, b1, dict(opts, n_outer=1, n_gn=1, n_cg=1), maps)  # warm-up
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    ev[0].record()
+    rep = _lib.mpm_fit(case["proto"], dims, X, b1, opts, maps)[0]
+    ev[1].record()
+    _lib.mpm_uncertainty(case["proto"], dims, X, b1, opts, maps, var, mom)
+    ev[2].record()
+    ev[2].synchronize()
+    map_ms, unc_ms = ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2])
+    err = (maps - truth).float()
+    rmse = err.pow(2).mean(dim=1).sqrt().cpu().tolist()
+    sd = var.sqrt()
+    out = {"metric": "voxel-iters/s (GN+JTV-CG), high-resolution MAP + uncertainty",
+           "value": round(N * 80 / ((map_ms + unc_ms) * 1e-3), 1), "unit": "voxel-GN-iterations/s",
+           "n_gpus": 1, "higher_is_better": True, "dtype": "f32 (f16 echo storage)", "data": "synthetic",
+           "config": {"workload": "JTV-MAP 10x8x32 + Laplace variance, 416x384x320, 8/8/6 echoes, FP16 echoes, "
+                                  "B1 0.7-1.3, sigma 2% of mean PD", "voxels": N},
+           "map_fit_ms": round(map_ms, 2), "uncertainty_ms": round(unc_ms, 2),
+           "map_voxel_cg_iters_per_s": round(N * rep["cg_done"] / (map_ms * 1e-3), 1),
+           "report": rep, "rmse_vs_truth_log_maps": rmse,
+           "median_sd_log_maps": sd.median(dim=1).values.cpu().tolist(),
+           "device_footprint_GiB": round(_lib.mpm_footprint_bytes(case["proto"], dims, _lib.MPM_F16, _lib.MPM_MAP_JTV)
+                                         / 2 ** 30, 2)}
     print(json.dumps(out), flush=True)
 
 

@@ -231,9 +231,9 @@ __device__ __forceinline__ bool solve_sym4(const float P[10], const float g[4], 
         for (int m = 0; m < j; m++) piv -= L[j][m] * L[j][m];
         bad |= !(piv >= PIVOT_MIN);
         piv = fmaxf(piv, PIVOT_MIN);
-        float lj = sqrtf(piv);
-        L[j][j] = lj;
-        inv[j] = 1.0f / lj;
+        const float ij = rsqrtf(piv);  // 1 / L_jj
+        L[j][j] = piv * ij;
+        inv[j] = ij;
 #pragma unroll
         for (int i = j + 1; i < 4; i++) {
             float v = S[i][j];
