@@ -26,7 +26,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
-KERNEL_SOURCE = os.path.join(ROOT, "paper_2102_01604_amd", "csrc", "k_map.hip")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2102_01604_amd", "csrc", f)
+                  for f in ("k_map.hip", "mpm_map.h", "mpm_device.h", "mpm_kernels.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_map_brain.txt")
 
 
@@ -34,14 +35,17 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def source_hash(path):
-    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+def source_hash(paths):
+    h = hashlib.sha256()
+    for p in paths:
+        h.update(open(p, "rb").read())
+    return h.hexdigest()[:16]
 
 
 def read_traffic(kernel):
     """HBM bytes per launch measured by rocprofv3 counters (FETCH_SIZE +
     WRITE_SIZE, scaled by a copy-kernel calibration), recorded together with
-    the hash of the kernel source they were taken on; None if absent or stale."""
+    the hash of the kernel sources they were taken on; None if absent or stale."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     kv = {}
@@ -49,7 +53,7 @@ def read_traffic(kernel):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
-    if kv.get("source_sha256_16") != source_hash(KERNEL_SOURCE) or kv.get("kernel") != kernel:
+    if kv.get("source_sha256_16") != source_hash(KERNEL_SOURCES) or kv.get("kernel") != kernel:
         return None
     try:
         return float(kv["bytes_per_launch"])

@@ -35,6 +35,9 @@
  *              skipped.
  *   R-init   : default initial maps from per-image volume means (see
  *              orc_default_init).
+ *   R-missing: a non-finite echo value is a missing observation: it adds
+ *              nothing to the NLL, gradient or Hessian of its voxel (and is
+ *              left out of the volume means of the default initialisation).
  */
 #include "mpm_oracle.h"
 
@@ -158,8 +161,10 @@ void orc_lik_voxel(const orc_protocol *p, const double *x, int64_t stride,
     for (int i = 0; i < I; i++) {
         int c = contrast_of(p, i);
         double s, ds[4], d2s[4];
+        double xi = x[(int64_t)i * stride];
+        if (!isfinite(xi)) continue; /* R-missing: no observation */
         orc_spgr_derivs(y, p->flip[c] * b1, p->tr[c], p->te[i], p->mt[c], &s, ds, d2s);
-        double res = s - x[(int64_t)i * stride];
+        double res = s - xi;
         double wgt = 1.0 / (p->sigma[i] * p->sigma[i]);
         l += 0.5 * wgt * res * res;
         for (int k = 0; k < 4; k++) {
@@ -469,8 +474,15 @@ int orc_default_init(const orc_protocol *p, int64_t n, const double *x, const do
     double m[ORC_MAX_IMAGES];
     for (int i = 0; i < I; i++) {
         double s = 0.0;
-        for (int64_t v = 0; v < n; v++) s += x[(int64_t)i * n + v];
-        m[i] = s / (double)n;
+        int64_t cnt = 0;
+        for (int64_t v = 0; v < n; v++) {
+            double xi = x[(int64_t)i * n + v];
+            if (isfinite(xi)) {
+                s += xi;
+                cnt++;
+            }
+        }
+        m[i] = cnt > 0 ? s / (double)cnt : NAN; /* no observation: left out below */
     }
     double b1m = 1.0;
     if (b1) {
@@ -483,6 +495,7 @@ int orc_default_init(const orc_protocol *p, int64_t n, const double *x, const do
     double A[ORC_MAX_CONTRASTS + 1][ORC_MAX_CONTRASTS + 2];
     memset(A, 0, sizeof(A));
     for (int i = 0; i < I; i++) {
+        if (!isfinite(m[i])) continue;
         int c = contrast_of(p, i);
         double row[ORC_MAX_CONTRASTS + 1];
         memset(row, 0, sizeof(row));

@@ -232,7 +232,9 @@ __device__ __forceinline__ float nll_only(const DevProto &P, const T *__restrict
     for (int c = 0; c < P.C; c++) {
         const float s0 = contrast_factors(p, P.tr[c], make_angle(P.flip[c] * b), P.mt[c]).s0;
         for (int i = P.first[c]; i < P.first[c + 1]; i++) {
-            const float res = s0 * __expf(-p.r2 * P.te[i]) - load_echo(X + (int64_t)i * N + n);
+            const float x = load_echo(X + (int64_t)i * N + n);
+            if (!(fabsf(x) < INFINITY)) continue;  // missing observation
+            const float res = s0 * __expf(-p.r2 * P.te[i]) - x;
             nll += 0.5f * P.wgt[i] * res * res;
         }
     }

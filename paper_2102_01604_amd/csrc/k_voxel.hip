@@ -81,7 +81,9 @@ hipError_t launch_simulate(const LaunchCtx &c, const DevProto &P, const float *m
 }
 
 // ---------------------------------------------------------------------------
-// per-image sums (for the default initialisation): grid (nblk, I + 1)
+// per-image sums (for the default initialisation): grid (nblk, 2I + 1).
+// Row i < I: sum of the finite values of image i; row I + i: their count;
+// row 2I: sum of b1.  Non-finite echoes are missing observations.
 // ---------------------------------------------------------------------------
 constexpr int SUM_ITEMS = 16;  // voxels per thread
 
@@ -103,8 +105,12 @@ __global__ __launch_bounds__(BLOCK) void k_echo_sums(int I, const T *__restrict_
     for (int j = 0; j < SUM_ITEMS; j++) {
         int64_t n = base + (int64_t)j * BLOCK;
         if (n >= N) break;
-        if (row < I) v[0] += (double)load_echo(X + (int64_t)row * N + n);
-        else v[0] += b1 ? (double)b1[n] : 1.0;
+        if (row < 2 * I) {
+            const float x = load_echo(X + (int64_t)(row < I ? row : row - I) * N + n);
+            if (fabsf(x) < INFINITY) v[0] += row < I ? (double)x : 1.0;
+        } else {
+            v[0] += b1 ? (double)b1[n] : 1.0;
+        }
     }
     block_sum<1>(v, lds);
     if (threadIdx.x == 0) partials[(int64_t)row * gridDim.x + blockIdx.x] = v[0];
@@ -113,7 +119,7 @@ __global__ __launch_bounds__(BLOCK) void k_echo_sums(int I, const T *__restrict_
 hipError_t launch_echo_sums(const LaunchCtx &c, const DevProto &P, int dtype, const void *X,
                             const float *b1, int64_t N, double *partials, int nblk)
 {
-    dim3 g(nblk, P.I + 1);
+    dim3 g(nblk, 2 * P.I + 1);
     if (dtype == DT_F32)
         hipLaunchKernelGGL(k_echo_sums<float>, g, dim3(BLOCK), 0, c.stream, P.I, (const float *)X, b1, N,
                            partials);

@@ -207,6 +207,7 @@ mpm_status default_init_from_means(const mpm_protocol *p, const double *mean, do
     int i = 0;
     for (int c = 0; c < C; c++)
         for (int e = 0; e < p->n_echoes[c]; e++, i++) {
+            if (!std::isfinite(mean[i])) continue;  // image without any finite value
             double lm = std::log(std::max(mean[i], 1e-12));
             double te = p->te_s[i];
             A[c][c] += 1.0;
@@ -316,20 +317,21 @@ mpm_status image_means(Workspace &ws, Prof &prof, const DevProto &P, int dtype, 
 {
     LaunchCtx c{ws.stream};
     int nblk = echo_sums_blocks(N);
+    const int rows = 2 * P.I + 1;
     double *part = nullptr, *sums = nullptr;
-    if (ws.alloc((void **)&part, sizeof(double) * (size_t)nblk * (P.I + 1)) != hipSuccess ||
-        ws.alloc((void **)&sums, sizeof(double) * (P.I + 1)) != hipSuccess)
+    if (ws.alloc((void **)&part, sizeof(double) * (size_t)nblk * rows) != hipSuccess ||
+        ws.alloc((void **)&sums, sizeof(double) * rows) != hipSuccess)
         return fail(MPM_ERR_OUT_OF_MEMORY, "workspace allocation failed");
     hipError_t e = prof.launch("echo_sums", (double)N * ((double)P.I * dtype_size(dtype) + (b1 ? 4 : 0)),
                                [&] { return launch_echo_sums(c, P, dtype, X, b1, N, part, nblk); });
-    if (e == hipSuccess) e = launch_reduce_rows(c, part, P.I + 1, nblk, sums);
-    std::vector<double> host(P.I + 1);
-    if (e == hipSuccess) e = hipMemcpyAsync(host.data(), sums, sizeof(double) * (P.I + 1), hipMemcpyDeviceToHost, ws.stream);
+    if (e == hipSuccess) e = launch_reduce_rows(c, part, rows, nblk, sums);
+    std::vector<double> host(rows);
+    if (e == hipSuccess) e = hipMemcpyAsync(host.data(), sums, sizeof(double) * rows, hipMemcpyDeviceToHost, ws.stream);
     if (e == hipSuccess) e = hipStreamSynchronize(ws.stream);
     if (e != hipSuccess) return fail(MPM_ERR_DEVICE, "image means: %s", hipGetErrorString(e));
     mean.resize(P.I);
-    for (int i = 0; i < P.I; i++) mean[i] = host[i] / (double)N;
-    b1m = host[P.I] / (double)N;
+    for (int i = 0; i < P.I; i++) mean[i] = host[P.I + i] > 0.0 ? host[i] / host[P.I + i] : NAN;
+    b1m = host[2 * P.I] / (double)N;
     return MPM_OK;
 }
 

@@ -148,6 +148,7 @@ struct EchoAcc {
     float R0 = 0.f, R1 = 0.f, A0 = 0.f, A1 = 0.f, A2 = 0.f, B0 = 0.f, B2 = 0.f, L = 0.f;
     __device__ __forceinline__ void add(float s, float x, float te, float w, float r2)
     {
+        if (!(fabsf(x) < INFINITY)) return;  // missing observation
         float res = s - x;
         float wr = w * res;
         float ws = w * s;

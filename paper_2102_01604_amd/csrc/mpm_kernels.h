@@ -20,7 +20,8 @@ hipError_t launch_fill_maps(const LaunchCtx &c, float *maps, int64_t N, const fl
 hipError_t launch_fill(const LaunchCtx &c, float *p, int64_t n, float v);
 hipError_t launch_simulate(const LaunchCtx &c, const DevProto &P, const float *maps, const float *b1,
                            const float *noise, int dtype, void *out, int64_t N);
-// per-image sums over voxels (+ the b1 sum in row I) -> partials[(I+1)][nblk]
+// per-image sums and counts of the finite echo values (+ the b1 sum in row
+// 2I) -> partials[(2I+1)][nblk]
 hipError_t launch_echo_sums(const LaunchCtx &c, const DevProto &P, int dtype, const void *X,
                             const float *b1, int64_t N, double *partials, int nblk);
 int echo_sums_blocks(int64_t N);

@@ -10,7 +10,7 @@ last `last` dispatches, default all): FETCH_SIZE and WRITE_SIZE (KiB per
 dispatch) scaled by what the same counters read for a
 plain device-to-device copy of 1 GiB in the same run (the copy kernel whose
 name contains "copyBuffer" with the largest FETCH_SIZE), in the key: value
-format bench.py reads, tagged with the hash of the MAP kernel source.
+format bench.py reads, tagged with the hash of the MAP kernel sources.
 """
 from __future__ import annotations
 
@@ -21,7 +21,7 @@ import statistics
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-KERNEL_SOURCE = os.path.join(HERE, "csrc", "k_map.hip")
+KERNEL_SOURCES = [os.path.join(HERE, "csrc", f) for f in ("k_map.hip", "mpm_map.h", "mpm_device.h", "mpm_kernels.h")]
 
 
 def _short(name):
@@ -56,7 +56,10 @@ def traffic(fetch_csv, write_csv, kernel, voxels, last=0):
     fv, wv = f[name][-last:] if last else f[name], w[name][-last:] if last else w[name]
     fk, wk = statistics.mean(fv), statistics.mean(wv)
     b = (fk * fs + wk * ws) * 1024.0
-    src = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        h.update(open(p, "rb").read())
+    src = h.hexdigest()[:16]
     print(f"kernel: {kernel}")
     print(f"dispatches: {len(fv)} (of {len(f[name])})")
     print(f"fetch_kib_min_max: {min(fv):.1f} {max(fv):.1f}")

@@ -129,3 +129,25 @@ def test_default_init_near_truth(orc):
     assert math.exp(y0[1]) == pytest.approx(1.0, rel=0.05)
     assert math.exp(y0[2]) == pytest.approx(25.0, rel=0.05)
     assert 1 / (1 + math.exp(-y0[3])) == pytest.approx(0.0125, rel=0.1)
+
+
+def test_missing_echo_equals_removed_image(orc):
+    """A non-finite echo is a missing observation: fitting with image 9 set to
+    NaN equals fitting with image 9 removed from the protocol."""
+    c = _case(256, seed=14)
+    x = observations(orc, c).astype(np.float64)
+    xm = x.copy()
+    xm[9, :] = np.nan
+    proto2 = dict(c["proto"])
+    proto2["n_echoes"] = [6, 5, 6]
+    proto2["te"] = [t for i, t in enumerate(c["proto"]["te"]) if i != 9]
+    proto2["sigma"] = [s for i, s in enumerate(c["proto"]["sigma"]) if i != 9]
+    x2 = np.delete(x, 9, axis=0)
+    y0 = orc.default_init(c["proto"], x)
+    opts = {"mode": "ml", "n_gn": 15, "init": "const", "init_const": y0}
+    m1, r1, _ = orc.fit(c["proto"], c["dims"], xm, None, opts)
+    m2, r2, _ = orc.fit(proto2, c["dims"], x2, None, opts)
+    assert np.abs(m1 - m2).max() <= 1e-12
+    assert r1["nll"] == pytest.approx(r2["nll"], rel=1e-13)
+    # the default initialisation averages the finite values only
+    assert np.allclose(orc.default_init(c["proto"], xm), orc.default_init(proto2, x2), rtol=1e-12)
