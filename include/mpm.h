@@ -71,7 +71,7 @@ typedef struct {
 } mpm_protocol;
 
 typedef struct {
-    int64_t nx, ny, nz; /* each >= 1 */
+    int64_t nx, ny, nz; /* each in [1, 2^20], nx*ny*nz < 2^30 */
 } mpm_grid;
 
 typedef struct {

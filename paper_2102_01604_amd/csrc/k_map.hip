@@ -6,10 +6,11 @@
 // "fin_*" kernels that follow each reduction, so the host never waits inside
 // a fit.  Reductions are two-stage and fixed-order (deterministic).
 //
-// Voxel mapping: workgroups of 64 x 4 threads cover 64 x 4 tiles of one
-// z-plane; the 1-D workgroup index is remapped so that each of the 8 XCDs
-// receives a contiguous run of tiles (consecutive tiles share stencil halos
-// in that XCD's L2).
+// Voxel mapping: the echo kernels (lik, accept, final) give each thread one
+// voxel of a 64 x 4 tile of one z-plane; the stencil-only kernels walk z-runs
+// of such tiles, and the CG sweeps z-runs of 64 x 16 tiles.  The 1-D workgroup
+// index is remapped so that each of the 8 XCDs receives a contiguous run of
+// tiles (neighbouring tiles and planes share stencil halos in that XCD's L2).
 #include <cstdlib>
 
 #include "mpm_map.h"
@@ -196,51 +197,6 @@ __device__ __forceinline__ void store_H(const HessArrays &h, int64_t n, const fl
     __builtin_nontemporal_store(r, (v2f *)(h.r + n));
 }
 
-// Likelihood block of one voxel: NLL, gradient and loaded Hessian summed over
-// all echoes (paper eq. precond with the Sec. 2.4 derivatives).
-template <typename T>
-__device__ __forceinline__ float lik_block(const DevProto &P, const T *__restrict__ X, int64_t N, int64_t n,
-                                           float b, const float y[4], int loading, float g[4], float H[10])
-{
-    Params p = decode(y);
-    float nll = 0.f;
-#pragma unroll
-    for (int k = 0; k < 4; k++) g[k] = 0.f;
-#pragma unroll
-    for (int k = 0; k < 10; k++) H[k] = 0.f;
-    for (int c = 0; c < P.C; c++) {
-        ContrastK K = contrast_factors(p, P.tr[c], make_angle(P.flip[c] * b), P.mt[c]);
-        EchoAcc acc;
-        for (int i = P.first[c]; i < P.first[c + 1]; i++) {
-            const float te = P.te[i];
-            const float s = K.s0 * __expf(-p.r2 * te);
-            acc.add(s, load_echo(X + (int64_t)i * N + n), te, P.wgt[i], p.r2);
-        }
-        nll += 0.5f * acc.L;
-        accumulate_contrast(acc, K, p.r2, loading, g, H);
-    }
-    return nll;
-}
-
-// NLL of one voxel at maps y (value only).
-template <typename T>
-__device__ __forceinline__ float nll_only(const DevProto &P, const T *__restrict__ X, int64_t N, int64_t n,
-                                          float b, const float y[4])
-{
-    Params p = decode(y);
-    float nll = 0.f;
-    for (int c = 0; c < P.C; c++) {
-        const float s0 = contrast_factors(p, P.tr[c], make_angle(P.flip[c] * b), P.mt[c]).s0;
-        for (int i = P.first[c]; i < P.first[c + 1]; i++) {
-            const float x = load_echo(X + (int64_t)i * N + n);
-            if (!(fabsf(x) < INFINITY)) continue;  // missing observation
-            const float res = s0 * __expf(-p.r2 * P.te[i]) - x;
-            nll += 0.5f * P.wgt[i] * res * res;
-        }
-    }
-    return nll;
-}
-
 // ---------------------------------------------------------------------------
 // control block
 // ---------------------------------------------------------------------------
@@ -256,13 +212,13 @@ __global__ void k_ctl_init(MapCtl *ctl, double *trace, int trace_len)
 
 // ---------------------------------------------------------------------------
 // lik: likelihood block, L y, b = g + L y, and the CG start r = b,
-// z = M^{-1} r.  Partials: NLL, y.Ly, r.z
+// z = M^{-1} r.  One voxel per thread.  Partials: NLL, y.Ly, r.z
 // ---------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(BLOCK) void k_lik(Grid3 g, DevProto P, const T *__restrict__ X,
-                                               const float *__restrict__ b1, const float *__restrict__ Y,
-                                               const float *__restrict__ w, float l0, float l1, float l2,
-                                               float l3, int loading, HessArrays Hs,
+template <typename T, int CM, int EM>
+__global__ __launch_bounds__(BLOCK) void k_lik(Grid3 g, typename VoxelEchoes<T, CM, EM>::Proto P,
+                                               const T *__restrict__ X, const float *__restrict__ b1,
+                                               const float *__restrict__ Y, const float *__restrict__ w, float l0,
+                                               float l1, float l2, float l3, int loading, HessArrays Hs,
                                                float4 *__restrict__ R, float4 *__restrict__ Z,
                                                const MapCtl *__restrict__ ctl, double *__restrict__ partials)
 {
@@ -270,49 +226,38 @@ __global__ __launch_bounds__(BLOCK) void k_lik(Grid3 g, DevProto P, const T *__r
     const int64_t N = g.N;
     const float lam[4] = {l0, l1, l2, l3};
     const Col c = locate_col(g);
+    const auto K = VoxelEchoes<T, CM, EM>::stage(P);
     double part[3] = {0.0, 0.0, 0.0};
     if (c.act) {
-        int64_t n = c.base + (int64_t)c.z0 * c.sxy;
-        float ym[4], y0[4], yp[4], wm = 0.f, w0, wp = 0.f;
-        if (c.z0 > 0) {
-            load4(Y, N, n - c.sxy, ym);
-            wm = w[n - c.sxy];
-        }
+        const int64_t n = c.base + (int64_t)c.z0 * c.sxy;
+        VoxelEchoes<T, CM, EM> ve;
+        ve.load(P, X, N, n, b1 ? b1[n] : 1.0f);
+        float y0[4];
         load4(Y, N, n, y0);
-        w0 = w[n];
-        for (int z = c.z0; z < c.z1; z++, n += c.sxy) {
-            const bool hzp = z < g.nz - 1;
-            if (hzp) {
-                load4(Y, N, n + c.sxy, yp);
-                wp = w[n + c.sxy];
-            }
-            float acc[4] = {0.f, 0.f, 0.f, 0.f}, d = 0.f;
-            for_inplane(c, n, g.nx, [&](int64_t m) {
-                float vm[4];
-                load4(Y, N, m, vm);
-                edge(w0, w[m], y0, vm, acc, d);
-            });
-            if (z > 0) edge(w0, wm, y0, ym, acc, d);
-            if (hzp) edge(w0, wp, y0, yp, acc, d);
-            float gr[4], H[10], r[4], zz[4];
-            const float nll = lik_block(P, X, N, n, b1 ? b1[n] : 1.0f, y0, loading, gr, H);
+        const float w0 = w[n];
+        float acc[4] = {0.f, 0.f, 0.f, 0.f}, d = 0.f;
+        const auto nb = [&](int64_t m) {
+            float vm[4];
+            load4(Y, N, m, vm);
+            edge(w0, w[m], y0, vm, acc, d);
+        };
+        for_inplane(c, n, g.nx, nb);
+        if (c.z0 > 0) nb(n - c.sxy);
+        if (c.z0 < g.nz - 1) nb(n + c.sxy);
+        float gr[4], H[10], r[4], zz[4];
+        const float nll = ve.lik(P, K, y0, loading, true, gr, H);
 #pragma unroll
-            for (int k = 0; k < 4; k++) {
-                acc[k] *= lam[k];  // (L y)_k
-                r[k] = gr[k] + acc[k];
-            }
-            precond(H, lam, d, r, zz);
-            store_H(Hs, n, H);
-            vstore_nt(R, n, r);
-            vstore_nt(Z, n, zz);
-            part[0] += nll;
-            part[1] += dot4(y0, acc);
-            part[2] += dot4(r, zz);
-            copy4(ym, y0);
-            copy4(y0, yp);
-            wm = w0;
-            w0 = wp;
+        for (int k = 0; k < 4; k++) {
+            acc[k] *= lam[k];  // (L y)_k
+            r[k] = gr[k] + acc[k];
         }
+        precond(H, lam, d, r, zz);
+        store_H(Hs, n, H);
+        vstore_nt(R, n, r);
+        vstore_nt(Z, n, zz);
+        part[0] = nll;
+        part[1] = dot4(y0, acc);
+        part[2] = dot4(r, zz);
     }
     write_partials<3>(part, partials);
 }
@@ -569,13 +514,13 @@ struct DeltaF {
 // accept, pass 1: the NLL at the full step y - delta_f and the prior pieces
 // c1 = delta_f.(L y), c2 = delta_f.(L delta_f), so that
 // F_w(y - t delta_f) = NLL(y - t delta_f) + (y.Ly - 2 t c1 + t^2 c2) / 2.
-// Partials: NLL_0, c1, c2
+// One voxel per thread.  Partials: NLL_0, c1, c2
 // ---------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(BLOCK) void k_accept(Grid3 g, DevProto P, const T *__restrict__ X,
-                                                  const float *__restrict__ b1, const float *__restrict__ Y,
-                                                  const float *__restrict__ w, float l0, float l1, float l2,
-                                                  float l3, const float4 *__restrict__ D,
+template <typename T, int CM, int EM>
+__global__ __launch_bounds__(BLOCK) void k_accept(Grid3 g, typename VoxelEchoes<T, CM, EM>::Proto P,
+                                                  const T *__restrict__ X, const float *__restrict__ b1,
+                                                  const float *__restrict__ Y, const float *__restrict__ w, float l0,
+                                                  float l1, float l2, float l3, const float4 *__restrict__ D,
                                                   const float4 *__restrict__ P0, const float4 *__restrict__ P1,
                                                   const MapCtl *__restrict__ ctl, double *__restrict__ partials)
 {
@@ -584,98 +529,78 @@ __global__ __launch_bounds__(BLOCK) void k_accept(Grid3 g, DevProto P, const T *
     const float lam[4] = {l0, l1, l2, l3};
     const DeltaF getd{D, ctl->p_buf ? P1 : P0, (float)ctl->alpha_pend, ctl->delta_valid != 0};
     const Col c = locate_col(g);
+    const auto K = VoxelEchoes<T, CM, EM>::stage(P);
     double part[3] = {0.0, 0.0, 0.0};
     if (c.act) {
-        int64_t n = c.base + (int64_t)c.z0 * c.sxy;
-        float ym[4], y0[4], yp[4], dm[4], d0[4], dp[4], wm = 0.f, w0, wp = 0.f;
-        if (c.z0 > 0) {
-            load4(Y, N, n - c.sxy, ym);
-            getd(n - c.sxy, dm);
-            wm = w[n - c.sxy];
-        }
+        const int64_t n = c.base + (int64_t)c.z0 * c.sxy;
+        VoxelEchoes<T, CM, EM> ve;
+        ve.load(P, X, N, n, b1 ? b1[n] : 1.0f);
+        float y0[4], d0[4];
         load4(Y, N, n, y0);
         getd(n, d0);
-        w0 = w[n];
-        for (int z = c.z0; z < c.z1; z++, n += c.sxy) {
-            const bool hzp = z < g.nz - 1;
-            if (hzp) {
-                load4(Y, N, n + c.sxy, yp);
-                getd(n + c.sxy, dp);
-                wp = w[n + c.sxy];
-            }
-            float ay[4] = {0.f, 0.f, 0.f, 0.f}, ad[4] = {0.f, 0.f, 0.f, 0.f}, d = 0.f, d2 = 0.f;
-            for_inplane(c, n, g.nx, [&](int64_t m) {
-                float vm[4], um[4];
-                load4(Y, N, m, vm);
-                getd(m, um);
-                const float wmm = w[m];
-                edge(w0, wmm, y0, vm, ay, d);
-                edge(w0, wmm, d0, um, ad, d2);
-            });
-            if (z > 0) {
-                edge(w0, wm, y0, ym, ay, d);
-                edge(w0, wm, d0, dm, ad, d2);
-            }
-            if (hzp) {
-                edge(w0, wp, y0, yp, ay, d);
-                edge(w0, wp, d0, dp, ad, d2);
-            }
+        const float w0 = w[n];
+        float ay[4] = {0.f, 0.f, 0.f, 0.f}, ad[4] = {0.f, 0.f, 0.f, 0.f}, d = 0.f, d2 = 0.f;
+        const auto nb = [&](int64_t m) {
+            float vm[4], um[4];
+            load4(Y, N, m, vm);
+            getd(m, um);
+            const float wmm = w[m];
+            edge(w0, wmm, y0, vm, ay, d);
+            edge(w0, wmm, d0, um, ad, d2);
+        };
+        for_inplane(c, n, g.nx, nb);
+        if (c.z0 > 0) nb(n - c.sxy);
+        if (c.z0 < g.nz - 1) nb(n + c.sxy);
+        float yt[4];
 #pragma unroll
-            for (int k = 0; k < 4; k++) {
-                ay[k] *= lam[k];
-                ad[k] *= lam[k];
-            }
-            float yt[4];
-#pragma unroll
-            for (int k = 0; k < 4; k++) yt[k] = y0[k] - d0[k];
-            part[0] += nll_only(P, X, N, n, b1 ? b1[n] : 1.0f, yt);
-            part[1] += dot4(d0, ay);
-            part[2] += dot4(d0, ad);
-            copy4(ym, y0);
-            copy4(y0, yp);
-            copy4(dm, d0);
-            copy4(d0, dp);
-            wm = w0;
-            w0 = wp;
+        for (int k = 0; k < 4; k++) {
+            ay[k] *= lam[k];
+            ad[k] *= lam[k];
+            yt[k] = y0[k] - d0[k];
         }
+        part[0] = ve.nll(P, K, yt);
+        part[1] = dot4(d0, ay);
+        part[2] = dot4(d0, ad);
     }
     write_partials<3>(part, partials);
 }
 
 // accept, pass 2 (only after the full step was rejected): the NLL at the
 // halved steps y - 2^-h delta_f, h = 1 .. ntrial-1.  Partial row h.
-template <typename T>
-__global__ __launch_bounds__(BLOCK) void k_accept2(Grid3 g, DevProto P, const T *__restrict__ X,
-                                                   const float *__restrict__ b1, const float *__restrict__ Y,
-                                                   const float4 *__restrict__ D, const float4 *__restrict__ P0,
-                                                   const float4 *__restrict__ P1, int ntrial,
-                                                   const MapCtl *__restrict__ ctl, double *__restrict__ partials)
+template <typename T, int CM, int EM>
+__global__ __launch_bounds__(BLOCK) void k_accept2(Grid3 g, typename VoxelEchoes<T, CM, EM>::Proto P,
+                                                   const T *__restrict__ X, const float *__restrict__ b1,
+                                                   const float *__restrict__ Y, const float4 *__restrict__ D,
+                                                   const float4 *__restrict__ P0, const float4 *__restrict__ P1,
+                                                   int ntrial, const MapCtl *__restrict__ ctl,
+                                                   double *__restrict__ partials)
 {
     if (ctl->gn_stop || !ctl->accept_more) return;
     const int64_t N = g.N;
     const DeltaF getd{D, ctl->p_buf ? P1 : P0, (float)ctl->alpha_pend, ctl->delta_valid != 0};
     const Col c = locate_col(g);
+    const auto K = VoxelEchoes<T, CM, EM>::stage(P);
     double part[MAX_TRIALS];
 #pragma unroll
     for (int h = 0; h < MAX_TRIALS; h++) part[h] = 0.0;
     if (c.act) {
-        for (int z = c.z0; z < c.z1; z++) {
-            const int64_t n = c.base + (int64_t)z * c.sxy;
-            float y[4], df[4];
-            load4(Y, N, n, y);
-            getd(n, df);
-            const float b = b1 ? b1[n] : 1.0f;
-            float step = 0.5f;
+        const int64_t n = c.base + (int64_t)c.z0 * c.sxy;
+        VoxelEchoes<T, CM, EM> ve;
+        ve.load(P, X, N, n, b1 ? b1[n] : 1.0f);
+        float y[4], df[4];
+        load4(Y, N, n, y);
+        getd(n, df);
+        float step = 0.5f;
+#pragma unroll 1
+        for (int h = 1; h < ntrial; h++) {
+            float yt[4];
 #pragma unroll
-            for (int h = 1; h < MAX_TRIALS; h++) {
-                if (h < ntrial) {
-                    float yt[4];
+            for (int k = 0; k < 4; k++) yt[k] = y[k] - step * df[k];
+            const float v = ve.nll(P, K, yt);
 #pragma unroll
-                    for (int k = 0; k < 4; k++) yt[k] = y[k] - step * df[k];
-                    part[h] += nll_only(P, X, N, n, b, yt);
-                }
-                step *= 0.5f;
-            }
+            for (int j = 1; j < MAX_TRIALS; j++)
+                if (j == h) part[j] = v;
+            step *= 0.5f;
         }
     }
     write_partials<MAX_TRIALS>(part, partials);
@@ -754,70 +679,67 @@ __global__ __launch_bounds__(BLOCK) void k_weights(Grid3 g, const float *__restr
 // voxels.  With var != NULL also the Laplace variance of paper Sec. 3.6 (and
 // with mom != NULL the log-normal moments of r1 and t1).
 // ---------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(BLOCK) void k_final(Grid3 g, DevProto P, const T *__restrict__ X,
-                                                 const float *__restrict__ b1, const float *__restrict__ Y,
-                                                 const float *__restrict__ w, float l0, float l1, float l2,
-                                                 float l3, int loading, float *__restrict__ var,
+template <typename T, int CM, int EM>
+__global__ __launch_bounds__(BLOCK) void k_final(Grid3 g, typename VoxelEchoes<T, CM, EM>::Proto P,
+                                                 const T *__restrict__ X, const float *__restrict__ b1,
+                                                 const float *__restrict__ Y, const float *__restrict__ w, float l0,
+                                                 float l1, float l2, float l3, int loading, float *__restrict__ var,
                                                  float *__restrict__ mom, double *__restrict__ partials)
 {
     const int64_t N = g.N;
     const float lam[4] = {l0, l1, l2, l3};
     const Col c = locate_col(g);
+    const auto K = VoxelEchoes<T, CM, EM>::stage(P);
     double part[3] = {0.0, 0.0, 0.0};
     if (c.act) {
-        int64_t n = c.base + (int64_t)c.z0 * c.sxy;
-        float wm = c.z0 > 0 ? w[n - c.sxy] : 0.f, w0 = w[n], wp = 0.f;
-        for (int z = c.z0; z < c.z1; z++, n += c.sxy) {
-            const bool hzp = z < g.nz - 1;
-            if (hzp) wp = w[n + c.sxy];
-            float d = 0.f;
-            for_inplane(c, n, g.nx, [&](int64_t m) { d += w0 + w[m]; });
-            if (z > 0) d += w0 + wm;
-            if (hzp) d += w0 + wp;
-            float y[4], gr[4], H[10];
-            load4(Y, N, n, y);
-            const float nll = lik_block(P, X, N, n, b1 ? b1[n] : 1.0f, y, loading, gr, H);
-            float M[10];
+        const int64_t n = c.base + (int64_t)c.z0 * c.sxy;
+        VoxelEchoes<T, CM, EM> ve;
+        ve.load(P, X, N, n, b1 ? b1[n] : 1.0f);
+        const float w0 = w[n];
+        float d = 0.f;
+        for_inplane(c, n, g.nx, [&](int64_t m) { d += w0 + w[m]; });
+        if (c.z0 > 0) d += w0 + w[n - c.sxy];
+        if (c.z0 < g.nz - 1) d += w0 + w[n + c.sxy];
+        float y[4], gr[4], H[10];
+        load4(Y, N, n, y);
+        const float nll = ve.lik(P, K, y, loading, true, gr, H);
+        float M[10];
 #pragma unroll
-            for (int k = 0; k < 10; k++) M[k] = H[k];
-            M[0] += lam[0] * d;
-            M[4] += lam[1] * d;
-            M[7] += lam[2] * d;
-            M[9] += lam[3] * d;
-            const float e0[4] = {1.f, 0.f, 0.f, 0.f};
-            float tmp[4];
-            const bool degen = solve_sym4(M, e0, tmp);
-            bool bad = false;
+        for (int k = 0; k < 10; k++) M[k] = H[k];
+        M[0] += lam[0] * d;
+        M[4] += lam[1] * d;
+        M[7] += lam[2] * d;
+        M[9] += lam[3] * d;
+        const float e0[4] = {1.f, 0.f, 0.f, 0.f};
+        float tmp[4];
+        const bool degen = solve_sym4(M, e0, tmp);
+        bool bad = false;
 #pragma unroll
-            for (int k = 0; k < 4; k++) bad |= !(fabsf(y[k]) < INFINITY);
-            part[0] += nll;
-            part[1] += degen ? 1.0 : 0.0;
-            part[2] += bad ? 1.0 : 0.0;
-            if (var) {
-                const float dg[4] = {M[0], M[4], M[7], M[9]};
-                const float maxd = fmaxf(fmaxf(dg[0], dg[1]), fmaxf(dg[2], dg[3]));
-                float vv[4];
+        for (int k = 0; k < 4; k++) bad |= !(fabsf(y[k]) < INFINITY);
+        part[0] = nll;
+        part[1] = degen ? 1.0 : 0.0;
+        part[2] = bad ? 1.0 : 0.0;
+        if (var) {
+            const float dg[4] = {M[0], M[4], M[7], M[9]};
+            const float maxd = fmaxf(fmaxf(dg[0], dg[1]), fmaxf(dg[2], dg[3]));
+            float vv[4];
 #pragma unroll
-                for (int k = 0; k < 4; k++) {
-                    float e[4] = {0.f, 0.f, 0.f, 0.f}, col[4];
-                    e[k] = 1.0f;
-                    const bool frozen = !(dg[k] > FROZEN_REL * maxd);
-                    const bool dk = solve_sym4(M, e, col);
-                    vv[k] = (frozen || dk) ? INFINITY : col[k];
-                    var[k * N + n] = vv[k];
-                }
-                if (mom) {
-                    const float ev = expf(vv[1]);
-                    const float er = expf(y[1]), et = expf(-y[1]);
-                    mom[n] = sqrtf(ev) * er;
-                    mom[N + n] = (ev - 1.0f) * ev * er * er;
-                    mom[2 * N + n] = sqrtf(ev) * et;
-                    mom[3 * N + n] = (ev - 1.0f) * ev * et * et;
-                }
+            for (int k = 0; k < 4; k++) {
+                float e[4] = {0.f, 0.f, 0.f, 0.f}, col[4];
+                e[k] = 1.0f;
+                const bool frozen = !(dg[k] > FROZEN_REL * maxd);
+                const bool dk = solve_sym4(M, e, col);
+                vv[k] = (frozen || dk) ? INFINITY : col[k];
+                var[k * N + n] = vv[k];
             }
-            wm = w0;
-            w0 = wp;
+            if (mom) {
+                const float ev = expf(vv[1]);
+                const float er = expf(y[1]), et = expf(-y[1]);
+                mom[n] = sqrtf(ev) * er;
+                mom[N + n] = (ev - 1.0f) * ev * er * er;
+                mom[2 * N + n] = sqrtf(ev) * et;
+                mom[3 * N + n] = (ev - 1.0f) * ev * et * et;
+            }
         }
     }
     write_partials<3>(part, partials);
@@ -974,38 +896,40 @@ hipError_t launch_ctl_init(hipStream_t s, MapCtl *ctl, double *trace, int trace_
     return hipGetLastError();
 }
 
-#define DISPATCH_T(KERNEL, ...)                                                         \
-    do {                                                                                \
-        if (a.dtype == DT_F32) {                                                        \
-            using T = float;                                                            \
-            hipLaunchKernelGGL(KERNEL<T>, cols(a.gp), dim3(BLOCK), 0, s, __VA_ARGS__); \
-        } else if (a.dtype == DT_F16) {                                                 \
-            using T = F16;                                                              \
-            hipLaunchKernelGGL(KERNEL<T>, cols(a.gp), dim3(BLOCK), 0, s, __VA_ARGS__); \
-        } else {                                                                        \
-            using T = BF16;                                                             \
-            hipLaunchKernelGGL(KERNEL<T>, cols(a.gp), dim3(BLOCK), 0, s, __VA_ARGS__); \
-        }                                                                               \
+// Launch KERNEL<T, CM, EM>(G, protocol, X, ...) for the echo storage type T
+// and the register shape (CM, EM) of the protocol (echo_shape).
+#define LAUNCH_ONE(KERNEL, T, CM, EM, G, ...)                                                          \
+    hipLaunchKernelGGL((KERNEL<T, CM, EM>), cols(G), dim3(BLOCK), 0, s, G,                             \
+                       (ProtoArg<T, CM, EM>::make(a.P, (const T *)a.X, a.g.N)), (const T *)a.X, __VA_ARGS__)
+
+#define LAUNCH_SHAPED(KERNEL, T, G, ...)                                     \
+    do {                                                                     \
+        switch (echo_shape(a.P)) {                                           \
+        case 1: LAUNCH_ONE(KERNEL, T, 4, 8, G, __VA_ARGS__); break;          \
+        case 2: LAUNCH_ONE(KERNEL, T, 4, 16, G, __VA_ARGS__); break;         \
+        case 3: LAUNCH_ONE(KERNEL, T, 8, 8, G, __VA_ARGS__); break;          \
+        default: LAUNCH_ONE(KERNEL, T, 0, 0, G, __VA_ARGS__); break;         \
+        }                                                                    \
     } while (0)
 
-#define DISPATCH_COL_T(KERNEL, ...)                                                    \
-    do {                                                                               \
-        if (a.dtype == DT_F32) {                                                       \
-            using T = float;                                                           \
-            hipLaunchKernelGGL(KERNEL<T>, cols(a.g), dim3(BLOCK), 0, s, __VA_ARGS__); \
-        } else if (a.dtype == DT_F16) {                                                \
-            using T = F16;                                                             \
-            hipLaunchKernelGGL(KERNEL<T>, cols(a.g), dim3(BLOCK), 0, s, __VA_ARGS__); \
-        } else {                                                                       \
-            using T = BF16;                                                            \
-            hipLaunchKernelGGL(KERNEL<T>, cols(a.g), dim3(BLOCK), 0, s, __VA_ARGS__); \
-        }                                                                              \
+#define DISPATCH_T(KERNEL, G, ...)                                           \
+    do {                                                                     \
+        if (a.dtype == DT_F32) {                                             \
+            using T = float;                                                 \
+            LAUNCH_SHAPED(KERNEL, T, G, __VA_ARGS__);                        \
+        } else if (a.dtype == DT_F16) {                                      \
+            using T = F16;                                                   \
+            LAUNCH_SHAPED(KERNEL, T, G, __VA_ARGS__);                        \
+        } else {                                                             \
+            using T = BF16;                                                  \
+            LAUNCH_SHAPED(KERNEL, T, G, __VA_ARGS__);                        \
+        }                                                                    \
     } while (0)
 
 hipError_t launch_lik(hipStream_t s, const MapArgs &a)
 {
     const float *l = a.lam;
-    DISPATCH_T(k_lik, a.gp, a.P, (const T *)a.X, a.b1, a.Y, a.w, l[0], l[1], l[2], l[3], a.loading, a.H, a.R, a.Z,
+    DISPATCH_T(k_lik, a.gp, a.b1, a.Y, a.w, l[0], l[1], l[2], l[3], a.loading, a.H, a.R, a.Z,
                a.ctl, a.partials);
     return hipGetLastError();
 }
@@ -1034,14 +958,14 @@ int cg_blocks(const MapArgs &a) { return grid_blocks(a.gt); }
 hipError_t launch_accept(hipStream_t s, const MapArgs &a)
 {
     const float *l = a.lam;
-    DISPATCH_COL_T(k_accept, a.g, a.P, (const T *)a.X, a.b1, a.Y, a.w, l[0], l[1], l[2], l[3], a.D, a.P0, a.P1, a.ctl,
+    DISPATCH_T(k_accept, a.gp, a.b1, a.Y, a.w, l[0], l[1], l[2], l[3], a.D, a.P0, a.P1, a.ctl,
                a.partials);
     return hipGetLastError();
 }
 
 hipError_t launch_accept2(hipStream_t s, const MapArgs &a, int ntrial)
 {
-    DISPATCH_T(k_accept2, a.gp, a.P, (const T *)a.X, a.b1, a.Y, a.D, a.P0, a.P1, ntrial, a.ctl, a.partials);
+    DISPATCH_T(k_accept2, a.gp, a.b1, a.Y, a.D, a.P0, a.P1, ntrial, a.ctl, a.partials);
     return hipGetLastError();
 }
 
@@ -1063,7 +987,7 @@ hipError_t launch_weights(hipStream_t s, const MapArgs &a, int prior_on)
 hipError_t launch_final(hipStream_t s, const MapArgs &a, float *var, float *mom)
 {
     const float *l = a.lam;
-    DISPATCH_T(k_final, a.gp, a.P, (const T *)a.X, a.b1, a.Y, a.w, l[0], l[1], l[2], l[3], a.loading, var, mom,
+    DISPATCH_T(k_final, a.gp, a.b1, a.Y, a.w, l[0], l[1], l[2], l[3], a.loading, var, mom,
                a.partials);
     return hipGetLastError();
 }

@@ -153,14 +153,15 @@ hipError_t launch_reduce_rows(const LaunchCtx &c, const double *in, int nrows, i
 }
 
 // ---------------------------------------------------------------------------
-// ML fit (paper Sec. 2.3-2.4): each thread owns one voxel, keeps its echoes in
-// registers and runs all n_gn Newton-like steps y <- y - P~^{-1} g.
-// CM x EM bounds the echoes held in registers (contrasts x echoes each).
+// ML fit (paper Sec. 2.3-2.4): each thread owns one voxel and runs all n_gn
+// Newton-like steps y <- y - P~^{-1} g.  Protocols of at most CM contrasts x
+// EM echoes keep the echoes in registers; CM = EM = 0 re-reads them from
+// memory at every step (any protocol).
 // ---------------------------------------------------------------------------
 int ml_fit_blocks(int64_t N) { return (int)((N + BLOCK - 1) / BLOCK); }
 
 template <typename T, int CM, int EM>
-__global__ __launch_bounds__(BLOCK) void k_ml_fit(DevProto P, const T *__restrict__ X,
+__global__ __launch_bounds__(BLOCK) void k_ml_fit(typename VoxelEchoes<T, CM, EM>::Proto P, const T *__restrict__ X,
                                                   const float *__restrict__ b1, float *__restrict__ maps,
                                                   int64_t N, int n_gn, int loading,
                                                   double *__restrict__ partials)
@@ -171,47 +172,17 @@ __global__ __launch_bounds__(BLOCK) void k_ml_fit(DevProto P, const T *__restric
     const bool active = n < N;
     const int64_t nn = active ? n : 0;
 
-    float x[CM][EM];
-    Angle an[CM];
-    float b = b1 ? b1[nn] : 1.0f;
-#pragma unroll
-    for (int c = 0; c < CM; c++) {
-        if (c < P.C) {
-            an[c] = make_angle(P.flip[c] * b);
-            int i0 = P.first[c], ne = P.first[c + 1] - i0;
-#pragma unroll
-            for (int e = 0; e < EM; e++)
-                x[c][e] = (e < ne) ? load_echo(X + (int64_t)(i0 + e) * N + nn) : 0.0f;
-        }
-    }
+    const auto K = VoxelEchoes<T, CM, EM>::stage(P);
+    VoxelEchoes<T, CM, EM> ve;
+    ve.load(P, X, N, nn, b1 ? b1[nn] : 1.0f);
     float y[4] = {maps[nn], maps[N + nn], maps[2 * N + nn], maps[3 * N + nn]};
 
     float prev_nll = 0.0f;
     double cnt_inc = 0.0, degen = 0.0;
     for (int it = 0; it <= n_gn; it++) {
         const bool last = (it == n_gn);
-        Params p = decode(y);
-        float g[4] = {0.f, 0.f, 0.f, 0.f};
-        float H[10] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-        float nll = 0.0f;
-#pragma unroll
-        for (int c = 0; c < CM; c++) {
-            if (c < P.C) {
-                ContrastK K = contrast_factors(p, P.tr[c], an[c], P.mt[c]);
-                int i0 = P.first[c], ne = P.first[c + 1] - i0;
-                EchoAcc acc;
-#pragma unroll
-                for (int e = 0; e < EM; e++) {
-                    if (e < ne) {
-                        float te = P.te[i0 + e];
-                        float s = K.s0 * __expf(-p.r2 * te);
-                        acc.add(s, x[c][e], te, P.wgt[i0 + e], p.r2);
-                    }
-                }
-                nll += 0.5f * acc.L;
-                if (!last) accumulate_contrast(acc, K, p.r2, loading, g, H);
-            }
-        }
+        float g[4], H[10];
+        const float nll = ve.lik(P, K, y, loading, !last, g, H);
         if (it > 0 && nll > prev_nll * (1.0f + 1e-5f)) cnt_inc += 1.0;
         prev_nll = nll;
         double v[1] = {active ? (double)nll : 0.0};
@@ -246,17 +217,20 @@ template <typename T>
 static hipError_t ml_dispatch(const LaunchCtx &c, const DevProto &P, const T *X, const float *b1,
                               float *maps, int64_t N, int n_gn, int loading, double *partials, int nblk)
 {
-    int emax = 0;
-    for (int k = 0; k < P.C; k++) emax = max(emax, P.first[k + 1] - P.first[k]);
     dim3 g(nblk), b(BLOCK);
-    if (P.C <= 4 && emax <= 8)
-        hipLaunchKernelGGL((k_ml_fit<T, 4, 8>), g, b, 0, c.stream, P, X, b1, maps, N, n_gn, loading, partials);
-    else if (P.C <= 4 && emax <= 16)
-        hipLaunchKernelGGL((k_ml_fit<T, 4, 16>), g, b, 0, c.stream, P, X, b1, maps, N, n_gn, loading, partials);
-    else if (emax <= 8)
-        hipLaunchKernelGGL((k_ml_fit<T, 8, 8>), g, b, 0, c.stream, P, X, b1, maps, N, n_gn, loading, partials);
+    const int shape = echo_shape(P);
+    if (shape == 1)
+        hipLaunchKernelGGL((k_ml_fit<T, 4, 8>), g, b, 0, c.stream, (ProtoArg<T, 4, 8>::make(P, X, N)), X, b1,
+                           maps, N, n_gn, loading, partials);
+    else if (shape == 2)
+        hipLaunchKernelGGL((k_ml_fit<T, 4, 16>), g, b, 0, c.stream, (ProtoArg<T, 4, 16>::make(P, X, N)), X, b1,
+                           maps, N, n_gn, loading, partials);
+    else if (shape == 3)
+        hipLaunchKernelGGL((k_ml_fit<T, 8, 8>), g, b, 0, c.stream, (ProtoArg<T, 8, 8>::make(P, X, N)), X, b1,
+                           maps, N, n_gn, loading, partials);
     else
-        return hipErrorInvalidValue;  // rejected on the host before launch
+        hipLaunchKernelGGL((k_ml_fit<T, 0, 0>), g, b, 0, c.stream, (ProtoArg<T, 0, 0>::make(P, X, N)), X, b1,
+                           maps, N, n_gn, loading, partials);
     return hipGetLastError();
 }
 

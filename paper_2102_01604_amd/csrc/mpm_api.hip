@@ -147,7 +147,8 @@ mpm_status check_grid(const mpm_grid *g, int64_t *N)
     if (g->nx > (1 << 20) || g->ny > (1 << 20) || g->nz > (1 << 20))
         return fail(MPM_ERR_INVALID_ARG, "grid axis longer than 2^20");
     int64_t n = g->nx * g->ny * g->nz;
-    if (n > ((int64_t)1 << 31) - 1) return fail(MPM_ERR_INVALID_ARG, "grid has more than 2^31-1 voxels");
+    // byte offsets into one echo image are 32-bit in the kernels
+    if (n > ((int64_t)1 << 30) - 1) return fail(MPM_ERR_INVALID_ARG, "grid has more than 2^30-1 voxels");
     *N = n;
     return MPM_OK;
 }
@@ -287,12 +288,6 @@ mpm_status check_fit_args(const mpm_protocol *protocol, const mpm_grid *grid, in
     if (!has_mt(protocol))
         return fail(MPM_ERR_UNSUPPORTED, "the four-parameter model needs at least one MT contrast");
     if (opt->mode == MPM_MAP_JTV && *N < 2) return fail(MPM_ERR_UNSUPPORTED, "MAP needs at least 2 voxels");
-    if (opt->mode == MPM_ML) {
-        int emax = 0;
-        for (int c = 0; c < protocol->n_contrasts; c++) emax = std::max(emax, (int)protocol->n_echoes[c]);
-        if (!((protocol->n_contrasts <= 4 && emax <= 16) || emax <= 8))
-            return fail(MPM_ERR_UNSUPPORTED, "ML fit keeps echoes in registers: at most 4 contrasts x 16 echoes or 8 x 8");
-    }
     return MPM_OK;
 }
 

@@ -85,7 +85,7 @@ __device__ __forceinline__ Params decode(const float y[4])
     p.a = __expf(y[0]);
     p.r1 = __expf(y[1]);
     p.r2 = __expf(y[2]);
-    p.dl = 1.0f / (1.0f + __expf(-y[3]));
+    p.dl = __builtin_amdgcn_rcpf(1.0f + __expf(-y[3]));
     return p;
 }
 
@@ -102,17 +102,46 @@ struct ContrastK {
     float s0, phi, psi, kap, mu;
 };
 
-// Flip-angle terms of one (voxel, contrast), computed once per voxel.
+// Flip-angle terms of one (voxel, contrast), computed once per voxel, all
+// from the half angle h = alpha / 2:
+//   sin(alpha) = 2 sin(h) cos(h),  cos(alpha) = 1 - 2 sin^2(h),
+//   1 - cos(alpha) = 2 sin^2(h)  (no cancellation for small flip angles).
+// sin(h) and cos(h): h = r + q pi/2 with integer q and |r| <= pi/4 (pi/2 split
+// in two parts, so r is exact to FP32 rounding for |h| < 1e4), then the Taylor
+// series of sin r and cos r, truncated where the next term is below 1e-11,
+// and the quadrant identities.  Flip angles of the configs give q = 0.
 struct Angle {
-    float sa, ca, omc;  // sin(alpha), cos(alpha), 1 - cos(alpha) = 2 sin^2(alpha/2)
+    float sa, ca, omc;  // sin(alpha), cos(alpha), 1 - cos(alpha)
 };
 
 __device__ __forceinline__ Angle make_angle(float alpha)
 {
+    const float h = 0.5f * alpha;
+    const float q = rintf(h * 0.63661977f);  // 2 / pi
+    const float r = fmaf(q, 4.3711388e-8f, fmaf(-q, 1.5707964f, h));  // h - q pi/2, pi/2 = 1.5707964 - 4.3711388e-8
+    const float u = r * r;
+    // sin r = r (1 - u/3! + u^2/5! - u^3/7! + u^4/9! - u^5/11!)
+    float ps = -2.5052108e-8f;
+    ps = fmaf(ps, u, 2.7557319e-6f);
+    ps = fmaf(ps, u, -1.9841270e-4f);
+    ps = fmaf(ps, u, 8.3333333e-3f);
+    ps = fmaf(ps, u, -1.6666667e-1f);
+    const float sr = fmaf(r * u, ps, r);
+    // cos r = 1 - u/2! + u^2/4! - u^3/6! + u^4/8! - u^5/10! + u^6/12!
+    float pc = 2.0876757e-9f;
+    pc = fmaf(pc, u, -2.7557319e-7f);
+    pc = fmaf(pc, u, 2.4801587e-5f);
+    pc = fmaf(pc, u, -1.3888889e-3f);
+    pc = fmaf(pc, u, 4.1666667e-2f);
+    pc = fmaf(pc, u, -0.5f);
+    const float cr = fmaf(u, pc, 1.0f);
+    const int iq = (int)q & 3;
+    const float sh = iq == 0 ? sr : iq == 1 ? cr : iq == 2 ? -sr : -cr;
+    const float ch = iq == 0 ? cr : iq == 1 ? -sr : iq == 2 ? -cr : sr;
     Angle a;
-    sincosf(alpha, &a.sa, &a.ca);
-    float sh = sinf(0.5f * alpha);
     a.omc = 2.0f * sh * sh;
+    a.sa = 2.0f * sh * ch;
+    a.ca = 1.0f - a.omc;
     return a;
 }
 
@@ -124,10 +153,10 @@ __device__ __forceinline__ ContrastK contrast_factors(const Params &p, float tr,
     float e1 = 1.0f - ome;                      // E
     float one_m_omega = an.omc + dl * an.ca;    // 1 - (1 - delta) cos(alpha)
     float den = ome + e1 * one_m_omega;         // 1 - omega E
-    float inv_den = 1.0f / den;
+    float inv_den = __builtin_amdgcn_rcpf(den);
     ContrastK k;
     k.s0 = p.a * an.sa * (1.0f - dl) * ome * inv_den;
-    k.phi = x * one_m_omega * e1 * inv_den / ome;
+    k.phi = x * one_m_omega * e1 * inv_den * __builtin_amdgcn_rcpf(ome);
     k.kap = 1.0f - x * (2.0f - den) * inv_den;  // 1 + omega E = 2 - den
     k.psi = -dl * inv_den;
     k.mu = 2.0f * (1.0f - dl) * (ome + e1 * an.omc) * inv_den - 1.0f;
@@ -146,25 +175,37 @@ __device__ __forceinline__ ContrastK contrast_factors(const Params &p, float tr,
 // ---------------------------------------------------------------------------
 struct EchoAcc {
     float R0 = 0.f, R1 = 0.f, A0 = 0.f, A1 = 0.f, A2 = 0.f, B0 = 0.f, B2 = 0.f, L = 0.f;
-    __device__ __forceinline__ void add(float s, float x, float te, float w, float r2)
+    // One echo: model value s, observation x at echo time te (te2 = te^2),
+    // weight w.  A non-finite x is a missing observation: its weight and value
+    // are replaced by 0, so every term it adds is exactly 0.
+    __device__ __forceinline__ void add(float s, float x, float te, float te2, float w, float r2)
     {
-        if (!(fabsf(x) < INFINITY)) return;  // missing observation
-        float res = s - x;
-        float wr = w * res;
-        float ws = w * s;
-        float wrs = wr * s;
+        const bool ok = fabsf(x) < INFINITY;
+        const float wv = ok ? w : 0.0f;
+        const float res = s - (ok ? x : 0.0f);
+        const float wr = wv * res;
+        const float ws = wv * s;
+        const float wrs = wr * s;
         R0 += wrs;
-        R1 += wrs * te;
-        float ws2 = ws * s;
+        R1 = fmaf(wrs, te, R1);
+        const float ws2 = ws * s;
         A0 += ws2;
-        A1 += ws2 * te;
-        A2 += ws2 * te * te;
-        float ab = fabsf(wrs);
-        B0 += ab;
-        B2 += ab * te * fabsf(1.0f - te * r2);
-        L += wr * res;
+        A1 = fmaf(ws2, te, A1);
+        A2 = fmaf(ws2, te2, A2);
+        B0 += fabsf(wrs);
+        B2 = fmaf(fabsf(wrs), fabsf(fmaf(-te2, r2, te)), B2);  // te |1 - te r2|, te >= 0
+        L = fmaf(wr, res, L);
     }
 };
+
+// The same echo's contribution to sum w res^2 (value only, same arithmetic
+// as EchoAcc::L).
+__device__ __forceinline__ float nll_add(float s, float x, float w, float L)
+{
+    const bool ok = fabsf(x) < INFINITY;
+    const float res = s - (ok ? x : 0.0f);
+    return fmaf((ok ? w : 0.0f) * res, res, L);
+}
 
 __device__ __forceinline__ void accumulate_contrast(const EchoAcc &e, const ContrastK &K, float r2,
                                                     int loading, float g[4], float H[10])
@@ -190,6 +231,238 @@ __device__ __forceinline__ void accumulate_contrast(const EchoAcc &e, const Cont
         H[9] += fabsf(K.mu * K.psi) * e.B0;
     }
 }
+
+// ---------------------------------------------------------------------------
+// The echoes of one voxel and its likelihood terms.
+//
+// Protocols of at most CM contrasts with at most EM echoes each use a table
+// with one slot (c, e) per contrast and echo at fixed offsets of the kernel
+// arguments (ShapedProto), and keep the voxel's echoes in registers, x[c][e],
+// with every load issued before any arithmetic uses them.  Slots past the last
+// echo of a contrast repeat its last image with weight 0: they read valid
+// memory and add exactly 0, so the per-echo loops carry no guards.  Other
+// protocols use DevProto and read each echo inside the per-echo loop.  Both
+// evaluate the same per-echo arithmetic:
+//   K = stage(P): per-workgroup constants (called by every thread first);
+//   lik(P, K, y, loading, grad, g, H): NLL; with grad also g and the loaded
+//       Hessian (paper Sec. 2.3 eq. precond with the Sec. 2.4 derivatives);
+//   nll(P, K, y): the NLL alone (bitwise equal to lik's).
+// ---------------------------------------------------------------------------
+template <typename T, int CM, int EM>
+struct ShapedProto {
+    int C;
+    uint32_t stride;          // bytes between consecutive images (N * sizeof(T))
+    const T *base[CM];        // first image of contrast c
+    int last[CM];             // echo index of the last image of contrast c
+    float tr[CM], flip[CM];
+    int mt[CM];
+    float te[CM][EM], te2[CM][EM], wgt[CM][EM];
+};
+
+// Host: the slot table of protocol P for echoes X [I][N] (N < 2^30).  Needs
+// at most CM contrasts of at most EM echoes.
+template <typename T, int CM, int EM>
+inline ShapedProto<T, CM, EM> make_shaped(const DevProto &P, const T *X, int64_t N)
+{
+    ShapedProto<T, CM, EM> s = {};
+    s.C = P.C;
+    s.stride = (uint32_t)(N * (int64_t)sizeof(T));
+    for (int c = 0; c < CM; c++) {
+        const bool on = c < P.C;
+        const int ne = on ? P.first[c + 1] - P.first[c] : 1;
+        s.base[c] = X + (on ? (int64_t)P.first[c] * N : 0);
+        s.last[c] = ne - 1;
+        s.tr[c] = on ? P.tr[c] : 1.0f;
+        s.flip[c] = on ? P.flip[c] : 0.0f;
+        s.mt[c] = on ? P.mt[c] : 0;
+        for (int e = 0; e < EM; e++) {
+            const int i = on ? P.first[c] + (e < ne ? e : ne - 1) : 0;
+            s.te[c][e] = P.te[i];
+            s.te2[c][e] = P.te[i] * P.te[i];
+            s.wgt[c][e] = on && e < ne ? P.wgt[i] : 0.0f;
+        }
+    }
+    return s;
+}
+
+typedef float slot4 __attribute__((ext_vector_type(4)));  // te, te^2, weight, 0 of one slot
+typedef const volatile __attribute__((address_space(3))) slot4 lds_slot4;
+
+template <typename T, int CM, int EM>
+struct VoxelEchoes {
+    using Proto = ShapedProto<T, CM, EM>;
+    using Consts = lds_slot4 *;
+    float x[CM][EM];
+    Angle an[CM];
+
+    // Stage the per-slot constants in LDS, read back at each use (volatile:
+    // one broadcast LDS read per slot and evaluation, instead of holding all
+    // of them in scalar registers).  Every thread of the workgroup calls this
+    // before load; it ends with a barrier.
+    static __device__ __forceinline__ Consts stage(const Proto &P)
+    {
+        __shared__ slot4 tab[CM * EM];
+        if (threadIdx.x == 0) {
+#pragma unroll
+            for (int c = 0; c < CM; c++)
+#pragma unroll
+                for (int e = 0; e < EM; e++) tab[c * EM + e] = slot4{P.te[c][e], P.te2[c][e], P.wgt[c][e], 0.0f};
+        }
+        __syncthreads();
+        return (lds_slot4 *)tab;
+    }
+
+    // n: voxel index; byte offsets n * sizeof(T) fit 32 bits (N < 2^30)
+    __device__ __forceinline__ void load(const Proto &P, const T *__restrict__, int64_t, int64_t n, float b)
+    {
+        const uint32_t off = (uint32_t)n * (uint32_t)sizeof(T);
+#pragma unroll
+        for (int c = 0; c < CM; c++) {
+            if (c < P.C) {
+                const char *img0 = (const char *)P.base[c] + off;
+#pragma unroll
+                for (int e = 0; e < EM; e++) {
+                    const uint64_t k = (uint64_t)(e < P.last[c] ? e : P.last[c]);  // slots past the last echo
+                    x[c][e] = load_echo((const T *)(img0 + k * P.stride));
+                }
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < CM; c++)
+            if (c < P.C) an[c] = make_angle(P.flip[c] * b);
+    }
+
+    __device__ __forceinline__ float lik(const Proto &P, Consts K, const float y[4], int loading, bool grad,
+                                         float g[4], float H[10]) const
+    {
+        const Params p = decode(y);
+        const float k2 = -p.r2 * 1.4426950f;  // exp(-r2 te) = 2^(k2 te)
+        float nll = 0.f;
+#pragma unroll
+        for (int k = 0; k < 4; k++) g[k] = 0.f;
+#pragma unroll
+        for (int k = 0; k < 10; k++) H[k] = 0.f;
+#pragma unroll
+        for (int c = 0; c < CM; c++) {
+            if (c < P.C) {
+                const ContrastK F = contrast_factors(p, P.tr[c], an[c], P.mt[c]);
+                EchoAcc acc;
+#pragma unroll
+                for (int e = 0; e < EM; e++) {
+                    const slot4 k = K[c * EM + e];
+                    acc.add(F.s0 * __builtin_amdgcn_exp2f(k2 * k.x), x[c][e], k.x, k.y, k.z, p.r2);
+                }
+                nll += 0.5f * acc.L;
+                if (grad) accumulate_contrast(acc, F, p.r2, loading, g, H);
+            }
+        }
+        return nll;
+    }
+
+    __device__ __forceinline__ float nll(const Proto &P, Consts K, const float y[4]) const
+    {
+        const Params p = decode(y);
+        const float k2 = -p.r2 * 1.4426950f;
+        float v = 0.f;
+#pragma unroll
+        for (int c = 0; c < CM; c++) {
+            if (c < P.C) {
+                const float s0 = contrast_factors(p, P.tr[c], an[c], P.mt[c]).s0;
+                float L = 0.f;
+#pragma unroll
+                for (int e = 0; e < EM; e++) {
+                    const slot4 k = K[c * EM + e];
+                    L = nll_add(s0 * __builtin_amdgcn_exp2f(k2 * k.x), x[c][e], k.z, L);
+                }
+                v += 0.5f * L;
+            }
+        }
+        return v;
+    }
+};
+
+template <typename T>
+struct VoxelEchoes<T, 0, 0> {
+    using Proto = DevProto;
+    using Consts = const void *;
+    const T *__restrict__ X;
+    int64_t N, n;
+    float b;
+
+    static __device__ __forceinline__ Consts stage(const Proto &) { return nullptr; }
+
+    __device__ __forceinline__ void load(const Proto &, const T *__restrict__ X_, int64_t N_, int64_t n_, float b_)
+    {
+        X = X_;
+        N = N_;
+        n = n_;
+        b = b_;
+    }
+
+    __device__ __forceinline__ float lik(const Proto &P, Consts, const float y[4], int loading, bool grad,
+                                         float g[4], float H[10]) const
+    {
+        const Params p = decode(y);
+        const float k2 = -p.r2 * 1.4426950f;
+        float nll = 0.f;
+#pragma unroll
+        for (int k = 0; k < 4; k++) g[k] = 0.f;
+#pragma unroll
+        for (int k = 0; k < 10; k++) H[k] = 0.f;
+        for (int c = 0; c < P.C; c++) {
+            const ContrastK K = contrast_factors(p, P.tr[c], make_angle(P.flip[c] * b), P.mt[c]);
+            EchoAcc acc;
+            for (int i = P.first[c]; i < P.first[c + 1]; i++) {
+                const float te = P.te[i];
+                acc.add(K.s0 * __builtin_amdgcn_exp2f(k2 * te), load_echo(X + (int64_t)i * N + n), te, te * te,
+                        P.wgt[i], p.r2);
+            }
+            nll += 0.5f * acc.L;
+            if (grad) accumulate_contrast(acc, K, p.r2, loading, g, H);
+        }
+        return nll;
+    }
+
+    __device__ __forceinline__ float nll(const Proto &P, Consts, const float y[4]) const
+    {
+        const Params p = decode(y);
+        const float k2 = -p.r2 * 1.4426950f;
+        float v = 0.f;
+        for (int c = 0; c < P.C; c++) {
+            const float s0 = contrast_factors(p, P.tr[c], make_angle(P.flip[c] * b), P.mt[c]).s0;
+            float L = 0.f;
+            for (int i = P.first[c]; i < P.first[c + 1]; i++)
+                L = nll_add(s0 * __builtin_amdgcn_exp2f(k2 * P.te[i]), load_echo(X + (int64_t)i * N + n), P.wgt[i], L);
+            v += 0.5f * L;
+        }
+        return v;
+    }
+};
+
+// Register shape of a protocol: 1 = at most 4 contrasts x 8 echoes, 2 = 4 x 16,
+// 3 = 8 x 8, 0 = any other protocol (echoes read from memory echo by echo).
+inline int echo_shape(const DevProto &P)
+{
+    int emax = 0;
+    for (int c = 0; c < P.C; c++) emax = emax > P.first[c + 1] - P.first[c] ? emax : P.first[c + 1] - P.first[c];
+    if (P.C <= 4 && emax <= 8) return 1;
+    if (P.C <= 4 && emax <= 16) return 2;
+    if (emax <= 8) return 3;
+    return 0;
+}
+
+// Host: the kernel-argument form of the protocol for register shape (CM, EM).
+template <typename T, int CM, int EM>
+struct ProtoArg {
+    static ShapedProto<T, CM, EM> make(const DevProto &P, const T *X, int64_t N)
+    {
+        return make_shaped<T, CM, EM>(P, X, N);
+    }
+};
+template <typename T>
+struct ProtoArg<T, 0, 0> {
+    static DevProto make(const DevProto &P, const T *, int64_t) { return P; }
+};
 
 // ---------------------------------------------------------------------------
 // packed symmetric 4x4: 0:00 1:01 2:02 3:03 4:11 5:12 6:13 7:22 8:23 9:33

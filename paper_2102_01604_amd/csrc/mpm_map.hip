@@ -156,7 +156,7 @@ struct MapJob : FitJob {
                 RUN("fin", 0.0, fin(FIN_B, i, nb_cg));
             }
             RUN("map_accept", N * (xb + bb + 16 + 16 + 16 + 4), launch_accept(s, m));
-            RUN("fin", 0.0, fin(FIN_ACCEPT, t * S + j + 1, nb_col));
+            RUN("fin", 0.0, fin(FIN_ACCEPT, t * S + j + 1, nb_pl));
             if (ntrial > 1) {
                 // runs only when the full step was rejected (device flag)
                 RUN("map_accept2", 0.0, launch_accept2(s, m, ntrial));

@@ -60,8 +60,31 @@ def test_missing_echoes(torch_cuda, orc, mode):
         assert np.allclose(y_gpu[:, 77], y0)
 
 
-@pytest.mark.parametrize("echoes", [(2, 2, 2, 2, 2), (12, 12, 10), (1, 1, 1), (8, 8, 6, 8, 8, 6),
-                                    (16, 16, 17)])
+# Echo counts per contrast covering every register shape of the kernels
+# (4 x 8, 4 x 16, 8 x 8) and protocols beyond them, whose echoes are read from
+# memory at every use.
+SHAPES = [(2, 2, 2, 2, 2), (12, 12, 10), (1, 1, 1), (8, 8, 6, 8, 8, 6), (16, 16, 17), (9, 9, 9, 9, 9)]
+
+
+def _shape_case(orc, echoes, dims):
+    n = len(echoes)
+    flips = [6.0, 21.0, 6.0, 10.0, 15.0, 8.0][:n]
+    mt = [0, 0, 1, 0, 0, 1][:n]
+    c = synth.make_case("map_brain", dims=dims, seed=43, echoes=echoes)
+    c["proto"] = synth.protocol(echoes=echoes, flips_deg=flips, mt=mt, sigma=c["sigma"])
+    c["b1"] = f32(c["b1"])
+    return c, observations(orc, c)
+
+
+@pytest.mark.parametrize("echoes", SHAPES[1:2] + SHAPES[3:])
+def test_map_protocol_shapes(torch_cuda, orc, echoes):
+    c, x = _shape_case(orc, echoes, (26, 20, 9))
+    y0 = f32(orc.default_init(c["proto"], x.astype(np.float64), c["b1"]))
+    opts = dict(c["opts"], n_outer=2, n_gn=3, n_cg=10, init="const", init_const=[float(v) for v in y0])
+    _compare(orc, torch_cuda, c, x, opts)
+
+
+@pytest.mark.parametrize("echoes", SHAPES)
 def test_ml_protocol_shapes(torch_cuda, orc, echoes):
     n = len(echoes)
     flips = [6.0, 21.0, 6.0, 10.0, 15.0, 8.0][:n]
@@ -71,11 +94,6 @@ def test_ml_protocol_shapes(torch_cuda, orc, echoes):
     x = observations(orc, c)
     y0 = f32(orc.default_init(c["proto"], x.astype(np.float64)))
     opts = {"mode": "ml", "n_gn": 15, "init": "const", "init_const": y0}
-    supported = (n <= 4 and max(echoes) <= 16) or max(echoes) <= 8
-    if not supported:
-        with pytest.raises(_lib.MpmError):
-            _gpu(torch_cuda, c, x, opts)
-        return
     y_orc = orc.fit(c["proto"], c["dims"], x.astype(np.float64), None, opts)[0]
     good = well_posed(y_orc, c["truth"])
     if not good.any():  # under-determined protocol (3 observations, 4 unknowns): every voxel degenerate
