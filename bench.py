@@ -79,6 +79,9 @@ def main():
                          "[0.7, 1.3], sigma 2%% of mean PD, JTV-MAP 10 x 8 x 32 then the Laplace variance")
     ap.add_argument("--requests", type=int, default=64)
     ap.add_argument("--rate", type=float, default=2.0, help="serving: arrivals per second")
+    ap.add_argument("--schedule-seeds", default="4000",
+                    help="serving: comma-separated seeds of the arrival schedules (request mix and gaps)")
+    ap.add_argument("--budget-gib", type=float, default=16.0, help="serving: HBM budget of the server (GiB)")
     ap.add_argument("--counters", action="store_true",
                     help="for hardware-counter runs: two outer loops of one Newton step each of the MAP fit "
                          "(2 x 1 x 32; the second loop has JTV weights, so its 32 CG iterations all run, as in "
@@ -310,49 +313,44 @@ SERVE_SIZES = [(64, 64, 64), (96, 128, 128), (128, 160, 160), (192, 240, 256)]
 
 def serving(args, torch, _lib, synth, dev):
     """Continuous batching against serial plain fits on the same arrival
-    schedule.  Each size class has one seeded tissue volume; each request
-    draws its own noise (seeded) on the GPU; all inputs are resident in HBM
-    before the clock starts."""
-    rng = np.random.default_rng(4000)
+    schedule, for each schedule seed.  Each size class has one seeded tissue
+    volume; each request draws its own noise (seeded) on the GPU; all inputs
+    are resident in HBM before the clock starts."""
+    seeds = [int(v) for v in args.schedule_seeds.split(",")]
     n = args.requests
-    cls = rng.integers(0, len(SERVE_SIZES), n)
-    is_map = rng.random(n) < 0.5
-    gaps = rng.exponential(1.0 / args.rate, n)
-    arrive = np.cumsum(gaps) - gaps[0]
     vols = {}
     for k, dims in enumerate(SERVE_SIZES):
-        if k in set(cls.tolist()):
-            c = synth.make_case("map_brain", dims=dims, seed=4100 + k)
-            vols[k] = {"case": c, "truth": torch.from_numpy(c["truth"].astype(np.float32)).to(dev),
-                       "b1": torch.from_numpy(c["b1"].astype(np.float32)).to(dev)}
+        c = synth.make_case("map_brain", dims=dims, seed=4100 + k)
+        vols[k] = {"case": c, "truth": torch.from_numpy(c["truth"].astype(np.float32)).to(dev),
+                   "b1": torch.from_numpy(c["b1"].astype(np.float32)).to(dev)}
     log(f"serving: generated {len(vols)} volume classes")
-    reqs = []
-    for r in range(n):
-        v = vols[int(cls[r])]
-        c = v["case"]
-        dims = c["dims"]
-        N = int(np.prod(dims))
-        g = torch.Generator(device=dev).manual_seed(4100 + r)
-        eps = torch.randn((22, N), generator=g, device=dev)
-        X = torch.empty((22, N), dtype=torch.float32, device=dev)
-        _lib.mpm_simulate(c["proto"], dims, v["truth"], v["b1"], eps, X)
-        del eps
-        opts = ({"mode": "map", "n_outer": 10, "n_gn": 8, "n_cg": 32, "max_halvings": 4, "lam": c["lam"]}
-                if is_map[r] else {"mode": "ml", "n_gn": 20})
-        reqs.append({"proto": c["proto"], "dims": dims, "X": X, "b1": v["b1"], "opts": opts, "N": N,
-                     "iters": N * (80 if is_map[r] else 20)})
-    torch.cuda.synchronize()
-    log(f"serving: {n} requests resident ({sum(r['N'] for r in reqs) / 1e6:.1f} M voxels)")
-    # warm-up: one small fit of each mode
-    small = min(range(n), key=lambda i: reqs[i]["N"])
-    for mode in ("ml", "map"):
-        r = reqs[small]
-        o = torch.empty((4, r["N"]), device=dev)
-        _lib.mpm_fit(r["proto"], r["dims"], r["X"], r["b1"], dict(r["opts"], mode=mode, lam=r["opts"].get("lam", [1e-3] * 4),
-                                                                  n_outer=1, n_gn=1, n_cg=2), o)
-    torch.cuda.synchronize()
+    budget = int(args.budget_gib * (1 << 30))
 
-    def run_serial(times):
+    def make_requests(seed):
+        rng = np.random.default_rng(seed)
+        cls = rng.integers(0, len(SERVE_SIZES), n)
+        is_map = rng.random(n) < 0.5
+        gaps = rng.exponential(1.0 / args.rate, n)
+        arrive = np.cumsum(gaps) - gaps[0]
+        reqs = []
+        for r in range(n):
+            v = vols[int(cls[r])]
+            c = v["case"]
+            dims = c["dims"]
+            N = int(np.prod(dims))
+            g = torch.Generator(device=dev).manual_seed(seed * 1000 + r)
+            eps = torch.randn((22, N), generator=g, device=dev)
+            X = torch.empty((22, N), dtype=torch.float32, device=dev)
+            _lib.mpm_simulate(c["proto"], dims, v["truth"], v["b1"], eps, X)
+            del eps
+            opts = ({"mode": "map", "n_outer": 10, "n_gn": 8, "n_cg": 32, "max_halvings": 4, "lam": c["lam"]}
+                    if is_map[r] else {"mode": "ml", "n_gn": 20})
+            reqs.append({"proto": c["proto"], "dims": dims, "X": X, "b1": v["b1"], "opts": opts, "N": N,
+                         "iters": N * (80 if is_map[r] else 20)})
+        torch.cuda.synchronize()
+        return reqs, arrive, int(is_map.sum())
+
+    def run_serial(reqs, times):
         outs, done = [], np.zeros(n)
         t0 = time.perf_counter()
         for i, r in enumerate(reqs):
@@ -365,11 +363,11 @@ def serving(args, torch, _lib, synth, dev):
             outs.append(o)
         return outs, done
 
-    def run_batched(times):
+    def run_batched(reqs, times):
         outs = [torch.empty((4, r["N"]), device=dev) for r in reqs]
         done = np.full(n, np.nan)
         tickets = [None] * n
-        srv = _lib.MpmServer(hbm_budget=int(args_budget), max_active=4)
+        srv = _lib.MpmServer(hbm_budget=budget, max_active=4)
         t0 = time.perf_counter()
         nxt = 0
         while np.isnan(done).any():
@@ -387,34 +385,57 @@ def serving(args, torch, _lib, synth, dev):
         srv.close()
         return outs, done
 
-    args_budget = 64 << 30
-    res = {}
-    for label, times in (("poisson", arrive), ("burst", np.zeros(n))):
-        so, sd = run_serial(times)
-        torch.cuda.synchronize()
-        bo, bd = run_batched(times)
-        torch.cuda.synchronize()
-        lat_s, lat_b = sd - times, bd - times
-        diff = max(float((a - b).abs().max()) for a, b in zip(so, bo))
-        nr = lambda v, q: float(np.sort(v)[max(0, int(np.ceil(q * len(v))) - 1)])
-        iters = sum(r["iters"] for r in reqs)
-        res[label] = {
-            "serial": {"p50_s": round(nr(lat_s, 0.5), 3), "p99_s": round(nr(lat_s, 0.99), 3),
-                       "makespan_s": round(float(sd.max()), 3),
-                       "voxel_iters_per_s": round(iters / float(sd.max()), 1)},
-            "batched": {"p50_s": round(nr(lat_b, 0.5), 3), "p99_s": round(nr(lat_b, 0.99), 3),
-                        "makespan_s": round(float(bd.max()), 3),
-                        "voxel_iters_per_s": round(iters / float(bd.max()), 1)},
-            "max_abs_map_diff_batched_vs_serial": diff,
-        }
-        log(f"serving {label}: {res[label]}")
-    out = {"metric": "p50/p99 fit latency, batched vs plain (serving)", "value": res["poisson"]["batched"]["p99_s"],
-           "unit": "s (p99 latency, batched)", "n_gpus": 1, "higher_is_better": False, "data": "synthetic",
+    nr = lambda v, q: float(np.sort(v)[max(0, int(np.ceil(q * len(v))) - 1)])  # nearest rank
+    per_seed, n_map = {}, {}
+    for seed in seeds:
+        reqs, arrive, n_map[seed] = make_requests(seed)
+        if seed == seeds[0]:  # warm-up: one small fit of each mode
+            small = min(range(n), key=lambda i: reqs[i]["N"])
+            for mode in ("ml", "map"):
+                r = reqs[small]
+                o = torch.empty((4, r["N"]), device=dev)
+                _lib.mpm_fit(r["proto"], r["dims"], r["X"], r["b1"],
+                             dict(r["opts"], mode=mode, lam=r["opts"].get("lam", [1e-3] * 4), n_outer=1, n_gn=1,
+                                  n_cg=2), o)
+            torch.cuda.synchronize()
+        log(f"serving seed {seed}: {n} requests resident ({sum(r['N'] for r in reqs) / 1e6:.1f} M voxels)")
+        res = {}
+        for label, times in (("poisson", arrive), ("burst", np.zeros(n))):
+            so, sd = run_serial(reqs, times)
+            torch.cuda.synchronize()
+            bo, bd = run_batched(reqs, times)
+            torch.cuda.synchronize()
+            lat_s, lat_b = sd - times, bd - times
+            diff = max(float((a - b).abs().max()) for a, b in zip(so, bo))
+            iters = sum(r["iters"] for r in reqs)
+            res[label] = {
+                "serial": {"p50_s": round(nr(lat_s, 0.5), 3), "p99_s": round(nr(lat_s, 0.99), 3),
+                           "makespan_s": round(float(sd.max()), 3),
+                           "voxel_iters_per_s": round(iters / float(sd.max()), 1)},
+                "batched": {"p50_s": round(nr(lat_b, 0.5), 3), "p99_s": round(nr(lat_b, 0.99), 3),
+                            "makespan_s": round(float(bd.max()), 3),
+                            "voxel_iters_per_s": round(iters / float(bd.max()), 1)},
+                "max_abs_map_diff_batched_vs_serial": diff,
+            }
+            log(f"serving seed {seed} {label}: {res[label]}")
+            del so, bo
+        per_seed[seed] = res
+        del reqs
+        torch.cuda.empty_cache()
+    med = lambda f: round(float(np.median([f(per_seed[s_]) for s_ in seeds])), 3)
+    summary = {lab: {kind: {q: med(lambda r, lab=lab, kind=kind, q=q: r[lab][kind][q])
+                            for q in ("p50_s", "p99_s", "makespan_s")} for kind in ("serial", "batched")}
+               for lab in ("poisson", "burst")}
+    out = {"metric": "p50/p99 fit latency, batched vs plain (serving)",
+           "value": summary["poisson"]["batched"]["p99_s"],
+           "unit": "s (p99 latency, batched; median over schedules)", "n_gpus": 1, "higher_is_better": False,
+           "data": "synthetic",
            "config": {"workload": f"{n} fit requests, sizes uniform over {SERVE_SIZES}, 22 echoes, ML (20 GN) or "
                                   f"JTV-MAP (10x8x32) with p=0.5, Poisson arrivals {args.rate}/s; burst = all at t=0",
-                      "max_active": 4, "hbm_budget_bytes": args_budget,
-                      "n_map": int(is_map.sum()), "n_ml": int((~is_map).sum())},
-           "serving": res}
+                      "max_active": 4, "hbm_budget_bytes": budget, "schedule_seeds": seeds,
+                      "n_map": n_map},
+           "serving_median_over_schedules": summary,
+           "serving": {str(k): v for k, v in per_seed.items()}}
     print(json.dumps(out), flush=True)
 
 

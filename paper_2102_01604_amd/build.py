@@ -1,4 +1,5 @@
-"""Build libmpm.so (gfx950) in-tree with hipcc."""
+"""Build libmpm.so (gfx950) in-tree with hipcc, and the hbm_probe program
+(plain streaming kernels that measure the GPU's achievable HBM bandwidth)."""
 from __future__ import annotations
 
 import os
@@ -8,6 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmpm.so")
+PROBE = os.path.join(HERE, "hbm_probe")
 SOURCES = ["mpm_api.hip", "mpm_fit.hip", "mpm_map.hip", "mpm_serve.hip", "k_voxel.hip", "k_map.hip"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
@@ -25,6 +27,12 @@ def build(verbose: bool = False) -> str:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd, cwd=CSRC)
     os.replace(LIB + ".tmp", LIB)
+    pflags = [f for f in FLAGS if f not in ("-fPIC", "-shared")]
+    cmd = [hipcc] + pflags + ["-o", PROBE + ".tmp", os.path.join(CSRC, "hbm_probe.hip")]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd, cwd=CSRC)
+    os.replace(PROBE + ".tmp", PROBE)
     return LIB
 
 

@@ -99,6 +99,7 @@ struct MapArgs {
     float *w;      // JTV weights [N]
     Grid3 gp;      // one plane per workgroup
     Grid3 gt;      // tall tiles (TILE_X x TALL_Y) for the CG sweeps
+    Grid3 gv;      // CG sweep B: one voxel per thread, tiles of TILE_X x cg_b_rows() (plane grid)
     HessArrays H;  // loaded Hessian per voxel
     float4 *R, *Z, *P0, *P1, *D;  // CG vectors, one float4 per voxel
     float lam[4];
@@ -118,7 +119,9 @@ hipError_t launch_accept2(hipStream_t s, const MapArgs &a, int ntrial);
 hipError_t launch_update(hipStream_t s, const MapArgs &a);
 hipError_t launch_weights(hipStream_t s, const MapArgs &a, int prior_on);
 hipError_t launch_final(hipStream_t s, const MapArgs &a, float *var, float *mom);
-int cg_blocks(const MapArgs &a);  // workgroups (partials) of the CG sweeps
+int cg_a_blocks(const MapArgs &a);  // workgroups (partials) of CG sweep A
+int cg_b_blocks(const MapArgs &a);  // ... and of sweep B
+int cg_b_rows();                    // tile rows of sweep B
 int tall_workgroups();
 hipError_t launch_fin(hipStream_t s, const MapArgs &a, int stage, int arg, int nblk, double cg_stop_rel,
                       int ntrial, int accept_off);

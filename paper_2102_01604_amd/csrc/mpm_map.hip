@@ -44,7 +44,8 @@ static mpm_status alloc_map(const FitArgs &a, Workspace &ws, MapArgs &m, int tra
     m.Y = a.maps;
     m.gp = plane_grid(m.g);
     m.gt = make_grid3(a.nx, a.ny, a.nz, TALL_Y, tall_workgroups());
-    const int nblk = std::max(std::max(grid_blocks(m.g), grid_blocks(m.gp)), grid_blocks(m.gt));
+    m.gv = plane_grid(make_grid3(a.nx, a.ny, a.nz, cg_b_rows()));
+    const int nblk = std::max(std::max(grid_blocks(m.g), grid_blocks(m.gp)), std::max(grid_blocks(m.gt), grid_blocks(m.gv)));
     float *big = nullptr;
     const size_t nf = map_workspace_floats_per_voxel() * (size_t)N;
     if (ws.alloc((void **)&big, nf * sizeof(float)) != hipSuccess ||
@@ -91,7 +92,7 @@ struct MapJob : FitJob {
     MapArgs m;
     int prior_on = 0, ntrial = 1, accept_off = 0;
     int T = 0, J = 0, K = 0, S = 0, tl = 0;
-    int nb_col = 0, nb_pl = 0, nb_cg = 0;
+    int nb_col = 0, nb_pl = 0, nb_cga = 0, nb_cgb = 0;
     int t = 0, j = 0;  // next Newton-like step
     bool started = false, finished = false;
     PinnedBuf host;    // MapCtl followed by the trace
@@ -115,7 +116,8 @@ struct MapJob : FitJob {
         accept_off = o->max_halvings < 0;
         nb_col = grid_blocks(m.g);
         nb_pl = grid_blocks(m.gp);
-        nb_cg = cg_blocks(m);
+        nb_cga = cg_a_blocks(m);
+        nb_cgb = cg_b_blocks(m);
         return MPM_OK;
     }
 
@@ -151,16 +153,16 @@ struct MapJob : FitJob {
             for (int i = 0; i < K && e == hipSuccess; i++) {
                 double ab = 16 + (i > 0 ? 16 : 0) + 40 + 4 + 16 + (i == 1 ? 16 : i >= 2 ? 32 : 0);
                 RUN("cg_a", N * ab, launch_cg_a(s, m, i));
-                RUN("fin", 0.0, fin(FIN_A, i, nb_cg));
+                RUN("fin", 0.0, fin(FIN_A, i, nb_cga));
                 RUN("cg_b", N * (16 + 4 + 40 + 32 + 16), launch_cg_b(s, m, i));
-                RUN("fin", 0.0, fin(FIN_B, i, nb_cg));
+                RUN("fin", 0.0, fin(FIN_B, i, nb_cgb));
             }
             RUN("map_accept", N * (xb + bb + 16 + 16 + 16 + 4), launch_accept(s, m));
             RUN("fin", 0.0, fin(FIN_ACCEPT, t * S + j + 1, nb_pl));
             if (ntrial > 1) {
                 // runs only when the full step was rejected (device flag)
                 RUN("map_accept2", 0.0, launch_accept2(s, m, ntrial));
-                RUN("fin", 0.0, fin(FIN_ACCEPT2, t * S + j + 1, nb_pl));
+                RUN("fin", 0.0, fin(FIN_ACCEPT2, t * S + j + 1, nb_col));
             }
             RUN("map_update", N * 64.0, launch_update(s, m));
             if (++j == J) {

@@ -27,6 +27,13 @@ namespace {
 
 constexpr int DEPTH = 2;  // pieces of one fit in flight at a time
 
+// A MAP fit of at least this many voxels fills the device by itself for a long
+// time (each of its ~13,000 kernels runs several rounds of workgroups on every
+// CU): two such fits side by side only share the bandwidth and both finish
+// later.  At most one of them runs at a time (FIFO among them); ML fits (one
+// short launch) and smaller MAP fits fill the gaps around it.
+constexpr int64_t LARGE_FIT_VOXELS = (int64_t)1 << 21;
+
 enum State { QUEUED = 0, RUNNING = 1, DONE = 2 };
 
 struct Entry {
@@ -46,6 +53,8 @@ struct Entry {
     std::string error;
     mpm_report report;
 };
+
+bool is_large(const Entry &e) { return e.req.options.mode == MPM_MAP_JTV && e.N >= LARGE_FIT_VOXELS; }
 
 }  // namespace
 
@@ -142,13 +151,23 @@ void step_locked(mpm_server *s)
         Entry &e = *kv.second;
         if (e.state == RUNNING) advance(s, e);
     }
-    // admit from the head of the queue (FIFO)
-    while (!s->queue.empty()) {
-        Entry &e = *s->entries[s->queue.front()];
+    // admit in submission order; a large fit waits while another large one
+    // runs and smaller ones may pass it, but none passes a fit that waits for
+    // memory (so a large request cannot starve)
+    int large_running = 0;
+    for (auto &kv : s->entries)
+        if (kv.second->state == RUNNING && is_large(*kv.second)) large_running++;
+    for (auto it = s->queue.begin(); it != s->queue.end();) {
+        Entry &e = *s->entries[*it];
         if (e.footprint > s->budget) {
-            s->queue.pop_front();
+            it = s->queue.erase(it);
             finish_failed(s, e, fail(MPM_ERR_OUT_OF_MEMORY, "request needs %zu bytes, server budget is %zu",
                                      e.footprint, s->budget));
+            continue;
+        }
+        const bool large = is_large(e);
+        if (large && large_running > 0) {
+            ++it;
             continue;
         }
         int free_stream = -1;
@@ -158,12 +177,13 @@ void step_locked(mpm_server *s)
                 break;
             }
         if (free_stream < 0 || s->used + e.footprint > s->budget) break;
-        s->queue.pop_front();
+        it = s->queue.erase(it);
         mpm_status st = admit(s, e, free_stream);
         if (st) {
             finish_failed(s, e, st);
             continue;
         }
+        if (large) large_running++;
         advance(s, e);
     }
 }
