@@ -31,7 +31,8 @@ MAX_CONTRASTS = 8
 MAX_IMAGES = 64
 ML, MAP = 0, 1
 INIT_DEFAULT, INIT_CONST, INIT_FROM_MAPS = 0, 1, 2
-LOAD_PROPOSED, LOAD_GN = 0, 1
+LOAD_PROPOSED, LOAD_GN, LOAD_PLUS = 0, 1, 2
+LOADINGS = {"proposed": LOAD_PROPOSED, "gn": LOAD_GN, "plus": LOAD_PLUS}
 
 
 def build(force: bool = True) -> str:
@@ -78,6 +79,7 @@ def _load():
         lib = C.CDLL(_LIB_PATH)
         lib.orc_spgr_derivs.argtypes = [_dp, C.c_double, C.c_double, C.c_double, C.c_int,
                                         _dp, _dp, _dp]
+        lib.orc_spgr_hess.argtypes = [_dp, C.c_double, C.c_double, C.c_double, C.c_int, _dp]
         lib.orc_simulate.argtypes = [C.POINTER(Protocol), C.c_int64, _dp, _dp, _dp]
         lib.orc_lik_voxel.argtypes = [C.POINTER(Protocol), _dp, C.c_int64, _dp, C.c_double,
                                       C.c_int, _dp, _dp, _dp]
@@ -136,7 +138,7 @@ def make_options(opts: dict) -> Options:
     o.n_gn = int(opts.get("n_gn", 20))
     o.n_cg = int(opts.get("n_cg", 32))
     o.max_halvings = int(opts.get("max_halvings", 4))
-    o.loading = {"proposed": LOAD_PROPOSED, "gn": LOAD_GN}[opts.get("loading", "proposed")]
+    o.loading = LOADINGS[opts.get("loading", "proposed")]
     kind = opts.get("init", "default")
     o.init_kind = {"default": INIT_DEFAULT, "const": INIT_CONST, "maps": INIT_FROM_MAPS}[kind]
     lam = opts.get("lam", (0.0, 0.0, 0.0, 0.0))
@@ -170,6 +172,15 @@ def spgr_derivs(y, alpha, tr, te, mt):
     return float(s[0]), ds, d2s
 
 
+def spgr_hess(y, alpha, tr, te, mt):
+    """Full 4x4 matrix of second derivatives of the signal of one image."""
+    lib = _load()
+    yv = _f64(np.asarray(y))
+    H = np.zeros(16)
+    lib.orc_spgr_hess(_ptr(yv), alpha, tr, te, int(mt), _ptr(H))
+    return H.reshape(4, 4)
+
+
 def simulate(proto, maps, b1=None):
     """Noise-free echoes [I][N] from maps [4][N]."""
     lib = _load()
@@ -192,7 +203,7 @@ def lik_voxel(proto, x, y, b1=1.0, loading="proposed"):
     P = np.zeros(16)
     p = make_protocol(proto)
     lib.orc_lik_voxel(C.byref(p), _ptr(xv), 1, _ptr(yv), float(b1),
-                      {"proposed": LOAD_PROPOSED, "gn": LOAD_GN}[loading],
+                      LOADINGS[loading],
                       _ptr(nll), _ptr(g), _ptr(P))
     return float(nll[0]), g, P.reshape(4, 4)
 

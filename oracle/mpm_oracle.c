@@ -117,6 +117,40 @@ void orc_spgr_derivs(const double y[4], double alpha, double tr, double te, int 
     d2s[3] = mt ? (2.0 * (1.0 - delta) * (1.0 - ca * e1) / den - 1.0) * ds[3] : 0.0;
 }
 
+/* The full 4x4 matrix of second derivatives of s with respect to (y0..y3),
+ * row-major.  The paper prints only the diagonal (Sec. 2.4); the rest follows
+ * from the same factorisation s = a * f(r1, delta) * exp(-r2 te):
+ *   d2s/dy0 dyk = ds/dyk                 (s is proportional to a)
+ *   d2s/dy1 dy2 = -te r2 ds/dy1          (ds/dy1 / s does not depend on r2)
+ *   d2s/dy2 dy3 = -te r2 ds/dy3
+ *   d2s/dy1 dy3 = s * (d phi/dy3 + phi psi), with phi = (ds/dy1)/s and
+ *                 psi = (ds/dy3)/s; writing w = (1 - delta) cos(alpha),
+ *                 E = exp(-r1 tr), x = r1 tr this is
+ *                 -x E delta ((1 - w) - w (1 - E)) / ((1 - E)(1 - w E)^2) * s
+ * (zero without an MT pulse).  The "Proposed+" loading of Sec. 2.3 needs the
+ * absolute row sums of this matrix. */
+void orc_spgr_hess(const double y[4], double alpha, double tr, double te, int mt, double H[16])
+{
+    double s, ds[4], d2s[4];
+    orc_spgr_derivs(y, alpha, tr, te, mt, &s, ds, d2s);
+    double r1 = exp(y[1]), r2 = exp(y[2]);
+    double delta = mt ? 1.0 / (1.0 + exp(-y[3])) : 0.0;
+    double e1 = exp(-r1 * tr);
+    double w = (1.0 - delta) * cos(alpha);
+    double x = r1 * tr;
+    double chi = mt ? -x * e1 * delta * ((1.0 - w) - w * (1.0 - e1)) / ((1.0 - e1) * (1.0 - w * e1) * (1.0 - w * e1))
+                    : 0.0;
+    for (int k = 0; k < 16; k++) H[k] = 0.0;
+    for (int k = 0; k < 4; k++) {
+        H[4 * k + k] = d2s[k];
+        H[k] = H[4 * k] = ds[k];
+    }
+    H[0] = d2s[0];
+    H[4 * 1 + 2] = H[4 * 2 + 1] = -te * r2 * ds[1];
+    H[4 * 2 + 3] = H[4 * 3 + 2] = -te * r2 * ds[3];
+    H[4 * 1 + 3] = H[4 * 3 + 1] = chi * s;
+}
+
 /* Noise-free echoes of every image at every voxel.  The flip angle of a voxel
  * is the nominal one times the transmit-field efficiency b1 (Sec. 2.4,
  * footnote on B1).  maps: [4][n]; b1: [n] or NULL (= 1); out: [I][n]. */
@@ -146,7 +180,10 @@ void orc_simulate(const orc_protocol *p, int64_t n, const double *maps,
  *   P   = sum_i [ grad s_i grad s_i^T + |s_i - x_i| diag|d2 s_i| ] / sigma_i^2
  *
  * (R-sigma.)  With loading == ORC_LOAD_GN the |.| term is dropped, giving
- * the Gauss-Newton / Fisher-scoring matrix of Sec. 2.3.
+ * the Gauss-Newton / Fisher-scoring matrix of Sec. 2.3; with
+ * ORC_LOAD_PROPOSED_PLUS diag|d2 s_i| is replaced by the absolute row sums of
+ * the full second-derivative matrix, diag(|H_s_i| 1) (the "Proposed+" choice
+ * of Sec. 2.3, which majorises the Hessian of the NLL).
  * x points at image 0 of this voxel; image i is at x[i*stride].
  * P is the full 4x4 matrix, row-major.
  * ------------------------------------------------------------------------ */
@@ -166,11 +203,18 @@ void orc_lik_voxel(const orc_protocol *p, const double *x, int64_t stride,
         orc_spgr_derivs(y, p->flip[c] * b1, p->tr[c], p->te[i], p->mt[c], &s, ds, d2s);
         double res = s - xi;
         double wgt = 1.0 / (p->sigma[i] * p->sigma[i]);
+        double Hs[16];
+        if (loading == ORC_LOAD_PROPOSED_PLUS) orc_spgr_hess(y, p->flip[c] * b1, p->tr[c], p->te[i], p->mt[c], Hs);
         l += 0.5 * wgt * res * res;
         for (int k = 0; k < 4; k++) {
             g[k] += wgt * res * ds[k];
             for (int j = 0; j < 4; j++) P[4 * k + j] += wgt * ds[k] * ds[j];
             if (loading == ORC_LOAD_PROPOSED) P[4 * k + k] += wgt * fabs(res) * fabs(d2s[k]);
+            if (loading == ORC_LOAD_PROPOSED_PLUS) {
+                double rowsum = 0.0;
+                for (int j = 0; j < 4; j++) rowsum += fabs(Hs[4 * k + j]);
+                P[4 * k + k] += wgt * fabs(res) * rowsum;
+            }
         }
     }
     *nll = l;

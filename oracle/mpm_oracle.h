@@ -39,7 +39,7 @@ typedef struct {
 
 enum { ORC_ML = 0, ORC_MAP = 1 };
 enum { ORC_INIT_DEFAULT = 0, ORC_INIT_CONST = 1, ORC_INIT_FROM_MAPS = 2 };
-enum { ORC_LOAD_PROPOSED = 0, ORC_LOAD_GN = 1 };
+enum { ORC_LOAD_PROPOSED = 0, ORC_LOAD_GN = 1, ORC_LOAD_PROPOSED_PLUS = 2 };
 
 typedef struct {
     int32_t mode;           /* ORC_ML or ORC_MAP                                  */
@@ -47,7 +47,7 @@ typedef struct {
     int32_t n_gn;           /* Newton-like steps (per outer loop for MAP)         */
     int32_t n_cg;           /* conjugate-gradient iterations per Newton step      */
     int32_t max_halvings;   /* MAP step acceptance: halvings tried; <0 = no test  */
-    int32_t loading;        /* ORC_LOAD_PROPOSED (paper) or ORC_LOAD_GN           */
+    int32_t loading;        /* ORC_LOAD_PROPOSED (paper), ORC_LOAD_GN or _PLUS    */
     int32_t init_kind;      /* ORC_INIT_*                                         */
     int32_t pad_;
     double  lambda[4];      /* JTV regularisation per map                         */
@@ -72,6 +72,7 @@ typedef struct {
 /* ---- forward model ---- */
 void orc_spgr_derivs(const double y[4], double alpha, double tr, double te, int mt,
                      double *s, double ds[4], double d2s[4]);
+void orc_spgr_hess(const double y[4], double alpha, double tr, double te, int mt, double H[16]);
 void orc_simulate(const orc_protocol *p, int64_t n, const double *maps,
                   const double *b1, double *out);
 
