@@ -52,7 +52,12 @@ typedef enum {
 typedef enum { MPM_F32 = 0, MPM_F16 = 1, MPM_BF16 = 2 } mpm_dtype; /* echo storage only */
 typedef enum { MPM_ML = 0, MPM_MAP_JTV = 1 } mpm_mode;
 typedef enum { MPM_INIT_DEFAULT = 0, MPM_INIT_CONST = 1, MPM_INIT_FROM_MAPS = 2 } mpm_init_kind;
-typedef enum { MPM_LOAD_PROPOSED = 0, MPM_LOAD_GN = 1 } mpm_loading;
+/* Loading of the approximate Hessian (paper Sec. 2.3): PROPOSED adds
+ * |res| |diag of the signal's second derivatives| per echo (the paper's
+ * choice), PROPOSED_PLUS adds |res| times the absolute row sums of the full
+ * second-derivative matrix ("Proposed+", a majoriser of the NLL Hessian), GN
+ * adds nothing (Gauss-Newton / Fisher scoring). */
+typedef enum { MPM_LOAD_PROPOSED = 0, MPM_LOAD_GN = 1, MPM_LOAD_PROPOSED_PLUS = 2 } mpm_loading;
 
 #define MPM_MAX_CONTRASTS 8
 #define MPM_MAX_IMAGES 64
@@ -80,7 +85,7 @@ typedef struct {
     int32_t n_gn;          /* ML: Newton-like steps; MAP: steps per outer loop       */
     int32_t n_cg;          /* MAP: CG iterations per Newton-like step                */
     int32_t max_halvings;  /* MAP: step halvings tried by the acceptance test (<= 7); <0 off */
-    int32_t loading;       /* mpm_loading: the paper's loaded Hessian or plain GN    */
+    int32_t loading;       /* mpm_loading                                            */
     int32_t init_kind;     /* mpm_init_kind                                          */
     int32_t flags;         /* reserved, must be 0                                    */
     double lambda[4];      /* MAP: JTV weight per map, >= 0 (paper Sec. 2.5)         */

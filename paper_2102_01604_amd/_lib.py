@@ -20,7 +20,7 @@ MPM_MAX_IMAGES = 64
 MPM_F32, MPM_F16, MPM_BF16 = 0, 1, 2
 MPM_ML, MPM_MAP_JTV = 0, 1
 MPM_INIT_DEFAULT, MPM_INIT_CONST, MPM_INIT_FROM_MAPS = 0, 1, 2
-MPM_LOAD_PROPOSED, MPM_LOAD_GN = 0, 1
+MPM_LOAD_PROPOSED, MPM_LOAD_GN, MPM_LOAD_PROPOSED_PLUS = 0, 1, 2
 STATUS = {0: "MPM_OK", 1: "MPM_ERR_INVALID_ARG", 2: "MPM_ERR_UNSUPPORTED", 3: "MPM_ERR_OUT_OF_MEMORY",
           4: "MPM_ERR_DEVICE", 5: "MPM_ERR_BUSY", 6: "MPM_ERR_NOT_FOUND"}
 
@@ -142,7 +142,8 @@ def make_options(opts: dict) -> mpm_options:
     o.n_gn = int(opts.get("n_gn", 20))
     o.n_cg = int(opts.get("n_cg", 32))
     o.max_halvings = int(opts.get("max_halvings", 4))
-    o.loading = {"proposed": MPM_LOAD_PROPOSED, "gn": MPM_LOAD_GN}[opts.get("loading", "proposed")]
+    o.loading = {"proposed": MPM_LOAD_PROPOSED, "gn": MPM_LOAD_GN,
+                 "plus": MPM_LOAD_PROPOSED_PLUS}[opts.get("loading", "proposed")]
     o.init_kind = {"default": MPM_INIT_DEFAULT, "const": MPM_INIT_CONST,
                    "maps": MPM_INIT_FROM_MAPS}[opts.get("init", "default")]
     o.flags = int(opts.get("flags", 0))

@@ -214,13 +214,13 @@ __global__ void k_ctl_init(MapCtl *ctl, double *trace, int trace_len)
 // lik: likelihood block, L y, b = g + L y, and the CG start r = b,
 // z = M^{-1} r.  One voxel per thread.  Partials: NLL, y.Ly, r.z
 // ---------------------------------------------------------------------------
-template <typename T, int CM, int EM>
-__global__ __launch_bounds__(BLOCK) void k_lik(Grid3 g, typename VoxelEchoes<T, CM, EM>::Proto P,
-                                               const T *__restrict__ X, const float *__restrict__ b1,
-                                               const float *__restrict__ Y, const float *__restrict__ w, float l0,
-                                               float l1, float l2, float l3, int loading, HessArrays Hs,
-                                               float4 *__restrict__ R, float4 *__restrict__ Z,
-                                               const MapCtl *__restrict__ ctl, double *__restrict__ partials)
+template <bool PLUS, typename T, int CM, int EM>
+__device__ __forceinline__ void lik_body(const Grid3 &g, const typename VoxelEchoes<T, CM, EM>::Proto &P,
+                                         const T *__restrict__ X, const float *__restrict__ b1,
+                                         const float *__restrict__ Y, const float *__restrict__ w, float l0, float l1,
+                                         float l2, float l3, int loading, const HessArrays &Hs,
+                                         float4 *__restrict__ R, float4 *__restrict__ Z,
+                                         const MapCtl *__restrict__ ctl, double *__restrict__ partials)
 {
     if (ctl->gn_stop) return;
     const int64_t N = g.N;
@@ -245,7 +245,7 @@ __global__ __launch_bounds__(BLOCK) void k_lik(Grid3 g, typename VoxelEchoes<T, 
         if (c.z0 > 0) nb(n - c.sxy);
         if (c.z0 < g.nz - 1) nb(n + c.sxy);
         float gr[4], H[10], r[4], zz[4];
-        const float nll = ve.lik(P, K, y0, loading, true, gr, H);
+        const float nll = ve.template lik<PLUS>(P, K, y0, loading, true, gr, H);
 #pragma unroll
         for (int k = 0; k < 4; k++) {
             acc[k] *= lam[k];  // (L y)_k
@@ -261,6 +261,18 @@ __global__ __launch_bounds__(BLOCK) void k_lik(Grid3 g, typename VoxelEchoes<T, 
     }
     write_partials<3>(part, partials);
 }
+
+#define LIK_PARAMS                                                                                           \
+    Grid3 g, typename VoxelEchoes<T, CM, EM>::Proto P, const T *__restrict__ X, const float *__restrict__ b1, \
+        const float *__restrict__ Y, const float *__restrict__ w, float l0, float l1, float l2, float l3,       \
+        int loading, HessArrays Hs, float4 *__restrict__ R, float4 *__restrict__ Z,                             \
+        const MapCtl *__restrict__ ctl, double *__restrict__ partials
+#define LIK_ARGS g, P, X, b1, Y, w, l0, l1, l2, l3, loading, Hs, R, Z, ctl, partials
+
+template <typename T, int CM, int EM>
+__global__ __launch_bounds__(BLOCK) void k_lik(LIK_PARAMS) { lik_body<false, T, CM, EM>(LIK_ARGS); }
+template <typename T, int CM, int EM>  // Proposed+ loading
+__global__ __launch_bounds__(BLOCK) void k_lik_plus(LIK_PARAMS) { lik_body<true, T, CM, EM>(LIK_ARGS); }
 
 // ---------------------------------------------------------------------------
 // CG sweeps (paper Sec. 2.6, preconditioned CG on (H + L) delta = g + L y).
@@ -671,12 +683,12 @@ __global__ __launch_bounds__(BLOCK) void k_weights(Grid3 g, const float *__restr
 // voxels.  With var != NULL also the Laplace variance of paper Sec. 3.6 (and
 // with mom != NULL the log-normal moments of r1 and t1).
 // ---------------------------------------------------------------------------
-template <typename T, int CM, int EM>
-__global__ __launch_bounds__(BLOCK) void k_final(Grid3 g, typename VoxelEchoes<T, CM, EM>::Proto P,
-                                                 const T *__restrict__ X, const float *__restrict__ b1,
-                                                 const float *__restrict__ Y, const float *__restrict__ w, float l0,
-                                                 float l1, float l2, float l3, int loading, float *__restrict__ var,
-                                                 float *__restrict__ mom, double *__restrict__ partials)
+template <bool PLUS, typename T, int CM, int EM>
+__device__ __forceinline__ void final_body(const Grid3 &g, const typename VoxelEchoes<T, CM, EM>::Proto &P,
+                                           const T *__restrict__ X, const float *__restrict__ b1,
+                                           const float *__restrict__ Y, const float *__restrict__ w, float l0,
+                                           float l1, float l2, float l3, int loading, float *__restrict__ var,
+                                           float *__restrict__ mom, double *__restrict__ partials)
 {
     const int64_t N = g.N;
     const float lam[4] = {l0, l1, l2, l3};
@@ -694,7 +706,7 @@ __global__ __launch_bounds__(BLOCK) void k_final(Grid3 g, typename VoxelEchoes<T
         if (c.z0 < g.nz - 1) d += w0 + w[n + c.sxy];
         float y[4], gr[4], H[10];
         load4(Y, N, n, y);
-        const float nll = ve.lik(P, K, y, loading, true, gr, H);
+        const float nll = ve.template lik<PLUS>(P, K, y, loading, true, gr, H);
         float M[10];
 #pragma unroll
         for (int k = 0; k < 10; k++) M[k] = H[k];
@@ -736,6 +748,17 @@ __global__ __launch_bounds__(BLOCK) void k_final(Grid3 g, typename VoxelEchoes<T
     }
     write_partials<3>(part, partials);
 }
+
+#define FINAL_PARAMS                                                                                         \
+    Grid3 g, typename VoxelEchoes<T, CM, EM>::Proto P, const T *__restrict__ X, const float *__restrict__ b1, \
+        const float *__restrict__ Y, const float *__restrict__ w, float l0, float l1, float l2, float l3,       \
+        int loading, float *__restrict__ var, float *__restrict__ mom, double *__restrict__ partials
+#define FINAL_ARGS g, P, X, b1, Y, w, l0, l1, l2, l3, loading, var, mom, partials
+
+template <typename T, int CM, int EM>
+__global__ __launch_bounds__(BLOCK) void k_final(FINAL_PARAMS) { final_body<false, T, CM, EM>(FINAL_ARGS); }
+template <typename T, int CM, int EM>  // Proposed+ loading
+__global__ __launch_bounds__(BLOCK) void k_final_plus(FINAL_PARAMS) { final_body<true, T, CM, EM>(FINAL_ARGS); }
 
 // ---------------------------------------------------------------------------
 // one-workgroup finalisers: fixed-order reduction of the partials, then the
@@ -921,8 +944,11 @@ hipError_t launch_ctl_init(hipStream_t s, MapCtl *ctl, double *trace, int trace_
 hipError_t launch_lik(hipStream_t s, const MapArgs &a)
 {
     const float *l = a.lam;
-    DISPATCH_T(k_lik, a.gp, a.b1, a.Y, a.w, l[0], l[1], l[2], l[3], a.loading, a.H, a.R, a.Z,
-               a.ctl, a.partials);
+    if (a.loading == 2)
+        DISPATCH_T(k_lik_plus, a.gp, a.b1, a.Y, a.w, l[0], l[1], l[2], l[3], a.loading, a.H, a.R, a.Z, a.ctl,
+                   a.partials);
+    else
+        DISPATCH_T(k_lik, a.gp, a.b1, a.Y, a.w, l[0], l[1], l[2], l[3], a.loading, a.H, a.R, a.Z, a.ctl, a.partials);
     return hipGetLastError();
 }
 
@@ -981,8 +1007,10 @@ hipError_t launch_weights(hipStream_t s, const MapArgs &a, int prior_on)
 hipError_t launch_final(hipStream_t s, const MapArgs &a, float *var, float *mom)
 {
     const float *l = a.lam;
-    DISPATCH_T(k_final, a.gp, a.b1, a.Y, a.w, l[0], l[1], l[2], l[3], a.loading, var, mom,
-               a.partials);
+    if (a.loading == 2)
+        DISPATCH_T(k_final_plus, a.gp, a.b1, a.Y, a.w, l[0], l[1], l[2], l[3], a.loading, var, mom, a.partials);
+    else
+        DISPATCH_T(k_final, a.gp, a.b1, a.Y, a.w, l[0], l[1], l[2], l[3], a.loading, var, mom, a.partials);
     return hipGetLastError();
 }
 

@@ -160,7 +160,7 @@ hipError_t launch_reduce_rows(const LaunchCtx &c, const double *in, int nrows, i
 // ---------------------------------------------------------------------------
 int ml_fit_blocks(int64_t N) { return (int)((N + BLOCK - 1) / BLOCK); }
 
-template <typename T, int CM, int EM>
+template <typename T, int CM, int EM, bool PLUS>
 __global__ __launch_bounds__(BLOCK) void k_ml_fit(typename VoxelEchoes<T, CM, EM>::Proto P, const T *__restrict__ X,
                                                   const float *__restrict__ b1, float *__restrict__ maps,
                                                   int64_t N, int n_gn, int loading,
@@ -182,7 +182,7 @@ __global__ __launch_bounds__(BLOCK) void k_ml_fit(typename VoxelEchoes<T, CM, EM
     for (int it = 0; it <= n_gn; it++) {
         const bool last = (it == n_gn);
         float g[4], H[10];
-        const float nll = ve.lik(P, K, y, loading, !last, g, H);
+        const float nll = ve.template lik<PLUS>(P, K, y, loading, !last, g, H);
         if (it > 0 && nll > prev_nll * (1.0f + 1e-5f)) cnt_inc += 1.0;
         prev_nll = nll;
         double v[1] = {active ? (double)nll : 0.0};
@@ -213,25 +213,33 @@ __global__ __launch_bounds__(BLOCK) void k_ml_fit(typename VoxelEchoes<T, CM, EM
     }
 }
 
-template <typename T>
-static hipError_t ml_dispatch(const LaunchCtx &c, const DevProto &P, const T *X, const float *b1,
+template <typename T, bool PLUS>
+static hipError_t ml_launch(const LaunchCtx &c, const DevProto &P, const T *X, const float *b1,
                               float *maps, int64_t N, int n_gn, int loading, double *partials, int nblk)
 {
     dim3 g(nblk), b(BLOCK);
     const int shape = echo_shape(P);
     if (shape == 1)
-        hipLaunchKernelGGL((k_ml_fit<T, 4, 8>), g, b, 0, c.stream, (ProtoArg<T, 4, 8>::make(P, X, N)), X, b1,
+        hipLaunchKernelGGL((k_ml_fit<T, 4, 8, PLUS>), g, b, 0, c.stream, (ProtoArg<T, 4, 8>::make(P, X, N)), X, b1,
                            maps, N, n_gn, loading, partials);
     else if (shape == 2)
-        hipLaunchKernelGGL((k_ml_fit<T, 4, 16>), g, b, 0, c.stream, (ProtoArg<T, 4, 16>::make(P, X, N)), X, b1,
+        hipLaunchKernelGGL((k_ml_fit<T, 4, 16, PLUS>), g, b, 0, c.stream, (ProtoArg<T, 4, 16>::make(P, X, N)), X, b1,
                            maps, N, n_gn, loading, partials);
     else if (shape == 3)
-        hipLaunchKernelGGL((k_ml_fit<T, 8, 8>), g, b, 0, c.stream, (ProtoArg<T, 8, 8>::make(P, X, N)), X, b1,
+        hipLaunchKernelGGL((k_ml_fit<T, 8, 8, PLUS>), g, b, 0, c.stream, (ProtoArg<T, 8, 8>::make(P, X, N)), X, b1,
                            maps, N, n_gn, loading, partials);
     else
-        hipLaunchKernelGGL((k_ml_fit<T, 0, 0>), g, b, 0, c.stream, (ProtoArg<T, 0, 0>::make(P, X, N)), X, b1,
+        hipLaunchKernelGGL((k_ml_fit<T, 0, 0, PLUS>), g, b, 0, c.stream, (ProtoArg<T, 0, 0>::make(P, X, N)), X, b1,
                            maps, N, n_gn, loading, partials);
     return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t ml_dispatch(const LaunchCtx &c, const DevProto &P, const T *X, const float *b1,
+                              float *maps, int64_t N, int n_gn, int loading, double *partials, int nblk)
+{
+    return loading == 2 ? ml_launch<T, true>(c, P, X, b1, maps, N, n_gn, loading, partials, nblk)
+                        : ml_launch<T, false>(c, P, X, b1, maps, N, n_gn, loading, partials, nblk);
 }
 
 hipError_t launch_ml_fit(const LaunchCtx &c, const DevProto &P, int dtype, const void *X,

@@ -273,7 +273,7 @@ mpm_status check_fit_args(const mpm_protocol *protocol, const mpm_grid *grid, in
         opt->n_cg > 100000)
         return fail(MPM_ERR_INVALID_ARG, "iteration counts must be in [0, 100000]");
     if (opt->max_halvings > 7) return fail(MPM_ERR_INVALID_ARG, "max_halvings must be <= 7");
-    if (opt->loading != MPM_LOAD_PROPOSED && opt->loading != MPM_LOAD_GN)
+    if (opt->loading != MPM_LOAD_PROPOSED && opt->loading != MPM_LOAD_GN && opt->loading != MPM_LOAD_PROPOSED_PLUS)
         return fail(MPM_ERR_INVALID_ARG, "unknown loading %d", opt->loading);
     if (opt->init_kind < MPM_INIT_DEFAULT || opt->init_kind > MPM_INIT_FROM_MAPS)
         return fail(MPM_ERR_INVALID_ARG, "unknown init_kind %d", opt->init_kind);

@@ -96,10 +96,12 @@ __device__ __forceinline__ Params decode(const float y[4])
 //   ds/d log r1  = phi * s,      d2s = kap * phi * s
 //   ds/d log r2  = -TE r2 s,     d2s = (1 - TE r2)(-TE r2) s
 //   ds/d logit d = psi * s,      d2s = mu * psi * s      (MT contrasts)
+//   cross terms:  d2s/d log a d(.) = ds/d(.),  d2s/d log r2 d(.) = -TE r2 ds/d(.),
+//                 d2s/d log r1 d logit d = chi * s
 // 1 - E, 1 - omega, 1 - omega E and 1 - cos(alpha) E are formed without
 // cancellation (expm1 and 2 sin^2(alpha/2)), which FP32 needs at TR = 25 ms.
 struct ContrastK {
-    float s0, phi, psi, kap, mu;
+    float s0, phi, psi, kap, mu, chi;
 };
 
 // Flip-angle terms of one (voxel, contrast), computed once per voxel, all
@@ -160,6 +162,10 @@ __device__ __forceinline__ ContrastK contrast_factors(const Params &p, float tr,
     k.kap = 1.0f - x * (2.0f - den) * inv_den;  // 1 + omega E = 2 - den
     k.psi = -dl * inv_den;
     k.mu = 2.0f * (1.0f - dl) * (ome + e1 * an.omc) * inv_den - 1.0f;
+    // d2s/d log r1 d logit delta = chi s (not printed in the paper; the cross
+    // derivative of the same factorisation): -x E delta ((1 - w) - w (1 - E))
+    // / ((1 - E)(1 - w E)^2) with w = (1 - delta) cos(alpha)
+    k.chi = -x * e1 * dl * (one_m_omega - (1.0f - one_m_omega) * ome) * inv_den * inv_den * __builtin_amdgcn_rcpf(ome);
     return k;
 }
 
@@ -171,10 +177,11 @@ __device__ __forceinline__ ContrastK contrast_factors(const Params &p, float tr,
 //   sum_i w s^2 v v^T              from A0 = sum w s^2, A1 = .. TE, A2 = .. TE^2
 //   sum_i w |res| |d2 s_i| (diag)  = (B0, |kap phi| B0, r2 B2, |mu psi| B0)
 // with B0 = sum w |res s|, B2 = sum w |res s| TE |1 - TE r2|  (paper Sec. 2.3
-// eq. precond applied to the Sec. 2.4 derivatives, weights 1/sigma_i^2).
+// eq. precond applied to the Sec. 2.4 derivatives, weights 1/sigma_i^2).  The
+// Proposed+ loading (absolute row sums of d2s) also needs BT = sum w |res s| TE.
 // ---------------------------------------------------------------------------
 struct EchoAcc {
-    float R0 = 0.f, R1 = 0.f, A0 = 0.f, A1 = 0.f, A2 = 0.f, B0 = 0.f, B2 = 0.f, L = 0.f;
+    float R0 = 0.f, R1 = 0.f, A0 = 0.f, A1 = 0.f, A2 = 0.f, B0 = 0.f, BT = 0.f, B2 = 0.f, L = 0.f;
     // One echo: model value s, observation x at echo time te (te2 = te^2),
     // weight w.  A non-finite x is a missing observation: its weight and value
     // are replaced by 0, so every term it adds is exactly 0.
@@ -193,6 +200,7 @@ struct EchoAcc {
         A1 = fmaf(ws2, te, A1);
         A2 = fmaf(ws2, te2, A2);
         B0 += fabsf(wrs);
+        BT = fmaf(fabsf(wrs), te, BT);
         B2 = fmaf(fabsf(wrs), fabsf(fmaf(-te2, r2, te)), B2);  // te |1 - te r2|, te >= 0
         L = fmaf(wr, res, L);
     }
@@ -207,6 +215,10 @@ __device__ __forceinline__ float nll_add(float s, float x, float w, float L)
     return fmaf((ok ? w : 0.0f) * res, res, L);
 }
 
+// PLUS: the Proposed+ loading (loading is then ignored); otherwise loading 0
+// (|diag|) or 1 (none).  Without PLUS, BT and chi are never read, so the
+// compiler drops their arithmetic.
+template <bool PLUS>
 __device__ __forceinline__ void accumulate_contrast(const EchoAcc &e, const ContrastK &K, float r2,
                                                     int loading, float g[4], float H[10])
 {
@@ -224,7 +236,13 @@ __device__ __forceinline__ void accumulate_contrast(const EchoAcc &e, const Cont
     H[7] += r2 * r2 * e.A2;
     H[8] -= r2 * K.psi * e.A1;
     H[9] += K.psi * K.psi * e.A0;
-    if (loading == 0) {
+    if (PLUS) {  // absolute row sums of d2s (Proposed+)
+        const float ap = fabsf(K.phi), as = fabsf(K.psi), ac = fabsf(K.chi), rt = r2 * e.BT;
+        H[0] += e.B0 * (1.0f + ap + as) + rt;
+        H[4] += e.B0 * (ap + fabsf(K.kap * K.phi) + ac) + rt * ap;
+        H[7] += r2 * (e.BT * (1.0f + ap + as) + e.B2);
+        H[9] += e.B0 * (as + ac + fabsf(K.mu * K.psi)) + rt * as;
+    } else if (loading == 0) {  // |diag of d2s|
         H[0] += e.B0;
         H[4] += fabsf(K.kap * K.phi) * e.B0;
         H[7] += r2 * e.B2;
@@ -244,8 +262,9 @@ __device__ __forceinline__ void accumulate_contrast(const EchoAcc &e, const Cont
 // protocols use DevProto and read each echo inside the per-echo loop.  Both
 // evaluate the same per-echo arithmetic:
 //   K = stage(P): per-workgroup constants (called by every thread first);
-//   lik(P, K, y, loading, grad, g, H): NLL; with grad also g and the loaded
-//       Hessian (paper Sec. 2.3 eq. precond with the Sec. 2.4 derivatives);
+//   lik<PLUS>(P, K, y, loading, grad, g, H): NLL; with grad also g and the
+//       loaded Hessian (paper Sec. 2.3 eq. precond with the Sec. 2.4
+//       derivatives; PLUS selects the Proposed+ loading);
 //   nll(P, K, y): the NLL alone (bitwise equal to lik's).
 // ---------------------------------------------------------------------------
 template <typename T, int CM, int EM>
@@ -332,6 +351,7 @@ struct VoxelEchoes {
             if (c < P.C) an[c] = make_angle(P.flip[c] * b);
     }
 
+    template <bool PLUS>
     __device__ __forceinline__ float lik(const Proto &P, Consts K, const float y[4], int loading, bool grad,
                                          float g[4], float H[10]) const
     {
@@ -353,7 +373,7 @@ struct VoxelEchoes {
                     acc.add(F.s0 * __builtin_amdgcn_exp2f(k2 * k.x), x[c][e], k.x, k.y, k.z, p.r2);
                 }
                 nll += 0.5f * acc.L;
-                if (grad) accumulate_contrast(acc, F, p.r2, loading, g, H);
+                if (grad) accumulate_contrast<PLUS>(acc, F, p.r2, loading, g, H);
             }
         }
         return nll;
@@ -399,6 +419,7 @@ struct VoxelEchoes<T, 0, 0> {
         b = b_;
     }
 
+    template <bool PLUS>
     __device__ __forceinline__ float lik(const Proto &P, Consts, const float y[4], int loading, bool grad,
                                          float g[4], float H[10]) const
     {
@@ -418,7 +439,7 @@ struct VoxelEchoes<T, 0, 0> {
                         P.wgt[i], p.r2);
             }
             nll += 0.5f * acc.L;
-            if (grad) accumulate_contrast(acc, K, p.r2, loading, g, H);
+            if (grad) accumulate_contrast<PLUS>(acc, K, p.r2, loading, g, H);
         }
         return nll;
     }

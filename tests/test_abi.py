@@ -93,6 +93,20 @@ def test_host_validation(lib, mutate, status):
     assert lib.mpm_last_error()
 
 
+def test_unknown_loading_and_oversized_grid_rejected(lib):
+    proto = synth.protocol()
+    proto["sigma"] = [1.0] * 22
+    o = _lib.make_options({"mode": "ml", "n_gn": 5})
+    o.loading = 3
+    rep = _lib.mpm_report()
+    st = lib.mpm_fit(C.byref(_lib.make_protocol(proto)), C.byref(_lib.make_grid([8, 8, 8])), 0, C.c_void_p(16), None,
+                     C.byref(o), C.c_void_p(16), C.byref(rep), None, 0, None)
+    assert st == 1 and "loading" in lib.mpm_last_error().decode()
+    # byte offsets into one image are 32-bit in the kernels: N < 2^30
+    st = _fit_raw(lib, proto, [1024, 1024, 1024], {"mode": "ml", "n_gn": 5})
+    assert st == 1 and "2^30" in lib.mpm_last_error().decode()
+
+
 def test_null_pointers_rejected(lib):
     proto = synth.protocol()
     proto["sigma"] = [1.0] * 22

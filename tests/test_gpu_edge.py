@@ -1,6 +1,7 @@
 """GPU parity on the less common paths: missing (non-finite) echoes, other
-protocol shapes, the Gauss-Newton loading, acceptance off, early CG stop, the
-default initialisation in the MAP fit, reduced-precision uncertainty."""
+protocol shapes, the Proposed+ and Gauss-Newton loadings, acceptance off,
+early CG stop, the default initialisation in the MAP fit, reduced-precision
+uncertainty."""
 import numpy as np
 import pytest
 
@@ -101,6 +102,17 @@ def test_ml_protocol_shapes(torch_cuda, orc, echoes):
     _compare(orc, torch_cuda, c, x, opts, mask=good)
 
 
+def test_ml_proposed_plus_loading(torch_cuda, orc):
+    """The Proposed+ loading (absolute row sums of the signal's second
+    derivatives, Sec. 2.3) through the ML kernel, bench-like protocol and B1."""
+    c = synth.make_case("map_brain", dims=(40, 30, 8), seed=46)
+    c["b1"] = f32(c["b1"])
+    x = observations(orc, c)
+    y0 = f32(orc.default_init(c["proto"], x.astype(np.float64), c["b1"]))
+    _compare(orc, torch_cuda, c, x, {"mode": "ml", "n_gn": 15, "init": "const", "init_const": [float(v) for v in y0],
+                                      "loading": "plus"})
+
+
 def test_ml_gauss_newton_loading(torch_cuda, orc):
     c = synth.make_case("ml32", dims=(30, 20, 4), seed=43)
     x = observations(orc, c)
@@ -115,7 +127,7 @@ def test_ml_gauss_newton_loading(torch_cuda, orc):
     assert (rel <= 1e-3).all()
 
 
-@pytest.mark.parametrize("variant", ["accept_off", "cg_stop", "default_init", "halvings_0"])
+@pytest.mark.parametrize("variant", ["accept_off", "cg_stop", "default_init", "halvings_0", "loading_plus"])
 def test_map_variants(torch_cuda, orc, variant):
     c = synth.make_case("map_brain", dims=(30, 26, 14), seed=44)
     c["b1"] = f32(c["b1"])
@@ -128,6 +140,8 @@ def test_map_variants(torch_cuda, orc, variant):
         opts["cg_stop"] = 1e-6
     elif variant == "default_init":
         opts["init"] = "default"
+    elif variant == "loading_plus":
+        opts["loading"] = "plus"
     else:
         opts["max_halvings"] = 0
     _compare(orc, torch_cuda, c, x, opts)
