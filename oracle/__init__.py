@@ -52,6 +52,10 @@ class Protocol(C.Structure):
                 ("sigma", C.c_double * MAX_IMAGES)]
 
 
+class Space(C.Structure):
+    _fields_ = [("dims", C.c_int64 * 3), ("affine", C.c_double * 12)]
+
+
 class Options(C.Structure):
     _fields_ = [("mode", C.c_int32), ("n_outer", C.c_int32), ("n_gn", C.c_int32),
                 ("n_cg", C.c_int32), ("max_halvings", C.c_int32), ("loading", C.c_int32),
@@ -100,6 +104,20 @@ def _load():
                                         C.POINTER(Options), _dp, _dp, _dp]
         lib.orc_uncertainty.restype = C.c_int
         lib.orc_num_threads.restype = C.c_int
+        sp = C.POINTER(Space)
+        lib.orc_pull.argtypes = [C.POINTER(C.c_int64), sp, _dp, _dp]
+        lib.orc_push.argtypes = [C.POINTER(C.c_int64), sp, _dp, _dp]
+        lib.orc_proj_lik.argtypes = [C.POINTER(Protocol), C.POINTER(C.c_int64), sp, _dp, _dp, C.c_int, _dp,
+                                     _dp, _dp]
+        lib.orc_proj_lik.restype = C.c_double
+        lib.orc_default_init_projected.argtypes = [C.POINTER(Protocol), C.POINTER(C.c_int64), sp, _dp, _dp, _dp]
+        lib.orc_default_init_projected.restype = C.c_int
+        lib.orc_fit_projected.argtypes = [C.POINTER(Protocol), C.POINTER(C.c_int64), sp, _dp, _dp,
+                                          C.POINTER(Options), _dp, C.POINTER(Report), _dp, C.c_int32]
+        lib.orc_fit_projected.restype = C.c_int
+        lib.orc_uncertainty_projected.argtypes = [C.POINTER(Protocol), C.POINTER(C.c_int64), sp, _dp, _dp,
+                                                  C.POINTER(Options), _dp, _dp, _dp]
+        lib.orc_uncertainty_projected.restype = C.c_int
         _lib = lib
     return _lib
 
@@ -318,3 +336,118 @@ def uncertainty(proto, dims, x, b1, opts: dict, maps, moments=False):
 
 def default_eps(lam) -> float:
     return 1e-3 * math.sqrt(float(sum(lam)))
+
+
+# ---------------------------------------------------------------------------
+# spatial projection (Sec. 2.4): each contrast has its own acquisition space,
+# {"dims": (mx, my, mz), "affine": 3x4 map from its voxel indices to
+# reconstruction-grid coordinates}; echoes are one flat array with the images
+# back to back (image i holds the voxels of its contrast's space), or a list
+# of per-contrast arrays [E_c][M_c].
+# ---------------------------------------------------------------------------
+def make_spaces(spaces):
+    arr = (Space * len(spaces))()
+    for c, sp in enumerate(spaces):
+        for d in range(3):
+            arr[c].dims[d] = int(sp["dims"][d])
+        a = np.asarray(sp["affine"], dtype=np.float64).reshape(3, 4)
+        for k in range(12):
+            arr[c].affine[k] = float(a.reshape(-1)[k])
+    return arr
+
+
+def space_voxels(sp) -> int:
+    return int(np.prod(sp["dims"]))
+
+
+def flat_echoes(proto, spaces, x):
+    if isinstance(x, (list, tuple)):
+        x = np.concatenate([np.asarray(v, dtype=np.float64).reshape(-1) for v in x])
+    x = _f64(x).reshape(-1)
+    need = sum(int(proto["n_echoes"][c]) * space_voxels(sp) for c, sp in enumerate(spaces))
+    if x.size != need:
+        raise ValueError(f"projected echoes hold {x.size} values, the spaces need {need}")
+    return x
+
+
+def pull(dims, space, vol):
+    """Psi vol: recon [N] -> acquisition [M] (0 outside the field of view)."""
+    lib = _load()
+    vol = _f64(vol).reshape(-1)
+    out = np.empty(space_voxels(space))
+    lib.orc_pull(_dims(dims), make_spaces([space]), _ptr(vol), _ptr(out))
+    return out
+
+
+def push(dims, space, acq):
+    """Psi^T acq: acquisition [M] -> recon [N]."""
+    lib = _load()
+    acq = _f64(acq).reshape(-1)
+    out = np.empty(int(np.prod(dims)))
+    lib.orc_push(_dims(dims), make_spaces([space]), _ptr(acq), _ptr(out))
+    return out
+
+
+def proj_lik(proto, dims, spaces, x, b1, maps, loading="proposed"):
+    """(total NLL, pushed g [4][N], pushed blocks P [N][4][4]) with projection."""
+    lib = _load()
+    N = int(np.prod(dims))
+    x = flat_echoes(proto, spaces, x)
+    b1 = None if b1 is None else _f64(b1).reshape(N)
+    maps = _f64(maps).reshape(4, N)
+    g = np.empty((4, N))
+    P = np.empty((N, 16))
+    p = make_protocol(proto)
+    nll = lib.orc_proj_lik(C.byref(p), _dims(dims), make_spaces(spaces), _ptr(x), _ptr(b1), LOADINGS[loading],
+                           _ptr(maps), _ptr(g), _ptr(P))
+    return float(nll), g, P.reshape(N, 4, 4)
+
+
+def default_init_projected(proto, dims, spaces, x, b1=None):
+    lib = _load()
+    x = flat_echoes(proto, spaces, x)
+    b1 = None if b1 is None else _f64(b1).reshape(-1)
+    y0 = np.zeros(4)
+    p = make_protocol(proto)
+    if lib.orc_default_init_projected(C.byref(p), _dims(dims), make_spaces(spaces), _ptr(x), _ptr(b1), _ptr(y0)):
+        raise ValueError("protocol has no usable PDw/T1w/MTw contrasts for the default init")
+    return y0
+
+
+def fit_projected(proto, dims, spaces, x, b1, opts: dict, maps0=None):
+    """The fit with spatial projection.  Returns (maps [4][N], report, trace)."""
+    lib = _load()
+    N = int(np.prod(dims))
+    x = flat_echoes(proto, spaces, x)
+    b1 = None if b1 is None else _f64(b1).reshape(N)
+    o = make_options(opts)
+    if maps0 is not None:
+        maps = _f64(maps0).reshape(4, N).copy()
+        o.init_kind = INIT_FROM_MAPS
+    else:
+        maps = np.zeros((4, N))
+        if o.init_kind == INIT_FROM_MAPS:
+            raise ValueError("init='maps' needs maps0")
+    tl = trace_len(opts)
+    trace = np.empty(tl)
+    rep = Report()
+    p = make_protocol(proto)
+    st = lib.orc_fit_projected(C.byref(p), _dims(dims), make_spaces(spaces), _ptr(x), _ptr(b1), C.byref(o),
+                               _ptr(maps), C.byref(rep), _ptr(trace), tl)
+    if st:
+        raise ValueError("default initialisation failed")
+    return maps, {f[0]: getattr(rep, f[0]) for f in Report._fields_}, trace
+
+
+def uncertainty_projected(proto, dims, spaces, x, b1, opts: dict, maps):
+    lib = _load()
+    N = int(np.prod(dims))
+    x = flat_echoes(proto, spaces, x)
+    b1 = None if b1 is None else _f64(b1).reshape(N)
+    maps = _f64(maps).reshape(4, N)
+    var = np.empty((4, N))
+    p = make_protocol(proto)
+    lib.orc_uncertainty_projected(C.byref(p), _dims(dims), make_spaces(spaces), _ptr(x), _ptr(b1),
+                                  C.byref(make_options(opts)), _ptr(maps), _ptr(var), None)
+    return var
+

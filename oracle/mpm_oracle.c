@@ -450,25 +450,6 @@ int orc_pcg(const int64_t dims[3], const double *P, const double *w, const doubl
     return it_done;
 }
 
-/* ------------------------------------------------------------------------
- * Likelihood blocks of every voxel.  maps: [4][N]; nll: [N]; g: [4][N] or
- * NULL; P: [N][16] or NULL.
- * ------------------------------------------------------------------------ */
-static void lik_all(const orc_protocol *p, int64_t N, const double *x, const double *b1,
-                    int loading, const double *maps, double *nll, double *g, double *P)
-{
-#pragma omp parallel for schedule(static)
-    for (int64_t n = 0; n < N; n++) {
-        double y[4] = {maps[n], maps[N + n], maps[2 * N + n], maps[3 * N + n]};
-        double gl[4], Pl[16], l;
-        orc_lik_voxel(p, x + n, N, y, b1 ? b1[n] : 1.0, loading, &l, gl, Pl);
-        nll[n] = l;
-        if (g)
-            for (int k = 0; k < 4; k++) g[k * N + n] = gl[k];
-        if (P) memcpy(P + 16 * n, Pl, sizeof(Pl));
-    }
-}
-
 static double sum(const double *v, int64_t n)
 {
     double s = 0.0;
@@ -476,16 +457,171 @@ static double sum(const double *v, int64_t n)
     return s;
 }
 
-/* F_w(y) = sum_n nll_n + 1/2 y^T L y  (Sec. 2.6 objective at fixed weights). */
-static double objective_w(const orc_protocol *p, const int64_t dims[3], const double *x,
-                          const double *b1, int loading, const double *w,
-                          const double lambda[4], const double *maps, double *nll_buf,
-                          double *Ly_buf)
+/* ------------------------------------------------------------------------
+ * Spatial projection (Sec. 2.4, "Spatial projection"; reading R-proj).
+ *
+ * Contrast c is acquired on its own grid; acquisition voxel (i, j, k) lies at
+ * reconstruction-grid coordinates r = A (i, j, k, 1)^T (A row-major 3x4).  The
+ * reslicing Psi is trilinear interpolation with replicated borders (corner
+ * indices clamped to the grid, so every row of Psi sums to 1); acquisition
+ * voxels with r outside [-1/2, n_d - 1/2] in any axis d lie outside the
+ * reconstruction field of view and carry no observation.
+ * proj_weights: the 8 recon voxels and weights of acquisition voxel (i,j,k);
+ * returns 0 outside the field of view.
+ * ------------------------------------------------------------------------ */
+static int proj_weights(const int64_t dims[3], const orc_space *sp, int64_t i, int64_t j, int64_t k,
+                        int64_t idx[8], double wt[8])
 {
-    int64_t N = dims[0] * dims[1] * dims[2];
-    lik_all(p, N, x, b1, loading, maps, nll_buf, NULL, NULL);
-    orc_apply_L(dims, w, lambda, maps, Ly_buf);
-    return sum(nll_buf, N) + 0.5 * dot(maps, Ly_buf, 4 * N);
+    double r[3], t[3];
+    int64_t lo[3], hi[3];
+    for (int d = 0; d < 3; d++) {
+        const double *a = sp->affine + 4 * d;
+        r[d] = a[0] * (double)i + a[1] * (double)j + a[2] * (double)k + a[3];
+        if (!(r[d] >= -0.5 && r[d] <= (double)dims[d] - 0.5)) return 0;
+        double f = floor(r[d]);
+        t[d] = r[d] - f;
+        lo[d] = (int64_t)f < 0 ? 0 : (int64_t)f;
+        hi[d] = (int64_t)f + 1 > dims[d] - 1 ? dims[d] - 1 : (int64_t)f + 1;
+    }
+    for (int c = 0; c < 8; c++) {
+        int bx = c & 1, by = (c >> 1) & 1, bz = (c >> 2) & 1;
+        int64_t x = bx ? hi[0] : lo[0], y = by ? hi[1] : lo[1], z = bz ? hi[2] : lo[2];
+        idx[c] = x + dims[0] * (y + dims[1] * z);
+        wt[c] = (bx ? t[0] : 1.0 - t[0]) * (by ? t[1] : 1.0 - t[1]) * (bz ? t[2] : 1.0 - t[2]);
+    }
+    return 1;
+}
+
+static int64_t space_voxels(const orc_space *sp) { return sp->dims[0] * sp->dims[1] * sp->dims[2]; }
+
+/* out = Psi vol (0 outside the field of view).  vol: recon [N]; out: [M]. */
+void orc_pull(const int64_t dims[3], const orc_space *sp, const double *vol, double *out)
+{
+    int64_t m = 0, idx[8];
+    double wt[8];
+    for (int64_t k = 0; k < sp->dims[2]; k++)
+        for (int64_t j = 0; j < sp->dims[1]; j++)
+            for (int64_t i = 0; i < sp->dims[0]; i++, m++) {
+                double v = 0.0;
+                if (proj_weights(dims, sp, i, j, k, idx, wt))
+                    for (int c = 0; c < 8; c++) v += wt[c] * vol[idx[c]];
+                out[m] = v;
+            }
+}
+
+/* vol = Psi^T acq (the adjoint: push).  acq: [M]; vol: recon [N]. */
+void orc_push(const int64_t dims[3], const orc_space *sp, const double *acq, double *vol)
+{
+    int64_t N = dims[0] * dims[1] * dims[2], m = 0, idx[8];
+    double wt[8];
+    for (int64_t n = 0; n < N; n++) vol[n] = 0.0;
+    for (int64_t k = 0; k < sp->dims[2]; k++)
+        for (int64_t j = 0; j < sp->dims[1]; j++)
+            for (int64_t i = 0; i < sp->dims[0]; i++, m++)
+                if (proj_weights(dims, sp, i, j, k, idx, wt))
+                    for (int c = 0; c < 8; c++) vol[idx[c]] += wt[c] * acq[m];
+}
+
+/* Everything a likelihood evaluation needs.  spaces == NULL: every image on
+ * the reconstruction grid, echoes [I][N]; otherwise images lie back to back,
+ * image i holding the voxels of its contrast's space. */
+typedef struct {
+    const orc_protocol *p;
+    const int64_t *dims;
+    const orc_space *spaces;
+    const double *x;
+    const double *b1;
+} lik_ctx;
+
+/* The protocol restricted to contrast c. */
+static orc_protocol sub_protocol(const orc_protocol *p, int c)
+{
+    orc_protocol q;
+    memset(&q, 0, sizeof(q));
+    int first = 0;
+    for (int k = 0; k < c; k++) first += p->n_echoes[k];
+    q.n_contrasts = 1;
+    q.n_echoes[0] = p->n_echoes[c];
+    q.tr[0] = p->tr[c];
+    q.flip[0] = p->flip[c];
+    q.mt[0] = p->mt[c];
+    for (int e = 0; e < p->n_echoes[c]; e++) {
+        q.te[e] = p->te[first + e];
+        q.sigma[e] = p->sigma[first + e];
+    }
+    return q;
+}
+
+/* ------------------------------------------------------------------------
+ * Likelihood of every voxel; returns the total NLL (summed in a fixed order).
+ * maps: [4][N]; g: [4][N] or NULL; P: [N][16] or NULL.
+ * Without projection nll[N] receives the per-voxel NLL.  With projection the
+ * blocks are evaluated per acquisition voxel on the pulled maps (and pulled
+ * b1) and pushed back: g_n = sum_m Psi_mn g_m and, as the block-diagonal
+ * majoriser of Psi^T H Psi (Sec. 2.4), P_n = sum_m Psi_mn (sum_n' Psi_mn') P_m
+ * = sum_m Psi_mn P_m; nll is not used.
+ * ------------------------------------------------------------------------ */
+static double lik_all(const lik_ctx *L, int loading, const double *maps, double *nll, double *g, double *P)
+{
+    const orc_protocol *p = L->p;
+    const int64_t N = L->dims[0] * L->dims[1] * L->dims[2];
+    if (!L->spaces) {
+#pragma omp parallel for schedule(static)
+        for (int64_t n = 0; n < N; n++) {
+            double y[4] = {maps[n], maps[N + n], maps[2 * N + n], maps[3 * N + n]};
+            double gl[4], Pl[16], l;
+            orc_lik_voxel(p, L->x + n, N, y, L->b1 ? L->b1[n] : 1.0, loading, &l, gl, Pl);
+            nll[n] = l;
+            if (g)
+                for (int k = 0; k < 4; k++) g[k * N + n] = gl[k];
+            if (P) memcpy(P + 16 * n, Pl, sizeof(Pl));
+        }
+        return sum(nll, N);
+    }
+    if (g)
+        for (int64_t i = 0; i < 4 * N; i++) g[i] = 0.0;
+    if (P)
+        for (int64_t i = 0; i < 16 * N; i++) P[i] = 0.0;
+    double total = 0.0;
+    const double *img = L->x; /* first image of contrast c */
+    for (int c = 0; c < p->n_contrasts; c++) {
+        const orc_space *sp = L->spaces + c;
+        const int64_t M = space_voxels(sp);
+        orc_protocol pc = sub_protocol(p, c);
+        int64_t m = 0, idx[8];
+        double wt[8];
+        for (int64_t k = 0; k < sp->dims[2]; k++)
+            for (int64_t j = 0; j < sp->dims[1]; j++)
+                for (int64_t i = 0; i < sp->dims[0]; i++, m++) {
+                    if (!proj_weights(L->dims, sp, i, j, k, idx, wt)) continue;
+                    double y[4] = {0.0, 0.0, 0.0, 0.0}, b = 0.0;
+                    for (int q = 0; q < 8; q++) {
+                        for (int a = 0; a < 4; a++) y[a] += wt[q] * maps[a * N + idx[q]];
+                        b += wt[q] * (L->b1 ? L->b1[idx[q]] : 1.0);
+                    }
+                    double gl[4], Pl[16], l;
+                    orc_lik_voxel(&pc, img + m, M, y, b, loading, &l, gl, Pl);
+                    total += l;
+                    for (int q = 0; q < 8; q++) {
+                        if (g)
+                            for (int a = 0; a < 4; a++) g[a * N + idx[q]] += wt[q] * gl[a];
+                        if (P)
+                            for (int e = 0; e < 16; e++) P[16 * idx[q] + e] += wt[q] * Pl[e];
+                    }
+                }
+        img += (int64_t)p->n_echoes[c] * M;
+    }
+    return total;
+}
+
+/* F_w(y) = sum_n nll_n + 1/2 y^T L y  (Sec. 2.6 objective at fixed weights). */
+static double objective_w(const lik_ctx *L, int loading, const double *w, const double lambda[4],
+                          const double *maps, double *nll_buf, double *Ly_buf)
+{
+    int64_t N = L->dims[0] * L->dims[1] * L->dims[2];
+    double nll = lik_all(L, loading, maps, nll_buf, NULL, NULL);
+    orc_apply_L(L->dims, w, lambda, maps, Ly_buf);
+    return nll + 0.5 * dot(maps, Ly_buf, 4 * N);
 }
 
 static double logit(double v) { return log(v / (1.0 - v)); }
@@ -511,29 +647,60 @@ static double clampd(double v, double lo, double hi)
  *   4. Clamp R1 to [0.05, 20], R2* to [0.5, 500], delta to [1e-4, 0.2].
  * Returns 0, or 1 when the protocol lacks the contrasts above.
  * ------------------------------------------------------------------------ */
+/* Mean of the finite values of x[0..n) (NaN if there are none). */
+static double finite_mean(const double *x, int64_t n)
+{
+    double s = 0.0;
+    int64_t cnt = 0;
+    for (int64_t v = 0; v < n; v++)
+        if (isfinite(x[v])) {
+            s += x[v];
+            cnt++;
+        }
+    return cnt > 0 ? s / (double)cnt : NAN; /* no observation: left out below */
+}
+
+static int init_from_means(const orc_protocol *p, const double *m, double b1m, double y0[4]);
+
 int orc_default_init(const orc_protocol *p, int64_t n, const double *x, const double *b1,
                      double y0[4])
 {
-    int I = n_images(p), C = p->n_contrasts;
+    int I = n_images(p);
     double m[ORC_MAX_IMAGES];
-    for (int i = 0; i < I; i++) {
-        double s = 0.0;
-        int64_t cnt = 0;
-        for (int64_t v = 0; v < n; v++) {
-            double xi = x[(int64_t)i * n + v];
-            if (isfinite(xi)) {
-                s += xi;
-                cnt++;
-            }
-        }
-        m[i] = cnt > 0 ? s / (double)cnt : NAN; /* no observation: left out below */
-    }
+    for (int i = 0; i < I; i++) m[i] = finite_mean(x + (int64_t)i * n, n);
     double b1m = 1.0;
     if (b1) {
         double s = 0.0;
         for (int64_t v = 0; v < n; v++) s += b1[v];
         b1m = s / (double)n;
     }
+    return init_from_means(p, m, b1m, y0);
+}
+
+/* The same with projection: image i's mean runs over its own space. */
+int orc_default_init_projected(const orc_protocol *p, const int64_t dims[3], const orc_space *spaces,
+                               const double *x, const double *b1, double y0[4])
+{
+    double m[ORC_MAX_IMAGES];
+    int i = 0;
+    const double *img = x;
+    for (int c = 0; c < p->n_contrasts; c++) {
+        int64_t M = space_voxels(spaces + c);
+        for (int e = 0; e < p->n_echoes[c]; e++, i++, img += M) m[i] = finite_mean(img, M);
+    }
+    int64_t N = dims[0] * dims[1] * dims[2];
+    double b1m = 1.0;
+    if (b1) {
+        double s = 0.0;
+        for (int64_t v = 0; v < N; v++) s += b1[v];
+        b1m = s / (double)N;
+    }
+    return init_from_means(p, m, b1m, y0);
+}
+
+static int init_from_means(const orc_protocol *p, const double *m, double b1m, double y0[4])
+{
+    int I = n_images(p), C = p->n_contrasts;
     /* normal equations of the (C+1)-unknown linear least squares */
     int U = C + 1;
     double A[ORC_MAX_CONTRASTS + 1][ORC_MAX_CONTRASTS + 2];
@@ -623,10 +790,11 @@ int orc_default_init(const orc_protocol *p, int64_t n, const double *x, const do
  *        NLL + sum sqrt(q + eps^2) at the end of the loop; skipped steps NaN.
  * Returns 0, or 1 on an unusable default initialisation.
  * ------------------------------------------------------------------------ */
-int orc_fit(const orc_protocol *p, const int64_t dims[3], const double *x, const double *b1,
-            const orc_options *opt, double *maps, orc_report *rep, double *trace,
-            int32_t trace_len)
+static int fit_impl(const lik_ctx *L, const orc_options *opt, double *maps, orc_report *rep, double *trace,
+                    int32_t trace_len)
 {
+    const orc_protocol *p = L->p;
+    const int64_t *dims = L->dims;
     int64_t N = dims[0] * dims[1] * dims[2];
     int64_t V = 4 * N;
     orc_report R;
@@ -637,7 +805,8 @@ int orc_fit(const orc_protocol *p, const int64_t dims[3], const double *x, const
         double y0[4];
         if (opt->init_kind == ORC_INIT_CONST) {
             for (int k = 0; k < 4; k++) y0[k] = opt->init_const[k];
-        } else if (orc_default_init(p, N, x, b1, y0)) {
+        } else if (L->spaces ? orc_default_init_projected(p, dims, L->spaces, L->x, L->b1, y0)
+                             : orc_default_init(p, N, L->x, L->b1, y0)) {
             return 1;
         }
         for (int k = 0; k < 4; k++)
@@ -652,9 +821,9 @@ int orc_fit(const orc_protocol *p, const int64_t dims[3], const double *x, const
     if (opt->mode == ORC_ML) {
         double *prev = (double *)malloc(sizeof(double) * (size_t)N);
         for (int it = 0; it < opt->n_gn; it++) {
-            lik_all(p, N, x, b1, opt->loading, maps, nll, g, P);
-            if (trace && it < trace_len) trace[it] = sum(nll, N);
-            if (it > 0)
+            double tot = lik_all(L, opt->loading, maps, nll, g, P);
+            if (trace && it < trace_len) trace[it] = tot;
+            if (it > 0 && !L->spaces) /* per-voxel NLL exists only without projection */
                 for (int64_t n = 0; n < N; n++)
                     if (nll[n] > prev[n] * (1.0 + NLL_RISE_REL)) R.nll_increases++;
             memcpy(prev, nll, sizeof(double) * (size_t)N);
@@ -667,11 +836,10 @@ int orc_fit(const orc_protocol *p, const int64_t dims[3], const double *x, const
             }
             R.gn_done++;
         }
-        lik_all(p, N, x, b1, opt->loading, maps, nll, NULL, NULL);
-        if (opt->n_gn > 0)
+        R.nll = lik_all(L, opt->loading, maps, nll, NULL, NULL);
+        if (opt->n_gn > 0 && !L->spaces)
             for (int64_t n = 0; n < N; n++)
                 if (nll[n] > prev[n] * (1.0 + NLL_RISE_REL)) R.nll_increases++;
-        R.nll = sum(nll, N);
         R.objective = R.nll;
         if (trace && opt->n_gn < trace_len) trace[opt->n_gn] = R.nll;
         for (int64_t n = 0; n < N; n++) R.degenerate_voxels += degen[n];
@@ -691,9 +859,9 @@ int orc_fit(const orc_protocol *p, const int64_t dims[3], const double *x, const
         for (int t = 0; t < opt->n_outer; t++) {
             if (t >= 1 && lam_sum > 0.0) orc_jtv_weights(dims, maps, opt->lambda, eps, w, d);
             for (int j = 0; j < opt->n_gn; j++) {
-                lik_all(p, N, x, b1, opt->loading, maps, nll, g, P);
+                double tot = lik_all(L, opt->loading, maps, nll, g, P);
                 orc_apply_L(dims, w, opt->lambda, maps, Ly);
-                double F = sum(nll, N) + 0.5 * dot(maps, Ly, V);
+                double F = tot + 0.5 * dot(maps, Ly, V);
                 if (trace && j == 0 && t * slots < trace_len) trace[t * slots] = F;
                 for (int64_t i = 0; i < V; i++) b[i] = g[i] + Ly[i];
                 R.cg_done += orc_pcg(dims, P, w, d, opt->lambda, b, opt->n_cg, cg_stop, delta);
@@ -702,14 +870,13 @@ int orc_fit(const orc_protocol *p, const int64_t dims[3], const double *x, const
                 double Fnew = F;
                 if (opt->max_halvings < 0) {
                     for (int64_t i = 0; i < V; i++) maps[i] -= delta[i];
-                    Fnew = objective_w(p, dims, x, b1, opt->loading, w, opt->lambda, maps, nll, Ly);
+                    Fnew = objective_w(L, opt->loading, w, opt->lambda, maps, nll, Ly);
                     accepted = 1;
                 } else {
                     double step = 1.0;
                     for (int h = 0; h <= opt->max_halvings; h++) {
                         for (int64_t i = 0; i < V; i++) trial[i] = maps[i] - step * delta[i];
-                        double Ft = objective_w(p, dims, x, b1, opt->loading, w, opt->lambda,
-                                                trial, nll, Ly);
+                        double Ft = objective_w(L, opt->loading, w, opt->lambda, trial, nll, Ly);
                         if (Ft <= F) {
                             memcpy(maps, trial, sizeof(double) * (size_t)V);
                             Fnew = Ft;
@@ -729,8 +896,7 @@ int orc_fit(const orc_protocol *p, const int64_t dims[3], const double *x, const
             R.outer_done++;
             if (trace && t * slots + opt->n_gn + 1 < trace_len) {
                 double jt = lam_sum > 0.0 ? orc_jtv_weights(dims, maps, opt->lambda, eps, Ly, NULL) : 0.0;
-                lik_all(p, N, x, b1, opt->loading, maps, nll, NULL, NULL);
-                trace[t * slots + opt->n_gn + 1] = sum(nll, N) + jt;
+                trace[t * slots + opt->n_gn + 1] = lik_all(L, opt->loading, maps, nll, NULL, NULL) + jt;
             }
         }
         /* final weights, objective and degenerate count (R-w0) */
@@ -738,8 +904,7 @@ int orc_fit(const orc_protocol *p, const int64_t dims[3], const double *x, const
         if (lam_sum > 0.0) jt = orc_jtv_weights(dims, maps, opt->lambda, eps, w, d);
         else
             for (int64_t n = 0; n < N; n++) w[n] = d[n] = 0.0;
-        lik_all(p, N, x, b1, opt->loading, maps, nll, NULL, P);
-        R.nll = sum(nll, N);
+        R.nll = lik_all(L, opt->loading, maps, nll, NULL, P);
         R.jtv = jt;
         R.objective = R.nll + jt;
         for (int64_t n = 0; n < N; n++) {
@@ -769,6 +934,34 @@ int orc_fit(const orc_protocol *p, const int64_t dims[3], const double *x, const
     return 0;
 }
 
+int orc_fit(const orc_protocol *p, const int64_t dims[3], const double *x, const double *b1,
+            const orc_options *opt, double *maps, orc_report *rep, double *trace, int32_t trace_len)
+{
+    lik_ctx L = {p, dims, NULL, x, b1};
+    return fit_impl(&L, opt, maps, rep, trace, trace_len);
+}
+
+/* The fit with spatial projection (R-proj): spaces[c] is the acquisition
+ * space of contrast c; echoes lie back to back (image i holds the voxels of
+ * its contrast's space); maps and b1 live on the reconstruction grid dims.
+ * ML takes the Newton-like step y <- y - P~^{-1} g with the pushed blocks. */
+int orc_fit_projected(const orc_protocol *p, const int64_t dims[3], const orc_space *spaces, const double *x,
+                      const double *b1, const orc_options *opt, double *maps, orc_report *rep, double *trace,
+                      int32_t trace_len)
+{
+    lik_ctx L = {p, dims, spaces, x, b1};
+    return fit_impl(&L, opt, maps, rep, trace, trace_len);
+}
+
+/* Total NLL, pushed gradient g [4][N] and pushed blocks P [N][16] (either may
+ * be NULL) at maps, with projection. */
+double orc_proj_lik(const orc_protocol *p, const int64_t dims[3], const orc_space *spaces, const double *x,
+                    const double *b1, int loading, const double *maps, double *g, double *P)
+{
+    lik_ctx L = {p, dims, spaces, x, b1};
+    return lik_all(&L, loading, maps, NULL, g, P);
+}
+
 /* ------------------------------------------------------------------------
  * Laplace posterior variance (Sec. 3.6): the diagonal of
  * (P~ + diag(G^T W G) (x) diag(lambda))^{-1} at the fitted maps, with W from
@@ -777,10 +970,10 @@ int orc_fit(const orc_protocol *p, const int64_t dims[3], const double *x, const
  * moments (optional, [4][N]): E[r1], V[r1], E[t1], V[t1] of the log-normal
  * posterior of r1 = exp(y1) and t1 = exp(-y1) (Sec. 3.6).
  * ------------------------------------------------------------------------ */
-int orc_uncertainty(const orc_protocol *p, const int64_t dims[3], const double *x,
-                    const double *b1, const orc_options *opt, const double *maps,
-                    double *var, double *moments)
+static int uncertainty_impl(const lik_ctx *L, const orc_options *opt, const double *maps, double *var,
+                            double *moments)
 {
+    const int64_t *dims = L->dims;
     int64_t N = dims[0] * dims[1] * dims[2];
     double lam[4] = {0.0, 0.0, 0.0, 0.0};
     double *d = (double *)calloc((size_t)N, sizeof(double));
@@ -796,7 +989,7 @@ int orc_uncertainty(const orc_protocol *p, const int64_t dims[3], const double *
             for (int k = 0; k < 4; k++) lam[k] = opt->lambda[k];
         }
     }
-    lik_all(p, N, x, b1, opt->loading, maps, nll, NULL, P);
+    lik_all(L, opt->loading, maps, nll, NULL, P);
 #pragma omp parallel for schedule(static)
     for (int64_t n = 0; n < N; n++) {
         double M[16];
@@ -825,4 +1018,19 @@ int orc_uncertainty(const orc_protocol *p, const int64_t dims[3], const double *
     free(nll);
     free(P);
     return 0;
+}
+
+int orc_uncertainty(const orc_protocol *p, const int64_t dims[3], const double *x, const double *b1,
+                    const orc_options *opt, const double *maps, double *var, double *moments)
+{
+    lik_ctx L = {p, dims, NULL, x, b1};
+    return uncertainty_impl(&L, opt, maps, var, moments);
+}
+
+int orc_uncertainty_projected(const orc_protocol *p, const int64_t dims[3], const orc_space *spaces,
+                              const double *x, const double *b1, const orc_options *opt, const double *maps,
+                              double *var, double *moments)
+{
+    lik_ctx L = {p, dims, spaces, x, b1};
+    return uncertainty_impl(&L, opt, maps, var, moments);
 }

@@ -37,6 +37,14 @@ typedef struct {
     double  sigma[ORC_MAX_IMAGES];      /* noise standard deviation per image */
 } orc_protocol;
 
+/* Acquisition space of one contrast (spatial projection, Sec. 2.4): its grid
+ * and the affine map from its voxel indices (i, j, k) to coordinates on the
+ * reconstruction grid, r = A (i, j, k, 1)^T, A row-major 3x4. */
+typedef struct {
+    int64_t dims[3];
+    double  affine[12];
+} orc_space;
+
 enum { ORC_ML = 0, ORC_MAP = 1 };
 enum { ORC_INIT_DEFAULT = 0, ORC_INIT_CONST = 1, ORC_INIT_FROM_MAPS = 2 };
 enum { ORC_LOAD_PROPOSED = 0, ORC_LOAD_GN = 1, ORC_LOAD_PROPOSED_PLUS = 2 };
@@ -101,6 +109,20 @@ int  orc_uncertainty(const orc_protocol *p, const int64_t dims[3], const double 
                      const double *b1, const orc_options *opt, const double *maps,
                      double *var, double *moments);
 int  orc_num_threads(void);
+
+/* Spatial projection (R-proj): trilinear pull Psi and its adjoint push. */
+void orc_pull(const int64_t dims[3], const orc_space *sp, const double *vol, double *out);
+void orc_push(const int64_t dims[3], const orc_space *sp, const double *acq, double *vol);
+double orc_proj_lik(const orc_protocol *p, const int64_t dims[3], const orc_space *spaces, const double *x,
+                    const double *b1, int loading, const double *maps, double *g, double *P);
+int orc_default_init_projected(const orc_protocol *p, const int64_t dims[3], const orc_space *spaces,
+                               const double *x, const double *b1, double y0[4]);
+int orc_fit_projected(const orc_protocol *p, const int64_t dims[3], const orc_space *spaces, const double *x,
+                      const double *b1, const orc_options *opt, double *maps, orc_report *rep, double *trace,
+                      int32_t trace_len);
+int orc_uncertainty_projected(const orc_protocol *p, const int64_t dims[3], const orc_space *spaces,
+                              const double *x, const double *b1, const orc_options *opt, const double *maps,
+                              double *var, double *moments);
 
 #ifdef __cplusplus
 }
