@@ -163,6 +163,50 @@ mpm_status mpm_simulate(const mpm_protocol *protocol, const mpm_grid *grid, cons
                         const float *b1, const float *noise, mpm_dtype out_dtype, void *out,
                         void *stream);
 
+/*
+ * Spatial projection (paper Sec. 2.4, "Spatial projection"): each contrast may
+ * be acquired on its own grid, e.g. after head motion between scans.  The
+ * maps and b1 stay on the reconstruction grid `grid`; the model is evaluated
+ * on maps resliced into each acquisition space and its gradient and loaded
+ * Hessian are sent back with the adjoint; the Hessian blocks that come back
+ * are the block-diagonal majoriser of the reslicing the paper cites.
+ *
+ * mpm_space: the grid of one contrast and the affine map from its voxel
+ * indices (i, j, k) to coordinates on the reconstruction grid,
+ * r = affine (i, j, k, 1)^T, affine row-major 3x4 (unit: reconstruction
+ * voxels).  Reslicing is trilinear with replicated borders; acquisition voxels
+ * with r outside [-1/2, n - 1/2] on some axis lie outside the reconstruction
+ * field of view and carry no observation.  Each axis of the affine must have
+ * length in [1/8, 8] (acquisition voxel size relative to the reconstruction
+ * voxel) and the affine must be invertible.
+ *
+ * spaces: host array of n_contrasts spaces.  echoes: device, the images back
+ * to back, image i holding nx*ny*nz values of its contrast's space (image
+ * order as mpm_protocol).  All else as mpm_fit / mpm_uncertainty.  An ML fit
+ * takes the step y - P~^{-1} g with the pushed blocks in every iteration; its
+ * report counts nll_increases as 0 (the NLL per voxel is not defined here)
+ * and degenerate_voxels at the final maps.
+ */
+typedef struct {
+    int64_t nx, ny, nz;
+    double affine[12];
+} mpm_space;
+
+mpm_status mpm_fit_projected(const mpm_protocol *protocol, const mpm_grid *grid, const mpm_space *spaces,
+                             mpm_dtype dtype, const void *echoes, const float *b1, const mpm_options *options,
+                             float *maps, mpm_report *report, double *trace, int32_t trace_len, void *stream);
+mpm_status mpm_uncertainty_projected(const mpm_protocol *protocol, const mpm_grid *grid, const mpm_space *spaces,
+                                     mpm_dtype dtype, const void *echoes, const float *b1,
+                                     const mpm_options *options, const float *maps, float *var, float *moments,
+                                     void *stream);
+/* Echoes in every acquisition space (layout as mpm_fit_projected's echoes)
+ * from maps and b1 on the reconstruction grid: the model at the resliced maps
+ * and b1, plus sigma_i * noise (noise: device float, same layout, or NULL);
+ * NaN (no observation) outside the reconstruction field of view. */
+mpm_status mpm_simulate_projected(const mpm_protocol *protocol, const mpm_grid *grid, const mpm_space *spaces,
+                                  const float *maps, const float *b1, const float *noise, mpm_dtype out_dtype,
+                                  void *out, void *stream);
+
 /* Device bytes a fit of this size needs: inputs, maps and the library's
  * workspace.  Returns 0 for invalid arguments. */
 size_t mpm_footprint_bytes(const mpm_protocol *protocol, const mpm_grid *grid, mpm_dtype dtype,

@@ -63,6 +63,10 @@ class mpm_request(C.Structure):
 MPM_SERVER_THREAD = 1
 
 
+class mpm_space(C.Structure):
+    _fields_ = [("nx", C.c_int64), ("ny", C.c_int64), ("nz", C.c_int64), ("affine", C.c_double * 12)]
+
+
 class MpmError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"{STATUS.get(status, status)}: {msg}")
@@ -80,6 +84,12 @@ SIGNATURES = {
                                   C.c_void_p, C.c_void_p]),
     "mpm_simulate": (C.c_int, [_P, _G, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]),
     "mpm_footprint_bytes": (C.c_size_t, [_P, _G, C.c_int, C.c_int32]),
+    "mpm_fit_projected": (C.c_int, [_P, _G, C.POINTER(mpm_space), C.c_int, C.c_void_p, C.c_void_p, _O, C.c_void_p,
+                                    _R, C.POINTER(C.c_double), C.c_int32, C.c_void_p]),
+    "mpm_uncertainty_projected": (C.c_int, [_P, _G, C.POINTER(mpm_space), C.c_int, C.c_void_p, C.c_void_p, _O,
+                                            C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "mpm_simulate_projected": (C.c_int, [_P, _G, C.POINTER(mpm_space), C.c_void_p, C.c_void_p, C.c_void_p, C.c_int,
+                                         C.c_void_p, C.c_void_p]),
     "mpm_last_error": (C.c_char_p, []),
     "mpm_version": (C.c_char_p, []),
     "mpm_profile_enable": (None, [C.c_int32]),
@@ -179,6 +189,17 @@ def _ptr(t):
     return None if t is None else C.c_void_p(t.data_ptr())
 
 
+def _f32(t, name):
+    """Device pointer of a float32 tensor argument (maps, b1, var, moments,
+    noise): the library reads these as FP32, so any other dtype is an error."""
+    if t is None:
+        return None
+    import torch
+    if t.dtype != torch.float32 or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous float32 tensor (got {t.dtype})")
+    return C.c_void_p(t.data_ptr())
+
+
 def mpm_fit(protocol: dict, dims, echoes, b1, options: dict, maps, stream=None):
     """Run mpm_fit on device tensors.  ``maps`` (float32 [4][N]) is updated in
     place.  Returns (report dict, trace numpy array)."""
@@ -187,7 +208,7 @@ def mpm_fit(protocol: dict, dims, echoes, b1, options: dict, maps, stream=None):
     trace = (C.c_double * tl)()
     rep = mpm_report()
     _check(lib.mpm_fit(C.byref(make_protocol(protocol)), C.byref(make_grid(dims)), _dtype_code(echoes),
-                       _ptr(echoes), _ptr(b1), C.byref(make_options(options)), _ptr(maps), C.byref(rep),
+                       _ptr(echoes), _f32(b1, "b1"), C.byref(make_options(options)), _f32(maps, "maps"), C.byref(rep),
                        trace, tl, _stream(stream)))
     report = {f[0]: getattr(rep, f[0]) for f in mpm_report._fields_}
     return report, np.array(trace[:], dtype=np.float64)
@@ -196,14 +217,57 @@ def mpm_fit(protocol: dict, dims, echoes, b1, options: dict, maps, stream=None):
 def mpm_uncertainty(protocol: dict, dims, echoes, b1, options: dict, maps, var, moments=None, stream=None):
     lib = load()
     _check(lib.mpm_uncertainty(C.byref(make_protocol(protocol)), C.byref(make_grid(dims)), _dtype_code(echoes),
-                               _ptr(echoes), _ptr(b1), C.byref(make_options(options)), _ptr(maps), _ptr(var),
-                               _ptr(moments), _stream(stream)))
+                               _ptr(echoes), _f32(b1, "b1"), C.byref(make_options(options)), _f32(maps, "maps"), _f32(var, "var"),
+                               _f32(moments, "moments"), _stream(stream)))
 
 
 def mpm_simulate(protocol: dict, dims, maps, b1, noise, out, stream=None):
     lib = load()
-    _check(lib.mpm_simulate(C.byref(make_protocol(protocol)), C.byref(make_grid(dims)), _ptr(maps), _ptr(b1),
-                            _ptr(noise), _dtype_code(out), _ptr(out), _stream(stream)))
+    _check(lib.mpm_simulate(C.byref(make_protocol(protocol)), C.byref(make_grid(dims)), _f32(maps, "maps"), _f32(b1, "b1"),
+                            _f32(noise, "noise"), _dtype_code(out), _ptr(out), _stream(stream)))
+
+
+def make_spaces(spaces):
+    """Acquisition spaces: a list (one per contrast) of {"dims": (nx, ny, nz),
+    "affine": 3x4 map from the space's voxel indices to reconstruction-grid
+    coordinates}."""
+    arr = (mpm_space * len(spaces))()
+    for c, sp in enumerate(spaces):
+        arr[c].nx, arr[c].ny, arr[c].nz = (int(v) for v in sp["dims"])
+        a = np.asarray(sp["affine"], dtype=np.float64).reshape(-1)
+        for k in range(12):
+            arr[c].affine[k] = float(a[k])
+    return arr
+
+
+def mpm_fit_projected(protocol: dict, dims, spaces, echoes, b1, options: dict, maps, stream=None):
+    """mpm_fit_projected on device tensors; echoes: the images back to back,
+    each on its contrast's space.  Returns (report dict, trace)."""
+    lib = load()
+    tl = trace_len(options)
+    trace = (C.c_double * tl)()
+    rep = mpm_report()
+    _check(lib.mpm_fit_projected(C.byref(make_protocol(protocol)), C.byref(make_grid(dims)), make_spaces(spaces),
+                                 _dtype_code(echoes), _ptr(echoes), _f32(b1, "b1"), C.byref(make_options(options)),
+                                 _f32(maps, "maps"), C.byref(rep), trace, tl, _stream(stream)))
+    report = {f[0]: getattr(rep, f[0]) for f in mpm_report._fields_}
+    return report, np.array(trace[:], dtype=np.float64)
+
+
+def mpm_uncertainty_projected(protocol: dict, dims, spaces, echoes, b1, options: dict, maps, var, moments=None,
+                              stream=None):
+    lib = load()
+    _check(lib.mpm_uncertainty_projected(C.byref(make_protocol(protocol)), C.byref(make_grid(dims)),
+                                         make_spaces(spaces), _dtype_code(echoes), _ptr(echoes), _f32(b1, "b1"),
+                                         C.byref(make_options(options)), _f32(maps, "maps"), _f32(var, "var"), _f32(moments, "moments"),
+                                         _stream(stream)))
+
+
+def mpm_simulate_projected(protocol: dict, dims, spaces, maps, b1, noise, out, stream=None):
+    lib = load()
+    _check(lib.mpm_simulate_projected(C.byref(make_protocol(protocol)), C.byref(make_grid(dims)), make_spaces(spaces),
+                                      _f32(maps, "maps"), _f32(b1, "b1"), _f32(noise, "noise"), _dtype_code(out), _ptr(out),
+                                      _stream(stream)))
 
 
 def mpm_footprint_bytes(protocol: dict, dims, dtype: int, mode: int) -> int:

@@ -13,57 +13,9 @@
 // tiles (neighbouring tiles and planes share stencil halos in that XCD's L2).
 #include <cstdlib>
 
-#include "mpm_map.h"
+#include "mpm_proj.h"
 
 namespace mpm {
-
-// ---------------------------------------------------------------------------
-// Column walk.  A workgroup owns a TILE_X x TILE_Y tile of the x-y plane and
-// the planes [z0, z1); each thread walks its own (x, y) column.  The values
-// at z - 1, z, z + 1 of the thread's own column rotate through registers; the
-// four in-plane neighbours are loaded (they are L2-resident: adjacent tiles of
-// the same z-run are processed by the same XCD at the same time).
-// ---------------------------------------------------------------------------
-struct Col {
-    int x, y, z0, z1;
-    bool act;
-    bool xm, xp, ym, yp;  // in-plane neighbours inside the grid
-    int64_t base;         // voxel index of (x, y, 0)
-    int64_t sxy;          // plane stride
-};
-
-__device__ __forceinline__ Col locate_col(const Grid3 &g)
-{
-    const int L = blockIdx.x, T = gridDim.x;
-    const int q = T >> 3, r = T & 7, j = L & 7;
-    const int lid = j * q + min(j, r) + (L >> 3);  // XCD-contiguous workgroup index
-    const int bx = lid % g.gx;
-    const int t2 = lid / g.gx;
-    const int by = t2 % g.gy;
-    const int bz = t2 / g.gy;
-    Col c;
-    c.x = bx * TILE_X + (threadIdx.x & (TILE_X - 1));
-    c.y = by * g.ty + (threadIdx.x / TILE_X);
-    c.z0 = bz * g.zc;
-    c.z1 = min(c.z0 + g.zc, g.nz);
-    c.act = c.x < g.nx && c.y < g.ny;
-    c.xm = c.x > 0;
-    c.xp = c.x < g.nx - 1;
-    c.ym = c.y > 0;
-    c.yp = c.y < g.ny - 1;
-    c.sxy = (int64_t)g.nx * g.ny;
-    c.base = c.act ? (int64_t)c.x + (int64_t)g.nx * c.y : 0;
-    return c;
-}
-
-template <class Visit>
-__device__ __forceinline__ void for_inplane(const Col &c, int64_t n, int nx, Visit visit)
-{
-    if (c.xm) visit(n - 1);
-    if (c.xp) visit(n + 1);
-    if (c.ym) visit(n - nx);
-    if (c.yp) visit(n + nx);
-}
 
 __device__ __forceinline__ void load4(const float *__restrict__ a, int64_t N, int64_t n, float v[4])
 {
@@ -122,79 +74,6 @@ __device__ __forceinline__ bool precond(const float H[10], const float lam[4], f
     M[7] += lam[2] * d;
     M[9] += lam[3] * d;
     return solve_sym4(M, r, z);
-}
-
-template <int NV>
-__device__ __forceinline__ void write_partials(double (&v)[NV], double *__restrict__ partials)
-{
-    __shared__ double lds[NV][NWAVE];
-    block_sum<NV>(v, lds);
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int k = 0; k < NV; k++) partials[(int64_t)k * gridDim.x + blockIdx.x] = v[k];
-    }
-}
-
-// Non-temporal access for arrays that a kernel streams exactly once (no
-// stencil reuse), so they do not evict the stencil operands' halos from L2.
-typedef float v4f __attribute__((ext_vector_type(4)));
-typedef float v2f __attribute__((ext_vector_type(2)));
-
-__device__ __forceinline__ void vload_nt(const float4 *__restrict__ a, int64_t n, float v[4])
-{
-    const v4f t = __builtin_nontemporal_load((const v4f *)(a + n));
-    v[0] = t.x;
-    v[1] = t.y;
-    v[2] = t.z;
-    v[3] = t.w;
-}
-
-__device__ __forceinline__ void vstore_nt(float4 *__restrict__ a, int64_t n, const float v[4])
-{
-    const v4f t = {v[0], v[1], v[2], v[3]};
-    __builtin_nontemporal_store(t, (v4f *)(a + n));
-}
-
-__device__ __forceinline__ void vload(const float4 *__restrict__ a, int64_t n, float v[4])
-{
-    const float4 t = a[n];
-    v[0] = t.x;
-    v[1] = t.y;
-    v[2] = t.z;
-    v[3] = t.w;
-}
-
-__device__ __forceinline__ void vstore(float4 *__restrict__ a, int64_t n, const float v[4])
-{
-    a[n] = make_float4(v[0], v[1], v[2], v[3]);
-}
-
-// packed symmetric index: 0:00 1:01 2:02 3:03 4:11 5:12 6:13 7:22 8:23 9:33
-__device__ __forceinline__ void load_H(const HessArrays &h, int64_t n, float H[10])
-{
-    const v4f d = __builtin_nontemporal_load((const v4f *)(h.d + n));
-    const v4f o = __builtin_nontemporal_load((const v4f *)(h.o + n));
-    const v2f r = __builtin_nontemporal_load((const v2f *)(h.r + n));
-    H[0] = d.x;
-    H[4] = d.y;
-    H[7] = d.z;
-    H[9] = d.w;
-    H[1] = o.x;
-    H[2] = o.y;
-    H[3] = o.z;
-    H[5] = o.w;
-    H[6] = r.x;
-    H[8] = r.y;
-}
-
-__device__ __forceinline__ void store_H(const HessArrays &h, int64_t n, const float H[10])
-{
-    const v4f d = {H[0], H[4], H[7], H[9]};
-    const v4f o = {H[1], H[2], H[3], H[5]};
-    const v2f r = {H[6], H[8]};
-    __builtin_nontemporal_store(d, (v4f *)(h.d + n));
-    __builtin_nontemporal_store(o, (v4f *)(h.o + n));
-    __builtin_nontemporal_store(r, (v2f *)(h.r + n));
 }
 
 // ---------------------------------------------------------------------------
@@ -488,29 +367,6 @@ __global__ __launch_bounds__(CGB_THREADS) void k_cg_b(Grid3 g, HessArrays Hs, co
     write_partial1<CGB_THREADS>(part, partials);
 }
 
-// delta_f = delta + alpha_pend p_last at voxel m
-struct DeltaF {
-    const float4 *__restrict__ D;
-    const float4 *__restrict__ Pl;
-    float alpha;
-    bool dvalid;
-    __device__ __forceinline__ void operator()(int64_t m, float v[4]) const
-    {
-        float4 t = dvalid ? D[m] : make_float4(0.f, 0.f, 0.f, 0.f);
-        if (alpha != 0.0f) {
-            const float4 p = Pl[m];
-            t.x += alpha * p.x;
-            t.y += alpha * p.y;
-            t.z += alpha * p.z;
-            t.w += alpha * p.w;
-        }
-        v[0] = t.x;
-        v[1] = t.y;
-        v[2] = t.z;
-        v[3] = t.w;
-    }
-};
-
 // ---------------------------------------------------------------------------
 // accept, pass 1: the NLL at the full step y - delta_f and the prior pieces
 // c1 = delta_f.(L y), c2 = delta_f.(L delta_f), so that
@@ -792,7 +648,7 @@ __device__ __forceinline__ double reduce_row(const double *__restrict__ row, int
 __global__ __launch_bounds__(FIN_THREADS) void k_fin(int stage, int arg, int nblk,
                                                      const double *__restrict__ partials, MapCtl *__restrict__ ctl,
                                                      double *__restrict__ trace, double cg_stop_rel, int ntrial,
-                                                     int accept_off)
+                                                     int accept_off, ExtRows ext)
 {
     __shared__ double lds[FIN_THREADS / 64];
     const bool gated = (stage == FIN_W || stage == FIN_STATS) ? false : (ctl->gn_stop != 0);
@@ -804,6 +660,7 @@ __global__ __launch_bounds__(FIN_THREADS) void k_fin(int stage, int arg, int nbl
                      : stage == FIN_ACCEPT2                                          ? MAX_TRIALS
                                                                                      : 1;
     for (int k = 0; k < rows; k++) s[k] = reduce_row(partials + (int64_t)k * nblk, nblk, lds);
+    for (int k = 0; k < rows && k < ext.rows; k++) s[k] += reduce_row(ext.p + (int64_t)k * ext.stride, ext.cols, lds);
     if (threadIdx.x != 0) return;
     MapCtl &c = *ctl;
     switch (stage) {
@@ -1015,10 +872,36 @@ hipError_t launch_final(hipStream_t s, const MapArgs &a, float *var, float *mom)
 }
 
 hipError_t launch_fin(hipStream_t s, const MapArgs &a, int stage, int arg, int nblk, double cg_stop_rel,
-                      int ntrial, int accept_off)
+                      int ntrial, int accept_off, const ExtRows &ext)
 {
     hipLaunchKernelGGL(k_fin, dim3(1), dim3(FIN_THREADS), 0, s, stage, arg, nblk, a.partials, a.ctl, a.trace,
-                       cg_stop_rel, ntrial, accept_off);
+                       cg_stop_rel, ntrial, accept_off, ext);
+    return hipGetLastError();
+}
+
+// --- the MAP kernels on pushed blocks (projected fits) ---
+hipError_t launch_lik_pushed(hipStream_t s, const MapArgs &a, const PushedProto &pp)
+{
+    const float *l = a.lam;
+    hipLaunchKernelGGL((k_lik<Pushed, 0, 0>), cols(a.gp), dim3(BLOCK), 0, s, a.gp, pp, (const Pushed *)nullptr,
+                       (const float *)nullptr, a.Y, a.w, l[0], l[1], l[2], l[3], a.loading, a.H, a.R, a.Z, a.ctl,
+                       a.partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_accept_pushed(hipStream_t s, const MapArgs &a, const PushedProto &pp)
+{
+    const float *l = a.lam;
+    hipLaunchKernelGGL((k_accept<Pushed, 0, 0>), cols(a.gp), dim3(BLOCK), 0, s, a.gp, pp, (const Pushed *)nullptr,
+                       (const float *)nullptr, a.Y, a.w, l[0], l[1], l[2], l[3], a.D, a.P0, a.P1, a.ctl, a.partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_final_pushed(hipStream_t s, const MapArgs &a, const PushedProto &pp, float *var, float *mom)
+{
+    const float *l = a.lam;
+    hipLaunchKernelGGL((k_final<Pushed, 0, 0>), cols(a.gp), dim3(BLOCK), 0, s, a.gp, pp, (const Pushed *)nullptr,
+                       (const float *)nullptr, a.Y, a.w, l[0], l[1], l[2], l[3], a.loading, var, mom, a.partials);
     return hipGetLastError();
 }
 

@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "../../include/mpm.h"
+#include "mpm_proj.h"
 #include "mpm_api_internal.h"
 #include "mpm_kernels.h"
 
@@ -158,6 +159,50 @@ mpm_status check_dtype(int dtype)
     if (dtype != MPM_F32 && dtype != MPM_F16 && dtype != MPM_BF16)
         return fail(MPM_ERR_INVALID_ARG, "unknown echo dtype %d", dtype);
     return MPM_OK;
+}
+
+mpm_status check_spaces(const mpm_protocol *p, const mpm_space *spaces)
+{
+    if (!spaces) return fail(MPM_ERR_INVALID_ARG, "spaces is NULL");
+    for (int c = 0; c < p->n_contrasts; c++) {
+        const mpm_space &sp = spaces[c];
+        if (sp.nx < 1 || sp.ny < 1 || sp.nz < 1 || sp.nx > (1 << 20) || sp.ny > (1 << 20) || sp.nz > (1 << 20))
+            return fail(MPM_ERR_INVALID_ARG, "space %d: each axis must be in [1, 2^20]", c);
+        if (space_voxels(sp) > ((int64_t)1 << 30) - 1)
+            return fail(MPM_ERR_INVALID_ARG, "space %d has more than 2^30-1 voxels", c);
+        for (int k = 0; k < 12; k++)
+            if (!std::isfinite(sp.affine[k])) return fail(MPM_ERR_INVALID_ARG, "space %d: affine is not finite", c);
+        const double *a = sp.affine;
+        for (int col = 0; col < 3; col++) {
+            const double len = std::sqrt(a[col] * a[col] + a[4 + col] * a[4 + col] + a[8 + col] * a[8 + col]);
+            if (!(len >= 0.125 && len <= 8.0))
+                return fail(MPM_ERR_INVALID_ARG, "space %d: axis %d of the affine has length %g (must be in [1/8, 8])",
+                            c, col, len);
+        }
+        const double det = a[0] * (a[5] * a[10] - a[6] * a[9]) - a[1] * (a[4] * a[10] - a[6] * a[8]) +
+                           a[2] * (a[4] * a[9] - a[5] * a[8]);
+        if (!(std::fabs(det) > 1e-6)) return fail(MPM_ERR_INVALID_ARG, "space %d: affine is singular", c);
+    }
+    return MPM_OK;
+}
+
+DevProto sub_proto(const DevProto &P, int c)
+{
+    DevProto q;
+    memset(&q, 0, sizeof(q));
+    const int i0 = P.first[c], ne = P.first[c + 1] - i0;
+    q.C = 1;
+    q.I = ne;
+    q.first[0] = 0;
+    q.first[1] = ne;
+    q.tr[0] = P.tr[c];
+    q.flip[0] = P.flip[c];
+    q.mt[0] = P.mt[c];
+    for (int e = 0; e < ne; e++) {
+        q.te[e] = P.te[i0 + e];
+        q.wgt[e] = P.wgt[i0 + e];
+    }
+    return q;
 }
 
 bool has_mt(const mpm_protocol *p)
@@ -390,6 +435,48 @@ size_t mpm_footprint_bytes(const mpm_protocol *protocol, const mpm_grid *grid, m
     size_t inputs = (size_t)N * (I * dtype_size(dtype) + 4 /* b1 */ + 16 /* maps */);
     size_t ws = (size_t)N * (mode == MPM_ML ? 0 : map_workspace_floats_per_voxel() * 4) + ((size_t)1 << 20);
     return inputs + ws;
+}
+
+mpm_status mpm_simulate_projected(const mpm_protocol *protocol, const mpm_grid *grid, const mpm_space *spaces,
+                                  const float *maps, const float *b1, const float *noise, mpm_dtype out_dtype,
+                                  void *out, void *stream)
+{
+    clear_error();
+    int64_t N;
+    mpm_status st;
+    if ((st = check_protocol(protocol)) || (st = check_grid(grid, &N)) || (st = check_dtype(out_dtype)) ||
+        (st = check_spaces(protocol, spaces)))
+        return st;
+    if (!maps || !out) return fail(MPM_ERR_INVALID_ARG, "maps and out must be device pointers");
+    const DevProto P = to_dev(protocol);
+    const Grid3 g = make_grid3(grid->nx, grid->ny, grid->nz);
+    hipStream_t s = (hipStream_t)stream;
+    Prof prof(s);
+    LaunchCtx lc{s};
+    hipError_t e = hipSuccess;
+    {
+        Workspace ws(s);
+        int64_t off = 0;  // elements before the contrast's first image
+        for (int c = 0; c < protocol->n_contrasts && e == hipSuccess; c++) {
+            const ProjSpace S = make_proj_space(spaces[c]);
+            const DevProto Pc = sub_proto(P, c);
+            float *Yp = nullptr;
+            if (ws.alloc((void **)&Yp, sizeof(float) * 5 * (size_t)S.M) != hipSuccess)
+                return fail(MPM_ERR_OUT_OF_MEMORY, "simulate: workspace allocation failed");
+            e = prof.launch("proj_pull", (double)S.M * 20.0,
+                            [&] { return launch_proj_pull(s, g, S, maps, b1, Yp, Yp + 4 * S.M); });
+            char *dst = (char *)out + off * (int64_t)dtype_size(out_dtype);
+            const float *nz = noise ? noise + off : nullptr;
+            if (e == hipSuccess)
+                e = prof.launch("simulate", (double)S.M * (20.0 + Pc.I * (dtype_size(out_dtype) + (noise ? 4.0 : 0.0))),
+                                [&] { return launch_simulate(lc, Pc, Yp, Yp + 4 * S.M, nz, out_dtype, dst, S.M); });
+            off += (int64_t)Pc.I * S.M;
+        }
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+    }
+    prof.collect();
+    if (e != hipSuccess) return fail(MPM_ERR_DEVICE, "simulate: %s", hipGetErrorString(e));
+    return MPM_OK;
 }
 
 mpm_status mpm_fit(const mpm_protocol *protocol, const mpm_grid *grid, mpm_dtype dtype, const void *echoes,

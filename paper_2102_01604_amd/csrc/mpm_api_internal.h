@@ -22,6 +22,11 @@ bool has_mt(const mpm_protocol *p);
 DevProto to_dev(const mpm_protocol *p);
 size_t dtype_size(int dtype);
 mpm_status default_init_from_means(const mpm_protocol *p, const double *mean, double b1_mean, float y0[4]);
+// Spatial projection: validation of the spaces, the device protocol restricted
+// to contrast c, and the voxel count of a space.
+mpm_status check_spaces(const mpm_protocol *p, const mpm_space *spaces);
+DevProto sub_proto(const DevProto &P, int c);
+inline int64_t space_voxels(const mpm_space &s) { return s.nx * s.ny * s.nz; }
 
 // Launch wrapper: counts launches and algorithmic bytes per kernel name and,
 // when timing is enabled, brackets sampled launches with events on `stream`.
@@ -57,6 +62,7 @@ struct FitArgs {
     float *maps;
     int64_t N, nx, ny, nz;
     hipStream_t stream;
+    const mpm_space *spaces = nullptr;  // per-contrast acquisition spaces (projected fit) or NULL
 };
 
 mpm_status image_means(Workspace &ws, Prof &prof, const DevProto &P, int dtype, const void *X,

@@ -23,8 +23,29 @@ mpm_status enqueue_init(const FitArgs &a, Workspace &ws, Prof &prof)
     } else {
         std::vector<double> mean;
         double b1m;
-        mpm_status st = image_means(ws, prof, a.P, a.dtype, a.X, a.b1, a.N, mean, b1m);
-        if (st) return st;
+        mpm_status st;
+        if (!a.spaces) {
+            if ((st = image_means(ws, prof, a.P, a.dtype, a.X, a.b1, a.N, mean, b1m))) return st;
+        } else {
+            // projected: each image's mean over its own space; b1 over the reconstruction grid
+            const char *X = (const char *)a.X;
+            double unused;
+            for (int c = 0; c < a.P.C; c++) {
+                const DevProto Pc = sub_proto(a.P, c);
+                const int64_t M = space_voxels(a.spaces[c]);
+                std::vector<double> mc;
+                if ((st = image_means(ws, prof, Pc, a.dtype, X, nullptr, M, mc, unused))) return st;
+                mean.insert(mean.end(), mc.begin(), mc.end());
+                X += (int64_t)Pc.I * M * (int64_t)dtype_size(a.dtype);
+            }
+            b1m = 1.0;
+            if (a.b1) {
+                DevProto none;
+                memset(&none, 0, sizeof(none));
+                std::vector<double> m0;
+                if ((st = image_means(ws, prof, none, a.dtype, nullptr, a.b1, a.N, m0, b1m))) return st;
+            }
+        }
         if ((st = default_init_from_means(a.proto, mean.data(), b1m, y0))) return st;
     }
     LaunchCtx c{a.stream};

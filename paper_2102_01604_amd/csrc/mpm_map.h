@@ -87,6 +87,153 @@ struct MapCtl {
     int accept_more;    // the full step was rejected: evaluate the halvings
 };
 
+// ---------------------------------------------------------------------------
+// Column walk.  A workgroup owns a TILE_X x TILE_Y tile of the x-y plane and
+// the planes [z0, z1); each thread walks its own (x, y) column.  The values
+// at z - 1, z, z + 1 of the thread's own column rotate through registers; the
+// four in-plane neighbours are loaded (they are L2-resident: adjacent tiles of
+// the same z-run are processed by the same XCD at the same time).
+// ---------------------------------------------------------------------------
+struct Col {
+    int x, y, z0, z1;
+    bool act;
+    bool xm, xp, ym, yp;  // in-plane neighbours inside the grid
+    int64_t base;         // voxel index of (x, y, 0)
+    int64_t sxy;          // plane stride
+};
+
+__device__ __forceinline__ Col locate_col(const Grid3 &g)
+{
+    const int L = blockIdx.x, T = gridDim.x;
+    const int q = T >> 3, r = T & 7, j = L & 7;
+    const int lid = j * q + min(j, r) + (L >> 3);  // XCD-contiguous workgroup index
+    const int bx = lid % g.gx;
+    const int t2 = lid / g.gx;
+    const int by = t2 % g.gy;
+    const int bz = t2 / g.gy;
+    Col c;
+    c.x = bx * TILE_X + (threadIdx.x & (TILE_X - 1));
+    c.y = by * g.ty + (threadIdx.x / TILE_X);
+    c.z0 = bz * g.zc;
+    c.z1 = min(c.z0 + g.zc, g.nz);
+    c.act = c.x < g.nx && c.y < g.ny;
+    c.xm = c.x > 0;
+    c.xp = c.x < g.nx - 1;
+    c.ym = c.y > 0;
+    c.yp = c.y < g.ny - 1;
+    c.sxy = (int64_t)g.nx * g.ny;
+    c.base = c.act ? (int64_t)c.x + (int64_t)g.nx * c.y : 0;
+    return c;
+}
+
+template <class Visit>
+__device__ __forceinline__ void for_inplane(const Col &c, int64_t n, int nx, Visit visit)
+{
+    if (c.xm) visit(n - 1);
+    if (c.xp) visit(n + 1);
+    if (c.ym) visit(n - nx);
+    if (c.yp) visit(n + nx);
+}
+
+// ---------------------------------------------------------------------------
+// device helpers shared by the MAP kernels
+// ---------------------------------------------------------------------------
+template <int NV>
+__device__ __forceinline__ void write_partials(double (&v)[NV], double *__restrict__ partials)
+{
+    __shared__ double lds[NV][NWAVE];
+    block_sum<NV>(v, lds);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; k++) partials[(int64_t)k * gridDim.x + blockIdx.x] = v[k];
+    }
+}
+
+// Non-temporal access for arrays that a kernel streams exactly once (no
+// stencil reuse), so they do not evict the stencil operands' halos from L2.
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef float v2f __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ void vload_nt(const float4 *__restrict__ a, int64_t n, float v[4])
+{
+    const v4f t = __builtin_nontemporal_load((const v4f *)(a + n));
+    v[0] = t.x;
+    v[1] = t.y;
+    v[2] = t.z;
+    v[3] = t.w;
+}
+
+__device__ __forceinline__ void vstore_nt(float4 *__restrict__ a, int64_t n, const float v[4])
+{
+    const v4f t = {v[0], v[1], v[2], v[3]};
+    __builtin_nontemporal_store(t, (v4f *)(a + n));
+}
+
+__device__ __forceinline__ void vload(const float4 *__restrict__ a, int64_t n, float v[4])
+{
+    const float4 t = a[n];
+    v[0] = t.x;
+    v[1] = t.y;
+    v[2] = t.z;
+    v[3] = t.w;
+}
+
+__device__ __forceinline__ void vstore(float4 *__restrict__ a, int64_t n, const float v[4])
+{
+    a[n] = make_float4(v[0], v[1], v[2], v[3]);
+}
+
+// packed symmetric index: 0:00 1:01 2:02 3:03 4:11 5:12 6:13 7:22 8:23 9:33
+__device__ __forceinline__ void load_H(const HessArrays &h, int64_t n, float H[10])
+{
+    const v4f d = __builtin_nontemporal_load((const v4f *)(h.d + n));
+    const v4f o = __builtin_nontemporal_load((const v4f *)(h.o + n));
+    const v2f r = __builtin_nontemporal_load((const v2f *)(h.r + n));
+    H[0] = d.x;
+    H[4] = d.y;
+    H[7] = d.z;
+    H[9] = d.w;
+    H[1] = o.x;
+    H[2] = o.y;
+    H[3] = o.z;
+    H[5] = o.w;
+    H[6] = r.x;
+    H[8] = r.y;
+}
+
+__device__ __forceinline__ void store_H(const HessArrays &h, int64_t n, const float H[10])
+{
+    const v4f d = {H[0], H[4], H[7], H[9]};
+    const v4f o = {H[1], H[2], H[3], H[5]};
+    const v2f r = {H[6], H[8]};
+    __builtin_nontemporal_store(d, (v4f *)(h.d + n));
+    __builtin_nontemporal_store(o, (v4f *)(h.o + n));
+    __builtin_nontemporal_store(r, (v2f *)(h.r + n));
+}
+
+// delta_f = delta + alpha_pend p_last at voxel m
+struct DeltaF {
+    const float4 *__restrict__ D;
+    const float4 *__restrict__ Pl;
+    float alpha;
+    bool dvalid;
+    __device__ __forceinline__ void operator()(int64_t m, float v[4]) const
+    {
+        float4 t = dvalid ? D[m] : make_float4(0.f, 0.f, 0.f, 0.f);
+        if (alpha != 0.0f) {
+            const float4 p = Pl[m];
+            t.x += alpha * p.x;
+            t.y += alpha * p.y;
+            t.z += alpha * p.z;
+            t.w += alpha * p.w;
+        }
+        v[0] = t.x;
+        v[1] = t.y;
+        v[2] = t.z;
+        v[3] = t.w;
+    }
+};
+
 enum { FIN_LIK = 0, FIN_A = 1, FIN_B = 2, FIN_ACCEPT = 3, FIN_W = 4, FIN_STATS = 5, FIN_ACCEPT2 = 6 };
 
 struct MapArgs {
@@ -123,7 +270,13 @@ int cg_a_blocks(const MapArgs &a);  // workgroups (partials) of CG sweep A
 int cg_b_blocks(const MapArgs &a);  // ... and of sweep B
 int cg_b_rows();                    // tile rows of sweep B
 int tall_workgroups();
+// Extra partial rows added to a finaliser's sums (the acquisition-space NLL
+// of a projected fit): row k at p + k * stride, cols columns, rows rows.
+struct ExtRows {
+    const double *p = nullptr;
+    int stride = 0, cols = 0, rows = 0;
+};
 hipError_t launch_fin(hipStream_t s, const MapArgs &a, int stage, int arg, int nblk, double cg_stop_rel,
-                      int ntrial, int accept_off);
+                      int ntrial, int accept_off, const ExtRows &ext = ExtRows());
 
 }  // namespace mpm

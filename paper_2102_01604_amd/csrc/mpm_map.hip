@@ -5,7 +5,7 @@
 #include <cstring>
 
 #include "mpm_api_internal.h"
-#include "mpm_map.h"
+#include "mpm_proj.h"
 
 namespace mpm {
 
@@ -79,6 +79,64 @@ static void set_prior(const mpm_options *o, MapArgs &m, bool use_lambda, int &pr
 }
 
 // ---------------------------------------------------------------------------
+// Spatial projection (paper Sec. 2.4): per contrast its space, protocol, first
+// image and acquisition-space blocks; the pushed gradient and Hessian on the
+// reconstruction grid; extra partial rows carrying the acquisition-space NLL.
+// ---------------------------------------------------------------------------
+struct ProjState {
+    int C = 0;
+    ProjContrast pc[MAXC];
+    ProjPushArgs push;
+    float4 *G = nullptr;
+    double *ext = nullptr;
+    int ext_stride = 0;
+    PushedProto pp;
+    ExtRows rows(int n) const
+    {
+        ExtRows r;
+        r.p = ext;
+        r.stride = ext_stride;
+        r.cols = ext_stride;
+        r.rows = n;
+        return r;
+    }
+};
+
+static mpm_status alloc_proj(const FitArgs &a, Workspace &ws, ProjState &ps, HessArrays Hrecon)
+{
+    ps.C = a.P.C;
+    memset(&ps.push, 0, sizeof(ps.push));
+    ps.push.C = ps.C;
+    const char *X = (const char *)a.X;
+    int col = 0;
+    for (int c = 0; c < ps.C; c++) {
+        ProjContrast &pc = ps.pc[c];
+        pc.S = make_proj_space(a.spaces[c]);
+        pc.P = sub_proto(a.P, c);
+        pc.X = X;
+        X += (int64_t)pc.P.I * pc.S.M * (int64_t)dtype_size(a.dtype);
+        float4 *buf = nullptr;  // g, H d, H o (float4 each), H r (float2) per acquisition voxel
+        if (ws.alloc((void **)&buf, (size_t)pc.S.M * 56) != hipSuccess)
+            return fail(MPM_ERR_OUT_OF_MEMORY, "projection workspace allocation failed");
+        pc.B.G = buf;
+        pc.B.H.d = buf + pc.S.M;
+        pc.B.H.o = buf + 2 * pc.S.M;
+        pc.B.H.r = (float2 *)(buf + 3 * pc.S.M);
+        pc.ext_col = col;
+        col += proj_blocks(pc.S.M);
+        ps.push.S[c] = pc.S;
+        ps.push.B[c] = pc.B;
+    }
+    ps.ext_stride = col;
+    if (ws.alloc((void **)&ps.ext, sizeof(double) * MAX_TRIALS * (size_t)col) != hipSuccess ||
+        ws.alloc((void **)&ps.G, sizeof(float4) * (size_t)a.N) != hipSuccess)
+        return fail(MPM_ERR_OUT_OF_MEMORY, "projection workspace allocation failed");
+    ps.pp.G = ps.G;
+    ps.pp.H = Hrecon;
+    return MPM_OK;
+}
+
+// ---------------------------------------------------------------------------
 // MAP fit as a job: piece 0 initialises (maps, control block, w = 0); then
 // one piece per Newton-like step (preceded by the weight refresh at the start
 // of each outer loop after the first); the last piece refreshes the weights
@@ -96,11 +154,28 @@ struct MapJob : FitJob {
     int t = 0, j = 0;  // next Newton-like step
     bool started = false, finished = false;
     PinnedBuf host;    // MapCtl followed by the trace
+    bool proj = false;      // spatial projection
+    bool ml_as_map = false; // projected ML: one outer loop, no prior, one CG iteration, every step taken
+    mpm_options opt_local;
+    ProjState ps;
 
     MapJob(const FitArgs &a_, Workspace &ws_, Prof &prof_) : a(a_), ws(ws_), prof(prof_) { memset(&m, 0, sizeof(m)); }
 
     mpm_status setup()
     {
+        proj = a.spaces != nullptr;
+        if (proj && a.opt->mode == MPM_ML) {
+            // y - P~^{-1} g: with no prior the preconditioner is the system
+            // matrix, so one CG iteration solves it exactly
+            ml_as_map = true;
+            opt_local = *a.opt;
+            opt_local.mode = MPM_MAP_JTV;
+            opt_local.n_outer = 1;
+            opt_local.n_cg = 1;
+            opt_local.max_halvings = -1;
+            for (int k = 0; k < 4; k++) opt_local.lambda[k] = 0.0;
+            a.opt = &opt_local;
+        }
         const mpm_options *o = a.opt;
         T = o->n_outer;
         J = o->n_gn;
@@ -118,12 +193,42 @@ struct MapJob : FitJob {
         nb_pl = grid_blocks(m.gp);
         nb_cga = cg_a_blocks(m);
         nb_cgb = cg_b_blocks(m);
+        if (proj) return alloc_proj(a, ws, ps, m.H);
         return MPM_OK;
     }
 
-    hipError_t fin(int stage, int arg, int nblk)
+    hipError_t fin(int stage, int arg, int nblk, const ExtRows &ext = ExtRows())
     {
-        return launch_fin(a.stream, m, stage, arg, nblk, a.opt->cg_stop, ntrial, accept_off);
+        return launch_fin(a.stream, m, stage, arg, nblk, a.opt->cg_stop, ntrial, accept_off, ext);
+    }
+
+    // acquisition-space likelihood of every contrast, then the push
+    hipError_t proj_lik_push(int gated)
+    {
+        const hipStream_t s = a.stream;
+        hipError_t e = hipSuccess;
+        for (int c = 0; c < ps.C && e == hipSuccess; c++) {
+            const ProjContrast &pc = ps.pc[c];
+            e = prof.launch("proj_lik", (double)pc.S.M * (pc.P.I * dtype_size(a.dtype) + 16 + 4 + 56),
+                            [&] { return launch_proj_lik(s, m, pc, ps.ext, gated); });
+        }
+        double pushed = 0.0;
+        for (int c = 0; c < ps.C; c++) pushed += (double)ps.pc[c].S.M * 56;
+        if (e == hipSuccess)
+            e = prof.launch("proj_push", pushed + (double)a.N * 56,
+                            [&] { return launch_proj_push(s, m, ps.push, ps.G, ps.pp.H); });
+        return e;
+    }
+
+    hipError_t proj_nll(int h0, int h1)
+    {
+        hipError_t e = hipSuccess;
+        for (int c = 0; c < ps.C && e == hipSuccess; c++) {
+            const ProjContrast &pc = ps.pc[c];
+            e = prof.launch("proj_nll", (double)pc.S.M * (pc.P.I * dtype_size(a.dtype) + 16 + 4 + 32),
+                            [&] { return launch_proj_nll(a.stream, m, pc, ps.ext, ps.ext_stride, h0, h1); });
+        }
+        return e;
     }
 
     mpm_status enqueue_next(bool *more) override
@@ -148,8 +253,14 @@ struct MapJob : FitJob {
                 RUN("jtv_weights", N * 20.0, launch_weights(s, m, prior_on));
                 RUN("fin", 0.0, fin(FIN_W, (t - 1) * S + J + 1, nb_col));
             }
-            RUN("map_lik", N * (xb + bb + 16 + 4 + 40 + 16 + 16), launch_lik(s, m));
-            RUN("fin", 0.0, fin(FIN_LIK, j == 0 ? t * S : -1, nb_pl));
+            if (!proj) {
+                RUN("map_lik", N * (xb + bb + 16 + 4 + 40 + 16 + 16), launch_lik(s, m));
+                RUN("fin", 0.0, fin(FIN_LIK, j == 0 ? t * S : -1, nb_pl));
+            } else {
+                if (e == hipSuccess) e = proj_lik_push(1);
+                RUN("map_lik", N * (16 + 40 + 16 + 4 + 40 + 16 + 16), launch_lik_pushed(s, m, ps.pp));
+                RUN("fin", 0.0, fin(FIN_LIK, j == 0 ? t * S : -1, nb_pl, ps.rows(1)));
+            }
             for (int i = 0; i < K && e == hipSuccess; i++) {
                 double ab = 16 + (i > 0 ? 16 : 0) + 40 + 4 + 16 + (i == 1 ? 16 : i >= 2 ? 32 : 0);
                 RUN("cg_a", N * ab, launch_cg_a(s, m, i));
@@ -157,12 +268,22 @@ struct MapJob : FitJob {
                 RUN("cg_b", N * (16 + 4 + 40 + 32 + 16), launch_cg_b(s, m, i));
                 RUN("fin", 0.0, fin(FIN_B, i, nb_cgb));
             }
-            RUN("map_accept", N * (xb + bb + 16 + 16 + 16 + 4), launch_accept(s, m));
-            RUN("fin", 0.0, fin(FIN_ACCEPT, t * S + j + 1, nb_pl));
-            if (ntrial > 1) {
-                // runs only when the full step was rejected (device flag)
-                RUN("map_accept2", 0.0, launch_accept2(s, m, ntrial));
-                RUN("fin", 0.0, fin(FIN_ACCEPT2, t * S + j + 1, nb_col));
+            if (!proj) {
+                RUN("map_accept", N * (xb + bb + 16 + 16 + 16 + 4), launch_accept(s, m));
+                RUN("fin", 0.0, fin(FIN_ACCEPT, t * S + j + 1, nb_pl));
+                if (ntrial > 1) {
+                    // runs only when the full step was rejected (device flag)
+                    RUN("map_accept2", 0.0, launch_accept2(s, m, ntrial));
+                    RUN("fin", 0.0, fin(FIN_ACCEPT2, t * S + j + 1, nb_col));
+                }
+            } else {
+                if (e == hipSuccess) e = proj_nll(0, 1);
+                RUN("map_accept", N * (16 + 16 + 16 + 4), launch_accept_pushed(s, m, ps.pp));
+                RUN("fin", 0.0, fin(FIN_ACCEPT, t * S + j + 1, nb_pl, ps.rows(1)));
+                if (ntrial > 1) {
+                    if (e == hipSuccess) e = proj_nll(1, ntrial);
+                    RUN("fin", 0.0, fin(FIN_ACCEPT2, t * S + j + 1, 0, ps.rows(ntrial)));
+                }
             }
             RUN("map_update", N * 64.0, launch_update(s, m));
             if (++j == J) {
@@ -178,8 +299,14 @@ struct MapJob : FitJob {
             // final weights (objective and report), then statistics at the final maps
             RUN("jtv_weights", N * 20.0, launch_weights(s, m, prior_on));
             RUN("fin", 0.0, fin(FIN_W, T >= 1 ? (T - 1) * S + J + 1 : -1, nb_col));
-            RUN("map_final", N * (xb + bb + 16 + 4), launch_final(s, m, nullptr, nullptr));
-            RUN("fin", 0.0, fin(FIN_STATS, 0, nb_pl));
+            if (!proj) {
+                RUN("map_final", N * (xb + bb + 16 + 4), launch_final(s, m, nullptr, nullptr));
+                RUN("fin", 0.0, fin(FIN_STATS, 0, nb_pl));
+            } else {
+                if (e == hipSuccess) e = proj_lik_push(0);
+                RUN("map_final", N * (16 + 40 + 16 + 4), launch_final_pushed(s, m, ps.pp, nullptr, nullptr));
+                RUN("fin", 0.0, fin(FIN_STATS, 0, nb_pl, ps.rows(1)));
+            }
             if (e == hipSuccess) e = hipMemcpyAsync(host.p, m.ctl, sizeof(MapCtl), hipMemcpyDeviceToHost, s);
             if (e == hipSuccess && tl > 0)
                 e = hipMemcpyAsync((char *)host.p + sizeof(MapCtl), m.trace, sizeof(double) * tl,
@@ -202,7 +329,7 @@ struct MapJob : FitJob {
         rep.nll = h.nll_final;
         rep.jtv = prior_on ? h.jtv : 0.0;
         rep.objective = rep.nll + rep.jtv;
-        rep.outer_done = T;
+        rep.outer_done = ml_as_map ? 0 : T;
         rep.gn_done = h.gn_done;
         rep.cg_done = h.cg_done;
         rep.rejected = h.rejected;
@@ -224,18 +351,19 @@ std::unique_ptr<FitJob> make_map_job(const FitArgs &a, Workspace &ws, Prof &prof
 
 using namespace mpm;
 
-extern "C" mpm_status mpm_uncertainty(const mpm_protocol *protocol, const mpm_grid *grid, mpm_dtype dtype,
-                                      const void *echoes, const float *b1, const mpm_options *opt,
-                                      const float *maps, float *var, float *moments, void *stream)
+static mpm_status uncertainty_impl(const mpm_protocol *protocol, const mpm_grid *grid, const mpm_space *spaces,
+                                   mpm_dtype dtype, const void *echoes, const float *b1, const mpm_options *opt,
+                                   const float *maps, float *var, float *moments, void *stream)
 {
     clear_error();
     int64_t N;
     mpm_status st;
     if ((st = check_protocol(protocol)) || (st = check_grid(grid, &N)) || (st = check_dtype(dtype))) return st;
+    if (spaces && (st = check_spaces(protocol, spaces))) return st;
     if (!opt) return fail(MPM_ERR_INVALID_ARG, "options is NULL");
     if (!echoes || !maps || !var) return fail(MPM_ERR_INVALID_ARG, "echoes, maps and var must be device pointers");
     if (opt->mode != MPM_ML && opt->mode != MPM_MAP_JTV) return fail(MPM_ERR_INVALID_ARG, "unknown mode %d", opt->mode);
-    if (opt->loading != MPM_LOAD_PROPOSED && opt->loading != MPM_LOAD_GN)
+    if (opt->loading != MPM_LOAD_PROPOSED && opt->loading != MPM_LOAD_GN && opt->loading != MPM_LOAD_PROPOSED_PLUS)
         return fail(MPM_ERR_INVALID_ARG, "unknown loading %d", opt->loading);
     for (int k = 0; k < 4; k++)
         if (!(opt->lambda[k] >= 0.0) || !std::isfinite(opt->lambda[k]))
@@ -244,7 +372,7 @@ extern "C" mpm_status mpm_uncertainty(const mpm_protocol *protocol, const mpm_gr
     if (!has_mt(protocol)) return fail(MPM_ERR_UNSUPPORTED, "the four-parameter model needs at least one MT contrast");
     hipStream_t s = (hipStream_t)stream;
     FitArgs a{protocol, to_dev(protocol), dtype, echoes, b1, opt, const_cast<float *>(maps), N,
-              grid->nx, grid->ny, grid->nz, s};
+              grid->nx, grid->ny, grid->nz, s, spaces};
     {
         Workspace ws(s);
         Prof prof(s);
@@ -263,14 +391,84 @@ extern "C" mpm_status mpm_uncertainty(const mpm_protocol *protocol, const mpm_gr
             return fail(MPM_ERR_OUT_OF_MEMORY, "uncertainty workspace allocation failed");
         int prior_on;
         set_prior(opt, m, opt->mode == MPM_MAP_JTV, prior_on);
+        ProjState ps;
+        if (spaces) {
+            float4 *hb = nullptr;  // pushed Hessian blocks
+            if (ws.alloc((void **)&hb, (size_t)N * 40) != hipSuccess)
+                return fail(MPM_ERR_OUT_OF_MEMORY, "uncertainty workspace allocation failed");
+            HessArrays Hr{hb, hb + N, (float2 *)(hb + 2 * N)};
+            if ((st = alloc_proj(a, ws, ps, Hr))) return st;
+        }
         const double xb = (double)a.P.I * dtype_size(dtype), bb = b1 ? 4.0 : 0.0;
         hipError_t e = prof.launch("jtv_weights", (double)N * 20.0, [&] { return launch_weights(s, m, prior_on); });
-        if (e == hipSuccess)
-            e = prof.launch("uncertainty", (double)N * (xb + bb + 16 + 4 + 16 + (moments ? 16 : 0)),
-                            [&] { return launch_final(s, m, var, moments); });
+        if (!spaces) {
+            if (e == hipSuccess)
+                e = prof.launch("uncertainty", (double)N * (xb + bb + 16 + 4 + 16 + (moments ? 16 : 0)),
+                                [&] { return launch_final(s, m, var, moments); });
+        } else {
+            for (int c = 0; c < ps.C && e == hipSuccess; c++)
+                e = prof.launch("proj_lik", (double)ps.pc[c].S.M * (ps.pc[c].P.I * dtype_size(dtype) + 76),
+                                [&] { return launch_proj_lik(s, m, ps.pc[c], ps.ext, 0); });
+            if (e == hipSuccess)
+                e = prof.launch("proj_push", (double)N * 56,
+                                [&] { return launch_proj_push(s, m, ps.push, ps.G, ps.pp.H); });
+            if (e == hipSuccess)
+                e = prof.launch("uncertainty", (double)N * (56 + 4 + 16 + (moments ? 16 : 0)),
+                                [&] { return launch_final_pushed(s, m, ps.pp, var, moments); });
+        }
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         prof.collect();
         if (e != hipSuccess) return fail(MPM_ERR_DEVICE, "uncertainty: %s", hipGetErrorString(e));
     }
+    return MPM_OK;
+}
+
+extern "C" mpm_status mpm_uncertainty(const mpm_protocol *protocol, const mpm_grid *grid, mpm_dtype dtype,
+                                      const void *echoes, const float *b1, const mpm_options *opt,
+                                      const float *maps, float *var, float *moments, void *stream)
+{
+    return uncertainty_impl(protocol, grid, nullptr, dtype, echoes, b1, opt, maps, var, moments, stream);
+}
+
+extern "C" mpm_status mpm_uncertainty_projected(const mpm_protocol *protocol, const mpm_grid *grid,
+                                                const mpm_space *spaces, mpm_dtype dtype, const void *echoes,
+                                                const float *b1, const mpm_options *opt, const float *maps,
+                                                float *var, float *moments, void *stream)
+{
+    clear_error();
+    if (!spaces) return fail(MPM_ERR_INVALID_ARG, "spaces is NULL");
+    return uncertainty_impl(protocol, grid, spaces, dtype, echoes, b1, opt, maps, var, moments, stream);
+}
+
+extern "C" mpm_status mpm_fit_projected(const mpm_protocol *protocol, const mpm_grid *grid, const mpm_space *spaces,
+                                        mpm_dtype dtype, const void *echoes, const float *b1,
+                                        const mpm_options *opt, float *maps, mpm_report *report, double *trace,
+                                        int32_t trace_len, void *stream)
+{
+    clear_error();
+    int64_t N;
+    mpm_status st = check_fit_args(protocol, grid, dtype, echoes, opt, maps, &N);
+    if (st) return st;
+    if ((st = check_spaces(protocol, spaces))) return st;
+    if (trace_len < 0 || (trace_len > 0 && !trace)) return fail(MPM_ERR_INVALID_ARG, "trace is NULL");
+    for (int i = 0; i < trace_len; i++) trace[i] = NAN;
+    hipStream_t s = (hipStream_t)stream;
+    FitArgs a{protocol, to_dev(protocol), dtype, echoes, b1, opt, maps, N, grid->nx, grid->ny, grid->nz, s, spaces};
+    mpm_report rep;
+    memset(&rep, 0, sizeof(rep));
+    {
+        Workspace ws(s);
+        Prof prof(s);
+        std::unique_ptr<FitJob> job = make_map_job(a, ws, prof, &st);
+        if (st) return st;
+        bool more = true;
+        while (more)
+            if ((st = job->enqueue_next(&more))) return st;
+        hipError_t e = hipStreamSynchronize(s);
+        prof.collect();
+        if (e != hipSuccess) return fail(MPM_ERR_DEVICE, "fit: %s", hipGetErrorString(e));
+        if ((st = job->collect(rep, trace, trace_len))) return st;
+    }
+    if (report) *report = rep;
     return MPM_OK;
 }

@@ -41,7 +41,7 @@ def test_struct_layouts_match_header(tmp_path):
     import subprocess
     structs = {"mpm_protocol": _lib.mpm_protocol, "mpm_grid": _lib.mpm_grid, "mpm_options": _lib.mpm_options,
                "mpm_report": _lib.mpm_report, "mpm_kernel_stat": _lib.mpm_kernel_stat,
-               "mpm_request": _lib.mpm_request}
+               "mpm_request": _lib.mpm_request, "mpm_space": _lib.mpm_space}
     rename = {"lam": "lambda"}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "mpm.h"', "int main(void){"]
     for name, cls in structs.items():
@@ -105,6 +105,29 @@ def test_unknown_loading_and_oversized_grid_rejected(lib):
     # byte offsets into one image are 32-bit in the kernels: N < 2^30
     st = _fit_raw(lib, proto, [1024, 1024, 1024], {"mode": "ml", "n_gn": 5})
     assert st == 1 and "2^30" in lib.mpm_last_error().decode()
+
+
+def test_projected_argument_validation(lib):
+    """Spaces are checked on the host before any device work."""
+    proto = synth.protocol()
+    proto["sigma"] = [1.0] * 22
+    eye = [[1, 0, 0, 0], [0, 1, 0, 0], [0, 0, 1, 0]]
+
+    def run(spaces):
+        rep = _lib.mpm_report()
+        return lib.mpm_fit_projected(C.byref(_lib.make_protocol(proto)), C.byref(_lib.make_grid([8, 8, 8])),
+                                     None if spaces is None else _lib.make_spaces(spaces), 0, C.c_void_p(16), None,
+                                     C.byref(_lib.make_options({"mode": "map", "n_gn": 2})), C.c_void_p(16),
+                                     C.byref(rep), None, 0, None)
+    ok = {"dims": (8, 8, 8), "affine": eye}
+    assert run(None) == 1
+    for bad, what in (({"dims": (0, 8, 8), "affine": eye}, "axis"),
+                      ({"dims": (8, 8, 8), "affine": [[1, 0, 0, 0], [0, 1, 0, 0], [0, 0, float("nan"), 0]]}, "finite"),
+                      ({"dims": (8, 8, 8), "affine": [[20, 0, 0, 0], [0, 1, 0, 0], [0, 0, 1, 0]]}, "length"),
+                      ({"dims": (8, 8, 8), "affine": [[1, 0, 0, 0], [1, 0, 0, 0], [0, 0, 1, 0]]}, "length"),
+                      ({"dims": (8, 8, 8), "affine": [[1, 1, 0, 0], [1, 1, 0, 0], [0, 0, 1, 0]]}, "singular")):
+        st = run([ok, bad, ok])
+        assert st == 1 and what in lib.mpm_last_error().decode(), (what, lib.mpm_last_error())
 
 
 def test_null_pointers_rejected(lib):
