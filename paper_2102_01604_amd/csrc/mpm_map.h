@@ -183,12 +183,10 @@ __device__ __forceinline__ void vstore(float4 *__restrict__ a, int64_t n, const 
     a[n] = make_float4(v[0], v[1], v[2], v[3]);
 }
 
-// packed symmetric index: 0:00 1:01 2:02 3:03 4:11 5:12 6:13 7:22 8:23 9:33
-__device__ __forceinline__ void load_H(const HessArrays &h, int64_t n, float H[10])
+// packed symmetric index: 0:00 1:01 2:02 3:03 4:11 5:12 6:13 7:22 8:23 9:33;
+// stored as d = (00, 11, 22, 33), o = (01, 02, 03, 12), r = (13, 23)
+__device__ __forceinline__ void unpack_H(const v4f d, const v4f o, const v2f r, float H[10])
 {
-    const v4f d = __builtin_nontemporal_load((const v4f *)(h.d + n));
-    const v4f o = __builtin_nontemporal_load((const v4f *)(h.o + n));
-    const v2f r = __builtin_nontemporal_load((const v2f *)(h.r + n));
     H[0] = d.x;
     H[4] = d.y;
     H[7] = d.z;
@@ -199,6 +197,20 @@ __device__ __forceinline__ void load_H(const HessArrays &h, int64_t n, float H[1
     H[5] = o.w;
     H[6] = r.x;
     H[8] = r.y;
+}
+
+__device__ __forceinline__ void load_H(const HessArrays &h, int64_t n, float H[10])
+{
+    unpack_H(__builtin_nontemporal_load((const v4f *)(h.d + n)), __builtin_nontemporal_load((const v4f *)(h.o + n)),
+             __builtin_nontemporal_load((const v2f *)(h.r + n)), H);
+}
+
+// Cached load, for blocks that several threads gather (the projection's push).
+__device__ __forceinline__ void load_H_cached(const HessArrays &h, int64_t n, float H[10])
+{
+    const float4 d = h.d[n], o = h.o[n];
+    const float2 r = h.r[n];
+    unpack_H(v4f{d.x, d.y, d.z, d.w}, v4f{o.x, o.y, o.z, o.w}, v2f{r.x, r.y}, H);
 }
 
 __device__ __forceinline__ void store_H(const HessArrays &h, int64_t n, const float H[10])

@@ -91,6 +91,8 @@ struct ProjState {
     double *ext = nullptr;
     int ext_stride = 0;
     PushedProto pp;
+    PsiT psi{nullptr, nullptr};  // stored Psi^T (fits: pushed every Newton step)
+    int64_t *scan_tmp = nullptr;
     ExtRows rows(int n) const
     {
         ExtRows r;
@@ -102,7 +104,7 @@ struct ProjState {
     }
 };
 
-static mpm_status alloc_proj(const FitArgs &a, Workspace &ws, ProjState &ps, HessArrays Hrecon)
+static mpm_status alloc_proj(const FitArgs &a, Workspace &ws, ProjState &ps, HessArrays Hrecon, bool store_psi)
 {
     ps.C = a.P.C;
     memset(&ps.push, 0, sizeof(ps.push));
@@ -123,7 +125,7 @@ static mpm_status alloc_proj(const FitArgs &a, Workspace &ws, ProjState &ps, Hes
         pc.B.H.o = buf + 2 * pc.S.M;
         pc.B.H.r = (float2 *)(buf + 3 * pc.S.M);
         pc.ext_col = col;
-        col += proj_blocks(pc.S.M);
+        col += proj_blocks(pc.S);
         ps.push.S[c] = pc.S;
         ps.push.B[c] = pc.B;
     }
@@ -133,6 +135,15 @@ static mpm_status alloc_proj(const FitArgs &a, Workspace &ws, ProjState &ps, Hes
         return fail(MPM_ERR_OUT_OF_MEMORY, "projection workspace allocation failed");
     ps.pp.G = ps.G;
     ps.pp.H = Hrecon;
+    if (store_psi) {
+        int64_t cap = 0;  // each acquisition voxel has at most 8 nonzero weights
+        for (int c = 0; c < ps.C; c++) cap += 8 * ps.pc[c].S.M;
+        const int64_t rows = (int64_t)ps.C * a.N;
+        if (ws.alloc((void **)&ps.psi.row, sizeof(int64_t) * (size_t)(rows + 1)) != hipSuccess ||
+            ws.alloc((void **)&ps.psi.ent, sizeof(int2) * (size_t)cap) != hipSuccess ||
+            ws.alloc((void **)&ps.scan_tmp, sizeof(int64_t) * (size_t)psi_scan_blocks(rows)) != hipSuccess)
+            return fail(MPM_ERR_OUT_OF_MEMORY, "projection workspace allocation failed");
+    }
     return MPM_OK;
 }
 
@@ -193,7 +204,7 @@ struct MapJob : FitJob {
         nb_pl = grid_blocks(m.gp);
         nb_cga = cg_a_blocks(m);
         nb_cgb = cg_b_blocks(m);
-        if (proj) return alloc_proj(a, ws, ps, m.H);
+        if (proj) return alloc_proj(a, ws, ps, m.H, true);
         return MPM_OK;
     }
 
@@ -212,11 +223,14 @@ struct MapJob : FitJob {
             e = prof.launch("proj_lik", (double)pc.S.M * (pc.P.I * dtype_size(a.dtype) + 16 + 4 + 56),
                             [&] { return launch_proj_lik(s, m, pc, ps.ext, gated); });
         }
+        // algorithmic bytes: the blocks of every acquisition voxel once, the
+        // stored Psi^T (row pointers, 8 B per entry at 8 entries per
+        // acquisition voxel) and the pushed blocks
         double pushed = 0.0;
-        for (int c = 0; c < ps.C; c++) pushed += (double)ps.pc[c].S.M * 56;
+        for (int c = 0; c < ps.C; c++) pushed += (double)ps.pc[c].S.M * (56 + 64) + (double)a.N * 8;
         if (e == hipSuccess)
             e = prof.launch("proj_push", pushed + (double)a.N * 56,
-                            [&] { return launch_proj_push(s, m, ps.push, ps.G, ps.pp.H); });
+                            [&] { return launch_proj_push_csr(s, m, ps.push, ps.psi, ps.G, ps.pp.H); });
         return e;
     }
 
@@ -248,6 +262,7 @@ struct MapJob : FitJob {
             e = launch_ctl_init(s, m.ctl, m.trace, tl);
             LaunchCtx c{s};
             if (e == hipSuccess) e = launch_fill(c, m.w, a.N, 0.0f);
+            if (proj) RUN("psi_build", 0.0, launch_psi_build(s, m.g, ps.push, ps.psi, ps.scan_tmp));
         } else if (t < T && J > 0) {
             if (j == 0 && t >= 1) {
                 RUN("jtv_weights", N * 20.0, launch_weights(s, m, prior_on));
@@ -397,7 +412,7 @@ static mpm_status uncertainty_impl(const mpm_protocol *protocol, const mpm_grid 
             if (ws.alloc((void **)&hb, (size_t)N * 40) != hipSuccess)
                 return fail(MPM_ERR_OUT_OF_MEMORY, "uncertainty workspace allocation failed");
             HessArrays Hr{hb, hb + N, (float2 *)(hb + 2 * N)};
-            if ((st = alloc_proj(a, ws, ps, Hr))) return st;
+            if ((st = alloc_proj(a, ws, ps, Hr, false))) return st;
         }
         const double xb = (double)a.P.I * dtype_size(dtype), bb = b1 ? 4.0 : 0.0;
         hipError_t e = prof.launch("jtv_weights", (double)N * 20.0, [&] { return launch_weights(s, m, prior_on); });

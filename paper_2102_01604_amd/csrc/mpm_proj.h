@@ -13,6 +13,8 @@
 // Psi^T P~ Psi (rows of Psi sum to 1).
 #pragma once
 
+#include <cmath>
+
 #include "../../include/mpm.h"
 #include "mpm_map.h"
 
@@ -23,6 +25,7 @@ struct ProjSpace {
     int64_t M;        // mx * my * mz
     double A[12];     // acquisition index -> reconstruction coordinates (row-major 3x4)
     double Ainv[12];  // reconstruction coordinates -> acquisition index
+    double rA0[3];    // 1 / A[d][0], or 0 where |A[d][0]| < 1e-12 (no bound on i from axis d)
 };
 
 // Host: the space with its inverse affine (validated invertible beforehand).
@@ -47,6 +50,7 @@ inline ProjSpace make_proj_space(const mpm_space &sp)
         for (int c = 0; c < 3; c++) S.Ainv[4 * r + c] = inv[3 * r + c];
         S.Ainv[4 * r + 3] = -(inv[3 * r] * a[3] + inv[3 * r + 1] * a[7] + inv[3 * r + 2] * a[11]);
     }
+    for (int d = 0; d < 3; d++) S.rA0[d] = std::fabs(a[4 * d]) < 1e-12 ? 0.0 : 1.0 / a[4 * d];
     return S;
 }
 
@@ -137,9 +141,23 @@ hipError_t launch_proj_lik(hipStream_t s, const MapArgs &m, const ProjContrast &
 // after the full step was rejected.
 hipError_t launch_proj_nll(hipStream_t s, const MapArgs &m, const ProjContrast &pc, double *ext, int ext_stride,
                            int h0, int h1);
-int proj_blocks(int64_t M);  // workgroups (partial columns) of one contrast's launch
+// Column grid of an acquisition space; its workgroups are the partial columns
+// of one contrast's launch.
+inline Grid3 proj_grid(const ProjSpace &S) { return make_grid3(S.mx, S.my, S.mz); }
+int proj_blocks(const ProjSpace &S);
 // Reconstruction space: gather every contrast's blocks -> G [N], H.
 hipError_t launch_proj_push(hipStream_t s, const MapArgs &m, const ProjPushArgs &pa, float4 *G, HessArrays H);
+// Psi^T stored by reconstruction voxel: rows ci * N + n (contrast-major),
+// row pointers row[0 .. C N], entries (m, bits of w) in the order of the
+// direct push; at most 8 entries per acquisition voxel.
+struct PsiT {
+    int64_t *row;
+    int2 *ent;
+};
+int64_t psi_scan_blocks(int64_t rows);  // scratch int64 values of the build's scan
+hipError_t launch_psi_build(hipStream_t s, const Grid3 &g, const ProjPushArgs &pa, const PsiT &psi, int64_t *scan_tmp);
+hipError_t launch_proj_push_csr(hipStream_t s, const MapArgs &m, const ProjPushArgs &pa, const PsiT &psi, float4 *G,
+                                HessArrays H);
 // Pulled maps [4][M] and b1 [M] (NaN outside the field of view).
 hipError_t launch_proj_pull(hipStream_t s, const Grid3 &g, const ProjSpace &S, const float *Y, const float *b1,
                             float *Yp, float *bp);

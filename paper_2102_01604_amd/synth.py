@@ -98,6 +98,28 @@ def noise(n_images, n, rng):
     return rng.standard_normal((n_images, n), dtype=np.float32)
 
 
+def rigid_space(recon_dims, acq_dims, rng, rot_deg=2.0, shift=1.5):
+    """An acquisition space moved by a seeded rigid motion relative to the
+    reconstruction grid (subject motion between contrasts, Sec. 2.4): rotation
+    angles uniform in +-rot_deg about each axis, composed about the centre of
+    the reconstruction grid, and a translation uniform in +-shift voxels per
+    axis.  Returns {"dims": acq_dims, "affine": 3x4 array} mapping acquisition
+    voxel indices to reconstruction-grid coordinates."""
+    a, b, c = np.deg2rad(rng.uniform(-rot_deg, rot_deg, 3))
+    Rx = np.array([[1, 0, 0], [0, np.cos(a), -np.sin(a)], [0, np.sin(a), np.cos(a)]])
+    Ry = np.array([[np.cos(b), 0, np.sin(b)], [0, 1, 0], [-np.sin(b), 0, np.cos(b)]])
+    Rz = np.array([[np.cos(c), -np.sin(c), 0], [np.sin(c), np.cos(c), 0], [0, 0, 1]])
+    R = Rz @ Ry @ Rx
+    centre_r = (np.asarray(recon_dims, dtype=np.float64) - 1) / 2
+    centre_a = (np.asarray(acq_dims, dtype=np.float64) - 1) / 2
+    t = centre_r - R @ centre_a + rng.uniform(-shift, shift, 3)
+    return {"dims": tuple(int(v) for v in acq_dims), "affine": np.hstack([R, t[:, None]])}
+
+
+def identity_space(dims):
+    return {"dims": tuple(int(v) for v in dims), "affine": np.hstack([np.eye(3), np.zeros((3, 1))])}
+
+
 # --------------------------------------------------------------------------
 # Named workloads.  Shapes are (nx, ny, nz); arrays are flat with x fastest.
 # --------------------------------------------------------------------------

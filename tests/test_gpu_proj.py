@@ -22,17 +22,26 @@ def torch_cuda():
     return torch
 
 
-def _problem(orc, dims=(20, 18, 10), seed=61):
+def _problem(orc, dims=(20, 18, 10), seed=61, fine=False):
     """Three contrasts: the reconstruction grid itself, and two grids moved by a
     rigid motion (one with an extra row and a slice less); echoes simulated by
-    the oracle on the pulled maps and b1, rounded to FP32."""
+    the oracle on the pulled maps and b1, rounded to FP32.  fine: the third
+    grid has 0.55x the voxel size (and is rotated by up to 20 degrees), so the
+    push gathers more acquisition voxels per workgroup tile than its LDS
+    buffer holds and reads them from global memory."""
     rng = np.random.default_rng(seed)
     c = synth.make_case("map_brain", dims=dims, seed=seed)
     c["b1"] = f32(c["b1"])
     centre = (np.asarray(dims) - 1) / 2
+    if fine:
+        md = tuple(int(d / 0.55) + 6 for d in dims)
+        A = _affine(rng, 20.0, 0.7, scale=(0.55, 0.55, 0.55))
+        A[:, 3] = centre - A[:, :3] @ ((np.asarray(md) - 1) / 2) + rng.uniform(-0.7, 0.7, 3)  # centred, covers the FOV
+        third = _space(md, A)
+    else:
+        third = _space((dims[0] + 1, dims[1], dims[2] - 1), _affine(rng, 3.0, 0.7, centre=centre))
     spaces = [_identity(dims),
-              _space((dims[0], dims[1] + 1, dims[2]), _affine(rng, 3.0, 0.7, centre=centre)),
-              _space((dims[0] + 1, dims[1], dims[2] - 1), _affine(rng, 3.0, 0.7, centre=centre))]
+              _space((dims[0], dims[1] + 1, dims[2]), _affine(rng, 3.0, 0.7, centre=centre)), third]
     xs = []
     for ci, sp in enumerate(spaces):
         yp = np.stack([orc.pull(dims, sp, c["truth"][k]) for k in range(4)])
@@ -107,6 +116,14 @@ def test_projected_fit_parity(torch_cuda, orc, mode, loading):
     opts = (dict(c["opts"], n_outer=3, n_gn=3, n_cg=10) if mode == "map" else {"mode": "ml", "n_gn": 12})
     opts.update(init="const", init_const=[float(v) for v in y0], loading=loading)
     _compare(orc, torch_cuda, c, spaces, x, opts)
+
+
+def test_projected_fit_parity_fine_space(torch_cuda, orc):
+    """A finer, strongly rotated acquisition grid: the push takes its global-memory path."""
+    c, spaces, x = _problem(orc, dims=(16, 16, 10), seed=65, fine=True)
+    y0 = f32(orc.default_init_projected(c["proto"], c["dims"], spaces, x.astype(np.float64), c["b1"]))
+    for opts in ({"mode": "ml", "n_gn": 10}, dict(c["opts"], n_outer=2, n_gn=3, n_cg=10)):
+        _compare(orc, torch_cuda, c, spaces, x, dict(opts, init="const", init_const=[float(v) for v in y0]))
 
 
 def test_projected_default_init_matches_oracle(torch_cuda, orc):
