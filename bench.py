@@ -79,7 +79,8 @@ def main():
                          "[0.7, 1.3], sigma 2%% of mean PD, JTV-MAP 10 x 8 x 32 then the Laplace variance")
     ap.add_argument("--projected", action="store_true",
                     help="spatially projected workload instead: T1w and MTw on rigidly moved grids, JTV-MAP "
-                         "10 x 8 x 32 then the Laplace variance on the 192 x 240 x 256 reconstruction grid")
+                         "10 x 8 x 32 then the Laplace variance on the 192 x 240 x 256 reconstruction grid "
+                         "(with --counters: a 2 x 1 x 32 projected fit and the copy calibration, then exit)")
     ap.add_argument("--requests", type=int, default=64)
     ap.add_argument("--rate", type=float, default=2.0, help="serving: arrivals per second")
     ap.add_argument("--schedule-seeds", default="4000",
@@ -113,7 +114,7 @@ def main():
         hires(torch, _lib, synth, dev)
         return
     if args.projected:
-        projected(torch, _lib, synth, dev)
+        projected(args, torch, _lib, synth, dev)
         return
     dims = tuple(int(v) for v in args.dims.split(","))
     t0 = time.time()
@@ -314,7 +315,7 @@ def hires(torch, _lib, synth, dev):
     print(json.dumps(out), flush=True)
 
 
-def projected(torch, _lib, synth, dev):
+def projected(args, torch, _lib, synth, dev):
     """Spatially projected JTV-MAP fit + Laplace variance: the PDw contrast on
     the reconstruction grid, T1w and MTw acquired on grids moved by seeded
     rigid motions (up to 2 degrees and 1.5 voxels); echoes simulated on the GPU
@@ -341,6 +342,14 @@ def projected(torch, _lib, synth, dev):
     opts = {"mode": "map", "n_outer": 10, "n_gn": 8, "n_cg": 32, "max_halvings": 4, "lam": case["lam"]}
     maps = torch.empty((4, N), dtype=torch.float32, device=dev)
     var = torch.empty((4, N), dtype=torch.float32, device=dev)
+    if args.counters:
+        _lib.mpm_fit_projected(case["proto"], dims, spaces, X, b1, dict(opts, n_outer=2, n_gn=1), maps)
+        a = torch.ones(1 << 28, dtype=torch.float32, device=dev)  # 1 GiB
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log("counter workload done: projected MAP 2x1x32 + one 1 GiB copy")
+        return
     _lib.mpm_fit_projected(case["proto"], dims, spaces, X, b1, dict(opts, n_outer=1, n_gn=1, n_cg=1), maps)
     torch.cuda.synchronize()
     _lib.mpm_profile_reset()

@@ -51,18 +51,59 @@ __device__ __forceinline__ void pull_y_b1(const Grid3 &g, const Corners &cr, con
     }
 }
 
+// Pulled trial maps (float4 per reconstruction voxel) and b1 at the corners cr.
+__device__ __forceinline__ void pull_yt_b1(const Grid3 &g, const Corners &cr, const float4 *__restrict__ Yt,
+                                           const float *__restrict__ b1, float y[4], float &b)
+{
+#pragma unroll
+    for (int a = 0; a < 4; a++) y[a] = 0.0f;
+    b = 0.0f;
+#pragma unroll
+    for (int c = 0; c < 8; c++) {
+        const float4 v = Yt[cr.idx[c]];
+        y[0] += cr.w[c] * v.x;
+        y[1] += cr.w[c] * v.y;
+        y[2] += cr.w[c] * v.z;
+        y[3] += cr.w[c] * v.w;
+        b += cr.w[c] * (b1 ? b1[cr.idx[c]] : 1.0f);
+    }
+}
+
+// Trial point y - delta_f of the current Newton step, one float4 per voxel,
+// for the trial likelihood's pull.
+__global__ __launch_bounds__(BLOCK) void k_trial_point(int64_t N, const float *__restrict__ Y,
+                                                      const float4 *__restrict__ D, const float4 *__restrict__ P0,
+                                                      const float4 *__restrict__ P1, const MapCtl *__restrict__ ctl,
+                                                      float4 *__restrict__ Yt)
+{
+    if (ctl->gn_stop) return;
+    const int64_t n = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (n >= N) return;
+    const DeltaF getd{D, ctl->p_buf ? P1 : P0, (float)ctl->alpha_pend, ctl->delta_valid != 0};
+    float d[4];
+    getd(n, d);
+    Yt[n] = make_float4(Y[n] - d[0], Y[N + n] - d[1], Y[2 * N + n] - d[2], Y[3 * N + n] - d[3]);
+}
+
 // Acquisition-space kernels walk columns of their own grid ga (a 64 x 4 tile
 // of the x-y plane, a run of planes along z; workgroups XCD-contiguous), so
 // the reconstruction voxels that consecutive planes pull from stay in cache.
-template <typename T, int CM1, int EM, bool PLUS>
+//
+// k_proj_lik evaluates the blocks at the current maps (TRIAL = false) or at
+// the trial point y - delta_f of the current Newton step (TRIAL = true: its
+// NLL decides the acceptance, and when the full step is taken its blocks are
+// those of the next step).  gated (current maps, at the start of a step): skip
+// when the step is skipped, or when the previous step took its full step, so
+// that the blocks from its trial point are current.
+template <typename T, int CM1, int EM, bool PLUS, bool TRIAL>
 __global__ __launch_bounds__(BLOCK) void k_proj_lik(Grid3 g, Grid3 ga, ProjSpace S,
                                                     typename VoxelEchoes<T, CM1, EM>::Proto P,
                                                     const T *__restrict__ X, const float *__restrict__ Y,
                                                     const float *__restrict__ b1, int loading, ProjBlocks B,
                                                     const MapCtl *__restrict__ ctl, int gated,
-                                                    double *__restrict__ ext)
+                                                    double *__restrict__ ext, const float4 *__restrict__ Yt)
 {
-    if (gated && ctl->gn_stop) return;
+    if (TRIAL ? ctl->gn_stop != 0 : gated && (ctl->gn_stop || ctl->step == 1.0)) return;
     const auto K = VoxelEchoes<T, CM1, EM>::stage(P);
     const Col c = locate_col(ga);
     double part[1] = {0.0};
@@ -73,7 +114,10 @@ __global__ __launch_bounds__(BLOCK) void k_proj_lik(Grid3 g, Grid3 ga, ProjSpace
             Corners cr;
             if (proj_corners(g, S, c.x, c.y, k, cr)) {
                 float y[4], b;
-                pull_y_b1(g, cr, Y, b1, y, b);
+                if (TRIAL)
+                    pull_yt_b1(g, cr, Yt, b1, y, b);
+                else
+                    pull_y_b1(g, cr, Y, b1, y, b);
                 VoxelEchoes<T, CM1, EM> ve;
                 ve.load(P, X, S.M, m, b);
                 part[0] += ve.template lik<PLUS>(P, K, y, loading, true, gl, H);
@@ -362,10 +406,10 @@ __global__ __launch_bounds__(BLOCK) void k_scan_apply(int64_t *__restrict__ v, i
     }
 }
 
-// Push through the stored Psi^T: columns of the reconstruction grid (so the
-// acquisition blocks that consecutive planes share stay in cache); per
-// contrast, entries in chunks of four (their blocks loaded together, then
-// added in row order).
+// Push through the stored Psi^T: columns of the reconstruction grid (64 x 4
+// tiles, XCD-contiguous; measured faster than 8 x 8 x 4 bricks); per contrast,
+// entries in chunks of four (their blocks loaded together, then added in row
+// order).
 __global__ __launch_bounds__(BLOCK) void k_proj_push_csr(Grid3 g, ProjPushArgs A, const int64_t *__restrict__ row,
                                                         const int2 *__restrict__ ent, float4 *__restrict__ G,
                                                         HessArrays H)
@@ -420,18 +464,28 @@ __global__ __launch_bounds__(BLOCK) void k_proj_pull(Grid3 g, ProjSpace S, const
 int proj_blocks(const ProjSpace &S) { return grid_blocks(proj_grid(S)); }
 
 template <typename T, int CM1, int EM>
-static hipError_t lik_one(hipStream_t s, const MapArgs &m, const ProjContrast &pc, double *ext, int gated, bool plus)
+static hipError_t lik_one(hipStream_t s, const MapArgs &m, const ProjContrast &pc, double *ext, int gated, bool plus,
+                          const float4 *Yt)
 {
     const T *X = (const T *)pc.X;
     const auto P = ProtoArg<T, CM1, EM>::make(pc.P, X, pc.S.M);
     const Grid3 ga = proj_grid(pc.S);
     dim3 grid(grid_blocks(ga)), blk(BLOCK);
-    if (plus)
-        hipLaunchKernelGGL((k_proj_lik<T, CM1, EM, true>), grid, blk, 0, s, m.g, ga, pc.S, P, X, m.Y, m.b1,
-                           m.loading, pc.B, m.ctl, gated, ext + pc.ext_col);
-    else
-        hipLaunchKernelGGL((k_proj_lik<T, CM1, EM, false>), grid, blk, 0, s, m.g, ga, pc.S, P, X, m.Y, m.b1,
-                           m.loading, pc.B, m.ctl, gated, ext + pc.ext_col);
+#define PROJ_LIK(PL, TR)                                                                                       \
+    hipLaunchKernelGGL((k_proj_lik<T, CM1, EM, PL, TR>), grid, blk, 0, s, m.g, ga, pc.S, P, X, m.Y, m.b1,     \
+                       m.loading, pc.B, m.ctl, gated, ext + pc.ext_col, Yt)
+    if (plus) {
+        if (Yt)
+            PROJ_LIK(true, true);
+        else
+            PROJ_LIK(true, false);
+    } else {
+        if (Yt)
+            PROJ_LIK(false, true);
+        else
+            PROJ_LIK(false, false);
+    }
+#undef PROJ_LIK
     return hipGetLastError();
 }
 
@@ -461,9 +515,17 @@ static hipError_t nll_one(hipStream_t s, const MapArgs &m, const ProjContrast &p
                        : ne <= 16 ? FN<BF16, 1, 16>(__VA_ARGS__) : FN<BF16, 0, 0>(__VA_ARGS__);           \
     } while (0)
 
-hipError_t launch_proj_lik(hipStream_t s, const MapArgs &m, const ProjContrast &pc, double *ext, int gated)
+hipError_t launch_proj_lik(hipStream_t s, const MapArgs &m, const ProjContrast &pc, double *ext, int gated,
+                           const float4 *Yt)
 {
-    PROJ_DISPATCH(lik_one, s, m, pc, ext, gated, m.loading == 2);
+    PROJ_DISPATCH(lik_one, s, m, pc, ext, gated, m.loading == 2, Yt);
+}
+
+hipError_t launch_trial_point(hipStream_t s, const MapArgs &m, float4 *Yt)
+{
+    hipLaunchKernelGGL(k_trial_point, dim3((unsigned)((m.g.N + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, s, m.g.N, m.Y,
+                       m.D, m.P0, m.P1, m.ctl, Yt);
+    return hipGetLastError();
 }
 
 hipError_t launch_proj_nll(hipStream_t s, const MapArgs &m, const ProjContrast &pc, double *ext, int ext_stride,

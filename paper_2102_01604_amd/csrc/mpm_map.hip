@@ -92,6 +92,7 @@ struct ProjState {
     int ext_stride = 0;
     PushedProto pp;
     PsiT psi{nullptr, nullptr};  // stored Psi^T (fits: pushed every Newton step)
+    float4 *Yt = nullptr;        // trial point y - delta_f (fits)
     int64_t *scan_tmp = nullptr;
     ExtRows rows(int n) const
     {
@@ -141,7 +142,8 @@ static mpm_status alloc_proj(const FitArgs &a, Workspace &ws, ProjState &ps, Hes
         const int64_t rows = (int64_t)ps.C * a.N;
         if (ws.alloc((void **)&ps.psi.row, sizeof(int64_t) * (size_t)(rows + 1)) != hipSuccess ||
             ws.alloc((void **)&ps.psi.ent, sizeof(int2) * (size_t)cap) != hipSuccess ||
-            ws.alloc((void **)&ps.scan_tmp, sizeof(int64_t) * (size_t)psi_scan_blocks(rows)) != hipSuccess)
+            ws.alloc((void **)&ps.scan_tmp, sizeof(int64_t) * (size_t)psi_scan_blocks(rows)) != hipSuccess ||
+            ws.alloc((void **)&ps.Yt, sizeof(float4) * (size_t)a.N) != hipSuccess)
             return fail(MPM_ERR_OUT_OF_MEMORY, "projection workspace allocation failed");
     }
     return MPM_OK;
@@ -234,6 +236,20 @@ struct MapJob : FitJob {
         return e;
     }
 
+    // likelihood blocks at the trial point y - delta_f: NLL for the acceptance
+    // test, and the next step's blocks when the full step is taken
+    hipError_t proj_lik_trial()
+    {
+        hipError_t e = prof.launch("trial_point", (double)a.N * (16 + 32 + 16),
+                                   [&] { return launch_trial_point(a.stream, m, ps.Yt); });
+        for (int c = 0; c < ps.C && e == hipSuccess; c++) {
+            const ProjContrast &pc = ps.pc[c];
+            e = prof.launch("proj_lik_trial", (double)pc.S.M * (pc.P.I * dtype_size(a.dtype) + 16 + 4 + 56),
+                            [&] { return launch_proj_lik(a.stream, m, pc, ps.ext, 0, ps.Yt); });
+        }
+        return e;
+    }
+
     hipError_t proj_nll(int h0, int h1)
     {
         hipError_t e = hipSuccess;
@@ -292,7 +308,7 @@ struct MapJob : FitJob {
                     RUN("fin", 0.0, fin(FIN_ACCEPT2, t * S + j + 1, nb_col));
                 }
             } else {
-                if (e == hipSuccess) e = proj_nll(0, 1);
+                if (e == hipSuccess) e = proj_lik_trial();
                 RUN("map_accept", N * (16 + 16 + 16 + 4), launch_accept_pushed(s, m, ps.pp));
                 RUN("fin", 0.0, fin(FIN_ACCEPT, t * S + j + 1, nb_pl, ps.rows(1)));
                 if (ntrial > 1) {

@@ -134,9 +134,15 @@ struct ProjContrast {
     int ext_col;      // first partial column of this contrast in the extra rows
 };
 
-// Acquisition space: pull, likelihood blocks, NLL partial (extra row 0).
-// gated: return when the control block says the Newton step is skipped.
-hipError_t launch_proj_lik(hipStream_t s, const MapArgs &m, const ProjContrast &pc, double *ext, int gated);
+// Acquisition space: pull, likelihood blocks, NLL partial (extra row 0), at
+// the current maps, or at the trial point Yt (from launch_trial_point) when
+// Yt is given.  gated (current maps): return when the control block says the
+// Newton step is skipped or the blocks are current (the previous step took its
+// full step).
+hipError_t launch_proj_lik(hipStream_t s, const MapArgs &m, const ProjContrast &pc, double *ext, int gated,
+                           const float4 *Yt = nullptr);
+// Yt = y - delta_f [N] (float4 per reconstruction voxel), gated like the step.
+hipError_t launch_trial_point(hipStream_t s, const MapArgs &m, float4 *Yt);
 // NLL at y - 2^-h delta_f for h in [h0, h1) (extra rows h); h0 > 0 runs only
 // after the full step was rejected.
 hipError_t launch_proj_nll(hipStream_t s, const MapArgs &m, const ProjContrast &pc, double *ext, int ext_stride,
