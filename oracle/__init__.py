@@ -118,6 +118,9 @@ def _load():
         lib.orc_uncertainty_projected.argtypes = [C.POINTER(Protocol), C.POINTER(C.c_int64), sp, _dp, _dp,
                                                   C.POINTER(Options), _dp, _dp, _dp]
         lib.orc_uncertainty_projected.restype = C.c_int
+        lib.orc_fit_voxelwise.argtypes = [C.POINTER(Protocol), C.c_int64, _dp, _dp, _dp, _dp, C.POINTER(Options),
+                                          C.c_double, _dp, C.POINTER(C.c_int32), _dp, C.POINTER(Report)]
+        lib.orc_fit_voxelwise.restype = C.c_int
         _lib = lib
     return _lib
 
@@ -316,6 +319,34 @@ def fit(proto, dims, x, b1, opts: dict, maps0=None):
         raise ValueError("default initialisation failed")
     report = {f[0]: getattr(rep, f[0]) for f in Report._fields_}
     return maps, report, trace
+
+
+def fit_voxelwise(shape, tr, flip, te, x, opts: dict, maps0=None, rise_rel=1e-12):
+    """ML fit with a protocol per voxel (Sec. 3.1): shape gives n_echoes, mt and
+    sigma; tr, flip [C][N] and te [I][N] per voxel.  Starts from
+    opts["init_const"] or maps0.  Returns (maps [4][N], increases [N], final
+    NLL [N], report dict)."""
+    lib = _load()
+    tr = _f64(tr)
+    N = tr.shape[-1]
+    C_, I = len(shape["n_echoes"]), n_images(shape)
+    tr, flip, te = tr.reshape(C_, N), _f64(flip).reshape(C_, N), _f64(te).reshape(I, N)
+    x = _f64(x).reshape(I, N)
+    o = make_options(dict(opts, mode="ml"))
+    if maps0 is not None:
+        maps = _f64(maps0).reshape(4, N).copy()
+        o.init_kind = INIT_FROM_MAPS
+    else:
+        maps = np.zeros((4, N))
+    inc = np.zeros(N, dtype=np.int32)
+    nll = np.zeros(N)
+    rep = Report()
+    p = make_protocol(dict(shape, tr=[1.0] * C_, flip=[0.1] * C_, te=[0.0] * I))
+    st = lib.orc_fit_voxelwise(C.byref(p), N, _ptr(tr), _ptr(flip), _ptr(te), _ptr(x), C.byref(o), float(rise_rel),
+                               _ptr(maps), inc.ctypes.data_as(C.POINTER(C.c_int32)), _ptr(nll), C.byref(rep))
+    if st:
+        raise ValueError("fit_voxelwise needs init='const' or maps0")
+    return maps, inc, nll, {f[0]: getattr(rep, f[0]) for f in Report._fields_}
 
 
 def uncertainty(proto, dims, x, b1, opts: dict, maps, moments=False):

@@ -941,6 +941,77 @@ int orc_fit(const orc_protocol *p, const int64_t dims[3], const double *x, const
     return fit_impl(&L, opt, maps, rep, trace, trace_len);
 }
 
+/* ------------------------------------------------------------------------
+ * Per-voxel protocols (the convergence experiment of Sec. 3.1): voxel n has
+ * its own TR and flip angle per contrast, tr[c*N + n] and flip[c*N + n], and
+ * its own echo times te[i*N + n]; the contrast/echo structure, MT flags and
+ * noise levels come from shape (its tr, flip and te are ignored).  Each voxel
+ * takes opt->n_gn Newton-like steps y <- y - P~^{-1} g (Sec. 2.3) from
+ * init_const (ORC_INIT_CONST) or from maps (ORC_INIT_FROM_MAPS), as the ML
+ * fit does.  increases[n] (optional) counts the steps after which the
+ * voxel's NLL exceeds the one before by more than rise_rel (relative), or
+ * becomes non-finite from a finite value; nll[n] (optional) is the final NLL.
+ * Returns 0, or 1 if the options are not an ML fit with a given start.
+ * ------------------------------------------------------------------------ */
+int orc_fit_voxelwise(const orc_protocol *shape, int64_t N, const double *tr, const double *flip, const double *te,
+                      const double *x, const orc_options *opt, double rise_rel, double *maps, int32_t *increases,
+                      double *nll, orc_report *rep)
+{
+    if (opt->mode != ORC_ML || (opt->init_kind != ORC_INIT_CONST && opt->init_kind != ORC_INIT_FROM_MAPS)) return 1;
+    const int C = shape->n_contrasts;
+    int I = 0;
+    for (int c = 0; c < C; c++) I += shape->n_echoes[c];
+    /* per-voxel results; the totals are serial sums in voxel order */
+    int32_t *cnt = (int32_t *)malloc(sizeof(int32_t) * (size_t)N);
+    double *fnll = (double *)malloc(sizeof(double) * (size_t)N);
+    unsigned char *degen = (unsigned char *)malloc((size_t)N);
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t n = 0; n < N; n++) {
+        orc_protocol pv = *shape;
+        for (int c = 0; c < C; c++) {
+            pv.tr[c] = tr[c * N + n];
+            pv.flip[c] = flip[c * N + n];
+        }
+        for (int i = 0; i < I; i++) pv.te[i] = te[i * N + n];
+        double y[4];
+        for (int k = 0; k < 4; k++) y[k] = opt->init_kind == ORC_INIT_CONST ? opt->init_const[k] : maps[k * N + n];
+        double prev = 0.0, cur = 0.0, g[4], P[16];
+        int count = 0, dg = 0;
+        for (int it = 0; it <= opt->n_gn; it++) {
+            orc_lik_voxel(&pv, x + n, N, y, 1.0, opt->loading, &cur, g, P);
+            if (it > 0 && (cur > prev * (1.0 + rise_rel) || (isfinite(prev) && !isfinite(cur)))) count++;
+            prev = cur;
+            if (it == opt->n_gn) break;
+            double step[4];
+            dg = orc_solve4(P, g, step);
+            for (int k = 0; k < 4; k++) y[k] -= step[k];
+        }
+        for (int k = 0; k < 4; k++) maps[k * N + n] = y[k];
+        cnt[n] = count;
+        fnll[n] = cur;
+        degen[n] = (unsigned char)dg;
+    }
+    orc_report R;
+    memset(&R, 0, sizeof(R));
+    for (int64_t n = 0; n < N; n++) {
+        int fin = 1;
+        for (int k = 0; k < 4; k++) fin &= isfinite(maps[k * N + n]) != 0;
+        R.nll += fnll[n];
+        R.nll_increases += cnt[n];
+        R.degenerate_voxels += opt->n_gn > 0 ? degen[n] : 0;
+        R.nonfinite_voxels += !fin;
+        if (increases) increases[n] = cnt[n];
+        if (nll) nll[n] = fnll[n];
+    }
+    R.objective = R.nll;
+    R.gn_done = opt->n_gn;
+    if (rep) *rep = R;
+    free(cnt);
+    free(fnll);
+    free(degen);
+    return 0;
+}
+
 /* The fit with spatial projection (R-proj): spaces[c] is the acquisition
  * space of contrast c; echoes lie back to back (image i holds the voxels of
  * its contrast's space); maps and b1 live on the reconstruction grid dims.

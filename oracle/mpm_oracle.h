@@ -117,6 +117,12 @@ double orc_proj_lik(const orc_protocol *p, const int64_t dims[3], const orc_spac
                     const double *b1, int loading, const double *maps, double *g, double *P);
 int orc_default_init_projected(const orc_protocol *p, const int64_t dims[3], const orc_space *spaces,
                                const double *x, const double *b1, double y0[4]);
+/* Per-voxel protocols (Sec. 3.1 convergence experiment): tr, flip [C][N] and
+ * te [I][N] per voxel; ML steps from init_const or maps; per-voxel counts of
+ * NLL rises above rise_rel and final NLL (each optional). */
+int orc_fit_voxelwise(const orc_protocol *shape, int64_t N, const double *tr, const double *flip, const double *te,
+                      const double *x, const orc_options *opt, double rise_rel, double *maps, int32_t *increases,
+                      double *nll, orc_report *rep);
 int orc_fit_projected(const orc_protocol *p, const int64_t dims[3], const orc_space *spaces, const double *x,
                       const double *b1, const orc_options *opt, double *maps, orc_report *rep, double *trace,
                       int32_t trace_len);
