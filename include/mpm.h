@@ -207,6 +207,53 @@ mpm_status mpm_simulate_projected(const mpm_protocol *protocol, const mpm_grid *
                                   const float *maps, const float *b1, const float *noise, mpm_dtype out_dtype,
                                   void *out, void *stream);
 
+/*
+ * mpm_fit_voxelwise -- ML fit in which every voxel has its own protocol, as in
+ * the paper's convergence experiment (Sec. 3.1: random TR, flip angles and
+ * echo times per voxel).  The n_voxels voxels are independent (no grid).
+ *
+ * protocols: the contrast/echo structure, MT flags and per-image noise levels
+ * are shared (n_contrasts, n_echoes, mt, sigma: rules as mpm_protocol); the
+ * device arrays give, per voxel n, the repetition time tr_s[c * N + n] (s) and
+ * flip angle flip_rad[c * N + n] (rad, the effective angle: no B1 input) of
+ * each contrast c and the echo time te_s[i * N + n] (s) of each image i
+ * (N = n_voxels).  echoes: device [I][N] of dtype.  A voxel whose TR is not
+ * finite and > 0, whose flip is not in (0, pi) or whose TE is not finite and
+ * >= 0 is not fitted: its maps are NaN and it counts as non-finite.
+ *
+ * options: mode MPM_ML; n_gn steps y <- y - P~^{-1} g with the chosen loading
+ * (paper Sec. 2.3); init_kind MPM_INIT_CONST (init_const) or
+ * MPM_INIT_FROM_MAPS (maps holds the start); MPM_INIT_DEFAULT is
+ * MPM_ERR_UNSUPPORTED (the volume-mean initialisation assumes one protocol).
+ *
+ * Outputs (device, caller-owned): maps [4][N] (log A, log R1, log R2*,
+ * logit MTsat); nll_increases [N] int32 or NULL: the number of steps after
+ * which the voxel's NLL exceeds the previous value by more than 1e-5
+ * (relative, FP32 evaluation) or becomes non-finite from a finite value;
+ * nll [N] float or NULL: the final NLL.  report (host, may be NULL): total
+ * final NLL, degenerate and non-finite voxels, total NLL rises.  Validation
+ * on the host before any device work; blocks until done.
+ */
+typedef struct {
+    int32_t n_contrasts;
+    int32_t n_echoes[MPM_MAX_CONTRASTS];
+    int32_t mt[MPM_MAX_CONTRASTS];
+    double sigma[MPM_MAX_IMAGES];
+    const float *tr_s;      /* device [C][N] */
+    const float *flip_rad;  /* device [C][N] */
+    const float *te_s;      /* device [I][N] */
+} mpm_voxel_protocols;
+
+mpm_status mpm_fit_voxelwise(const mpm_voxel_protocols *protocols, int64_t n_voxels, mpm_dtype dtype,
+                             const void *echoes, const mpm_options *options, float *maps, int32_t *nll_increases,
+                             float *nll, mpm_report *report, void *stream);
+
+/* Echoes [I][N] of out_dtype for per-voxel protocols (layout and rules as
+ * mpm_fit_voxelwise): the model at maps [4][N] plus sigma_i * noise (device
+ * float [I][N], or NULL); NaN for a voxel whose protocol is invalid. */
+mpm_status mpm_simulate_voxelwise(const mpm_voxel_protocols *protocols, int64_t n_voxels, const float *maps,
+                                  const float *noise, mpm_dtype out_dtype, void *out, void *stream);
+
 /* Device bytes a fit of this size needs: inputs, maps and the library's
  * workspace.  Returns 0 for invalid arguments. */
 size_t mpm_footprint_bytes(const mpm_protocol *protocol, const mpm_grid *grid, mpm_dtype dtype,

@@ -67,6 +67,12 @@ class mpm_space(C.Structure):
     _fields_ = [("nx", C.c_int64), ("ny", C.c_int64), ("nz", C.c_int64), ("affine", C.c_double * 12)]
 
 
+class mpm_voxel_protocols(C.Structure):
+    _fields_ = [("n_contrasts", C.c_int32), ("n_echoes", C.c_int32 * MPM_MAX_CONTRASTS),
+                ("mt", C.c_int32 * MPM_MAX_CONTRASTS), ("sigma", C.c_double * MPM_MAX_IMAGES),
+                ("tr_s", C.c_void_p), ("flip_rad", C.c_void_p), ("te_s", C.c_void_p)]
+
+
 class MpmError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"{STATUS.get(status, status)}: {msg}")
@@ -89,6 +95,10 @@ SIGNATURES = {
     "mpm_uncertainty_projected": (C.c_int, [_P, _G, C.POINTER(mpm_space), C.c_int, C.c_void_p, C.c_void_p, _O,
                                             C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "mpm_simulate_projected": (C.c_int, [_P, _G, C.POINTER(mpm_space), C.c_void_p, C.c_void_p, C.c_void_p, C.c_int,
+                                         C.c_void_p, C.c_void_p]),
+    "mpm_fit_voxelwise": (C.c_int, [C.POINTER(mpm_voxel_protocols), C.c_int64, C.c_int, C.c_void_p, _O, C.c_void_p,
+                                    C.c_void_p, C.c_void_p, _R, C.c_void_p]),
+    "mpm_simulate_voxelwise": (C.c_int, [C.POINTER(mpm_voxel_protocols), C.c_int64, C.c_void_p, C.c_void_p, C.c_int,
                                          C.c_void_p, C.c_void_p]),
     "mpm_last_error": (C.c_char_p, []),
     "mpm_version": (C.c_char_p, []),
@@ -268,6 +278,49 @@ def mpm_simulate_projected(protocol: dict, dims, spaces, maps, b1, noise, out, s
     _check(lib.mpm_simulate_projected(C.byref(make_protocol(protocol)), C.byref(make_grid(dims)), make_spaces(spaces),
                                       _f32(maps, "maps"), _f32(b1, "b1"), _f32(noise, "noise"), _dtype_code(out), _ptr(out),
                                       _stream(stream)))
+
+
+def make_voxel_protocols(shape: dict, tr=None, flip=None, te=None) -> mpm_voxel_protocols:
+    """shape: {"n_echoes", "mt", "sigma"} shared by every voxel; tr, flip
+    [C][N] and te [I][N]: float32 device tensors (or None)."""
+    p = mpm_voxel_protocols()
+    nc = len(shape["n_echoes"])
+    p.n_contrasts = nc
+    for c in range(min(nc, MPM_MAX_CONTRASTS)):
+        p.n_echoes[c] = int(shape["n_echoes"][c])
+        p.mt[c] = int(shape["mt"][c])
+    for i in range(min(len(shape["sigma"]), MPM_MAX_IMAGES)):
+        p.sigma[i] = float(shape["sigma"][i])
+    p.tr_s = None if tr is None else _f32(tr, "tr").value
+    p.flip_rad = None if flip is None else _f32(flip, "flip").value
+    p.te_s = None if te is None else _f32(te, "te").value
+    return p
+
+
+def mpm_fit_voxelwise(shape: dict, tr, flip, te, echoes, options: dict, maps, nll_increases=None, nll=None,
+                      stream=None):
+    """mpm_fit_voxelwise on device tensors (a protocol per voxel): tr, flip
+    [C][N], te [I][N] float32; echoes [I][N]; maps [4][N] float32;
+    nll_increases [N] int32 and nll [N] float32 optional.  Returns the report
+    dict."""
+    import torch
+    lib = load()
+    if nll_increases is not None and (nll_increases.dtype != torch.int32 or not nll_increases.is_contiguous()):
+        raise TypeError("nll_increases must be a contiguous int32 tensor")
+    rep = mpm_report()
+    N = int(maps.shape[-1])
+    _check(lib.mpm_fit_voxelwise(C.byref(make_voxel_protocols(shape, tr, flip, te)), N, _dtype_code(echoes),
+                                 _ptr(echoes), C.byref(make_options(options)), _f32(maps, "maps"), _ptr(nll_increases),
+                                 _f32(nll, "nll"), C.byref(rep), _stream(stream)))
+    return {f[0]: getattr(rep, f[0]) for f in mpm_report._fields_}
+
+
+def mpm_simulate_voxelwise(shape: dict, tr, flip, te, maps, noise, out, stream=None):
+    """Echoes out [I][N] for per-voxel protocols (tr, flip [C][N], te [I][N])."""
+    lib = load()
+    N = int(maps.shape[-1])
+    _check(lib.mpm_simulate_voxelwise(C.byref(make_voxel_protocols(shape, tr, flip, te)), N, _f32(maps, "maps"),
+                                      _f32(noise, "noise"), _dtype_code(out), _ptr(out), _stream(stream)))
 
 
 def mpm_footprint_bytes(protocol: dict, dims, dtype: int, mode: int) -> int:

@@ -1,5 +1,6 @@
-"""Build libmpm.so (gfx950) in-tree with hipcc, and the hbm_probe program
-(plain streaming kernels that measure the GPU's achievable HBM bandwidth)."""
+"""Build libmpm.so (gfx950) in-tree with hipcc, and the hbm_probe and
+valu_probe programs (plain kernels that measure the GPU's achievable HBM
+bandwidth and VALU issue rate)."""
 from __future__ import annotations
 
 import os
@@ -10,6 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmpm.so")
 PROBE = os.path.join(HERE, "hbm_probe")
+VALU_PROBE = os.path.join(HERE, "valu_probe")
 SOURCES = ["mpm_api.hip", "mpm_fit.hip", "mpm_map.hip", "mpm_serve.hip", "k_voxel.hip", "k_map.hip",
            "k_proj.hip"]
 FLAGS = [
@@ -29,11 +31,12 @@ def build(verbose: bool = False) -> str:
     subprocess.check_call(cmd, cwd=CSRC)
     os.replace(LIB + ".tmp", LIB)
     pflags = [f for f in FLAGS if f not in ("-fPIC", "-shared")]
-    cmd = [hipcc] + pflags + ["-o", PROBE + ".tmp", os.path.join(CSRC, "hbm_probe.hip")]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.check_call(cmd, cwd=CSRC)
-    os.replace(PROBE + ".tmp", PROBE)
+    for out, src in ((PROBE, "hbm_probe.hip"), (VALU_PROBE, "valu_probe.hip")):
+        cmd = [hipcc] + pflags + ["-o", out + ".tmp", os.path.join(CSRC, src)]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.check_call(cmd, cwd=CSRC)
+        os.replace(out + ".tmp", out)
     return LIB
 
 

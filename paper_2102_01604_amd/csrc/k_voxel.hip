@@ -1,6 +1,8 @@
 // k_voxel.hip -- voxelwise kernels of libmpm: forward model, per-image means,
 // the maximum-likelihood fit (SPGR-ML) and a fixed-order row reduction.
-#include "mpm_kernels.h"
+#include <algorithm>
+
+#include "mpm_voxelwise.h"
 
 namespace mpm {
 
@@ -77,6 +79,48 @@ hipError_t launch_simulate(const LaunchCtx &c, const DevProto &P, const float *m
     else
         hipLaunchKernelGGL(k_simulate<BF16>, dim3(nb), dim3(BLOCK), 0, c.stream, P, maps, b1, noise,
                            (BF16 *)out, N);
+    return hipGetLastError();
+}
+
+// forward model with a protocol per voxel (tr, flip [C][N], te [I][N]); a
+// voxel whose protocol is invalid gets NaN
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_simulate_pv(DevProto P, PVArrays A, const float *__restrict__ maps,
+                                                       const float *__restrict__ noise, T *__restrict__ out,
+                                                       int64_t N)
+{
+    int64_t n = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (n >= N) return;
+    float y[4] = {maps[n], maps[N + n], maps[2 * N + n], maps[3 * N + n]};
+    Params p = decode(y);
+    bool ok = true;
+    for (int c = 0; c < P.C; c++) ok = ok && pv_valid(A.tr[(int64_t)c * N + n], A.flip[(int64_t)c * N + n]);
+    for (int i = 0; i < P.I; i++) {
+        const float t = A.te[(int64_t)i * N + n];
+        ok = ok && t >= 0.0f && t < INFINITY;
+    }
+    for (int c = 0; c < P.C; c++) {
+        ContrastK K = contrast_factors(p, A.tr[(int64_t)c * N + n], make_angle(A.flip[(int64_t)c * N + n]), P.mt[c]);
+        for (int i = P.first[c]; i < P.first[c + 1]; i++) {
+            float s = K.s0 * __expf(-p.r2 * A.te[(int64_t)i * N + n]);
+            if (noise) s += rsqrtf(P.wgt[i]) * noise[(int64_t)i * N + n];
+            store_echo(out + (int64_t)i * N + n, ok ? s : NAN);
+        }
+    }
+}
+
+hipError_t launch_simulate_pv(const LaunchCtx &c, const DevProto &P, const PVArrays &A, const float *maps,
+                              const float *noise, int dtype, void *out, int64_t N)
+{
+    int nb = (int)((N + BLOCK - 1) / BLOCK);
+    if (dtype == DT_F32)
+        hipLaunchKernelGGL(k_simulate_pv<float>, dim3(nb), dim3(BLOCK), 0, c.stream, P, A, maps, noise, (float *)out,
+                           N);
+    else if (dtype == DT_F16)
+        hipLaunchKernelGGL(k_simulate_pv<F16>, dim3(nb), dim3(BLOCK), 0, c.stream, P, A, maps, noise, (F16 *)out, N);
+    else
+        hipLaunchKernelGGL(k_simulate_pv<BF16>, dim3(nb), dim3(BLOCK), 0, c.stream, P, A, maps, noise, (BF16 *)out,
+                           N);
     return hipGetLastError();
 }
 
@@ -251,6 +295,106 @@ hipError_t launch_ml_fit(const LaunchCtx &c, const DevProto &P, int dtype, const
     if (dtype == DT_F16)
         return ml_dispatch(c, P, (const F16 *)X, b1, maps, N, n_gn, loading, partials, nblk);
     return ml_dispatch(c, P, (const BF16 *)X, b1, maps, N, n_gn, loading, partials, nblk);
+}
+
+// ---------------------------------------------------------------------------
+// ML fit with a protocol per voxel (paper Sec. 3.1): the same Newton-like
+// steps per thread; per voxel the count of steps after which its NLL rose
+// (more than 1e-5 relative, or finite to non-finite) and the final NLL.
+// Partials per workgroup: final NLL, degenerate, non-finite, rises.
+// ---------------------------------------------------------------------------
+template <typename T, int CM, int EM, bool PLUS>
+__global__ __launch_bounds__(BLOCK) void k_ml_fit_pv(DevProto P, PVArrays A, const T *__restrict__ X,
+                                                     float *__restrict__ maps, int64_t N, int n_gn, int loading,
+                                                     int32_t *__restrict__ incr, float *__restrict__ nll_out,
+                                                     double *__restrict__ partials)
+{
+    const int64_t n = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    const bool active = n < N;
+    const int64_t nn = active ? n : 0;
+    const auto W = VoxelEchoesPV<T, CM, EM>::stage(P);
+    VoxelEchoesPV<T, CM, EM> ve;
+    ve.load(P, A, X, N, nn);
+    float y[4] = {maps[nn], maps[N + nn], maps[2 * N + nn], maps[3 * N + nn]};
+    float prev = 0.0f, cur = NAN;
+    int cnt = 0;
+    bool degen = false;
+    if (ve.ok) {
+        for (int it = 0; it <= n_gn; it++) {
+            const bool last = (it == n_gn);
+            float g[4], H[10];
+            cur = ve.template lik<PLUS>(P, W, y, loading, !last, g, H);
+            if (it > 0 && (cur > prev * (1.0f + 1e-5f) || (fabsf(prev) < INFINITY && !(fabsf(cur) < INFINITY))))
+                cnt++;
+            prev = cur;
+            if (last) break;
+            float step[4];
+            degen = solve_sym4(H, g, step);
+#pragma unroll
+            for (int k = 0; k < 4; k++) y[k] -= step[k];
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < 4; k++) y[k] = NAN;
+    }
+    bool fin = true;
+#pragma unroll
+    for (int k = 0; k < 4; k++) fin = fin && fabsf(y[k]) < INFINITY;
+    double st[4] = {active ? (double)cur : 0.0, (active && n_gn > 0 && degen) ? 1.0 : 0.0,
+                    (active && !fin) ? 1.0 : 0.0, active ? (double)cnt : 0.0};
+    __shared__ double lds[4][NWAVE];
+    block_sum<4>(st, lds);
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 4; k++) partials[(int64_t)k * gridDim.x + blockIdx.x] = st[k];
+    if (active) {
+        maps[n] = y[0];
+        maps[N + n] = y[1];
+        maps[2 * N + n] = y[2];
+        maps[3 * N + n] = y[3];
+        if (incr) incr[n] = cnt;
+        if (nll_out) nll_out[n] = cur;
+    }
+}
+
+template <typename T, bool PLUS>
+static hipError_t ml_pv_launch(const LaunchCtx &c, const DevProto &P, const PVArrays &A, const T *X, float *maps,
+                               int64_t N, int n_gn, int loading, int32_t *incr, float *nll, double *partials)
+{
+    dim3 g(ml_fit_blocks(N)), b(BLOCK);
+    int emax = 0;
+    for (int k = 0; k < P.C; k++) emax = std::max(emax, P.first[k + 1] - P.first[k]);
+#define PV_LAUNCH(CM, EM)                                                                                      \
+    hipLaunchKernelGGL((k_ml_fit_pv<T, CM, EM, PLUS>), g, b, 0, c.stream, P, A, X, maps, N, n_gn, loading, incr, \
+                       nll, partials)
+    if (P.C <= 4 && emax <= 6)
+        PV_LAUNCH(4, 6);
+    else if (P.C <= 4 && emax <= 8)
+        PV_LAUNCH(4, 8);
+    else if (P.C <= 8 && emax <= 8)
+        PV_LAUNCH(8, 8);
+    else
+        PV_LAUNCH(0, 0);
+#undef PV_LAUNCH
+    return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t ml_pv_dispatch(const LaunchCtx &c, const DevProto &P, const PVArrays &A, const T *X, float *maps,
+                                 int64_t N, int n_gn, int loading, int32_t *incr, float *nll, double *partials)
+{
+    return loading == 2 ? ml_pv_launch<T, true>(c, P, A, X, maps, N, n_gn, loading, incr, nll, partials)
+                        : ml_pv_launch<T, false>(c, P, A, X, maps, N, n_gn, loading, incr, nll, partials);
+}
+
+hipError_t launch_ml_fit_pv(const LaunchCtx &c, const DevProto &P, const PVArrays &A, int dtype, const void *X,
+                            float *maps, int64_t N, int n_gn, int loading, int32_t *incr, float *nll,
+                            double *partials)
+{
+    if (dtype == DT_F32)
+        return ml_pv_dispatch(c, P, A, (const float *)X, maps, N, n_gn, loading, incr, nll, partials);
+    if (dtype == DT_F16)
+        return ml_pv_dispatch(c, P, A, (const F16 *)X, maps, N, n_gn, loading, incr, nll, partials);
+    return ml_pv_dispatch(c, P, A, (const BF16 *)X, maps, N, n_gn, loading, incr, nll, partials);
 }
 
 }  // namespace mpm

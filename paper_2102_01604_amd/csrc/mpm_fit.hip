@@ -3,6 +3,7 @@
 #include <cstring>
 
 #include "mpm_api_internal.h"
+#include "mpm_voxelwise.h"
 
 namespace mpm {
 
@@ -124,3 +125,130 @@ std::unique_ptr<FitJob> make_ml_job(const FitArgs &a, Workspace &ws, Prof &prof,
 }
 
 }  // namespace mpm
+
+// ---------------------------------------------------------------------------
+// ML fit with a protocol per voxel (paper Sec. 3.1 convergence experiment).
+// ---------------------------------------------------------------------------
+namespace mpm {
+// The shared structure of per-voxel protocols as a protocol (TR, flip and TE
+// are per voxel: placeholders here), validated; *I: number of images.
+static mpm_status voxelwise_shape(const mpm_voxel_protocols *vp, int64_t n_voxels, mpm_protocol &p, int *I)
+{
+    if (!vp) return fail(MPM_ERR_INVALID_ARG, "protocols is NULL");
+    if (vp->n_contrasts < 1 || vp->n_contrasts > MPM_MAX_CONTRASTS)
+        return fail(MPM_ERR_INVALID_ARG, "n_contrasts=%d outside [1, %d]", vp->n_contrasts, MPM_MAX_CONTRASTS);
+    memset(&p, 0, sizeof(p));
+    p.n_contrasts = vp->n_contrasts;
+    *I = 0;
+    for (int c = 0; c < vp->n_contrasts; c++) {
+        p.n_echoes[c] = vp->n_echoes[c];
+        p.mt[c] = vp->mt[c];
+        p.tr_s[c] = 1.0;
+        p.flip_rad[c] = 0.1;
+        if (vp->n_echoes[c] >= 1 && *I + vp->n_echoes[c] <= MPM_MAX_IMAGES) *I += vp->n_echoes[c];
+    }
+    for (int i = 0; i < *I; i++) p.sigma[i] = vp->sigma[i];
+    mpm_status st;
+    if ((st = check_protocol(&p))) return st;
+    if (n_voxels < 1 || n_voxels > ((int64_t)1 << 34))
+        return fail(MPM_ERR_INVALID_ARG, "n_voxels=%lld outside [1, 2^34]", (long long)n_voxels);
+    if (!vp->tr_s || !vp->flip_rad || !vp->te_s)
+        return fail(MPM_ERR_INVALID_ARG, "tr_s, flip_rad and te_s must be device pointers");
+    return MPM_OK;
+}
+}  // namespace mpm
+
+extern "C" mpm_status mpm_simulate_voxelwise(const mpm_voxel_protocols *vp, int64_t n_voxels, const float *maps,
+                                             const float *noise, mpm_dtype out_dtype, void *out, void *stream)
+{
+    using namespace mpm;
+    clear_error();
+    mpm_protocol p;
+    int I;
+    mpm_status st;
+    if ((st = voxelwise_shape(vp, n_voxels, p, &I)) || (st = check_dtype(out_dtype))) return st;
+    if (!maps || !out) return fail(MPM_ERR_INVALID_ARG, "maps and out must be device pointers");
+    hipStream_t s = (hipStream_t)stream;
+    Prof prof(s);
+    LaunchCtx c{s};
+    const DevProto P = to_dev(&p);
+    const PVArrays A{vp->tr_s, vp->flip_rad, vp->te_s};
+    hipError_t e = prof.launch("simulate_pv", (double)n_voxels * (16.0 + 8.0 * p.n_contrasts +
+                                                                    I * (4.0 + dtype_size(out_dtype) + (noise ? 4.0 : 0.0))),
+                               [&] { return launch_simulate_pv(c, P, A, maps, noise, out_dtype, out, n_voxels); });
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    prof.collect();
+    if (e != hipSuccess) return fail(MPM_ERR_DEVICE, "simulate: %s", hipGetErrorString(e));
+    return MPM_OK;
+}
+
+extern "C" mpm_status mpm_fit_voxelwise(const mpm_voxel_protocols *vp, int64_t n_voxels, mpm_dtype dtype,
+                                        const void *echoes, const mpm_options *opt, float *maps,
+                                        int32_t *nll_increases, float *nll, mpm_report *report, void *stream)
+{
+    using namespace mpm;
+    clear_error();
+    mpm_protocol p;
+    int I;
+    mpm_status st;
+    if ((st = voxelwise_shape(vp, n_voxels, p, &I)) || (st = check_dtype(dtype))) return st;
+    if (!echoes || !maps) return fail(MPM_ERR_INVALID_ARG, "echoes and maps must be device pointers");
+    if (!opt) return fail(MPM_ERR_INVALID_ARG, "options is NULL");
+    if (opt->mode != MPM_ML) return fail(MPM_ERR_INVALID_ARG, "mpm_fit_voxelwise is an ML fit (mode %d)", opt->mode);
+    if (opt->n_gn < 0 || opt->n_gn > 100000) return fail(MPM_ERR_INVALID_ARG, "n_gn must be in [0, 100000]");
+    if (opt->loading != MPM_LOAD_PROPOSED && opt->loading != MPM_LOAD_GN && opt->loading != MPM_LOAD_PROPOSED_PLUS)
+        return fail(MPM_ERR_INVALID_ARG, "unknown loading %d", opt->loading);
+    if (opt->flags != 0) return fail(MPM_ERR_INVALID_ARG, "flags must be 0");
+    if (opt->init_kind == MPM_INIT_DEFAULT)
+        return fail(MPM_ERR_UNSUPPORTED, "the default initialisation needs one protocol for all voxels");
+    if (opt->init_kind != MPM_INIT_CONST && opt->init_kind != MPM_INIT_FROM_MAPS)
+        return fail(MPM_ERR_INVALID_ARG, "unknown init_kind %d", opt->init_kind);
+    if (opt->init_kind == MPM_INIT_CONST)
+        for (int k = 0; k < 4; k++)
+            if (!std::isfinite(opt->init_const[k])) return fail(MPM_ERR_INVALID_ARG, "init_const[%d] is not finite", k);
+    if (!has_mt(&p)) return fail(MPM_ERR_UNSUPPORTED, "the four-parameter model needs at least one MT contrast");
+
+    const int64_t N = n_voxels;
+    const DevProto P = to_dev(&p);
+    const PVArrays A{vp->tr_s, vp->flip_rad, vp->te_s};
+    hipStream_t s = (hipStream_t)stream;
+    const int nblk = ml_fit_blocks(N);
+    mpm_report rep;
+    memset(&rep, 0, sizeof(rep));
+    {
+        Workspace ws(s);
+        Prof prof(s);
+        PinnedBuf host;
+        double *part = nullptr, *sums = nullptr;
+        if (ws.alloc((void **)&part, sizeof(double) * 4 * (size_t)nblk) != hipSuccess ||
+            ws.alloc((void **)&sums, sizeof(double) * 4) != hipSuccess || host.alloc(sizeof(double) * 4) != hipSuccess)
+            return fail(MPM_ERR_OUT_OF_MEMORY, "voxelwise fit: workspace allocation failed");
+        LaunchCtx c{s};
+        hipError_t e = hipSuccess;
+        if (opt->init_kind == MPM_INIT_CONST) {
+            float y0[4];
+            for (int k = 0; k < 4; k++) y0[k] = (float)opt->init_const[k];
+            e = launch_fill_maps(c, maps, N, y0);
+        }
+        const double bytes = (double)N * ((double)I * (dtype_size(dtype) + 4.0) + 8.0 * p.n_contrasts + 32.0 +
+                                          (nll_increases ? 4.0 : 0.0) + (nll ? 4.0 : 0.0));
+        if (e == hipSuccess)
+            e = prof.launch("ml_fit_pv", bytes, [&] {
+                return launch_ml_fit_pv(c, P, A, dtype, echoes, maps, N, opt->n_gn, opt->loading, nll_increases, nll,
+                                        part);
+            });
+        if (e == hipSuccess) e = launch_reduce_rows(c, part, 4, nblk, sums);
+        if (e == hipSuccess) e = hipMemcpyAsync(host.p, sums, sizeof(double) * 4, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        prof.collect();
+        if (e != hipSuccess) return fail(MPM_ERR_DEVICE, "voxelwise fit: %s", hipGetErrorString(e));
+        const double *h = (const double *)host.p;
+        rep.nll = rep.objective = h[0];
+        rep.gn_done = opt->n_gn;
+        rep.degenerate_voxels = (int64_t)llround(h[1]);
+        rep.nonfinite_voxels = (int64_t)llround(h[2]);
+        rep.nll_increases = (int64_t)llround(h[3]);
+    }
+    if (report) *report = rep;
+    return MPM_OK;
+}

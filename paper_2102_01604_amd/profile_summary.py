@@ -4,7 +4,14 @@
     python -m paper_2102_01604_amd.profile_summary traffic <FETCH run_counter_collection.csv>
                                                    <WRITE run_counter_collection.csv> <kernel> <voxels> [last]
 
+    python -m paper_2102_01604_amd.profile_summary valu <run_counter_collection.csv> <kernel> <voxels> <steps>
+
 `trace` prints a markdown table of per-kernel call counts and durations.
+`valu` prints the executed VALU instructions (SQ_INSTS_VALU, per wavefront,
+so x 64 lanes) and transcendental ones (SQ_INSTS_VALU_TRANS_F32) per voxel
+and evaluation, for each dispatch of a voxelwise kernel that evaluates the
+likelihood steps + 1 times per voxel, tagged with the hash of the voxel
+kernel sources.
 `traffic` prints the HBM bytes per dispatch of one kernel (averaged over its
 last `last` dispatches, default all): FETCH_SIZE and WRITE_SIZE (KiB per
 dispatch) scaled by what the same counters read for a
@@ -74,8 +81,32 @@ def traffic(fetch_csv, write_csv, kernel, voxels, last=0):
     print(f"source_sha256_16: {src}")
 
 
+VALU_SOURCES = [os.path.join(HERE, "csrc", f) for f in ("k_voxel.hip", "mpm_voxelwise.h", "mpm_device.h")]
+
+
+def valu(csv_path, kernel, voxels, steps):
+    per = {}
+    for r in csv.DictReader(open(csv_path)):
+        if _short(r["Kernel_Name"]).split("<")[0].endswith(kernel):
+            per.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    h = hashlib.sha256()
+    for p in VALU_SOURCES:
+        h.update(open(p, "rb").read())
+    evals = float(voxels) * (steps + 1)
+    print(f"kernel: {kernel}")
+    print(f"dispatches: {len(next(iter(per.values())))}")
+    for c in sorted(per):
+        for d, v in enumerate(per[c]):
+            print(f"{c}_dispatch{d}: {v:.6g}")
+            if c.startswith("SQ_INSTS_VALU"):
+                print(f"{c}_dispatch{d}_lanes_per_voxel_eval: {v * 64.0 / evals:.2f}")
+    print(f"source_sha256_16: {h.hexdigest()[:16]}")
+
+
 if __name__ == "__main__":
     if sys.argv[1] == "trace":
         trace(sys.argv[2])
+    elif sys.argv[1] == "valu":
+        valu(sys.argv[2], sys.argv[3], int(sys.argv[4]), int(sys.argv[5]))
     else:
         traffic(sys.argv[2], sys.argv[3], sys.argv[4], int(sys.argv[5]), int(sys.argv[6]) if len(sys.argv) > 6 else 0)

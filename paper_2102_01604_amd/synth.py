@@ -116,6 +116,21 @@ def rigid_space(recon_dims, acq_dims, rng, rot_deg=2.0, shift=1.5):
     return {"dims": tuple(int(v) for v in acq_dims), "affine": np.hstack([R, t[:, None]])}
 
 
+def e1_problems(n, rng):
+    """The paper's convergence experiment (Sec. 3.1; sampling as read from its
+    text): per voxel, log-parameters (log A, log R1, log R2*, logit MTsat) and
+    the log TR of each of three contrasts uniform in [-5, 5], flip angles
+    uniform in [0, pi/4], and the log TE of each of 15 echoes (5 per contrast)
+    uniform in [-5, 5].  Returns y [4][n], tr [3][n], flip [3][n], te [15][n];
+    draw order y, tr, flip, te.  The last contrast carries the MT pulse and
+    sigma = 1 (so x = s + eps with unit Gaussian eps)."""
+    y = rng.uniform(-5, 5, (4, n))
+    tr = np.exp(rng.uniform(-5, 5, (3, n)))
+    flip = rng.uniform(0, math.pi / 4, (3, n))
+    te = np.exp(rng.uniform(-5, 5, (15, n)))
+    return y, tr, flip, te
+
+
 def identity_space(dims):
     return {"dims": tuple(int(v) for v in dims), "affine": np.hstack([np.eye(3), np.zeros((3, 1))])}
 

@@ -41,7 +41,8 @@ def test_struct_layouts_match_header(tmp_path):
     import subprocess
     structs = {"mpm_protocol": _lib.mpm_protocol, "mpm_grid": _lib.mpm_grid, "mpm_options": _lib.mpm_options,
                "mpm_report": _lib.mpm_report, "mpm_kernel_stat": _lib.mpm_kernel_stat,
-               "mpm_request": _lib.mpm_request, "mpm_space": _lib.mpm_space}
+               "mpm_request": _lib.mpm_request, "mpm_space": _lib.mpm_space,
+               "mpm_voxel_protocols": _lib.mpm_voxel_protocols}
     rename = {"lam": "lambda"}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "mpm.h"', "int main(void){"]
     for name, cls in structs.items():
@@ -128,6 +129,38 @@ def test_projected_argument_validation(lib):
                       ({"dims": (8, 8, 8), "affine": [[1, 1, 0, 0], [1, 1, 0, 0], [0, 0, 1, 0]]}, "singular")):
         st = run([ok, bad, ok])
         assert st == 1 and what in lib.mpm_last_error().decode(), (what, lib.mpm_last_error())
+
+
+def test_voxelwise_argument_validation(lib):
+    """mpm_fit_voxelwise checks its arguments on the host before any device work."""
+    fake = C.c_void_p(16)
+    shape = {"n_echoes": [5, 5, 5], "mt": [0, 0, 1], "sigma": [1.0] * 15}
+
+    def run(shape=shape, n=1000, opts=None, arrays=True, echoes=fake):
+        p = _lib.make_voxel_protocols(shape)
+        if arrays:
+            p.tr_s = p.flip_rad = p.te_s = 16
+        o = _lib.make_options(opts if opts is not None else {"mode": "ml", "n_gn": 5, "init": "const",
+                                                               "init_const": [0.0] * 4})
+        rep = _lib.mpm_report()
+        return lib.mpm_fit_voxelwise(C.byref(p), n, 0, echoes, C.byref(o), fake, None, None, C.byref(rep), None)
+
+    cases = [
+        (dict(arrays=False), 1, "device pointers"),
+        (dict(echoes=None), 1, "device pointers"),
+        (dict(n=0), 1, "n_voxels"),
+        (dict(opts={"mode": "map", "n_gn": 5, "init": "const"}), 1, "ML fit"),
+        (dict(opts={"mode": "ml", "n_gn": 5, "init": "default"}), 2, "one protocol"),
+        (dict(opts={"mode": "ml", "n_gn": -1, "init": "const"}), 1, "n_gn"),
+        (dict(opts={"mode": "ml", "n_gn": 5, "init": "const", "init_const": [float("nan"), 0, 0, 0]}), 1, "init_const"),
+        (dict(shape={"n_echoes": [5, 5], "mt": [0, 0], "sigma": [1.0] * 10}), 2, "MT"),
+        (dict(shape={"n_echoes": [5, 0, 5], "mt": [0, 0, 1], "sigma": [1.0] * 10}), 1, "echoes"),
+        (dict(shape={"n_echoes": [5, 5, 5], "mt": [0, 0, 1], "sigma": [1.0] * 14 + [0.0]}), 1, "sigma"),
+        (dict(shape={"n_echoes": [5] * 9, "mt": [0] * 8 + [1], "sigma": [1.0] * 45}), 1, "n_contrasts"),
+    ]
+    for kw, status, what in cases:
+        st = run(**kw)
+        assert st == status and what in lib.mpm_last_error().decode(), (kw, st, lib.mpm_last_error())
 
 
 def test_null_pointers_rejected(lib):

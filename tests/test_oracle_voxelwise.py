@@ -10,8 +10,6 @@ times).
   voxels than plain Gauss-Newton, and the flags equal those of single-voxel
   fits.
 """
-import math
-
 import numpy as np
 
 from paper_2102_01604_amd import synth
@@ -83,11 +81,7 @@ def test_noise_free_recovery_with_per_voxel_protocols(orc):
 def _e1_problems(rng, N):
     """Sec. 3.1: log-parameters, log TR and log TE ~ U[-5, 5], flips ~ U[0, pi/4],
     three contrasts of five echoes (the last with MT), sigma = 1, start 0."""
-    y = rng.uniform(-5, 5, (4, N))
-    tr = np.exp(rng.uniform(-5, 5, (3, N)))
-    flip = rng.uniform(0, math.pi / 4, (3, N))
-    te = np.exp(rng.uniform(-5, 5, (15, N)))
-    return y, tr, flip, te
+    return synth.e1_problems(N, rng)
 
 
 def test_convergence_experiment_through_voxelwise_fit(orc):
