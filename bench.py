@@ -29,6 +29,12 @@ HBM_PEAK_GBPS = 8000.0
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2102_01604_amd", "csrc", f)
                   for f in ("k_map.hip", "mpm_map.h", "mpm_device.h", "mpm_kernels.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_map_brain.txt")
+VALU_SOURCES = [os.path.join(ROOT, "paper_2102_01604_amd", "csrc", f)
+                for f in ("k_voxel.hip", "mpm_voxelwise.h", "mpm_device.h")]
+VALU_FILE = os.path.join(ROOT, "profiles", "valu_ml_fit_pv_e1.txt")
+# Published FP32 vector peak 157.3 TFLOP/s = 256 CUs x 2.4 GHz x 128 FMA lanes
+# per clock: 2 wave64 VALU instructions per clock per CU, 78.6 T lane-instructions/s.
+VALU_PEAK_T = 256 * 2.4e9 * 128 / 1e12
 
 
 def log(*a):
@@ -58,6 +64,26 @@ def read_traffic(kernel):
     try:
         return float(kv["bytes_per_launch"])
     except (KeyError, ValueError):
+        return None
+
+
+def read_valu_counts():
+    """VALU lane-instructions per voxel evaluation of the voxelwise ML kernel,
+    per loading (dispatch order Proposed, Proposed+, Gauss-Newton), from the
+    committed counter summary; None if absent or taken on other sources."""
+    if not os.path.exists(VALU_FILE):
+        return None
+    kv = {}
+    for line in open(VALU_FILE):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("source_sha256_16") != source_hash(VALU_SOURCES):
+        return None
+    try:
+        return {load: float(kv[f"SQ_INSTS_VALU_dispatch{d}_lanes_per_voxel_eval"])
+                for d, load in enumerate(("proposed", "plus", "gn"))}
+    except KeyError:
         return None
 
 
@@ -436,13 +462,35 @@ def convergence_experiment(args, torch, _lib, synth, dev):
                      "frac_voxels_nll_rose": round(rose, 5), "mean_rises_per_voxel": round(rep["nll_increases"] / N, 3),
                      "frac_nonfinite": round(rep["nonfinite_voxels"] / N, 5)}
         log(f"e1 {load}: {ms:.1f} ms, NLL rose in {100 * rose:.2f}% of voxels")
+    cpu = None
+    if not args.no_cpu_baseline:
+        # the FP64 oracle on the first 32768 voxels of the same problems, 8000 steps, Proposed loading
+        import oracle
+        n_s, it_s = 32768, 8000
+        xs = X[:, :n_s].cpu().numpy().astype(np.float64)
+        t = time.perf_counter()
+        with np.errstate(all="ignore"):
+            oracle.fit_voxelwise(shape, tr[:, :n_s].astype(np.float32), flip[:, :n_s].astype(np.float32),
+                                 te[:, :n_s].astype(np.float32), xs, {"n_gn": it_s, "init": "const",
+                                                                      "init_const": [0.0] * 4})
+        dt = time.perf_counter() - t
+        cpu = {"value": round(n_s * it_s / dt, 1), "unit": "voxel-iterations/s", "cores": oracle.num_threads(),
+               "kind": "oracle", "seconds": round(dt, 2),
+               "sample": f"the first {n_s} voxels of the same problems, {it_s} steps, Proposed loading, FP64"}
+    roof = None
+    counts = read_valu_counts()
+    if counts is not None:
+        ach = counts["proposed"] * N * (its + 1) / (res["proposed"]["ms"] * 1e-3) / 1e12
+        roof = {"bound": "alu", "kernel": "ml_fit_pv", "achieved": round(ach, 2), "peak": round(VALU_PEAK_T, 2),
+                "unit": "T VALU lane-instructions/s", "frac": round(ach / VALU_PEAK_T, 4), "traffic": None,
+                "valu_per_voxel_iteration": counts["proposed"]}
     out = {"metric": "voxel-iterations/s (ML, a protocol per voxel: the Sec. 3.1 convergence experiment)",
            "value": res["proposed"]["voxel_iters_per_s"], "unit": "voxel-iterations/s", "n_gpus": 1,
            "higher_is_better": True, "dtype": "f32", "data": "synthetic",
            "config": {"workload": f"{N} voxels, each with its own random protocol (3 contrasts x 5 echoes, MT on the "
                                   f"last; log TR, log TE, log-parameters ~ U[-5, 5], flips ~ U[0, pi/4]), sigma 1, "
                                   f"{its} ML steps from 0", "voxels": N, "iterations": its},
-           "loadings": res}
+           "loadings": res, "roofline": roof, "cpu_baseline": cpu}
     print(json.dumps(out), flush=True)
 
 
