@@ -366,7 +366,9 @@ static hipError_t ml_pv_launch(const LaunchCtx &c, const DevProto &P, const PVAr
 #define PV_LAUNCH(CM, EM)                                                                                      \
     hipLaunchKernelGGL((k_ml_fit_pv<T, CM, EM, PLUS>), g, b, 0, c.stream, P, A, X, maps, N, n_gn, loading, incr, \
                        nll, partials)
-    if (P.C <= 4 && emax <= 6)
+    if (P.C <= 4 && emax <= 5)
+        PV_LAUNCH(4, 5);
+    else if (P.C <= 4 && emax <= 6)
         PV_LAUNCH(4, 6);
     else if (P.C <= 4 && emax <= 8)
         PV_LAUNCH(4, 8);

@@ -13,8 +13,8 @@ namespace mpm {
 // angle per contrast and TE per echo are arrays over voxels (tr, flip [C][N],
 // te [I][N]; DevProto's tr, flip, te are unused).  With CM, EM > 0 the
 // voxel's echoes, echo times, TRs and flip-angle terms are held in registers
-// (slots past a contrast's last echo are skipped: the echo counts are shared,
-// so the test is uniform); CM = EM = 0 reads them at every evaluation.  The
+// (slots past a contrast's last echo repeat it with weight 0, so the echo
+// loops carry no tests); CM = EM = 0 reads them at every evaluation.  The
 // per-echo arithmetic is the shared-protocol one.
 // ---------------------------------------------------------------------------
 struct PVArrays {
@@ -64,12 +64,11 @@ struct VoxelEchoesPV {
                 an[c] = make_angle(f);
 #pragma unroll
                 for (int e = 0; e < EM; e++) {
-                    if (e < ne) {
-                        const int64_t i = P.first[c] + e;
-                        x[c][e] = load_echo(X + i * N + n);
-                        te[c][e] = A.te[i * N + n];
-                        ok = ok && te[c][e] >= 0.0f && te[c][e] < INFINITY;
-                    }
+                    // slots past the last echo repeat it (weight 0 in the table)
+                    const int64_t i = P.first[c] + (e < ne ? e : ne - 1);
+                    x[c][e] = load_echo(X + i * N + n);
+                    te[c][e] = A.te[i * N + n];
+                    ok = ok && te[c][e] >= 0.0f && te[c][e] < INFINITY;
                 }
             }
         }
@@ -89,15 +88,12 @@ struct VoxelEchoesPV {
 #pragma unroll
         for (int c = 0; c < CM; c++) {
             if (c < P.C) {
-                const int ne = P.first[c + 1] - P.first[c];
                 const ContrastK F = contrast_factors(p, tr[c], an[c], P.mt[c]);
                 EchoAcc acc;
 #pragma unroll
                 for (int e = 0; e < EM; e++) {
-                    if (e < ne) {
-                        const float t = te[c][e];
-                        acc.add(F.s0 * __builtin_amdgcn_exp2f(k2 * t), x[c][e], t, t * t, W[c * EM + e], p.r2);
-                    }
+                    const float t = te[c][e];
+                    acc.add(F.s0 * __builtin_amdgcn_exp2f(k2 * t), x[c][e], t, t * t, W[c * EM + e], p.r2);
                 }
                 nll += 0.5f * acc.L;
                 if (grad) accumulate_contrast<PLUS>(acc, F, p.r2, loading, g, H);
