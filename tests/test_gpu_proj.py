@@ -183,3 +183,33 @@ def test_projected_uncertainty_parity(torch_cuda, orc):
     rel = np.abs(v[ok] - var_o[ok]) / var_o[ok]
     print("projected variance rel max", rel.max())
     assert rel.max() <= 1e-3
+
+
+def test_space_outside_the_field_of_view(torch_cuda, orc):
+    """A contrast acquired entirely outside the reconstruction field of view
+    carries no observation (all its echoes are missing): the fit equals the
+    oracle's, every map stays finite, and the MT map keeps its start (only the
+    MT contrast informs it)."""
+    torch = torch_cuda
+    c, spaces, x = _problem(orc, seed=66)
+    far = dict(spaces[2])
+    A = np.array(far["affine"], dtype=np.float64).reshape(3, 4).copy()
+    A[:, 3] += np.array([1000.0, 0.0, 0.0])
+    far["affine"] = A
+    spaces = [spaces[0], spaces[1], far]
+    sizes = [int(np.prod(sp["dims"])) * ne for sp, ne in zip(spaces, c["proto"]["n_echoes"])]
+    X = torch.empty(sum(sizes), dtype=torch.float32, device="cuda")
+    _lib.mpm_simulate_projected(c["proto"], c["dims"], spaces, cuda(c["truth"].astype(np.float32)),
+                                cuda(c["b1"].astype(np.float32)), None, X)
+    xs = X.cpu().numpy().astype(np.float64)
+    assert np.all(np.isnan(xs[sizes[0] + sizes[1]:]))
+    y0 = [6.6, 0.0, 3.2, -4.2]
+    opts = dict(c["opts"], n_outer=2, n_gn=2, n_cg=8, init="const", init_const=y0)
+    y_gpu, rep, _ = _gpu_fit(torch, c, spaces, xs, opts)
+    y_orc, rep_o, _ = orc.fit_projected(c["proto"], c["dims"], spaces, xs, c["b1"], dict(opts, init_const=f32(y0)))
+    assert np.all(np.isfinite(y_gpu)) and rep["nonfinite_voxels"] == 0
+    rel, _, _ = map_errors(y_gpu, y_orc)
+    print("outside-FOV contrast: rel", rel)
+    assert (rel <= TOL).all()
+    assert np.abs(y_gpu[3] - np.float32(y0[3])).max() <= 1e-6
+

@@ -183,3 +183,17 @@ def test_generic_shape_and_fp16_and_start_maps(torch_cuda, orc):
     rel, _, _ = map_errors(yg, yo, good)
     print("generic shape, FP16 storage: rel", rel, "well-posed", good.mean())
     assert good.mean() > 0.9 and (rel <= TOL).all()
+
+
+def test_single_voxel_and_zero_steps(torch_cuda, orc):
+    shape, tr, flip, te, x, truth = _jittered_problem(orc, 1, 75)
+    y0 = [6.5, 0.0, 3.2, -4.2]
+    for steps in (0, 12):
+        opts = {"n_gn": steps, "init": "const", "init_const": y0}
+        yg, ig, ng, rg = _gpu(torch_cuda, shape, tr, flip, te, x, opts)
+        yo, io, no, ro = orc.fit_voxelwise(shape, tr, flip, te, x, dict(opts, init_const=f32(y0)), rise_rel=1e-5)
+        assert np.allclose(yg, yo, rtol=1e-5, atol=1e-5)
+        assert ng[0] == pytest.approx(no[0], rel=1e-4)
+        if steps == 0:
+            assert np.array_equal(yg[:, 0], f32(y0)) and ig[0] == 0 and rg["degenerate_voxels"] == 0
+
