@@ -124,8 +124,8 @@ def main():
                          "calibration, then exit")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU z-slab design is "
-              "described in DESIGN.md but not built.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the fits are single-GPU; "
+              "a z-slab decomposition across GPUs is not built.", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -42,7 +42,7 @@ extern "C" {
 typedef enum {
     MPM_OK = 0,
     MPM_ERR_INVALID_ARG = 1,   /* a value or pointer failed validation          */
-    MPM_ERR_UNSUPPORTED = 2,   /* a valid request this build does not handle    */
+    MPM_ERR_UNSUPPORTED = 2,   /* a valid request the library does not handle  */
     MPM_ERR_OUT_OF_MEMORY = 3, /* workspace allocation failed                   */
     MPM_ERR_DEVICE = 4,        /* a HIP call failed                             */
     MPM_ERR_BUSY = 5,          /* server: request not finished yet              */

@@ -111,7 +111,7 @@ struct ContrastK {
 // sin(h) and cos(h): h = r + q pi/2 with integer q and |r| <= pi/4 (pi/2 split
 // in two parts, so r is exact to FP32 rounding for |h| < 1e4), then the Taylor
 // series of sin r and cos r, truncated where the next term is below 1e-11,
-// and the quadrant identities.  Flip angles of the configs give q = 0.
+// and the quadrant identities.  Flip angles up to pi/2 (h <= pi/4) give q = 0.
 struct Angle {
     float sa, ca, omc;  // sin(alpha), cos(alpha), 1 - cos(alpha)
 };

@@ -1,7 +1,7 @@
 """Pins for the oracle's ML fit (SPGR-ML, Sec. 2.3-2.4, Sec. 3.1, Sec. 4.1).
 
 * exact recovery of the ground truth from noise-free data;
-* no per-voxel NLL increase at the configs' parameter ranges (the paper's
+* no per-voxel NLL increase at the synthetic tissue parameter ranges (the paper's
   monotonicity claim, Sec. 4.1) and far fewer non-monotone voxels than plain
   Gauss-Newton on the paper's convergence experiment (Sec. 3.1);
 * the ML optimum's mean NLL equals the chi-square expectation (I - K)/2 and
@@ -30,7 +30,7 @@ def test_exact_recovery_noise_free(orc):
     assert np.abs(maps - c["truth"]).max() <= 1e-9
 
 
-def test_no_nll_increase_at_config_ranges(orc):
+def test_no_nll_increase_at_tissue_ranges(orc):
     c = _case(4096, seed=12)
     x = observations(orc, c).astype(np.float64)
     _, rep, trace = orc.fit(c["proto"], c["dims"], x, None, {"mode": "ml", "n_gn": 60})
@@ -123,7 +123,7 @@ def test_monotone_step_condition_1d(orc):
 
 
 def test_default_init_near_truth(orc):
-    # constant maps at the centre of the configs' ranges, noise-free
+    # constant maps at the centre of the synthetic tissue ranges, noise-free
     n = 64
     truth = synth.encode(np.full(n, 750.0), np.full(n, 1.0), np.full(n, 25.0), np.full(n, 0.0125))
     proto = synth.protocol()
