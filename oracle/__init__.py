@@ -61,7 +61,7 @@ class Options(C.Structure):
                 ("n_cg", C.c_int32), ("max_halvings", C.c_int32), ("loading", C.c_int32),
                 ("init_kind", C.c_int32), ("pad_", C.c_int32), ("lam", C.c_double * 4),
                 ("jtv_eps", C.c_double), ("cg_stop", C.c_double),
-                ("init_const", C.c_double * 4)]
+                ("init_const", C.c_double * 4), ("tol_gn", C.c_double), ("tol_outer", C.c_double)]
 
 
 class Report(C.Structure):
@@ -170,6 +170,8 @@ def make_options(opts: dict) -> Options:
     ic = opts.get("init_const", (0.0, 0.0, 0.0, 0.0))
     for k in range(4):
         o.init_const[k] = float(ic[k])
+    o.tol_gn = float(opts.get("tol_gn", 0.0))
+    o.tol_outer = float(opts.get("tol_outer", 0.0))
     return o
 
 

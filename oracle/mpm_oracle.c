@@ -855,6 +855,10 @@ static int fit_impl(const lik_ctx *L, const orc_options *opt, double *maps, orc_
         double *delta = (double *)malloc(sizeof(double) * (size_t)V);
         double *trial = (double *)malloc(sizeof(double) * (size_t)V);
         int slots = opt->n_gn + 2;
+        /* early stopping (reading R-stop): the gain of a step is the decrease it
+         * brings over the decrease since the first value of its sequence */
+        double F_loop0 = 0.0, obj_first = 0.0, obj_prev = 0.0;
+        int n_obj = 0;
 
         for (int t = 0; t < opt->n_outer; t++) {
             if (t >= 1 && lam_sum > 0.0) orc_jtv_weights(dims, maps, opt->lambda, eps, w, d);
@@ -862,6 +866,7 @@ static int fit_impl(const lik_ctx *L, const orc_options *opt, double *maps, orc_
                 double tot = lik_all(L, opt->loading, maps, nll, g, P);
                 orc_apply_L(dims, w, opt->lambda, maps, Ly);
                 double F = tot + 0.5 * dot(maps, Ly, V);
+                if (j == 0) F_loop0 = F;
                 if (trace && j == 0 && t * slots < trace_len) trace[t * slots] = F;
                 for (int64_t i = 0; i < V; i++) b[i] = g[i] + Ly[i];
                 R.cg_done += orc_pcg(dims, P, w, d, opt->lambda, b, opt->n_cg, cg_stop, delta);
@@ -892,11 +897,28 @@ static int fit_impl(const lik_ctx *L, const orc_options *opt, double *maps, orc_
                 }
                 R.gn_done++;
                 if (trace && t * slots + j + 1 < trace_len) trace[t * slots + j + 1] = Fnew;
+                if (opt->tol_gn > 0.0) {
+                    const double den = F_loop0 - Fnew;
+                    if (!(den > 0.0) || F - Fnew < opt->tol_gn * den) break;
+                }
             }
             R.outer_done++;
-            if (trace && t * slots + opt->n_gn + 1 < trace_len) {
+            if ((trace && t * slots + opt->n_gn + 1 < trace_len) || opt->tol_outer > 0.0) {
                 double jt = lam_sum > 0.0 ? orc_jtv_weights(dims, maps, opt->lambda, eps, Ly, NULL) : 0.0;
-                trace[t * slots + opt->n_gn + 1] = lik_all(L, opt->loading, maps, nll, NULL, NULL) + jt;
+                const double O = lik_all(L, opt->loading, maps, nll, NULL, NULL) + jt;
+                if (trace && t * slots + opt->n_gn + 1 < trace_len) trace[t * slots + opt->n_gn + 1] = O;
+                if (opt->tol_outer > 0.0) {
+                    int stop = 0;
+                    if (n_obj == 0) {
+                        obj_first = O;
+                    } else {
+                        const double den = obj_first - O;
+                        stop = !(den > 0.0) || obj_prev - O < opt->tol_outer * den;
+                    }
+                    obj_prev = O;
+                    n_obj++;
+                    if (stop) break;
+                }
             }
         }
         /* final weights, objective and degenerate count (R-w0) */

@@ -62,6 +62,10 @@ typedef struct {
     double  jtv_eps;        /* smoothing of the JTV norm; 0 -> 1e-3*sqrt(sum lambda) */
     double  cg_stop;        /* CG stops when r.z <= cg_stop * r0.z0 (0: fixed count) */
     double  init_const[4];  /* ORC_INIT_CONST values                              */
+    double  tol_gn;         /* MAP: stop an outer loop's Newton steps when the gain of a
+                               step falls below this (0: fixed count; reading R-stop) */
+    double  tol_outer;      /* MAP: stop the outer loops when the gain of one falls below
+                               this (0: fixed count; reading R-stop)                 */
 } orc_options;
 
 typedef struct {
