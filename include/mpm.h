@@ -92,6 +92,13 @@ typedef struct {
     double jtv_eps;        /* MAP: JTV smoothing; 0 -> 1e-3*sqrt(sum lambda)         */
     double cg_stop;        /* MAP: stop CG when r.z <= cg_stop*r0.z0; 0 -> fixed n_cg */
     double init_const[4];  /* MPM_INIT_CONST: the constant initial log-parameters    */
+    /* MAP early stopping (paper Sec. 2.7; the paper's "gain" read as the decrease a
+     * step brings over the decrease since the first value of its sequence): an outer
+     * loop's Newton steps end after the first step whose gain on F_w is below tol_gn;
+     * the outer loops end after the first whose gain on the objective (relative to the
+     * end of the first loop) is below tol_outer.  0 -> fixed counts; finite, >= 0. */
+    double tol_gn;
+    double tol_outer;
 } mpm_options;
 
 typedef struct {

@@ -40,7 +40,8 @@ class mpm_options(C.Structure):
     _fields_ = [("mode", C.c_int32), ("n_outer", C.c_int32), ("n_gn", C.c_int32), ("n_cg", C.c_int32),
                 ("max_halvings", C.c_int32), ("loading", C.c_int32), ("init_kind", C.c_int32),
                 ("flags", C.c_int32), ("lam", C.c_double * 4), ("jtv_eps", C.c_double),
-                ("cg_stop", C.c_double), ("init_const", C.c_double * 4)]
+                ("cg_stop", C.c_double), ("init_const", C.c_double * 4), ("tol_gn", C.c_double),
+                ("tol_outer", C.c_double)]
 
 
 class mpm_report(C.Structure):
@@ -175,6 +176,8 @@ def make_options(opts: dict) -> mpm_options:
     ic = opts.get("init_const", (0.0, 0.0, 0.0, 0.0))
     for k in range(4):
         o.init_const[k] = float(ic[k])
+    o.tol_gn = float(opts.get("tol_gn", 0.0))
+    o.tol_outer = float(opts.get("tol_outer", 0.0))
     return o
 
 

@@ -645,10 +645,21 @@ __device__ __forceinline__ double reduce_row(const double *__restrict__ row, int
     return r;
 }
 
+// Early stopping (reading of the gain in Sec. 2.7): a step from F to Fn ends
+// its outer loop when its decrease is below tol times the decrease since the
+// loop's first F_w (or there was none); the flag takes effect after the
+// step's update.
+__device__ __forceinline__ void stop_on_gain(MapCtl &c, double F, double Fn, double tol)
+{
+    if (!(tol > 0.0)) return;
+    const double den = c.F_loop0 - Fn;
+    if (!(den > 0.0) || F - Fn < tol * den) c.tol_stop = 1;
+}
+
 __global__ __launch_bounds__(FIN_THREADS) void k_fin(int stage, int arg, int nblk,
                                                      const double *__restrict__ partials, MapCtl *__restrict__ ctl,
                                                      double *__restrict__ trace, double cg_stop_rel, int ntrial,
-                                                     int accept_off, ExtRows ext)
+                                                     int accept_off, ExtRows ext, double tol_gn, double tol_outer)
 {
     __shared__ double lds[FIN_THREADS / 64];
     const bool gated = (stage == FIN_W || stage == FIN_STATS) ? false : (ctl->gn_stop != 0);
@@ -658,6 +669,7 @@ __global__ __launch_bounds__(FIN_THREADS) void k_fin(int stage, int arg, int nbl
     double s[MAX_TRIALS];
     const int rows = (stage == FIN_LIK || stage == FIN_ACCEPT || stage == FIN_STATS) ? 3
                      : stage == FIN_ACCEPT2                                          ? MAX_TRIALS
+                     : stage == FIN_STOP                                             ? 0
                                                                                      : 1;
     for (int k = 0; k < rows; k++) s[k] = reduce_row(partials + (int64_t)k * nblk, nblk, lds);
     for (int k = 0; k < rows && k < ext.rows; k++) s[k] += reduce_row(ext.p + (int64_t)k * ext.stride, ext.cols, lds);
@@ -676,7 +688,10 @@ __global__ __launch_bounds__(FIN_THREADS) void k_fin(int stage, int arg, int nbl
         c.p_buf = 0;
         c.accept_more = 0;
         c.cg_stop = !(s[2] > 0.0);
-        if (arg >= 0) trace[arg] = c.F;
+        if (arg >= 0) {  // the first Newton step of an outer loop
+            trace[arg] = c.F;
+            c.F_loop0 = c.F;
+        }
         break;
     case FIN_A: {  // arg: CG iteration
         const double pq = s[0];
@@ -703,6 +718,7 @@ __global__ __launch_bounds__(FIN_THREADS) void k_fin(int stage, int arg, int nbl
         c.c2 = s[2];
         const double F0 = s[0] + 0.5 * (c.yLy - 2.0 * c.c1 + c.c2);
         if (accept_off || F0 <= c.F) {
+            stop_on_gain(c, c.F, F0, tol_gn);
             c.step = 1.0;
             c.nll_cur = s[0];
             c.F = F0;
@@ -732,6 +748,7 @@ __global__ __launch_bounds__(FIN_THREADS) void k_fin(int stage, int arg, int nbl
         }
         c.accept_more = 0;
         if (chosen >= 0) {
+            stop_on_gain(c, c.F, Fc, tol_gn);
             c.step = t;
             c.nll_cur = s[chosen];
             c.F = Fc;
@@ -744,10 +761,31 @@ __global__ __launch_bounds__(FIN_THREADS) void k_fin(int stage, int arg, int nbl
         }
         break;
     }
-    case FIN_W:  // arg: trace slot for "objective at the end of the outer loop" or -1
+    case FIN_W: {  // the end of an outer loop; arg: its trace slot or -1
+        const bool stopped = c.outer_stop != 0;
+        const double O = c.nll_cur + s[0];
         c.jtv = s[0];
-        if (arg >= 0) trace[arg] = c.nll_cur + s[0];
-        c.gn_stop = 0;
+        if (!stopped) {
+            if (arg >= 0) trace[arg] = O;
+            c.outer_done++;
+            if (c.n_obj == 0) {
+                c.obj_first = O;
+            } else if (tol_outer > 0.0) {
+                const double den = c.obj_first - O;
+                if (!(den > 0.0) || c.obj_prev - O < tol_outer * den) c.outer_stop = 1;
+            }
+            c.obj_prev = O;
+            c.n_obj++;
+        }
+        c.gn_stop = c.outer_stop;
+        c.tol_stop = 0;
+        break;
+    }
+    case FIN_STOP:  // after the update of a step that ended its outer loop
+        if (c.tol_stop) {
+            c.gn_stop = 1;
+            c.tol_stop = 0;
+        }
         break;
     case FIN_STATS:
         c.nll_final = s[0];
@@ -875,7 +913,7 @@ hipError_t launch_fin(hipStream_t s, const MapArgs &a, int stage, int arg, int n
                       int ntrial, int accept_off, const ExtRows &ext)
 {
     hipLaunchKernelGGL(k_fin, dim3(1), dim3(FIN_THREADS), 0, s, stage, arg, nblk, a.partials, a.ctl, a.trace,
-                       cg_stop_rel, ntrial, accept_off, ext);
+                       cg_stop_rel, ntrial, accept_off, ext, a.tol_gn, a.tol_outer);
     return hipGetLastError();
 }
 

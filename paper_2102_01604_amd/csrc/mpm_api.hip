@@ -330,6 +330,8 @@ mpm_status check_fit_args(const mpm_protocol *protocol, const mpm_grid *grid, in
             return fail(MPM_ERR_INVALID_ARG, "init_const[%d] is not finite", k);
     }
     if (!(opt->jtv_eps >= 0.0) || !(opt->cg_stop >= 0.0)) return fail(MPM_ERR_INVALID_ARG, "jtv_eps and cg_stop must be >= 0");
+    if (!(opt->tol_gn >= 0.0) || !std::isfinite(opt->tol_gn) || !(opt->tol_outer >= 0.0) || !std::isfinite(opt->tol_outer))
+        return fail(MPM_ERR_INVALID_ARG, "tol_gn and tol_outer must be finite and >= 0");
     if (!has_mt(protocol))
         return fail(MPM_ERR_UNSUPPORTED, "the four-parameter model needs at least one MT contrast");
     if (opt->mode == MPM_MAP_JTV && *N < 2) return fail(MPM_ERR_UNSUPPORTED, "MAP needs at least 2 voxels");

@@ -85,6 +85,13 @@ struct MapCtl {
     int p_buf;          // buffer holding the last search direction
     int cg_done, gn_done, rejected;
     int accept_more;    // the full step was rejected: evaluate the halvings
+    // early stopping on the gain of a step (Newton) or an outer loop
+    double F_loop0;     // F_w before the first Newton step of this outer loop
+    double obj_first, obj_prev;  // objective at the end of the first / previous outer loop
+    int n_obj;          // outer loops ended so far
+    int outer_done;     // outer loops run
+    int outer_stop;     // the remaining outer loops are skipped
+    int tol_stop;       // the accepted step ends this outer loop (set after its update)
 };
 
 // ---------------------------------------------------------------------------
@@ -246,7 +253,7 @@ struct DeltaF {
     }
 };
 
-enum { FIN_LIK = 0, FIN_A = 1, FIN_B = 2, FIN_ACCEPT = 3, FIN_W = 4, FIN_STATS = 5, FIN_ACCEPT2 = 6 };
+enum { FIN_LIK = 0, FIN_A = 1, FIN_B = 2, FIN_ACCEPT = 3, FIN_W = 4, FIN_STATS = 5, FIN_ACCEPT2 = 6, FIN_STOP = 7 };
 
 struct MapArgs {
     Grid3 g;
@@ -267,6 +274,7 @@ struct MapArgs {
     MapCtl *ctl;
     double *partials;   // [MAX_TRIALS + 2][nblk]
     double *trace;      // device copy of the objective trace
+    double tol_gn, tol_outer;  // early-stopping tolerances (0: fixed counts)
 };
 
 hipError_t launch_ctl_init(hipStream_t s, MapCtl *ctl, double *trace, int trace_len);

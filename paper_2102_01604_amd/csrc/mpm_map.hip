@@ -186,6 +186,7 @@ struct MapJob : FitJob {
             opt_local.n_outer = 1;
             opt_local.n_cg = 1;
             opt_local.max_halvings = -1;
+            opt_local.tol_gn = opt_local.tol_outer = 0.0;  // tolerances are MAP options
             for (int k = 0; k < 4; k++) opt_local.lambda[k] = 0.0;
             a.opt = &opt_local;
         }
@@ -200,6 +201,8 @@ struct MapJob : FitJob {
         if (host.alloc(sizeof(MapCtl) + sizeof(double) * (size_t)(tl > 0 ? tl : 1)) != hipSuccess)
             return fail(MPM_ERR_OUT_OF_MEMORY, "pinned host allocation failed");
         set_prior(o, m, true, prior_on);
+        m.tol_gn = o->tol_gn;
+        m.tol_outer = o->tol_outer;
         ntrial = o->max_halvings < 0 ? 1 : o->max_halvings + 1;
         accept_off = o->max_halvings < 0;
         nb_col = grid_blocks(m.g);
@@ -317,6 +320,7 @@ struct MapJob : FitJob {
                 }
             }
             RUN("map_update", N * 64.0, launch_update(s, m));
+            if (m.tol_gn > 0.0) RUN("fin", 0.0, fin(FIN_STOP, -1, 0));
             if (++j == J) {
                 j = 0;
                 t++;
@@ -360,7 +364,7 @@ struct MapJob : FitJob {
         rep.nll = h.nll_final;
         rep.jtv = prior_on ? h.jtv : 0.0;
         rep.objective = rep.nll + rep.jtv;
-        rep.outer_done = ml_as_map ? 0 : T;
+        rep.outer_done = ml_as_map ? 0 : h.outer_done;
         rep.gn_done = h.gn_done;
         rep.cg_done = h.cg_done;
         rep.rejected = h.rejected;

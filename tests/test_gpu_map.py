@@ -187,3 +187,17 @@ def test_map_whole_brain_launch_configuration(torch_cuda, orc):
     rv = np.abs(v[:, ok] - var_o[:, ok]) / var_o[:, ok]
     print("whole brain: variance at the truth, rel err max", rv.max(axis=1))
     assert rv.max() <= 2e-3
+
+
+@pytest.mark.parametrize("which,seed,sched", [("tol_gn", 81, (3, 8, 16)), ("tol_outer", 82, (8, 2, 12))])
+def test_map_early_stopping_parity(torch_cuda, orc, which, seed, sched):
+    """Gain-based early stopping (Sec. 2.7): the same steps and loops are cut
+    as by the oracle (the trace's NaN pattern), and the maps agree."""
+    c, x = _inputs(orc, "map_brain", (24, 20, 12), seed=seed)
+    opts = _const_opts(orc, c, x, n_outer=sched[0], n_gn=sched[1], n_cg=sched[2])
+    opts[which] = 0.05
+    y_gpu, y_orc, rep, rep_o = _compare(orc, torch_cuda, c, x, opts)
+    print(which, "gpu", rep, "orc", rep_o)
+    assert rep["outer_done"] == rep_o["outer_done"]
+    full = sched[0] * sched[1]
+    assert rep["gn_done"] < full  # something was cut
