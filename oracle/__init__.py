@@ -61,7 +61,8 @@ class Options(C.Structure):
                 ("n_cg", C.c_int32), ("max_halvings", C.c_int32), ("loading", C.c_int32),
                 ("init_kind", C.c_int32), ("pad_", C.c_int32), ("lam", C.c_double * 4),
                 ("jtv_eps", C.c_double), ("cg_stop", C.c_double),
-                ("init_const", C.c_double * 4), ("tol_gn", C.c_double), ("tol_outer", C.c_double)]
+                ("init_const", C.c_double * 4), ("tol_gn", C.c_double), ("tol_outer", C.c_double),
+                ("b1_receive", C.c_void_p)]
 
 
 class Report(C.Structure):
@@ -172,6 +173,9 @@ def make_options(opts: dict) -> Options:
         o.init_const[k] = float(ic[k])
     o.tol_gn = float(opts.get("tol_gn", 0.0))
     o.tol_outer = float(opts.get("tol_outer", 0.0))
+    bm = opts.get("b1_receive")
+    if bm is not None:  # the caller keeps the array alive (fit and uncertainty hold it)
+        o.b1_receive = bm.ctypes.data
     return o
 
 
@@ -297,12 +301,20 @@ def trace_len(opts: dict) -> int:
     return int(opts.get("n_outer", 1)) * (int(opts.get("n_gn", 20)) + 2)
 
 
+def _with_receive(opts, N):
+    """opts with "b1_receive" (receive field [N]) as a contiguous float64 array."""
+    if opts.get("b1_receive") is None:
+        return opts
+    return dict(opts, b1_receive=np.ascontiguousarray(opts["b1_receive"], dtype=np.float64).reshape(N))
+
+
 def fit(proto, dims, x, b1, opts: dict, maps0=None):
     """Run the fit.  Returns (maps [4][N], report dict, trace array)."""
     lib = _load()
     N = int(np.prod(dims))
     x = _f64(x).reshape(n_images(proto), N)
     b1 = None if b1 is None else _f64(b1).reshape(N)
+    opts = _with_receive(opts, N)
     o = make_options(opts)
     if maps0 is not None:
         maps = _f64(maps0).reshape(4, N).copy()
@@ -358,6 +370,7 @@ def uncertainty(proto, dims, x, b1, opts: dict, maps, moments=False):
     x = _f64(x).reshape(n_images(proto), N)
     b1 = None if b1 is None else _f64(b1).reshape(N)
     maps = _f64(maps).reshape(4, N)
+    opts = _with_receive(opts, N)
     o = make_options(opts)
     var = np.empty((4, N))
     mom = np.empty((4, N)) if moments else None

@@ -531,6 +531,7 @@ typedef struct {
     const orc_space *spaces;
     const double *x;
     const double *b1;
+    const double *b1m; /* receive field [N] or NULL (reconstruction grid only) */
 } lik_ctx;
 
 /* The protocol restricted to contrast c. */
@@ -569,6 +570,9 @@ static double lik_all(const lik_ctx *L, int loading, const double *maps, double 
 #pragma omp parallel for schedule(static)
         for (int64_t n = 0; n < N; n++) {
             double y[4] = {maps[n], maps[N + n], maps[2 * N + n], maps[3 * N + n]};
+            /* the receive field multiplies the signal: s = b- A f(...) = exp(log A + log b-) f(...),
+             * so the likelihood, g and P~ are those at log A + log b- (Sec. 2.4) */
+            if (L->b1m) y[0] += log(L->b1m[n]);
             double gl[4], Pl[16], l;
             orc_lik_voxel(p, L->x + n, N, y, L->b1 ? L->b1[n] : 1.0, loading, &l, gl, Pl);
             nll[n] = l;
@@ -959,7 +963,7 @@ static int fit_impl(const lik_ctx *L, const orc_options *opt, double *maps, orc_
 int orc_fit(const orc_protocol *p, const int64_t dims[3], const double *x, const double *b1,
             const orc_options *opt, double *maps, orc_report *rep, double *trace, int32_t trace_len)
 {
-    lik_ctx L = {p, dims, NULL, x, b1};
+    lik_ctx L = {p, dims, NULL, x, b1, opt->b1_receive};
     return fit_impl(&L, opt, maps, rep, trace, trace_len);
 }
 
@@ -1116,7 +1120,7 @@ static int uncertainty_impl(const lik_ctx *L, const orc_options *opt, const doub
 int orc_uncertainty(const orc_protocol *p, const int64_t dims[3], const double *x, const double *b1,
                     const orc_options *opt, const double *maps, double *var, double *moments)
 {
-    lik_ctx L = {p, dims, NULL, x, b1};
+    lik_ctx L = {p, dims, NULL, x, b1, opt->b1_receive};
     return uncertainty_impl(&L, opt, maps, var, moments);
 }
 

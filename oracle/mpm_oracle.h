@@ -66,6 +66,8 @@ typedef struct {
                                step falls below this (0: fixed count; reading R-stop) */
     double  tol_outer;      /* MAP: stop the outer loops when the gain of one falls below
                                this (0: fixed count; reading R-stop)                 */
+    const double *b1_receive; /* [N] net receive field b-_n multiplying every image of
+                               voxel n (Sec. 2.4), or NULL; orc_fit and orc_uncertainty */
 } orc_options;
 
 typedef struct {
