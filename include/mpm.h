@@ -99,6 +99,11 @@ typedef struct {
      * end of the first loop) is below tol_outer.  0 -> fixed counts; finite, >= 0. */
     double tol_gn;
     double tol_outer;
+    /* Net receive field (paper Sec. 2.4, footnote): device float [N], > 0, that
+     * multiplies the modelled signal of each voxel (A -> A * b1_receive[n]), or
+     * NULL for none.  Read by mpm_fit, mpm_uncertainty and the server; the
+     * projected and per-voxel-protocol fits reject it (MPM_ERR_UNSUPPORTED). */
+    const float *b1_receive;
 } mpm_options;
 
 typedef struct {

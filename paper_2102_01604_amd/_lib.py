@@ -41,7 +41,7 @@ class mpm_options(C.Structure):
                 ("max_halvings", C.c_int32), ("loading", C.c_int32), ("init_kind", C.c_int32),
                 ("flags", C.c_int32), ("lam", C.c_double * 4), ("jtv_eps", C.c_double),
                 ("cg_stop", C.c_double), ("init_const", C.c_double * 4), ("tol_gn", C.c_double),
-                ("tol_outer", C.c_double)]
+                ("tol_outer", C.c_double), ("b1_receive", C.c_void_p)]
 
 
 class mpm_report(C.Structure):
@@ -178,6 +178,8 @@ def make_options(opts: dict) -> mpm_options:
         o.init_const[k] = float(ic[k])
     o.tol_gn = float(opts.get("tol_gn", 0.0))
     o.tol_outer = float(opts.get("tol_outer", 0.0))
+    bm = opts.get("b1_receive")
+    o.b1_receive = None if bm is None else _f32(bm, "b1_receive").value
     return o
 
 
@@ -375,7 +377,7 @@ class MpmServer:
         r.maps = maps.data_ptr()
         t = C.c_uint64()
         _check(load().mpm_server_submit(self._h, C.byref(r), C.byref(t)))
-        self._keep[t.value] = (echoes, b1, maps)
+        self._keep[t.value] = (echoes, b1, maps, options.get("b1_receive"))
         return t.value
 
     def step(self) -> int:

@@ -96,6 +96,7 @@ __global__ void k_ctl_init(MapCtl *ctl, double *trace, int trace_len)
 template <bool PLUS, typename T, int CM, int EM>
 __device__ __forceinline__ void lik_body(const Grid3 &g, const typename VoxelEchoes<T, CM, EM>::Proto &P,
                                          const T *__restrict__ X, const float *__restrict__ b1,
+                                         const float *__restrict__ bm,
                                          const float *__restrict__ Y, const float *__restrict__ w, float l0, float l1,
                                          float l2, float l3, int loading, const HessArrays &Hs,
                                          float4 *__restrict__ R, float4 *__restrict__ Z,
@@ -110,7 +111,7 @@ __device__ __forceinline__ void lik_body(const Grid3 &g, const typename VoxelEch
     if (c.act) {
         const int64_t n = c.base + (int64_t)c.z0 * c.sxy;
         VoxelEchoes<T, CM, EM> ve;
-        ve.load(P, X, N, n, b1 ? b1[n] : 1.0f);
+        ve.load(P, X, N, n, b1 ? b1[n] : 1.0f, bm ? bm[n] : 1.0f);
         float y0[4];
         load4(Y, N, n, y0);
         const float w0 = w[n];
@@ -143,10 +144,11 @@ __device__ __forceinline__ void lik_body(const Grid3 &g, const typename VoxelEch
 
 #define LIK_PARAMS                                                                                           \
     Grid3 g, typename VoxelEchoes<T, CM, EM>::Proto P, const T *__restrict__ X, const float *__restrict__ b1, \
+        const float *__restrict__ bm,                                                                        \
         const float *__restrict__ Y, const float *__restrict__ w, float l0, float l1, float l2, float l3,       \
         int loading, HessArrays Hs, float4 *__restrict__ R, float4 *__restrict__ Z,                             \
         const MapCtl *__restrict__ ctl, double *__restrict__ partials
-#define LIK_ARGS g, P, X, b1, Y, w, l0, l1, l2, l3, loading, Hs, R, Z, ctl, partials
+#define LIK_ARGS g, P, X, b1, bm, Y, w, l0, l1, l2, l3, loading, Hs, R, Z, ctl, partials
 
 template <typename T, int CM, int EM>
 __global__ __launch_bounds__(BLOCK) void k_lik(LIK_PARAMS) { lik_body<false, T, CM, EM>(LIK_ARGS); }
@@ -376,6 +378,7 @@ __global__ __launch_bounds__(CGB_THREADS) void k_cg_b(Grid3 g, HessArrays Hs, co
 template <typename T, int CM, int EM>
 __global__ __launch_bounds__(BLOCK) void k_accept(Grid3 g, typename VoxelEchoes<T, CM, EM>::Proto P,
                                                   const T *__restrict__ X, const float *__restrict__ b1,
+                                                  const float *__restrict__ bm,
                                                   const float *__restrict__ Y, const float *__restrict__ w, float l0,
                                                   float l1, float l2, float l3, const float4 *__restrict__ D,
                                                   const float4 *__restrict__ P0, const float4 *__restrict__ P1,
@@ -391,7 +394,7 @@ __global__ __launch_bounds__(BLOCK) void k_accept(Grid3 g, typename VoxelEchoes<
     if (c.act) {
         const int64_t n = c.base + (int64_t)c.z0 * c.sxy;
         VoxelEchoes<T, CM, EM> ve;
-        ve.load(P, X, N, n, b1 ? b1[n] : 1.0f);
+        ve.load(P, X, N, n, b1 ? b1[n] : 1.0f, bm ? bm[n] : 1.0f);
         float y0[4], d0[4];
         load4(Y, N, n, y0);
         getd(n, d0);
@@ -428,6 +431,7 @@ __global__ __launch_bounds__(BLOCK) void k_accept(Grid3 g, typename VoxelEchoes<
 template <typename T, int CM, int EM>
 __global__ __launch_bounds__(BLOCK) void k_accept2(Grid3 g, typename VoxelEchoes<T, CM, EM>::Proto P,
                                                    const T *__restrict__ X, const float *__restrict__ b1,
+                                                   const float *__restrict__ bm,
                                                    const float *__restrict__ Y, const float4 *__restrict__ D,
                                                    const float4 *__restrict__ P0, const float4 *__restrict__ P1,
                                                    int ntrial, const MapCtl *__restrict__ ctl,
@@ -445,7 +449,7 @@ __global__ __launch_bounds__(BLOCK) void k_accept2(Grid3 g, typename VoxelEchoes
         for (int z = c.z0; z < c.z1; z++) {
             const int64_t n = c.base + (int64_t)z * c.sxy;
             VoxelEchoes<T, CM, EM> ve;
-            ve.load(P, X, N, n, b1 ? b1[n] : 1.0f);
+            ve.load(P, X, N, n, b1 ? b1[n] : 1.0f, bm ? bm[n] : 1.0f);
             float y[4], df[4];
             load4(Y, N, n, y);
             getd(n, df);
@@ -542,6 +546,7 @@ __global__ __launch_bounds__(BLOCK) void k_weights(Grid3 g, const float *__restr
 template <bool PLUS, typename T, int CM, int EM>
 __device__ __forceinline__ void final_body(const Grid3 &g, const typename VoxelEchoes<T, CM, EM>::Proto &P,
                                            const T *__restrict__ X, const float *__restrict__ b1,
+                                           const float *__restrict__ bm,
                                            const float *__restrict__ Y, const float *__restrict__ w, float l0,
                                            float l1, float l2, float l3, int loading, float *__restrict__ var,
                                            float *__restrict__ mom, double *__restrict__ partials)
@@ -554,7 +559,7 @@ __device__ __forceinline__ void final_body(const Grid3 &g, const typename VoxelE
     if (c.act) {
         const int64_t n = c.base + (int64_t)c.z0 * c.sxy;
         VoxelEchoes<T, CM, EM> ve;
-        ve.load(P, X, N, n, b1 ? b1[n] : 1.0f);
+        ve.load(P, X, N, n, b1 ? b1[n] : 1.0f, bm ? bm[n] : 1.0f);
         const float w0 = w[n];
         float d = 0.f;
         for_inplane(c, n, g.nx, [&](int64_t m) { d += w0 + w[m]; });
@@ -607,9 +612,10 @@ __device__ __forceinline__ void final_body(const Grid3 &g, const typename VoxelE
 
 #define FINAL_PARAMS                                                                                         \
     Grid3 g, typename VoxelEchoes<T, CM, EM>::Proto P, const T *__restrict__ X, const float *__restrict__ b1, \
+        const float *__restrict__ bm,                                                                        \
         const float *__restrict__ Y, const float *__restrict__ w, float l0, float l1, float l2, float l3,       \
         int loading, float *__restrict__ var, float *__restrict__ mom, double *__restrict__ partials
-#define FINAL_ARGS g, P, X, b1, Y, w, l0, l1, l2, l3, loading, var, mom, partials
+#define FINAL_ARGS g, P, X, b1, bm, Y, w, l0, l1, l2, l3, loading, var, mom, partials
 
 template <typename T, int CM, int EM>
 __global__ __launch_bounds__(BLOCK) void k_final(FINAL_PARAMS) { final_body<false, T, CM, EM>(FINAL_ARGS); }
@@ -840,10 +846,11 @@ hipError_t launch_lik(hipStream_t s, const MapArgs &a)
 {
     const float *l = a.lam;
     if (a.loading == 2)
-        DISPATCH_T(k_lik_plus, a.gp, a.b1, a.Y, a.w, l[0], l[1], l[2], l[3], a.loading, a.H, a.R, a.Z, a.ctl,
+        DISPATCH_T(k_lik_plus, a.gp, a.b1, a.bm, a.Y, a.w, l[0], l[1], l[2], l[3], a.loading, a.H, a.R, a.Z, a.ctl,
                    a.partials);
     else
-        DISPATCH_T(k_lik, a.gp, a.b1, a.Y, a.w, l[0], l[1], l[2], l[3], a.loading, a.H, a.R, a.Z, a.ctl, a.partials);
+        DISPATCH_T(k_lik, a.gp, a.b1, a.bm, a.Y, a.w, l[0], l[1], l[2], l[3],
+                   a.loading, a.H, a.R, a.Z, a.ctl, a.partials);
     return hipGetLastError();
 }
 
@@ -873,14 +880,14 @@ int cg_b_rows() { return CGB_Y; }
 hipError_t launch_accept(hipStream_t s, const MapArgs &a)
 {
     const float *l = a.lam;
-    DISPATCH_T(k_accept, a.gp, a.b1, a.Y, a.w, l[0], l[1], l[2], l[3], a.D, a.P0, a.P1, a.ctl,
+    DISPATCH_T(k_accept, a.gp, a.b1, a.bm, a.Y, a.w, l[0], l[1], l[2], l[3], a.D, a.P0, a.P1, a.ctl,
                a.partials);
     return hipGetLastError();
 }
 
 hipError_t launch_accept2(hipStream_t s, const MapArgs &a, int ntrial)
 {
-    DISPATCH_T(k_accept2, a.g, a.b1, a.Y, a.D, a.P0, a.P1, ntrial, a.ctl, a.partials);
+    DISPATCH_T(k_accept2, a.g, a.b1, a.bm, a.Y, a.D, a.P0, a.P1, ntrial, a.ctl, a.partials);
     return hipGetLastError();
 }
 
@@ -903,9 +910,9 @@ hipError_t launch_final(hipStream_t s, const MapArgs &a, float *var, float *mom)
 {
     const float *l = a.lam;
     if (a.loading == 2)
-        DISPATCH_T(k_final_plus, a.gp, a.b1, a.Y, a.w, l[0], l[1], l[2], l[3], a.loading, var, mom, a.partials);
+        DISPATCH_T(k_final_plus, a.gp, a.b1, a.bm, a.Y, a.w, l[0], l[1], l[2], l[3], a.loading, var, mom, a.partials);
     else
-        DISPATCH_T(k_final, a.gp, a.b1, a.Y, a.w, l[0], l[1], l[2], l[3], a.loading, var, mom, a.partials);
+        DISPATCH_T(k_final, a.gp, a.b1, a.bm, a.Y, a.w, l[0], l[1], l[2], l[3], a.loading, var, mom, a.partials);
     return hipGetLastError();
 }
 
@@ -922,7 +929,8 @@ hipError_t launch_lik_pushed(hipStream_t s, const MapArgs &a, const PushedProto 
 {
     const float *l = a.lam;
     hipLaunchKernelGGL((k_lik<Pushed, 0, 0>), cols(a.gp), dim3(BLOCK), 0, s, a.gp, pp, (const Pushed *)nullptr,
-                       (const float *)nullptr, a.Y, a.w, l[0], l[1], l[2], l[3], a.loading, a.H, a.R, a.Z, a.ctl,
+                       (const float *)nullptr, (const float *)nullptr,
+                       a.Y, a.w, l[0], l[1], l[2], l[3], a.loading, a.H, a.R, a.Z, a.ctl,
                        a.partials);
     return hipGetLastError();
 }
@@ -931,7 +939,8 @@ hipError_t launch_accept_pushed(hipStream_t s, const MapArgs &a, const PushedPro
 {
     const float *l = a.lam;
     hipLaunchKernelGGL((k_accept<Pushed, 0, 0>), cols(a.gp), dim3(BLOCK), 0, s, a.gp, pp, (const Pushed *)nullptr,
-                       (const float *)nullptr, a.Y, a.w, l[0], l[1], l[2], l[3], a.D, a.P0, a.P1, a.ctl, a.partials);
+                       (const float *)nullptr, (const float *)nullptr,
+                       a.Y, a.w, l[0], l[1], l[2], l[3], a.D, a.P0, a.P1, a.ctl, a.partials);
     return hipGetLastError();
 }
 
@@ -939,7 +948,8 @@ hipError_t launch_final_pushed(hipStream_t s, const MapArgs &a, const PushedProt
 {
     const float *l = a.lam;
     hipLaunchKernelGGL((k_final<Pushed, 0, 0>), cols(a.gp), dim3(BLOCK), 0, s, a.gp, pp, (const Pushed *)nullptr,
-                       (const float *)nullptr, a.Y, a.w, l[0], l[1], l[2], l[3], a.loading, var, mom, a.partials);
+                       (const float *)nullptr, (const float *)nullptr,
+                       a.Y, a.w, l[0], l[1], l[2], l[3], a.loading, var, mom, a.partials);
     return hipGetLastError();
 }
 

@@ -206,7 +206,8 @@ int ml_fit_blocks(int64_t N) { return (int)((N + BLOCK - 1) / BLOCK); }
 
 template <typename T, int CM, int EM, bool PLUS>
 __global__ __launch_bounds__(BLOCK) void k_ml_fit(typename VoxelEchoes<T, CM, EM>::Proto P, const T *__restrict__ X,
-                                                  const float *__restrict__ b1, float *__restrict__ maps,
+                                                  const float *__restrict__ b1, const float *__restrict__ bm,
+                                                  float *__restrict__ maps,
                                                   int64_t N, int n_gn, int loading,
                                                   double *__restrict__ partials)
 {
@@ -218,7 +219,7 @@ __global__ __launch_bounds__(BLOCK) void k_ml_fit(typename VoxelEchoes<T, CM, EM
 
     const auto K = VoxelEchoes<T, CM, EM>::stage(P);
     VoxelEchoes<T, CM, EM> ve;
-    ve.load(P, X, N, nn, b1 ? b1[nn] : 1.0f);
+    ve.load(P, X, N, nn, b1 ? b1[nn] : 1.0f, bm ? bm[nn] : 1.0f);
     float y[4] = {maps[nn], maps[N + nn], maps[2 * N + nn], maps[3 * N + nn]};
 
     float prev_nll = 0.0f;
@@ -258,43 +259,44 @@ __global__ __launch_bounds__(BLOCK) void k_ml_fit(typename VoxelEchoes<T, CM, EM
 }
 
 template <typename T, bool PLUS>
-static hipError_t ml_launch(const LaunchCtx &c, const DevProto &P, const T *X, const float *b1,
+static hipError_t ml_launch(const LaunchCtx &c, const DevProto &P, const T *X, const float *b1, const float *bm,
                               float *maps, int64_t N, int n_gn, int loading, double *partials, int nblk)
 {
     dim3 g(nblk), b(BLOCK);
     const int shape = echo_shape(P);
     if (shape == 1)
-        hipLaunchKernelGGL((k_ml_fit<T, 4, 8, PLUS>), g, b, 0, c.stream, (ProtoArg<T, 4, 8>::make(P, X, N)), X, b1,
+        hipLaunchKernelGGL((k_ml_fit<T, 4, 8, PLUS>), g, b, 0, c.stream, (ProtoArg<T, 4, 8>::make(P, X, N)), X, b1, bm,
                            maps, N, n_gn, loading, partials);
     else if (shape == 2)
-        hipLaunchKernelGGL((k_ml_fit<T, 4, 16, PLUS>), g, b, 0, c.stream, (ProtoArg<T, 4, 16>::make(P, X, N)), X, b1,
+        hipLaunchKernelGGL((k_ml_fit<T, 4, 16, PLUS>), g, b, 0, c.stream, (ProtoArg<T, 4, 16>::make(P, X, N)),
+                           X, b1, bm,
                            maps, N, n_gn, loading, partials);
     else if (shape == 3)
-        hipLaunchKernelGGL((k_ml_fit<T, 8, 8, PLUS>), g, b, 0, c.stream, (ProtoArg<T, 8, 8>::make(P, X, N)), X, b1,
+        hipLaunchKernelGGL((k_ml_fit<T, 8, 8, PLUS>), g, b, 0, c.stream, (ProtoArg<T, 8, 8>::make(P, X, N)), X, b1, bm,
                            maps, N, n_gn, loading, partials);
     else
-        hipLaunchKernelGGL((k_ml_fit<T, 0, 0, PLUS>), g, b, 0, c.stream, (ProtoArg<T, 0, 0>::make(P, X, N)), X, b1,
+        hipLaunchKernelGGL((k_ml_fit<T, 0, 0, PLUS>), g, b, 0, c.stream, (ProtoArg<T, 0, 0>::make(P, X, N)), X, b1, bm,
                            maps, N, n_gn, loading, partials);
     return hipGetLastError();
 }
 
 template <typename T>
-static hipError_t ml_dispatch(const LaunchCtx &c, const DevProto &P, const T *X, const float *b1,
+static hipError_t ml_dispatch(const LaunchCtx &c, const DevProto &P, const T *X, const float *b1, const float *bm,
                               float *maps, int64_t N, int n_gn, int loading, double *partials, int nblk)
 {
-    return loading == 2 ? ml_launch<T, true>(c, P, X, b1, maps, N, n_gn, loading, partials, nblk)
-                        : ml_launch<T, false>(c, P, X, b1, maps, N, n_gn, loading, partials, nblk);
+    return loading == 2 ? ml_launch<T, true>(c, P, X, b1, bm, maps, N, n_gn, loading, partials, nblk)
+                        : ml_launch<T, false>(c, P, X, b1, bm, maps, N, n_gn, loading, partials, nblk);
 }
 
 hipError_t launch_ml_fit(const LaunchCtx &c, const DevProto &P, int dtype, const void *X,
-                         const float *b1, float *maps, int64_t N, int n_gn, int loading,
+                         const float *b1, const float *bm, float *maps, int64_t N, int n_gn, int loading,
                          double *partials, int nblk)
 {
     if (dtype == DT_F32)
-        return ml_dispatch(c, P, (const float *)X, b1, maps, N, n_gn, loading, partials, nblk);
+        return ml_dispatch(c, P, (const float *)X, b1, bm, maps, N, n_gn, loading, partials, nblk);
     if (dtype == DT_F16)
-        return ml_dispatch(c, P, (const F16 *)X, b1, maps, N, n_gn, loading, partials, nblk);
-    return ml_dispatch(c, P, (const BF16 *)X, b1, maps, N, n_gn, loading, partials, nblk);
+        return ml_dispatch(c, P, (const F16 *)X, b1, bm, maps, N, n_gn, loading, partials, nblk);
+    return ml_dispatch(c, P, (const BF16 *)X, b1, bm, maps, N, n_gn, loading, partials, nblk);
 }
 
 // ---------------------------------------------------------------------------

@@ -313,6 +313,7 @@ struct VoxelEchoes {
     using Consts = lds_slot4 *;
     float x[CM][EM];
     Angle an[CM];
+    float bm;  // net receive field of the voxel (multiplies its signal)
 
     // Stage the per-slot constants in LDS, read back at each use (volatile:
     // one broadcast LDS read per slot and evaluation, instead of holding all
@@ -331,9 +332,12 @@ struct VoxelEchoes {
         return (lds_slot4 *)tab;
     }
 
-    // n: voxel index; byte offsets n * sizeof(T) fit 32 bits (N < 2^30)
-    __device__ __forceinline__ void load(const Proto &P, const T *__restrict__, int64_t, int64_t n, float b)
+    // n: voxel index; byte offsets n * sizeof(T) fit 32 bits (N < 2^30); b, bm_:
+    // transmit and receive fields of the voxel
+    __device__ __forceinline__ void load(const Proto &P, const T *__restrict__, int64_t, int64_t n, float b,
+                                         float bm_ = 1.0f)
     {
+        bm = bm_;
         const uint32_t off = (uint32_t)n * (uint32_t)sizeof(T);
 #pragma unroll
         for (int c = 0; c < CM; c++) {
@@ -355,7 +359,8 @@ struct VoxelEchoes {
     __device__ __forceinline__ float lik(const Proto &P, Consts K, const float y[4], int loading, bool grad,
                                          float g[4], float H[10]) const
     {
-        const Params p = decode(y);
+        Params p = decode(y);
+        p.a *= bm;  // the receive field multiplies the whole signal (Sec. 2.4)
         const float k2 = -p.r2 * 1.4426950f;  // exp(-r2 te) = 2^(k2 te)
         float nll = 0.f;
 #pragma unroll
@@ -381,7 +386,8 @@ struct VoxelEchoes {
 
     __device__ __forceinline__ float nll(const Proto &P, Consts K, const float y[4]) const
     {
-        const Params p = decode(y);
+        Params p = decode(y);
+        p.a *= bm;  // the receive field multiplies the whole signal (Sec. 2.4)
         const float k2 = -p.r2 * 1.4426950f;
         float v = 0.f;
 #pragma unroll
@@ -407,23 +413,26 @@ struct VoxelEchoes<T, 0, 0> {
     using Consts = const void *;
     const T *__restrict__ X;
     int64_t N, n;
-    float b;
+    float b, bm;
 
     static __device__ __forceinline__ Consts stage(const Proto &) { return nullptr; }
 
-    __device__ __forceinline__ void load(const Proto &, const T *__restrict__ X_, int64_t N_, int64_t n_, float b_)
+    __device__ __forceinline__ void load(const Proto &, const T *__restrict__ X_, int64_t N_, int64_t n_, float b_,
+                                         float bm_ = 1.0f)
     {
         X = X_;
         N = N_;
         n = n_;
         b = b_;
+        bm = bm_;
     }
 
     template <bool PLUS>
     __device__ __forceinline__ float lik(const Proto &P, Consts, const float y[4], int loading, bool grad,
                                          float g[4], float H[10]) const
     {
-        const Params p = decode(y);
+        Params p = decode(y);
+        p.a *= bm;  // the receive field multiplies the whole signal (Sec. 2.4)
         const float k2 = -p.r2 * 1.4426950f;
         float nll = 0.f;
 #pragma unroll
@@ -446,7 +455,8 @@ struct VoxelEchoes<T, 0, 0> {
 
     __device__ __forceinline__ float nll(const Proto &P, Consts, const float y[4]) const
     {
-        const Params p = decode(y);
+        Params p = decode(y);
+        p.a *= bm;  // the receive field multiplies the whole signal (Sec. 2.4)
         const float k2 = -p.r2 * 1.4426950f;
         float v = 0.f;
         for (int c = 0; c < P.C; c++) {

@@ -90,9 +90,11 @@ struct MlJob : FitJob {
         *more = false;
         LaunchCtx c{a.stream};
         const int n_gn = a.opt->n_gn;
-        double bytes = (double)a.N * ((double)a.P.I * dtype_size(a.dtype) + (a.b1 ? 4.0 : 0.0) + 32.0);
+        const float *bm = a.opt->b1_receive;
+        double bytes = (double)a.N * ((double)a.P.I * dtype_size(a.dtype) + (a.b1 ? 4.0 : 0.0) + (bm ? 4.0 : 0.0) +
+                                      32.0);
         hipError_t e = prof.launch("ml_fit", bytes, [&] {
-            return launch_ml_fit(c, a.P, a.dtype, a.X, a.b1, a.maps, a.N, n_gn, a.opt->loading, part, nblk);
+            return launch_ml_fit(c, a.P, a.dtype, a.X, a.b1, bm, a.maps, a.N, n_gn, a.opt->loading, part, nblk);
         });
         if (e == hipSuccess) e = launch_reduce_rows(c, part, rows, nblk, sums);
         if (e == hipSuccess)
@@ -199,6 +201,7 @@ extern "C" mpm_status mpm_fit_voxelwise(const mpm_voxel_protocols *vp, int64_t n
     if (opt->loading != MPM_LOAD_PROPOSED && opt->loading != MPM_LOAD_GN && opt->loading != MPM_LOAD_PROPOSED_PLUS)
         return fail(MPM_ERR_INVALID_ARG, "unknown loading %d", opt->loading);
     if (opt->flags != 0) return fail(MPM_ERR_INVALID_ARG, "flags must be 0");
+    if (opt->b1_receive) return fail(MPM_ERR_UNSUPPORTED, "b1_receive is not supported by the per-voxel-protocol fit");
     if (opt->init_kind == MPM_INIT_DEFAULT)
         return fail(MPM_ERR_UNSUPPORTED, "the default initialisation needs one protocol for all voxels");
     if (opt->init_kind != MPM_INIT_CONST && opt->init_kind != MPM_INIT_FROM_MAPS)

@@ -28,7 +28,7 @@ int echo_sums_blocks(int64_t N);
 // ML fit: n_gn steps per voxel, echoes register-resident.  partials rows:
 // [0..n_gn] NLL before each step / final, then degenerate, nonfinite, increases
 hipError_t launch_ml_fit(const LaunchCtx &c, const DevProto &P, int dtype, const void *X,
-                         const float *b1, float *maps, int64_t N, int n_gn, int loading,
+                         const float *b1, const float *bm, float *maps, int64_t N, int n_gn, int loading,
                          double *partials, int nblk);
 int ml_fit_blocks(int64_t N);
 // out[r] = sum over b < ncols of in[r*ncols + b] (fixed order)

@@ -261,6 +261,7 @@ struct MapArgs {
     int dtype;
     const void *X;
     const float *b1;
+    const float *bm;  // net receive field [N] or NULL
     float *Y;      // maps [4][N]
     float *w;      // JTV weights [N]
     Grid3 gp;      // one plane per workgroup

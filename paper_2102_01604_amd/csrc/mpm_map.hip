@@ -41,6 +41,7 @@ static mpm_status alloc_map(const FitArgs &a, Workspace &ws, MapArgs &m, int tra
     m.dtype = a.dtype;
     m.X = a.X;
     m.b1 = a.b1;
+    m.bm = a.opt->b1_receive;
     m.Y = a.maps;
     m.gp = plane_grid(m.g);
     m.gt = make_grid3(a.nx, a.ny, a.nz, TALL_Y, tall_workgroups());
@@ -267,7 +268,8 @@ struct MapJob : FitJob {
     mpm_status enqueue_next(bool *more) override
     {
         const hipStream_t s = a.stream;
-        const double N = (double)a.N, xb = (double)a.P.I * dtype_size(a.dtype), bb = a.b1 ? 4.0 : 0.0;
+        const double N = (double)a.N, xb = (double)a.P.I * dtype_size(a.dtype);
+        const double bb = (a.b1 ? 4.0 : 0.0) + (m.bm ? 4.0 : 0.0);
         hipError_t e = hipSuccess;
 #define RUN(name, bytes, call)                                                    \
     do {                                                                          \
@@ -396,6 +398,8 @@ static mpm_status uncertainty_impl(const mpm_protocol *protocol, const mpm_grid 
     if ((st = check_protocol(protocol)) || (st = check_grid(grid, &N)) || (st = check_dtype(dtype))) return st;
     if (spaces && (st = check_spaces(protocol, spaces))) return st;
     if (!opt) return fail(MPM_ERR_INVALID_ARG, "options is NULL");
+    if (spaces && opt->b1_receive)
+        return fail(MPM_ERR_UNSUPPORTED, "b1_receive is not supported by the projected model");
     if (!echoes || !maps || !var) return fail(MPM_ERR_INVALID_ARG, "echoes, maps and var must be device pointers");
     if (opt->mode != MPM_ML && opt->mode != MPM_MAP_JTV) return fail(MPM_ERR_INVALID_ARG, "unknown mode %d", opt->mode);
     if (opt->loading != MPM_LOAD_PROPOSED && opt->loading != MPM_LOAD_GN && opt->loading != MPM_LOAD_PROPOSED_PLUS)
@@ -418,6 +422,7 @@ static mpm_status uncertainty_impl(const mpm_protocol *protocol, const mpm_grid 
         m.dtype = dtype;
         m.X = echoes;
         m.b1 = b1;
+        m.bm = opt->b1_receive;
         m.Y = a.maps;  // only read
         m.gp = plane_grid(m.g);
         const int nblk = std::max(grid_blocks(m.g), grid_blocks(m.gp));
@@ -434,7 +439,7 @@ static mpm_status uncertainty_impl(const mpm_protocol *protocol, const mpm_grid 
             HessArrays Hr{hb, hb + N, (float2 *)(hb + 2 * N)};
             if ((st = alloc_proj(a, ws, ps, Hr, false))) return st;
         }
-        const double xb = (double)a.P.I * dtype_size(dtype), bb = b1 ? 4.0 : 0.0;
+        const double xb = (double)a.P.I * dtype_size(dtype), bb = (b1 ? 4.0 : 0.0) + (m.bm ? 4.0 : 0.0);
         hipError_t e = prof.launch("jtv_weights", (double)N * 20.0, [&] { return launch_weights(s, m, prior_on); });
         if (!spaces) {
             if (e == hipSuccess)
@@ -485,6 +490,7 @@ extern "C" mpm_status mpm_fit_projected(const mpm_protocol *protocol, const mpm_
     mpm_status st = check_fit_args(protocol, grid, dtype, echoes, opt, maps, &N);
     if (st) return st;
     if ((st = check_spaces(protocol, spaces))) return st;
+    if (opt->b1_receive) return fail(MPM_ERR_UNSUPPORTED, "b1_receive is not supported by the projected model");
     if (trace_len < 0 || (trace_len > 0 && !trace)) return fail(MPM_ERR_INVALID_ARG, "trace is NULL");
     for (int i = 0; i < trace_len; i++) trace[i] = NAN;
     hipStream_t s = (hipStream_t)stream;

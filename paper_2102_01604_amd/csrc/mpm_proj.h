@@ -113,7 +113,10 @@ struct VoxelEchoes<Pushed, 0, 0> {
     using Consts = const void *;
     int64_t n;
     static __device__ __forceinline__ Consts stage(const Proto &) { return nullptr; }
-    __device__ __forceinline__ void load(const Proto &, const Pushed *, int64_t, int64_t n_, float) { n = n_; }
+    __device__ __forceinline__ void load(const Proto &, const Pushed *, int64_t, int64_t n_, float, float = 1.0f)
+    {
+        n = n_;
+    }
     template <bool PLUS>
     __device__ __forceinline__ float lik(const Proto &P, Consts, const float *, int, bool, float g[4],
                                          float H[10]) const

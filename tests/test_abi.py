@@ -129,6 +129,18 @@ def test_projected_argument_validation(lib):
                       ({"dims": (8, 8, 8), "affine": [[1, 1, 0, 0], [1, 1, 0, 0], [0, 0, 1, 0]]}, "singular")):
         st = run([ok, bad, ok])
         assert st == 1 and what in lib.mpm_last_error().decode(), (what, lib.mpm_last_error())
+    # the receive field is a reconstruction-grid option only
+    o = _lib.make_options({"mode": "map", "n_gn": 2})
+    o.b1_receive = 16
+    rep = _lib.mpm_report()
+    st = lib.mpm_fit_projected(C.byref(_lib.make_protocol(proto)), C.byref(_lib.make_grid([8, 8, 8])),
+                               _lib.make_spaces([ok, ok, ok]), 0, C.c_void_p(16), None, C.byref(o), C.c_void_p(16),
+                               C.byref(rep), None, 0, None)
+    assert st == 2 and "b1_receive" in lib.mpm_last_error().decode()
+    st = lib.mpm_uncertainty_projected(C.byref(_lib.make_protocol(proto)), C.byref(_lib.make_grid([8, 8, 8])),
+                                       _lib.make_spaces([ok, ok, ok]), 0, C.c_void_p(16), None, C.byref(o),
+                                       C.c_void_p(16), C.c_void_p(16), None, None)
+    assert st == 2 and "b1_receive" in lib.mpm_last_error().decode()
 
 
 def test_voxelwise_argument_validation(lib):
@@ -136,12 +148,14 @@ def test_voxelwise_argument_validation(lib):
     fake = C.c_void_p(16)
     shape = {"n_echoes": [5, 5, 5], "mt": [0, 0, 1], "sigma": [1.0] * 15}
 
-    def run(shape=shape, n=1000, opts=None, arrays=True, echoes=fake):
+    def run(shape=shape, n=1000, opts=None, arrays=True, echoes=fake, receive=False):
         p = _lib.make_voxel_protocols(shape)
         if arrays:
             p.tr_s = p.flip_rad = p.te_s = 16
         o = _lib.make_options(opts if opts is not None else {"mode": "ml", "n_gn": 5, "init": "const",
                                                                "init_const": [0.0] * 4})
+        if receive:
+            o.b1_receive = 16
         rep = _lib.mpm_report()
         return lib.mpm_fit_voxelwise(C.byref(p), n, 0, echoes, C.byref(o), fake, None, None, C.byref(rep), None)
 
@@ -149,6 +163,7 @@ def test_voxelwise_argument_validation(lib):
         (dict(arrays=False), 1, "device pointers"),
         (dict(echoes=None), 1, "device pointers"),
         (dict(n=0), 1, "n_voxels"),
+        (dict(receive=True), 2, "b1_receive"),
         (dict(opts={"mode": "map", "n_gn": 5, "init": "const"}), 1, "ML fit"),
         (dict(opts={"mode": "ml", "n_gn": 5, "init": "default"}), 2, "one protocol"),
         (dict(opts={"mode": "ml", "n_gn": -1, "init": "const"}), 1, "n_gn"),
