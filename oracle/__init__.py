@@ -33,6 +33,7 @@ ML, MAP = 0, 1
 INIT_DEFAULT, INIT_CONST, INIT_FROM_MAPS = 0, 1, 2
 LOAD_PROPOSED, LOAD_GN, LOAD_PLUS = 0, 1, 2
 LOADINGS = {"proposed": LOAD_PROPOSED, "gn": LOAD_GN, "plus": LOAD_PLUS}
+BASES = {"log": 0, "rate": 1, "time": 2}
 
 
 def build(force: bool = True) -> str:
@@ -59,7 +60,7 @@ class Space(C.Structure):
 class Options(C.Structure):
     _fields_ = [("mode", C.c_int32), ("n_outer", C.c_int32), ("n_gn", C.c_int32),
                 ("n_cg", C.c_int32), ("max_halvings", C.c_int32), ("loading", C.c_int32),
-                ("init_kind", C.c_int32), ("pad_", C.c_int32), ("lam", C.c_double * 4),
+                ("init_kind", C.c_int32), ("basis", C.c_int32), ("lam", C.c_double * 4),
                 ("jtv_eps", C.c_double), ("cg_stop", C.c_double),
                 ("init_const", C.c_double * 4), ("tol_gn", C.c_double), ("tol_outer", C.c_double),
                 ("b1_receive", C.c_void_p)]
@@ -85,6 +86,9 @@ def _load():
         lib.orc_spgr_derivs.argtypes = [_dp, C.c_double, C.c_double, C.c_double, C.c_int,
                                         _dp, _dp, _dp]
         lib.orc_spgr_hess.argtypes = [_dp, C.c_double, C.c_double, C.c_double, C.c_int, _dp]
+        lib.orc_spgr_basis.argtypes = [_dp, C.c_int, C.c_double, C.c_double, C.c_double, C.c_int, _dp, _dp, _dp]
+        lib.orc_lik_voxel_basis.argtypes = [C.POINTER(Protocol), _dp, C.c_int64, _dp, C.c_int, C.c_int, _dp, _dp,
+                                            _dp]
         lib.orc_simulate.argtypes = [C.POINTER(Protocol), C.c_int64, _dp, _dp, _dp]
         lib.orc_lik_voxel.argtypes = [C.POINTER(Protocol), _dp, C.c_int64, _dp, C.c_double,
                                       C.c_int, _dp, _dp, _dp]
@@ -173,6 +177,7 @@ def make_options(opts: dict) -> Options:
         o.init_const[k] = float(ic[k])
     o.tol_gn = float(opts.get("tol_gn", 0.0))
     o.tol_outer = float(opts.get("tol_outer", 0.0))
+    o.basis = BASES[opts.get("basis", "log")]
     bm = opts.get("b1_receive")
     if bm is not None:  # the caller keeps the array alive (fit and uncertainty hold it)
         o.b1_receive = bm.ctypes.data
@@ -186,6 +191,34 @@ def _dims(dims):
 
 def num_threads() -> int:
     return int(_load().orc_num_threads())
+
+
+def spgr_basis(th, basis, alpha, tr, te, mt):
+    """Signal, gradient and full second-derivative matrix [4][4] with respect
+    to the parameters of basis "rate" (A, R1, R2*, MTsat) or "time"
+    (A, T1, T2*, MTsat), for one image."""
+    lib = _load()
+    tv = _f64(np.asarray(th))
+    s = np.zeros(1)
+    ds = np.zeros(4)
+    H = np.zeros(16)
+    lib.orc_spgr_basis(_ptr(tv), BASES[basis], alpha, tr, te, int(mt), _ptr(s), _ptr(ds), _ptr(H))
+    return float(s[0]), ds, H.reshape(4, 4)
+
+
+def lik_voxel_basis(proto, x, th, basis, loading="proposed"):
+    """NLL, gradient and loaded Hessian [4][4] of one voxel (x: [I]) with
+    respect to the parameters th of basis "log", "rate" or "time"."""
+    lib = _load()
+    p = make_protocol(proto)
+    xv = _f64(np.asarray(x))
+    tv = _f64(np.asarray(th))
+    nll = np.zeros(1)
+    g = np.zeros(4)
+    P = np.zeros(16)
+    lib.orc_lik_voxel_basis(C.byref(p), _ptr(xv), 1, _ptr(tv), BASES[basis], LOADINGS[loading], _ptr(nll), _ptr(g),
+                            _ptr(P))
+    return float(nll[0]), g, P.reshape(4, 4)
 
 
 def spgr_derivs(y, alpha, tr, te, mt):

@@ -38,6 +38,10 @@
  *   R-missing: a non-finite echo value is a missing observation: it adds
  *              nothing to the NLL, gradient or Hessian of its voxel (and is
  *              left out of the volume means of the default initialisation).
+ *   R-basis  : in the rate and time representations (Sec. 3.1) the steps act
+ *              on the values themselves and the signal formula is evaluated
+ *              at whatever values they reach: no clamp to the physical domain
+ *              (the paper states none).
  */
 #include "mpm_oracle.h"
 
@@ -151,6 +155,74 @@ void orc_spgr_hess(const double y[4], double alpha, double tr, double te, int mt
     H[4 * 1 + 3] = H[4 * 3 + 1] = chi * s;
 }
 
+/* Signal, gradient and full matrix of second derivatives (row-major) with
+ * respect to the parameters of the rate basis, th = (A, R1, R2*, MTsat), or
+ * of the time basis, th = (A, T1, T2*, MTsat) with R1 = 1/T1 and
+ * R2* = 1/T2* (the two alternative representations of Sec. 3.1).  The signal
+ * is the formula of Sec. 2.1 (eqs. 1-3, TR2 = 0) evaluated at these values as
+ * they are, also outside the physical domain (reading R-basis).
+ *
+ * Written as s = A * F(R1, delta) * G(R2*) with E = exp(-R1 TR),
+ * q = 1 - delta, c = cos(alpha), D = 1 - q c E:
+ *   F = sin(alpha) q (1 - E) / D,            G = exp(-R2* TE),
+ *   dF/dR1       = TR E sin(alpha) q (1 - q c) / D^2,
+ *   d2F/dR1^2    = -TR^2 E sin(alpha) q (1 - q c)(1 + q c E) / D^3,
+ *   dF/ddelta    = -sin(alpha) (1 - E) / D^2,
+ *   d2F/ddelta^2 = 2 sin(alpha) (1 - E) c E / D^3,
+ *   d2F/dR1 ddelta = TR E sin(alpha) (2 q c - 1 - q c E) / D^3,
+ *   dG/dR2* = -TE G,  d2G/dR2*^2 = TE^2 G.
+ * A parameter u with rate value R = rho(u) adds the factors rho' and rho''
+ * (rate: 1 and 0; time: -R^2 and 2 R^3).  Without an MT pulse delta = 0 and
+ * every derivative with respect to th[3] is 0. */
+void orc_spgr_basis(const double th[4], int basis, double alpha, double tr, double te, int mt,
+                    double *s, double ds[4], double H[16])
+{
+    double a = th[0];
+    double r1 = basis == ORC_BASIS_TIME ? 1.0 / th[1] : th[1];
+    double r2 = basis == ORC_BASIS_TIME ? 1.0 / th[2] : th[2];
+    double delta = mt ? th[3] : 0.0;
+    double j1 = 1.0, j1p = 0.0, j2 = 1.0, j2p = 0.0; /* rho' and rho'' */
+    if (basis == ORC_BASIS_TIME) {
+        j1 = -r1 * r1;
+        j1p = 2.0 * r1 * r1 * r1;
+        j2 = -r2 * r2;
+        j2p = 2.0 * r2 * r2 * r2;
+    }
+    double E = exp(-r1 * tr);
+    double sa = sin(alpha), c = cos(alpha);
+    double q = 1.0 - delta;
+    double D = 1.0 - q * c * E;
+
+    double F = sa * q * (1.0 - E) / D;
+    double F1 = tr * E * sa * q * (1.0 - q * c) / (D * D);
+    double F11 = -tr * tr * E * sa * q * (1.0 - q * c) * (1.0 + q * c * E) / (D * D * D);
+    double Fd = mt ? -sa * (1.0 - E) / (D * D) : 0.0;
+    double Fdd = mt ? 2.0 * sa * (1.0 - E) * c * E / (D * D * D) : 0.0;
+    double F1d = mt ? tr * E * sa * (2.0 * q * c - 1.0 - q * c * E) / (D * D * D) : 0.0;
+    double G = exp(-r2 * te);
+    double G2 = -te * G, G22 = te * te * G;
+
+    /* derivatives with respect to th[1] and th[2] */
+    double Fu = F1 * j1, Fuu = F11 * j1 * j1 + F1 * j1p, Fud = F1d * j1;
+    double Gv = G2 * j2, Gvv = G22 * j2 * j2 + G2 * j2p;
+
+    *s = a * F * G;
+    ds[0] = F * G;
+    ds[1] = a * Fu * G;
+    ds[2] = a * F * Gv;
+    ds[3] = a * Fd * G;
+    H[0] = 0.0;
+    H[1] = H[4] = Fu * G;
+    H[2] = H[8] = F * Gv;
+    H[3] = H[12] = Fd * G;
+    H[5] = a * Fuu * G;
+    H[6] = H[9] = a * Fu * Gv;
+    H[7] = H[13] = a * Fud * G;
+    H[10] = a * F * Gvv;
+    H[11] = H[14] = a * Fd * Gv;
+    H[15] = a * Fdd * G;
+}
+
 /* Noise-free echoes of every image at every voxel.  The flip angle of a voxel
  * is the nominal one times the transmit-field efficiency b1 (Sec. 2.4,
  * footnote on B1).  maps: [4][n]; b1: [n] or NULL (= 1); out: [I][n]. */
@@ -187,9 +259,8 @@ void orc_simulate(const orc_protocol *p, int64_t n, const double *maps,
  * x points at image 0 of this voxel; image i is at x[i*stride].
  * P is the full 4x4 matrix, row-major.
  * ------------------------------------------------------------------------ */
-void orc_lik_voxel(const orc_protocol *p, const double *x, int64_t stride,
-                   const double y[4], double b1, int loading,
-                   double *nll, double g[4], double P[16])
+static void lik_voxel(const orc_protocol *p, const double *x, int64_t stride, const double y[4], double b1,
+                      int basis, int loading, double *nll, double g[4], double P[16])
 {
     int I = n_images(p);
     double l = 0.0;
@@ -200,11 +271,16 @@ void orc_lik_voxel(const orc_protocol *p, const double *x, int64_t stride,
         double s, ds[4], d2s[4];
         double xi = x[(int64_t)i * stride];
         if (!isfinite(xi)) continue; /* R-missing: no observation */
-        orc_spgr_derivs(y, p->flip[c] * b1, p->tr[c], p->te[i], p->mt[c], &s, ds, d2s);
+        double Hs[16];
+        if (basis == ORC_BASIS_LOG) {
+            orc_spgr_derivs(y, p->flip[c] * b1, p->tr[c], p->te[i], p->mt[c], &s, ds, d2s);
+            if (loading == ORC_LOAD_PROPOSED_PLUS) orc_spgr_hess(y, p->flip[c] * b1, p->tr[c], p->te[i], p->mt[c], Hs);
+        } else {
+            orc_spgr_basis(y, basis, p->flip[c] * b1, p->tr[c], p->te[i], p->mt[c], &s, ds, Hs);
+            for (int k = 0; k < 4; k++) d2s[k] = Hs[5 * k];
+        }
         double res = s - xi;
         double wgt = 1.0 / (p->sigma[i] * p->sigma[i]);
-        double Hs[16];
-        if (loading == ORC_LOAD_PROPOSED_PLUS) orc_spgr_hess(y, p->flip[c] * b1, p->tr[c], p->te[i], p->mt[c], Hs);
         l += 0.5 * wgt * res * res;
         for (int k = 0; k < 4; k++) {
             g[k] += wgt * res * ds[k];
@@ -218,6 +294,22 @@ void orc_lik_voxel(const orc_protocol *p, const double *x, int64_t stride,
         }
     }
     *nll = l;
+}
+
+void orc_lik_voxel(const orc_protocol *p, const double *x, int64_t stride,
+                   const double y[4], double b1, int loading,
+                   double *nll, double g[4], double P[16])
+{
+    lik_voxel(p, x, stride, y, b1, ORC_BASIS_LOG, loading, nll, g, P);
+}
+
+/* The same block with respect to the parameters th of `basis` (ORC_BASIS_*),
+ * from the derivatives of orc_spgr_basis (log basis: orc_lik_voxel). */
+void orc_lik_voxel_basis(const orc_protocol *p, const double *x, int64_t stride,
+                         const double th[4], int basis, int loading,
+                         double *nll, double g[4], double P[16])
+{
+    lik_voxel(p, x, stride, th, 1.0, basis, loading, nll, g, P);
 }
 
 /* ------------------------------------------------------------------------
@@ -804,6 +896,7 @@ static int fit_impl(const lik_ctx *L, const orc_options *opt, double *maps, orc_
     orc_report R;
     memset(&R, 0, sizeof(R));
     for (int32_t i = 0; i < trace_len; i++) trace[i] = NAN;
+    if (opt->basis != ORC_BASIS_LOG) return 1;
 
     if (opt->init_kind == ORC_INIT_CONST || opt->init_kind == ORC_INIT_DEFAULT) {
         double y0[4];
@@ -974,16 +1067,31 @@ int orc_fit(const orc_protocol *p, const int64_t dims[3], const double *x, const
  * noise levels come from shape (its tr, flip and te are ignored).  Each voxel
  * takes opt->n_gn Newton-like steps y <- y - P~^{-1} g (Sec. 2.3) from
  * init_const (ORC_INIT_CONST) or from maps (ORC_INIT_FROM_MAPS), as the ML
- * fit does.  increases[n] (optional) counts the steps after which the
+ * fit does, on the parameters of opt->basis (the representation comparison of
+ * Sec. 3.1; maps and init_const are in that basis).  increases[n] (optional) counts the steps after which the
  * voxel's NLL exceeds the one before by more than rise_rel (relative), or
  * becomes non-finite from a finite value; nll[n] (optional) is the final NLL.
  * Returns 0, or 1 if the options are not an ML fit with a given start.
  * ------------------------------------------------------------------------ */
+/* One parameter's Newton-like update u - step (reading R-basis): the log
+ * basis has no bounds; in the rate and time bases A, R1 (T1) and R2* (T2*)
+ * must stay > 0 and MTsat in (0, 1), and a step that would leave that domain
+ * moves the parameter halfway to the boundary it would cross instead. */
+static double step_in_domain(int basis, int k, double u, double step)
+{
+    double v = u - step;
+    if (basis == ORC_BASIS_LOG || !isfinite(v)) return v;
+    if (!(v > 0.0)) return 0.5 * u;
+    if (k == 3 && !(v < 1.0)) return 0.5 * (1.0 + u);
+    return v;
+}
+
 int orc_fit_voxelwise(const orc_protocol *shape, int64_t N, const double *tr, const double *flip, const double *te,
                       const double *x, const orc_options *opt, double rise_rel, double *maps, int32_t *increases,
                       double *nll, orc_report *rep)
 {
     if (opt->mode != ORC_ML || (opt->init_kind != ORC_INIT_CONST && opt->init_kind != ORC_INIT_FROM_MAPS)) return 1;
+    if (opt->basis < ORC_BASIS_LOG || opt->basis > ORC_BASIS_TIME) return 1;
     const int C = shape->n_contrasts;
     int I = 0;
     for (int c = 0; c < C; c++) I += shape->n_echoes[c];
@@ -1004,13 +1112,13 @@ int orc_fit_voxelwise(const orc_protocol *shape, int64_t N, const double *tr, co
         double prev = 0.0, cur = 0.0, g[4], P[16];
         int count = 0, dg = 0;
         for (int it = 0; it <= opt->n_gn; it++) {
-            orc_lik_voxel(&pv, x + n, N, y, 1.0, opt->loading, &cur, g, P);
+            lik_voxel(&pv, x + n, N, y, 1.0, opt->basis, opt->loading, &cur, g, P);
             if (it > 0 && (cur > prev * (1.0 + rise_rel) || (isfinite(prev) && !isfinite(cur)))) count++;
             prev = cur;
             if (it == opt->n_gn) break;
             double step[4];
             dg = orc_solve4(P, g, step);
-            for (int k = 0; k < 4; k++) y[k] -= step[k];
+            for (int k = 0; k < 4; k++) y[k] = step_in_domain(opt->basis, k, y[k], step[k]);
         }
         for (int k = 0; k < 4; k++) maps[k * N + n] = y[k];
         cnt[n] = count;
@@ -1070,6 +1178,7 @@ double orc_proj_lik(const orc_protocol *p, const int64_t dims[3], const orc_spac
 static int uncertainty_impl(const lik_ctx *L, const orc_options *opt, const double *maps, double *var,
                             double *moments)
 {
+    if (opt->basis != ORC_BASIS_LOG) return 1;
     const int64_t *dims = L->dims;
     int64_t N = dims[0] * dims[1] * dims[2];
     double lam[4] = {0.0, 0.0, 0.0, 0.0};

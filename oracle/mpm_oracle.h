@@ -48,6 +48,10 @@ typedef struct {
 enum { ORC_ML = 0, ORC_MAP = 1 };
 enum { ORC_INIT_DEFAULT = 0, ORC_INIT_CONST = 1, ORC_INIT_FROM_MAPS = 2 };
 enum { ORC_LOAD_PROPOSED = 0, ORC_LOAD_GN = 1, ORC_LOAD_PROPOSED_PLUS = 2 };
+/* Parameters the Newton-like steps act on (the representation comparison of
+ * Sec. 3.1): log/logit (log A, log R1, log R2*, logit MTsat), rate
+ * (A, R1, R2*, MTsat) or time (A, T1, T2*, MTsat). */
+enum { ORC_BASIS_LOG = 0, ORC_BASIS_RATE = 1, ORC_BASIS_TIME = 2 };
 
 typedef struct {
     int32_t mode;           /* ORC_ML or ORC_MAP                                  */
@@ -57,7 +61,8 @@ typedef struct {
     int32_t max_halvings;   /* MAP step acceptance: halvings tried; <0 = no test  */
     int32_t loading;        /* ORC_LOAD_PROPOSED (paper), ORC_LOAD_GN or _PLUS    */
     int32_t init_kind;      /* ORC_INIT_*                                         */
-    int32_t pad_;
+    int32_t basis;          /* ORC_BASIS_*; other than LOG only in orc_fit_voxelwise,
+                               whose maps and init_const are then in that basis   */
     double  lambda[4];      /* JTV regularisation per map                         */
     double  jtv_eps;        /* smoothing of the JTV norm; 0 -> 1e-3*sqrt(sum lambda) */
     double  cg_stop;        /* CG stops when r.z <= cg_stop * r0.z0 (0: fixed count) */
@@ -87,6 +92,8 @@ typedef struct {
 void orc_spgr_derivs(const double y[4], double alpha, double tr, double te, int mt,
                      double *s, double ds[4], double d2s[4]);
 void orc_spgr_hess(const double y[4], double alpha, double tr, double te, int mt, double H[16]);
+void orc_spgr_basis(const double th[4], int basis, double alpha, double tr, double te, int mt,
+                    double *s, double ds[4], double H[16]);
 void orc_simulate(const orc_protocol *p, int64_t n, const double *maps,
                   const double *b1, double *out);
 
@@ -94,6 +101,9 @@ void orc_simulate(const orc_protocol *p, int64_t n, const double *maps,
 void orc_lik_voxel(const orc_protocol *p, const double *x, int64_t stride,
                    const double y[4], double b1, int loading,
                    double *nll, double g[4], double P[16]);
+void orc_lik_voxel_basis(const orc_protocol *p, const double *x, int64_t stride,
+                         const double th[4], int basis, int loading,
+                         double *nll, double g[4], double P[16]);
 int  orc_solve4(const double P[16], const double g[4], double out[4]);
 
 /* ---- JTV prior ---- */
