@@ -471,6 +471,7 @@ def convergence_experiment(args, torch, _lib, synth, dev):
                      "frac_voxels_nll_rose": round(rose, 5), "mean_rises_per_voxel": round(rep["nll_increases"] / N, 3),
                      "frac_nonfinite": round(rep["nonfinite_voxels"] / N, 5)}
         log(f"e1 {load}: {ms:.1f} ms, NLL rose in {100 * rose:.2f}% of voxels")
+    reps = representation_comparison(args, torch, _lib, shape, TR, FL, TE, X, maps, inc, nll)
     cpu = None
     if not args.no_cpu_baseline:
         # the FP64 oracle on the first 32768 voxels of the same problems, 8000 steps, Proposed loading
@@ -499,8 +500,56 @@ def convergence_experiment(args, torch, _lib, synth, dev):
            "config": {"workload": f"{N} voxels, each with its own random protocol (3 contrasts x 5 echoes, MT on the "
                                   f"last; log TR, log TE, log-parameters ~ U[-5, 5], flips ~ U[0, pi/4]), sigma 1, "
                                   f"{its} ML steps from 0", "voxels": N, "iterations": its},
-           "loadings": res, "roofline": roof, "cpu_baseline": cpu}
+           "loadings": res, "representations": reps, "roofline": roof, "cpu_baseline": cpu}
     print(json.dumps(out), flush=True)
+
+
+def representation_comparison(args, torch, _lib, shape, TR, FL, TE, X, maps, inc, nll):
+    """Sec. 3.1 representation comparison on the same problems: the steps act
+    on the log/logit parameters, on (A, R1, R2*, MTsat) or on (A, T1, T2*,
+    MTsat), all with the |H| 1 (Proposed+) loading and from the point
+    log-parameters 0 give; the NLL of every voxel is read after 100, 1000 and
+    all steps (the fit continues from its maps), and compared with the lowest
+    final NLL any basis reached for that voxel."""
+    its = args.e1_iters
+    marks = [m for m in (100, 1000) if m < its] + [its]
+    finals, out = {}, {}
+    for basis, start in (("log", [0.0] * 4), ("rate", [1.0, 1.0, 1.0, 0.5]), ("time", [1.0, 1.0, 1.0, 0.5])):
+        base = {"mode": "ml", "loading": "plus", "basis": basis}
+        _lib.mpm_fit_voxelwise(shape, TR, FL, TE, X, dict(base, n_gn=1, init="const", init_const=start), maps, inc,
+                               nll)  # warm-up
+        torch.cuda.synchronize()
+        done, ms, rows = 0, 0.0, []
+        for m in marks:
+            o = dict(base, n_gn=m - done, **({"init": "const", "init_const": start} if done == 0 else {"init": "maps"}))
+            e0, e1_ = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            _lib.mpm_fit_voxelwise(shape, TR, FL, TE, X, o, maps, inc, nll)
+            e1_.record()
+            e1_.synchronize()
+            ms += e0.elapsed_time(e1_)
+            rows.append(nll.double().clone())
+            done = m
+        finals[basis] = rows
+        th = maps
+        fin = torch.isfinite(th).all(dim=0)
+        entry = {"ms": round(ms, 2), "voxel_iters_per_s": round(X.shape[1] * its / (ms * 1e-3), 1),
+                 "frac_finite": round(fin.double().mean().item(), 5)}
+        if basis != "log":
+            # the closed domain: repeated halving ends exactly on a boundary in FP32 (A = 0, MTsat = 1)
+            inside = (th[:3] >= 0).all(dim=0) & (th[3] >= 0) & (th[3] <= 1)
+            at_edge = (th[:3] == 0).any(dim=0) | (th[3] == 0) | (th[3] == 1)
+            entry["closed_domain_kept"] = bool((inside | ~fin).all().item())
+            entry["frac_on_boundary"] = round(at_edge.double().mean().item(), 5)
+        out[basis] = entry
+    best = torch.stack([finals[b][-1] for b in finals]).min(dim=0).values
+    for b in finals:
+        ex = [((r - best) / best.abs()) for r in finals[b]]
+        out[b]["steps"] = marks
+        out[b]["median_rel_nll_excess"] = [float(f"{e.nanmedian().item():.3e}") for e in ex]
+        out[b]["frac_within_1e-6_of_best"] = round((ex[-1] <= 1e-6).double().mean().item(), 4)
+        log(f"e1 basis {b}: {out[b]['ms']:.1f} ms, median NLL excess {out[b]['median_rel_nll_excess']}")
+    return out
 
 
 SERVE_SIZES = [(64, 64, 64), (96, 128, 128), (128, 160, 160), (192, 240, 256)]

@@ -58,6 +58,11 @@ typedef enum { MPM_INIT_DEFAULT = 0, MPM_INIT_CONST = 1, MPM_INIT_FROM_MAPS = 2 
  * second-derivative matrix ("Proposed+", a majoriser of the NLL Hessian), GN
  * adds nothing (Gauss-Newton / Fisher scoring). */
 typedef enum { MPM_LOAD_PROPOSED = 0, MPM_LOAD_GN = 1, MPM_LOAD_PROPOSED_PLUS = 2 } mpm_loading;
+/* Parameters the Newton-like steps act on (the representation comparison of
+ * paper Sec. 3.1): LOG = (log A, log R1, log R2*, logit MTsat), the default
+ * and the only one of every entry point but mpm_fit_voxelwise; RATE =
+ * (A, R1, R2*, MTsat); TIME = (A, T1, T2*, MTsat), T = 1/R. */
+typedef enum { MPM_BASIS_LOG = 0, MPM_BASIS_RATE = 1, MPM_BASIS_TIME = 2 } mpm_basis;
 
 #define MPM_MAX_CONTRASTS 8
 #define MPM_MAX_IMAGES 64
@@ -104,6 +109,7 @@ typedef struct {
      * NULL for none.  Read by mpm_fit, mpm_uncertainty and the server; the
      * projected and per-voxel-protocol fits reject it (MPM_ERR_UNSUPPORTED). */
     const float *b1_receive;
+    int32_t basis;  /* mpm_basis; other than MPM_BASIS_LOG: mpm_fit_voxelwise only */
 } mpm_options;
 
 typedef struct {
@@ -237,9 +243,14 @@ mpm_status mpm_simulate_projected(const mpm_protocol *protocol, const mpm_grid *
  * (paper Sec. 2.3); init_kind MPM_INIT_CONST (init_const) or
  * MPM_INIT_FROM_MAPS (maps holds the start); MPM_INIT_DEFAULT is
  * MPM_ERR_UNSUPPORTED (the volume-mean initialisation assumes one protocol).
+ * basis: the parameters y the steps act on (Sec. 3.1); with MPM_BASIS_RATE or
+ * MPM_BASIS_TIME, maps and init_const hold (A, R1, R2*, MTsat) or
+ * (A, T1, T2*, MTsat), and a step that would take A, R1 (T1) or R2* (T2*) to
+ * <= 0, or MTsat out of (0, 1), moves that parameter halfway to the boundary
+ * it would cross instead.
  *
  * Outputs (device, caller-owned): maps [4][N] (log A, log R1, log R2*,
- * logit MTsat); nll_increases [N] int32 or NULL: the number of steps after
+ * logit MTsat, or the basis' parameters); nll_increases [N] int32 or NULL: the number of steps after
  * which the voxel's NLL exceeds the previous value by more than 1e-5
  * (relative, FP32 evaluation) or becomes non-finite from a finite value;
  * nll [N] float or NULL: the final NLL.  report (host, may be NULL): total

@@ -21,6 +21,7 @@ MPM_F32, MPM_F16, MPM_BF16 = 0, 1, 2
 MPM_ML, MPM_MAP_JTV = 0, 1
 MPM_INIT_DEFAULT, MPM_INIT_CONST, MPM_INIT_FROM_MAPS = 0, 1, 2
 MPM_LOAD_PROPOSED, MPM_LOAD_GN, MPM_LOAD_PROPOSED_PLUS = 0, 1, 2
+MPM_BASES = {"log": 0, "rate": 1, "time": 2}
 STATUS = {0: "MPM_OK", 1: "MPM_ERR_INVALID_ARG", 2: "MPM_ERR_UNSUPPORTED", 3: "MPM_ERR_OUT_OF_MEMORY",
           4: "MPM_ERR_DEVICE", 5: "MPM_ERR_BUSY", 6: "MPM_ERR_NOT_FOUND"}
 
@@ -41,7 +42,7 @@ class mpm_options(C.Structure):
                 ("max_halvings", C.c_int32), ("loading", C.c_int32), ("init_kind", C.c_int32),
                 ("flags", C.c_int32), ("lam", C.c_double * 4), ("jtv_eps", C.c_double),
                 ("cg_stop", C.c_double), ("init_const", C.c_double * 4), ("tol_gn", C.c_double),
-                ("tol_outer", C.c_double), ("b1_receive", C.c_void_p)]
+                ("tol_outer", C.c_double), ("b1_receive", C.c_void_p), ("basis", C.c_int32)]
 
 
 class mpm_report(C.Structure):
@@ -180,6 +181,7 @@ def make_options(opts: dict) -> mpm_options:
     o.tol_outer = float(opts.get("tol_outer", 0.0))
     bm = opts.get("b1_receive")
     o.b1_receive = None if bm is None else _f32(bm, "b1_receive").value
+    o.basis = MPM_BASES[opts.get("basis", "log")]
     return o
 
 

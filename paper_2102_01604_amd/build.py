@@ -3,6 +3,7 @@ valu_probe programs (plain kernels that measure the GPU's achievable HBM
 bandwidth and VALU issue rate)."""
 from __future__ import annotations
 
+import concurrent.futures
 import os
 import subprocess
 import sys
@@ -12,6 +13,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmpm.so")
 PROBE = os.path.join(HERE, "hbm_probe")
 VALU_PROBE = os.path.join(HERE, "valu_probe")
+OBJ_DIR = os.path.join(HERE, "_build")
 SOURCES = ["mpm_api.hip", "mpm_fit.hip", "mpm_map.hip", "mpm_serve.hip", "k_voxel.hip", "k_map.hip",
            "k_proj.hip"]
 FLAGS = [
@@ -23,9 +25,29 @@ FLAGS = [
 
 
 def build(verbose: bool = False) -> str:
+    """Compile every source to an object (in parallel, one hipcc per file),
+    link libmpm.so, then build the two probe programs."""
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    cmd = [hipcc] + FLAGS + ["-o", LIB + ".tmp"] + srcs
+    os.makedirs(OBJ_DIR, exist_ok=True)
+    cflags = [f for f in FLAGS if f != "-shared"]
+    objs = [os.path.join(OBJ_DIR, os.path.splitext(s)[0] + ".o") for s in SOURCES]
+
+    def compile_one(src, obj):
+        cmd = [hipcc] + cflags + ["-c", "-o", obj, os.path.join(CSRC, src)]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        return subprocess.run(cmd, cwd=CSRC, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
+
+    jobs = max(1, min(len(SOURCES), os.cpu_count() or 1, 8))
+    with concurrent.futures.ThreadPoolExecutor(jobs) as pool:
+        results = list(pool.map(compile_one, SOURCES, objs))
+    for src, r in zip(SOURCES, results):
+        out = "\n".join(l for l in r.stdout.splitlines() if "packed-fp32-ops" not in l)
+        if out.strip():
+            print(out, file=sys.stderr, flush=True)
+        if r.returncode:
+            raise subprocess.CalledProcessError(r.returncode, f"hipcc -c {src}")
+    cmd = [hipcc] + FLAGS + ["-o", LIB + ".tmp"] + objs
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd, cwd=CSRC)

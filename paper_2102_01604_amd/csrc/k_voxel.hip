@@ -303,9 +303,12 @@ hipError_t launch_ml_fit(const LaunchCtx &c, const DevProto &P, int dtype, const
 // ML fit with a protocol per voxel (paper Sec. 3.1): the same Newton-like
 // steps per thread; per voxel the count of steps after which its NLL rose
 // (more than 1e-5 relative, or finite to non-finite) and the final NLL.
-// Partials per workgroup: final NLL, degenerate, non-finite, rises.
+// Partials per workgroup: final NLL, degenerate, non-finite, rises.  BASIS
+// selects the parameters the steps act on: 0 the log/logit ones, 1 the rates
+// (A, R1, R2*, MTsat), 2 the times (A, T1, T2*, MTsat), kept in their domain
+// by basis_step.
 // ---------------------------------------------------------------------------
-template <typename T, int CM, int EM, bool PLUS>
+template <typename T, int CM, int EM, bool PLUS, int BASIS>
 __global__ __launch_bounds__(BLOCK) void k_ml_fit_pv(DevProto P, PVArrays A, const T *__restrict__ X,
                                                      float *__restrict__ maps, int64_t N, int n_gn, int loading,
                                                      int32_t *__restrict__ incr, float *__restrict__ nll_out,
@@ -325,7 +328,10 @@ __global__ __launch_bounds__(BLOCK) void k_ml_fit_pv(DevProto P, PVArrays A, con
         for (int it = 0; it <= n_gn; it++) {
             const bool last = (it == n_gn);
             float g[4], H[10];
-            cur = ve.template lik<PLUS>(P, W, y, loading, !last, g, H);
+            if (BASIS == 0)
+                cur = ve.template lik<PLUS>(P, W, y, loading, !last, g, H);
+            else
+                cur = ve.template lik_basis<PLUS, BASIS>(P, W, y, loading, !last, g, H);
             if (it > 0 && (cur > prev * (1.0f + 1e-5f) || (fabsf(prev) < INFINITY && !(fabsf(cur) < INFINITY))))
                 cnt++;
             prev = cur;
@@ -333,7 +339,7 @@ __global__ __launch_bounds__(BLOCK) void k_ml_fit_pv(DevProto P, PVArrays A, con
             float step[4];
             degen = solve_sym4(H, g, step);
 #pragma unroll
-            for (int k = 0; k < 4; k++) y[k] -= step[k];
+            for (int k = 0; k < 4; k++) y[k] = BASIS == 0 ? y[k] - step[k] : basis_step(k, y[k], step[k]);
         }
     } else {
 #pragma unroll
@@ -358,16 +364,16 @@ __global__ __launch_bounds__(BLOCK) void k_ml_fit_pv(DevProto P, PVArrays A, con
     }
 }
 
-template <typename T, bool PLUS>
+template <typename T, bool PLUS, int BASIS>
 static hipError_t ml_pv_launch(const LaunchCtx &c, const DevProto &P, const PVArrays &A, const T *X, float *maps,
                                int64_t N, int n_gn, int loading, int32_t *incr, float *nll, double *partials)
 {
     dim3 g(ml_fit_blocks(N)), b(BLOCK);
     int emax = 0;
     for (int k = 0; k < P.C; k++) emax = std::max(emax, P.first[k + 1] - P.first[k]);
-#define PV_LAUNCH(CM, EM)                                                                                      \
-    hipLaunchKernelGGL((k_ml_fit_pv<T, CM, EM, PLUS>), g, b, 0, c.stream, P, A, X, maps, N, n_gn, loading, incr, \
-                       nll, partials)
+#define PV_LAUNCH(CM, EM)                                                                                          \
+    hipLaunchKernelGGL((k_ml_fit_pv<T, CM, EM, PLUS, BASIS>), g, b, 0, c.stream, P, A, X, maps, N, n_gn, loading, \
+                       incr, nll, partials)
     if (P.C <= 4 && emax <= 5)
         PV_LAUNCH(4, 5);
     else if (P.C <= 4 && emax <= 6)
@@ -382,23 +388,33 @@ static hipError_t ml_pv_launch(const LaunchCtx &c, const DevProto &P, const PVAr
     return hipGetLastError();
 }
 
+template <typename T, int BASIS>
+static hipError_t ml_pv_loading(const LaunchCtx &c, const DevProto &P, const PVArrays &A, const T *X, float *maps,
+                                int64_t N, int n_gn, int loading, int32_t *incr, float *nll, double *partials)
+{
+    return loading == 2 ? ml_pv_launch<T, true, BASIS>(c, P, A, X, maps, N, n_gn, loading, incr, nll, partials)
+                        : ml_pv_launch<T, false, BASIS>(c, P, A, X, maps, N, n_gn, loading, incr, nll, partials);
+}
+
 template <typename T>
 static hipError_t ml_pv_dispatch(const LaunchCtx &c, const DevProto &P, const PVArrays &A, const T *X, float *maps,
-                                 int64_t N, int n_gn, int loading, int32_t *incr, float *nll, double *partials)
+                                 int64_t N, int n_gn, int loading, int basis, int32_t *incr, float *nll,
+                                 double *partials)
 {
-    return loading == 2 ? ml_pv_launch<T, true>(c, P, A, X, maps, N, n_gn, loading, incr, nll, partials)
-                        : ml_pv_launch<T, false>(c, P, A, X, maps, N, n_gn, loading, incr, nll, partials);
+    if (basis == 1) return ml_pv_loading<T, 1>(c, P, A, X, maps, N, n_gn, loading, incr, nll, partials);
+    if (basis == 2) return ml_pv_loading<T, 2>(c, P, A, X, maps, N, n_gn, loading, incr, nll, partials);
+    return ml_pv_loading<T, 0>(c, P, A, X, maps, N, n_gn, loading, incr, nll, partials);
 }
 
 hipError_t launch_ml_fit_pv(const LaunchCtx &c, const DevProto &P, const PVArrays &A, int dtype, const void *X,
-                            float *maps, int64_t N, int n_gn, int loading, int32_t *incr, float *nll,
+                            float *maps, int64_t N, int n_gn, int loading, int basis, int32_t *incr, float *nll,
                             double *partials)
 {
     if (dtype == DT_F32)
-        return ml_pv_dispatch(c, P, A, (const float *)X, maps, N, n_gn, loading, incr, nll, partials);
+        return ml_pv_dispatch(c, P, A, (const float *)X, maps, N, n_gn, loading, basis, incr, nll, partials);
     if (dtype == DT_F16)
-        return ml_pv_dispatch(c, P, A, (const F16 *)X, maps, N, n_gn, loading, incr, nll, partials);
-    return ml_pv_dispatch(c, P, A, (const BF16 *)X, maps, N, n_gn, loading, incr, nll, partials);
+        return ml_pv_dispatch(c, P, A, (const F16 *)X, maps, N, n_gn, loading, basis, incr, nll, partials);
+    return ml_pv_dispatch(c, P, A, (const BF16 *)X, maps, N, n_gn, loading, basis, incr, nll, partials);
 }
 
 }  // namespace mpm

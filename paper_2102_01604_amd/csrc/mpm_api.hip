@@ -323,6 +323,10 @@ mpm_status check_fit_args(const mpm_protocol *protocol, const mpm_grid *grid, in
     if (opt->init_kind < MPM_INIT_DEFAULT || opt->init_kind > MPM_INIT_FROM_MAPS)
         return fail(MPM_ERR_INVALID_ARG, "unknown init_kind %d", opt->init_kind);
     if (opt->flags != 0) return fail(MPM_ERR_INVALID_ARG, "flags must be 0");
+    if (opt->basis != MPM_BASIS_LOG)
+        return opt->basis == MPM_BASIS_RATE || opt->basis == MPM_BASIS_TIME
+                   ? fail(MPM_ERR_UNSUPPORTED, "only mpm_fit_voxelwise takes a basis other than MPM_BASIS_LOG")
+                   : fail(MPM_ERR_INVALID_ARG, "unknown basis %d", opt->basis);
     for (int k = 0; k < 4; k++) {
         if (!(opt->lambda[k] >= 0.0) || !std::isfinite(opt->lambda[k]))
             return fail(MPM_ERR_INVALID_ARG, "lambda[%d] must be finite and >= 0", k);

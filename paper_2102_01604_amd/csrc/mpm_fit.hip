@@ -209,6 +209,13 @@ extern "C" mpm_status mpm_fit_voxelwise(const mpm_voxel_protocols *vp, int64_t n
     if (opt->init_kind == MPM_INIT_CONST)
         for (int k = 0; k < 4; k++)
             if (!std::isfinite(opt->init_const[k])) return fail(MPM_ERR_INVALID_ARG, "init_const[%d] is not finite", k);
+    if (opt->basis != MPM_BASIS_LOG && opt->basis != MPM_BASIS_RATE && opt->basis != MPM_BASIS_TIME)
+        return fail(MPM_ERR_INVALID_ARG, "unknown basis %d", opt->basis);
+    if (opt->basis != MPM_BASIS_LOG && opt->init_kind == MPM_INIT_CONST) {
+        const double *c = opt->init_const;
+        if (!(c[0] > 0.0 && c[1] > 0.0 && c[2] > 0.0 && c[3] > 0.0 && c[3] < 1.0))
+            return fail(MPM_ERR_INVALID_ARG, "init_const must lie in the basis' domain (A, R or T > 0, 0 < MTsat < 1)");
+    }
     if (!has_mt(&p)) return fail(MPM_ERR_UNSUPPORTED, "the four-parameter model needs at least one MT contrast");
 
     const int64_t N = n_voxels;
@@ -237,8 +244,8 @@ extern "C" mpm_status mpm_fit_voxelwise(const mpm_voxel_protocols *vp, int64_t n
                                           (nll_increases ? 4.0 : 0.0) + (nll ? 4.0 : 0.0));
         if (e == hipSuccess)
             e = prof.launch("ml_fit_pv", bytes, [&] {
-                return launch_ml_fit_pv(c, P, A, dtype, echoes, maps, N, opt->n_gn, opt->loading, nll_increases, nll,
-                                        part);
+                return launch_ml_fit_pv(c, P, A, dtype, echoes, maps, N, opt->n_gn, opt->loading, opt->basis,
+                                        nll_increases, nll, part);
             });
         if (e == hipSuccess) e = launch_reduce_rows(c, part, 4, nblk, sums);
         if (e == hipSuccess) e = hipMemcpyAsync(host.p, sums, sizeof(double) * 4, hipMemcpyDeviceToHost, s);

@@ -400,6 +400,8 @@ static mpm_status uncertainty_impl(const mpm_protocol *protocol, const mpm_grid 
     if (!opt) return fail(MPM_ERR_INVALID_ARG, "options is NULL");
     if (spaces && opt->b1_receive)
         return fail(MPM_ERR_UNSUPPORTED, "b1_receive is not supported by the projected model");
+    if (opt->basis != MPM_BASIS_LOG)
+        return fail(MPM_ERR_UNSUPPORTED, "the uncertainty is defined on the log-parameters (basis %d)", opt->basis);
     if (!echoes || !maps || !var) return fail(MPM_ERR_INVALID_ARG, "echoes, maps and var must be device pointers");
     if (opt->mode != MPM_ML && opt->mode != MPM_MAP_JTV) return fail(MPM_ERR_INVALID_ARG, "unknown mode %d", opt->mode);
     if (opt->loading != MPM_LOAD_PROPOSED && opt->loading != MPM_LOAD_GN && opt->loading != MPM_LOAD_PROPOSED_PLUS)

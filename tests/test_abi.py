@@ -81,6 +81,7 @@ def _fit_raw(lib, proto, dims, opts):
     (lambda p, d, o: o.update(n_gn=-1), 1),
     (lambda p, d, o: o.update(lam=[-1.0, 0, 0, 0]), 1),
     (lambda p, d, o: o.update(flags=3), 1),
+    (lambda p, d, o: o.update(basis="rate"), 2),
     (lambda p, d, o: (d.__setitem__(0, 1), d.__setitem__(1, 1), d.__setitem__(2, 1), o.update(mode="map")), 2),
 ])
 def test_host_validation(lib, mutate, status):
@@ -164,6 +165,10 @@ def test_voxelwise_argument_validation(lib):
         (dict(echoes=None), 1, "device pointers"),
         (dict(n=0), 1, "n_voxels"),
         (dict(receive=True), 2, "b1_receive"),
+        (dict(opts={"mode": "ml", "n_gn": 5, "init": "const", "init_const": [1.0, 1.0, 1.0, 1.5],
+                    "basis": "rate"}), 1, "domain"),
+        (dict(opts={"mode": "ml", "n_gn": 5, "init": "const", "init_const": [-1.0, 1.0, 1.0, 0.5],
+                    "basis": "time"}), 1, "domain"),
         (dict(opts={"mode": "map", "n_gn": 5, "init": "const"}), 1, "ML fit"),
         (dict(opts={"mode": "ml", "n_gn": 5, "init": "default"}), 2, "one protocol"),
         (dict(opts={"mode": "ml", "n_gn": -1, "init": "const"}), 1, "n_gn"),
@@ -176,6 +181,22 @@ def test_voxelwise_argument_validation(lib):
     for kw, status, what in cases:
         st = run(**kw)
         assert st == status and what in lib.mpm_last_error().decode(), (kw, st, lib.mpm_last_error())
+
+
+def test_unknown_basis_rejected(lib):
+    o = _lib.make_options({"mode": "ml", "n_gn": 5, "init": "const", "init_const": [1.0, 1.0, 1.0, 0.5]})
+    o.basis = 3
+    p = _lib.make_voxel_protocols({"n_echoes": [5, 5, 5], "mt": [0, 0, 1], "sigma": [1.0] * 15})
+    p.tr_s = p.flip_rad = p.te_s = 16
+    rep = _lib.mpm_report()
+    st = lib.mpm_fit_voxelwise(C.byref(p), 1000, 0, C.c_void_p(16), C.byref(o), C.c_void_p(16), None, None,
+                               C.byref(rep), None)
+    assert st == 1 and "basis" in lib.mpm_last_error().decode()
+    proto = synth.protocol()
+    proto["sigma"] = [1.0] * 22
+    st = lib.mpm_fit(C.byref(_lib.make_protocol(proto)), C.byref(_lib.make_grid([8, 8, 8])), 0, C.c_void_p(16),
+                     None, C.byref(o), C.c_void_p(16), C.byref(rep), None, 0, None)
+    assert st == 1 and "basis" in lib.mpm_last_error().decode()
 
 
 def test_null_pointers_rejected(lib):
