@@ -86,6 +86,14 @@ def _load():
         lib.orc_spgr_derivs.argtypes = [_dp, C.c_double, C.c_double, C.c_double, C.c_int,
                                         _dp, _dp, _dp]
         lib.orc_spgr_hess.argtypes = [_dp, C.c_double, C.c_double, C.c_double, C.c_int, _dp]
+        lib.orc_bessel_i01e.argtypes = [C.c_double, _dp, _dp]
+        lib.orc_histogram.argtypes = [_dp, C.c_int64, C.c_int, C.POINTER(C.c_int64)]
+        lib.orc_histogram.restype = C.c_float
+        lib.orc_rice_mixture.argtypes = [C.POINTER(C.c_int64), C.c_int, C.c_double, C.c_int, _dp, _dp, _dp, _dp, _dp]
+        lib.orc_rice_mixture.restype = C.c_int
+        lib.orc_estimate_noise.argtypes = [C.POINTER(Protocol), C.c_int64, _dp, _dp, C.c_int, C.c_int, _dp, _dp, _dp,
+                                           _dp]
+        lib.orc_estimate_noise.restype = C.c_int
         lib.orc_spgr_basis.argtypes = [_dp, C.c_int, C.c_double, C.c_double, C.c_double, C.c_int, _dp, _dp, _dp]
         lib.orc_lik_voxel_basis.argtypes = [C.POINTER(Protocol), _dp, C.c_int64, _dp, C.c_int, C.c_int, _dp, _dp,
                                             _dp]
@@ -191,6 +199,52 @@ def _dims(dims):
 
 def num_threads() -> int:
     return int(_load().orc_num_threads())
+
+
+def bessel_i01e(z):
+    """(e^-z I0(z), e^-z I1(z)) for z >= 0."""
+    a, b = np.zeros(1), np.zeros(1)
+    _load().orc_bessel_i01e(float(z), _ptr(a), _ptr(b))
+    return float(a[0]), float(b[0])
+
+
+def histogram(x, nbins):
+    """(counts [nbins] int64, FP32 scale) of one magnitude image."""
+    xv = _f64(np.asarray(x)).reshape(-1)
+    counts = np.zeros(nbins, dtype=np.int64)
+    scale = _load().orc_histogram(_ptr(xv), xv.size, int(nbins), counts.ctypes.data_as(C.POINTER(C.c_int64)))
+    return counts, float(scale)
+
+
+def rice_mixture(counts, scale, n_iter):
+    """Two-class Rician mixture on a histogram: dict of pi, nu, sigma, mean
+    (2 each) and the NLL trace [n_iter + 1]."""
+    counts = np.ascontiguousarray(counts, dtype=np.int64)
+    out = {k: np.zeros(2) for k in ("pi", "nu", "sigma", "mean")}
+    nll = np.zeros(n_iter + 1)
+    st = _load().orc_rice_mixture(counts.ctypes.data_as(C.POINTER(C.c_int64)), counts.size, float(scale),
+                                  int(n_iter), _ptr(out["pi"]), _ptr(out["nu"]), _ptr(out["sigma"]),
+                                  _ptr(out["mean"]), _ptr(nll))
+    if st:
+        raise ValueError("the histogram does not split in two classes")
+    out["nll"] = nll
+    return out
+
+
+def estimate_noise(proto, x, b1=None, nbins=1024, n_iter=200):
+    """Per-image sigma, per-contrast sigma (geometric mean of the variances),
+    per-image foreground mean and the initial maps y0 (Sec. 2.7)."""
+    I = n_images(proto)
+    x = _f64(x).reshape(I, -1)
+    N = x.shape[1]
+    b1 = None if b1 is None else _f64(b1).reshape(N)
+    si, sc, fg, y0 = np.zeros(I), np.zeros(len(proto["n_echoes"])), np.zeros(I), np.zeros(4)
+    p = make_protocol(dict(proto, sigma=[1.0] * I))
+    st = _load().orc_estimate_noise(C.byref(p), N, _ptr(x), _ptr(b1), int(nbins), int(n_iter), _ptr(si), _ptr(sc),
+                                    _ptr(fg), _ptr(y0))
+    if st:
+        raise ValueError("an image does not split in two classes")
+    return {"sigma_image": si, "sigma_contrast": sc, "fg_mean": fg, "y0": y0}
 
 
 def spgr_basis(th, basis, alpha, tr, te, mt):

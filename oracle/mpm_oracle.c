@@ -38,6 +38,13 @@
  *   R-missing: a non-finite echo value is a missing observation: it adds
  *              nothing to the NLL, gradient or Hessian of its voxel (and is
  *              left out of the volume means of the default initialisation).
+ *   R-rice   : noise estimation (Sec. 2.7): each image's histogram over
+ *              [0, max] (bins decided in FP32), a two-class Rician mixture fitted
+ *              to the bin centres by EM with the phase as latent variable, from
+ *              the split of the histogram at its mean; the class started on the
+ *              lower part is the background (air) and has no signal (nu = 0: a
+ *              free nu converges only sublinearly along the flat nu-sigma ridge);
+ *              a class's mean is its responsibility-weighted mean.
  *   R-basis  : in the rate and time representations (Sec. 3.1) the steps act
  *              on the values themselves and the signal formula is evaluated
  *              at whatever values they reach: no clamp to the physical domain
@@ -1239,4 +1246,178 @@ int orc_uncertainty_projected(const orc_protocol *p, const int64_t dims[3], cons
 {
     lik_ctx L = {p, dims, spaces, x, b1};
     return uncertainty_impl(&L, opt, maps, var, moments);
+}
+
+/* ------------------------------------------------------------------------
+ * Noise estimation (Sec. 2.7): per acquired volume, a two-class Rician
+ * mixture fitted to the image histogram; the class with the lower mean is the
+ * background, whose sigma is the noise level; variances of the echoes of one
+ * contrast are averaged with the geometric mean, and the mean of the other
+ * class feeds the constant initial maps.
+ * ------------------------------------------------------------------------ */
+
+/* e^-z I0(z), e^-z I1(z): the power series
+ *   I0(z) = sum_k (z^2/4)^k / (k!)^2,  I1(z) = (z/2) sum_k (z^2/4)^k / (k! (k+1)!)
+ * for z <= 25 (summed until a term is below 1e-17 of the sum), else the
+ * large-argument expansion
+ *   I_v(z) ~ e^z / sqrt(2 pi z) sum_k (-1)^k a_k(v) / z^k,
+ *   a_k(v) = prod_{j=1..k} (4 v^2 - (2j - 1)^2) / (k! 8^k),
+ * to 30 terms (at z > 25 the terms shrink past 1e-17 before they grow). */
+void orc_bessel_i01e(double z, double *i0e, double *i1e)
+{
+    if (z <= 25.0) {
+        double q = 0.25 * z * z, t0 = 1.0, t1 = 1.0, s0 = 1.0, s1 = 1.0;
+        for (int k = 1; k < 500; k++) {
+            t0 *= q / ((double)k * (double)k);
+            t1 *= q / ((double)k * (double)(k + 1));
+            s0 += t0;
+            s1 += t1;
+            if (t0 < 1e-17 * s0 && t1 < 1e-17 * s1) break;
+        }
+        double e = exp(-z);
+        *i0e = s0 * e;
+        *i1e = 0.5 * z * s1 * e;
+        return;
+    }
+    double s0 = 1.0, s1 = 1.0, a0 = 1.0, a1 = 1.0;
+    for (int k = 1; k <= 30; k++) {
+        double odd = (double)(2 * k - 1) * (double)(2 * k - 1);
+        a0 *= -(0.0 - odd) / ((double)k * 8.0 * z);
+        a1 *= -(4.0 - odd) / ((double)k * 8.0 * z);
+        s0 += a0;
+        s1 += a1;
+    }
+    double f = 1.0 / sqrt(2.0 * 3.14159265358979323846 * z);
+    *i0e = f * s0;
+    *i1e = f * s1;
+}
+
+float orc_histogram(const double *x, int64_t n, int nbins, int64_t *counts)
+{
+    float mx = 0.0f;
+    for (int64_t v = 0; v < n; v++) {
+        float f = (float)x[v];
+        if (isfinite(f) && f > mx) mx = f;
+    }
+    for (int b = 0; b < nbins; b++) counts[b] = 0;
+    if (!(mx > 0.0f)) return 0.0f;
+    float scale = (float)nbins / mx;
+    for (int64_t v = 0; v < n; v++) {
+        float f = (float)x[v];
+        if (!isfinite(f) || f < 0.0f) continue;
+        int b = (int)(f * scale);
+        counts[b < nbins ? b : nbins - 1]++;
+    }
+    return scale;
+}
+
+/* log of the Rice density at c, and the posterior mean of cos(phase),
+ * I1(z)/I0(z) with z = c nu / sigma^2:
+ *   log p = log c - 2 log sigma - (c - nu)^2 / (2 sigma^2) + log(e^-z I0(z)). */
+static double rice_logpdf(double c, double nu, double sigma, double *ratio)
+{
+    double s2 = sigma * sigma;
+    double i0e, i1e;
+    orc_bessel_i01e(c * nu / s2, &i0e, &i1e);
+    *ratio = i1e / i0e;
+    return log(c) - 2.0 * log(sigma) - (c - nu) * (c - nu) / (2.0 * s2) + log(i0e);
+}
+
+int orc_rice_mixture(const int64_t *counts, int nbins, double scale, int n_iter, double pi[2], double nu[2],
+                     double sigma[2], double mean[2], double *nll)
+{
+    double width = 1.0 / scale;
+    /* initial split at the mean of the values */
+    double tot = 0.0, m = 0.0;
+    for (int b = 0; b < nbins; b++) {
+        tot += (double)counts[b];
+        m += (double)counts[b] * (b + 0.5) * width;
+    }
+    if (!(tot > 0.0)) return 1;
+    m /= tot;
+    double w[2] = {0.0, 0.0}, s1[2] = {0.0, 0.0}, s2[2] = {0.0, 0.0};
+    for (int b = 0; b < nbins; b++) {
+        double c = (b + 0.5) * width;
+        int k = c < m ? 0 : 1;
+        w[k] += (double)counts[b];
+        s1[k] += (double)counts[b] * c;
+        s2[k] += (double)counts[b] * c * c;
+    }
+    if (!(w[0] > 0.0) || !(w[1] > 0.0)) return 1;
+    for (int k = 0; k < 2; k++) {
+        pi[k] = w[k] / tot;
+        nu[k] = s1[k] / w[k];
+        double var = s2[k] / w[k] - nu[k] * nu[k];
+        sigma[k] = sqrt(var > width * width ? var : width * width);
+    }
+    /* class 0 is the background: air carries no signal, nu = 0 (Rayleigh) */
+    nu[0] = 0.0;
+    sigma[0] = sqrt(0.5 * s2[0] / w[0]);
+    /* EM: the phase of each value is the latent variable (the magnitude of a
+     * complex Gaussian of mean nu and variance sigma^2 per part) */
+    for (int it = 0; it <= n_iter; it++) {
+        double N[2] = {0.0, 0.0}, Sx[2] = {0.0, 0.0}, Sx2[2] = {0.0, 0.0}, Sxa[2] = {0.0, 0.0}, L = 0.0;
+        for (int b = 0; b < nbins; b++) {
+            if (!counts[b]) continue;
+            double c = (b + 0.5) * width, n = (double)counts[b];
+            double lp[2], ra[2];
+            for (int k = 0; k < 2; k++) lp[k] = log(pi[k]) + rice_logpdf(c, nu[k], sigma[k], &ra[k]);
+            double mx = lp[0] > lp[1] ? lp[0] : lp[1];
+            double lse = mx + log(exp(lp[0] - mx) + exp(lp[1] - mx));
+            L -= n * lse;
+            for (int k = 0; k < 2; k++) {
+                double r = n * exp(lp[k] - lse);
+                N[k] += r;
+                Sx[k] += r * c;
+                Sx2[k] += r * c * c;
+                Sxa[k] += r * c * ra[k];
+            }
+        }
+        if (nll) nll[it] = L;
+        if (it == n_iter) {
+            for (int k = 0; k < 2; k++) mean[k] = Sx[k] / N[k];
+            break;
+        }
+        for (int k = 0; k < 2; k++) {
+            pi[k] = N[k] / tot;
+            nu[k] = k == 0 ? 0.0 : Sxa[k] / N[k];
+            sigma[k] = sqrt(0.5 * (Sx2[k] / N[k] - nu[k] * nu[k]));
+        }
+    }
+    return 0;
+}
+
+int orc_estimate_noise(const orc_protocol *p, int64_t n, const double *x, const double *b1, int nbins, int n_iter,
+                       double *sigma_image, double *sigma_contrast, double *fg_mean, double y0[4])
+{
+    int I = n_images(p);
+    int64_t *counts = (int64_t *)malloc(sizeof(int64_t) * (size_t)nbins);
+    int bad = 0;
+    for (int i = 0; i < I && !bad; i++) {
+        double scale = orc_histogram(x + (int64_t)i * n, n, nbins, counts);
+        double pi[2], nu[2], sg[2], mn[2];
+        if (!(scale > 0.0) || orc_rice_mixture(counts, nbins, scale, n_iter, pi, nu, sg, mn, NULL)) {
+            bad = 1;
+            break;
+        }
+        int bg = mn[0] <= mn[1] ? 0 : 1;
+        sigma_image[i] = sg[bg];
+        fg_mean[i] = mn[1 - bg];
+    }
+    free(counts);
+    if (bad) return 1;
+    int first = 0;
+    for (int c = 0; c < p->n_contrasts; c++) {
+        double lv = 0.0;
+        for (int e = 0; e < p->n_echoes[c]; e++) lv += log(sigma_image[first + e] * sigma_image[first + e]);
+        sigma_contrast[c] = sqrt(exp(lv / p->n_echoes[c]));
+        first += p->n_echoes[c];
+    }
+    double b1m = 1.0;
+    if (b1) {
+        double s = 0.0;
+        for (int64_t v = 0; v < n; v++) s += b1[v];
+        b1m = s / (double)n;
+    }
+    return init_from_means(p, fg_mean, b1m, y0);
 }

@@ -146,6 +146,31 @@ int orc_uncertainty_projected(const orc_protocol *p, const int64_t dims[3], cons
                               const double *x, const double *b1, const orc_options *opt, const double *maps,
                               double *var, double *moments);
 
+/* ---- noise estimation (Sec. 2.7) ---- */
+/* e^-z I0(z) and e^-z I1(z) for z >= 0 (modified Bessel functions). */
+void orc_bessel_i01e(double z, double *i0e, double *i1e);
+/* Histogram of one magnitude image (x [n]): finite values >= 0 in nbins
+ * bins over [0, max]; the bin of a value is decided in FP32 (R-rice).
+ * Returns the FP32 scale nbins / max (bin b covers [b, b+1) / scale), 0 if no
+ * value is > 0. */
+float orc_histogram(const double *x, int64_t n, int nbins, int64_t *counts);
+/* Two-class Rician mixture fitted to a histogram by n_iter EM iterations
+ * (R-rice; class 0, the background, has nu = 0); per class k: weight pi,
+ * Rice parameters nu and sigma, and the
+ * responsibility-weighted mean of the values; nll [n_iter + 1] (optional):
+ * the histogram's negative log-likelihood before each iteration and after
+ * the last.  Returns 0, or 1 if the values do not split in two classes. */
+int orc_rice_mixture(const int64_t *counts, int nbins, double scale, int n_iter, double pi[2], double nu[2],
+                     double sigma[2], double mean[2], double *nll);
+/* Noise level and initial maps as Sec. 2.7 obtains them (R-rice): per image
+ * the mixture above, whose lower-mean class is the background;
+ * sigma_image[i] its sigma; sigma_contrast[c] the square root of the
+ * geometric mean of the variances of contrast c's echoes; fg_mean[i] the mean
+ * of the other class; y0 the default initialisation from those means (b1:
+ * [n] or NULL).  Returns 0, or 1 if some image does not split in two classes. */
+int orc_estimate_noise(const orc_protocol *p, int64_t n, const double *x, const double *b1, int nbins, int n_iter,
+                       double *sigma_image, double *sigma_contrast, double *fg_mean, double y0[4]);
+
 #ifdef __cplusplus
 }
 #endif

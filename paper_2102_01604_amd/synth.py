@@ -186,3 +186,38 @@ def make_case(name=None, dims=None, seed=None, **over):
             "lam": lam if cfg["mode"] == "map" else [0.0] * 4}
     return {"name": name, "dims": cfg["dims"], "proto": proto, "truth": truth, "b1": b1,
             "eps": eps, "sigma": sigma, "lam": lam, "opts": opts, "seed": cfg["seed"]}
+
+
+def head_mask(dims, frac=0.8):
+    """Ellipsoid occupying `frac` of each axis' extent, centred: True inside
+    (the head), False outside (air).  Flat [N], x fastest."""
+    nx, ny, nz = (int(v) for v in dims)
+    z, y, x = np.meshgrid(*[(np.arange(n) + 0.5) / n - 0.5 for n in (nz, ny, nx)], indexing="ij")
+    r = (x / (0.5 * frac)) ** 2 + (y / (0.5 * frac)) ** 2 + (z / (0.5 * frac)) ** 2
+    return (r <= 1.0).reshape(-1)
+
+
+def head_case(dims, seed, noise_frac=0.02, echoes=(8, 8, 6)):
+    """Magnitude echoes of a head in air, as the paper's noise estimation
+    (Sec. 2.7) expects them: tissue maps inside an ellipsoid, no signal
+    outside; the noise is complex Gaussian of std sigma per channel, so every
+    value is |s + sigma (e1 + i e2)| (Rician; Rayleigh in the air).  Returns
+    the case dict of make_case plus ``mask`` [N] and ``rice`` = (e1, e2), two
+    float32 [I][N] noise arrays; the magnitudes are formed by the caller
+    from its own forward model."""
+    c = make_case("map_brain", dims=dims, seed=seed, noise_frac=noise_frac, echoes=echoes)
+    rng = np.random.default_rng(seed + 7)
+    n_img, n = len(c["proto"]["te"]), c["truth"].shape[1]
+    c["mask"] = head_mask(dims)
+    c["rice"] = (noise(n_img, n, rng), noise(n_img, n, rng))
+    # sigma relative to the mean PD inside the head
+    c["sigma"] = noise_frac * float(np.exp(c["truth"][0][c["mask"]]).mean())
+    c["proto"]["sigma"] = [c["sigma"]] * n_img
+    return c
+
+
+def magnitudes(signal, case):
+    """|s + sigma (e1 + i e2)| with the signal zeroed outside the head."""
+    s = np.where(case["mask"][None, :], signal, 0.0)
+    e1, e2 = case["rice"]
+    return np.hypot(s + case["sigma"] * e1, case["sigma"] * e2)
