@@ -277,6 +277,43 @@ mpm_status mpm_fit_voxelwise(const mpm_voxel_protocols *protocols, int64_t n_vox
 mpm_status mpm_simulate_voxelwise(const mpm_voxel_protocols *protocols, int64_t n_voxels, const float *maps,
                                   const float *noise, mpm_dtype out_dtype, void *out, void *stream);
 
+/*
+ * mpm_estimate_noise -- the noise level and the constant initial maps from
+ * the echoes, as paper Sec. 2.7 obtains them: per image a two-class Rician
+ * mixture fitted to its histogram; the class with the lower mean is the
+ * background (air), whose sigma is the image's noise level; the variances of
+ * one contrast's echoes are averaged with the geometric mean; the initial
+ * maps come from the other class's means (the default initialisation's
+ * closed forms).  Needs magnitude images with a background.
+ *
+ * Per image: the finite values >= 0 (others are not observations) in nbins
+ * bins over [0, max] (bin floor(x * (nbins / max)) taken in FP32, the top
+ * value in the last bin); n_iter EM iterations on the bin centres, the phase
+ * of each value as the latent variable, from the split of the histogram at its
+ * mean; class 0, started on the lower part, is a Rician without signal
+ * (nu = 0).
+ *
+ * protocol: as for mpm_fit, its sigma not read; echoes: device [I][N]
+ * (dtype); b1: device [N] or NULL (its mean enters the initial maps as in the
+ * default initialisation); nbins in [16, 4096] (1024 is a good choice);
+ * n_iter in [0, 100000] (200).  Host outputs, caller-owned:
+ * sigma_image [I], sigma_contrast [C], fg_mean [I] (the foreground class's
+ * mean), init_const [4] (log A, log R1, log R2*, logit MTsat: pass as
+ * mpm_options.init_const with MPM_INIT_CONST); fits [I] or NULL: each image's
+ * mixture; hist [I][nbins] or NULL: the histograms.  Blocks until done.
+ * MPM_ERR_UNSUPPORTED if an image's values do not split in two classes.
+ */
+typedef struct {
+    double pi[2], nu[2], sigma[2]; /* weights and Rice parameters; class 0: nu = 0 */
+    double mean[2];                /* responsibility-weighted mean value per class */
+    double nll;                    /* negative log-likelihood of the bin centres   */
+} mpm_rice_fit;
+
+mpm_status mpm_estimate_noise(const mpm_protocol *protocol, const mpm_grid *grid, mpm_dtype dtype,
+                              const void *echoes, const float *b1, int32_t nbins, int32_t n_iter,
+                              double *sigma_image, double *sigma_contrast, double *fg_mean, double *init_const,
+                              mpm_rice_fit *fits, uint32_t *hist, void *stream);
+
 /* Device bytes a fit of this size needs: inputs, maps and the library's
  * workspace.  Returns 0 for invalid arguments. */
 size_t mpm_footprint_bytes(const mpm_protocol *protocol, const mpm_grid *grid, mpm_dtype dtype,

@@ -75,6 +75,11 @@ class mpm_voxel_protocols(C.Structure):
                 ("tr_s", C.c_void_p), ("flip_rad", C.c_void_p), ("te_s", C.c_void_p)]
 
 
+class mpm_rice_fit(C.Structure):
+    _fields_ = [("pi", C.c_double * 2), ("nu", C.c_double * 2), ("sigma", C.c_double * 2), ("mean", C.c_double * 2),
+                ("nll", C.c_double)]
+
+
 class MpmError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"{STATUS.get(status, status)}: {msg}")
@@ -102,6 +107,10 @@ SIGNATURES = {
                                     C.c_void_p, C.c_void_p, _R, C.c_void_p]),
     "mpm_simulate_voxelwise": (C.c_int, [C.POINTER(mpm_voxel_protocols), C.c_int64, C.c_void_p, C.c_void_p, C.c_int,
                                          C.c_void_p, C.c_void_p]),
+    "mpm_estimate_noise": (C.c_int, [_P, _G, C.c_int, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32,
+                                     C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                     C.POINTER(C.c_double), C.POINTER(mpm_rice_fit), C.POINTER(C.c_uint32),
+                                     C.c_void_p]),
     "mpm_last_error": (C.c_char_p, []),
     "mpm_version": (C.c_char_p, []),
     "mpm_profile_enable": (None, [C.c_int32]),
@@ -328,6 +337,30 @@ def mpm_simulate_voxelwise(shape: dict, tr, flip, te, maps, noise, out, stream=N
     N = int(maps.shape[-1])
     _check(lib.mpm_simulate_voxelwise(C.byref(make_voxel_protocols(shape, tr, flip, te)), N, _f32(maps, "maps"),
                                       _f32(noise, "noise"), _dtype_code(out), _ptr(out), _stream(stream)))
+
+
+def mpm_estimate_noise(protocol: dict, dims, echoes, b1=None, nbins: int = 1024, n_iter: int = 200,
+                       want_hist: bool = False, stream=None) -> dict:
+    """Noise level and initial maps from magnitude echoes with a background
+    (Sec. 2.7).  Returns sigma_image [I], sigma_contrast [C], fg_mean [I],
+    init_const [4], the per-image mixtures and (want_hist) the histograms."""
+    lib = load()
+    proto = dict(protocol)
+    I = sum(proto["n_echoes"])
+    proto.setdefault("sigma", [1.0] * I)
+    n_c = len(proto["n_echoes"])
+    si, sc, fg, y0 = (C.c_double * I)(), (C.c_double * n_c)(), (C.c_double * I)(), (C.c_double * 4)()
+    fits = (mpm_rice_fit * I)()
+    hist = (C.c_uint32 * (I * nbins))() if want_hist else None
+    _check(lib.mpm_estimate_noise(C.byref(make_protocol(proto)), C.byref(make_grid(dims)), _dtype_code(echoes),
+                                  _ptr(echoes), _f32(b1, "b1"), int(nbins), int(n_iter), si, sc, fg, y0, fits, hist,
+                                  _stream(stream)))
+    out = {"sigma_image": list(si), "sigma_contrast": list(sc), "fg_mean": list(fg), "init_const": list(y0),
+           "fits": [{k: (list(getattr(f, k)) if k != "nll" else f.nll) for k, _ in mpm_rice_fit._fields_}
+                    for f in fits]}
+    if want_hist:
+        out["hist"] = list(hist)
+    return out
 
 
 def mpm_footprint_bytes(protocol: dict, dims, dtype: int, mode: int) -> int:

@@ -42,7 +42,7 @@ def test_struct_layouts_match_header(tmp_path):
     structs = {"mpm_protocol": _lib.mpm_protocol, "mpm_grid": _lib.mpm_grid, "mpm_options": _lib.mpm_options,
                "mpm_report": _lib.mpm_report, "mpm_kernel_stat": _lib.mpm_kernel_stat,
                "mpm_request": _lib.mpm_request, "mpm_space": _lib.mpm_space,
-               "mpm_voxel_protocols": _lib.mpm_voxel_protocols}
+               "mpm_voxel_protocols": _lib.mpm_voxel_protocols, "mpm_rice_fit": _lib.mpm_rice_fit}
     rename = {"lam": "lambda"}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "mpm.h"', "int main(void){"]
     for name, cls in structs.items():
@@ -197,6 +197,21 @@ def test_unknown_basis_rejected(lib):
     st = lib.mpm_fit(C.byref(_lib.make_protocol(proto)), C.byref(_lib.make_grid([8, 8, 8])), 0, C.c_void_p(16),
                      None, C.byref(o), C.c_void_p(16), C.byref(rep), None, 0, None)
     assert st == 1 and "basis" in lib.mpm_last_error().decode()
+
+
+def test_noise_estimation_argument_validation(lib):
+    proto = synth.protocol()
+    proto["sigma"] = [1.0] * 22
+    out = [(C.c_double * 22)(), (C.c_double * 3)(), (C.c_double * 22)(), (C.c_double * 4)()]
+
+    def run(nbins=1024, n_iter=200, echoes=C.c_void_p(16), outs=out, p=proto):
+        return lib.mpm_estimate_noise(C.byref(_lib.make_protocol(p)), C.byref(_lib.make_grid([8, 8, 8])), 0,
+                                      echoes, None, nbins, n_iter, *outs, None, None, None)
+    for kw, status, what in ((dict(nbins=8), 1, "nbins"), (dict(nbins=5000), 1, "nbins"), (dict(n_iter=-1), 1, "n_iter"),
+                             (dict(echoes=None), 1, "echoes"), (dict(outs=[None] + out[1:]), 1, "host"),
+                             (dict(p=dict(proto, mt=[0, 0, 0])), 2, "MT")):
+        st = run(**kw)
+        assert st == status and what in lib.mpm_last_error().decode(), (kw, st, lib.mpm_last_error())
 
 
 def test_null_pointers_rejected(lib):
