@@ -10,6 +10,17 @@ before the clock starts, so the timed region starts with every input resident
 in HBM.  Prints one JSON line.
 
     python bench.py [--steps K] [--warmup W] [--dtype f32|f16|bf16] [--no-cpu-baseline]
+
+Other workloads (one JSON line each; not the headline step):
+    --hires       JTV-MAP + variance on 416 x 384 x 320 voxels with FP16 echoes
+    --projected   the MAP fit with two contrasts acquired on moved grids (Sec. 2.4)
+    --e1          the convergence experiment of Sec. 3.1 at scale (1 M voxels, a
+                  protocol each, 10,000 steps) and its rate / time representation
+                  comparison
+    --noise       the noise estimation of Sec. 2.7 on the whole-brain volume in air
+    --serving     the continuous-batching queue on a mix of 64 ML and MAP requests
+    --counters    a short workload for rocprofv3 counter runs (with --projected or
+                  --e1: theirs)
 """
 from __future__ import annotations
 
