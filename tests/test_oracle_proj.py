@@ -84,6 +84,22 @@ def test_identity_spaces_equal_the_unprojected_fit(orc, mode):
     assert r1["gn_done"] == r0["gn_done"] and r1["nll"] == pytest.approx(r0["nll"], rel=1e-12)
 
 
+@pytest.mark.parametrize("mode", ["ml", "map"])
+def test_identity_spaces_equal_the_unprojected_uncertainty(orc, mode):
+    """With every contrast acquired on the reconstruction grid the pushed
+    blocks are the voxel blocks, so the projected Laplace variance is the plain
+    one (itself pinned by sampling, test_oracle_map)."""
+    c = synth.make_case("map_brain", dims=(12, 10, 6), seed=53)
+    x = orc.simulate(c["proto"], c["truth"], c["b1"]) + c["sigma"] * c["eps"].astype(np.float64)
+    opts = dict(c["opts"], mode=mode)
+    maps = c["truth"] + 0.05
+    v0 = orc.uncertainty(c["proto"], c["dims"], x, c["b1"], opts, maps)
+    v1 = orc.uncertainty_projected(c["proto"], c["dims"], [_identity(c["dims"])] * 3, x.reshape(-1), c["b1"], opts,
+                                   maps)
+    assert np.all(np.isfinite(v0)) and np.all(v0 > 0)
+    assert np.abs(v1 - v0).max() <= 1e-12 * np.abs(v0).max()
+
+
 def _moved_problem(orc, dims=(10, 9, 6), seed=52, noise=True):
     """Three contrasts, each acquired on its own moved grid; echoes simulated
     by pulling the true maps (and b1) into each space."""
