@@ -80,8 +80,9 @@ def read_traffic(kernel):
 
 def read_valu_counts():
     """VALU lane-instructions per voxel evaluation of the voxelwise ML kernel,
-    per loading (dispatch order Proposed, Proposed+, Gauss-Newton), from the
-    committed counter summary; None if absent or taken on other sources."""
+    per loading (dispatch order Proposed, Proposed+, Gauss-Newton, then the
+    rate and time representations with Proposed+), from the committed counter
+    summary; None if absent or taken on other sources."""
     if not os.path.exists(VALU_FILE):
         return None
     kv = {}
@@ -92,10 +93,15 @@ def read_valu_counts():
     if kv.get("source_sha256_16") != source_hash(VALU_SOURCES):
         return None
     try:
-        return {load: float(kv[f"SQ_INSTS_VALU_dispatch{d}_lanes_per_voxel_eval"])
-                for d, load in enumerate(("proposed", "plus", "gn"))}
+        out = {load: float(kv[f"SQ_INSTS_VALU_dispatch{d}_lanes_per_voxel_eval"])
+               for d, load in enumerate(("proposed", "plus", "gn"))}
     except KeyError:
         return None
+    for d, basis in ((3, "rate"), (4, "time")):
+        v = kv.get(f"SQ_INSTS_VALU_dispatch{d}_lanes_per_voxel_eval")
+        if v is not None:
+            out[basis] = float(v)
+    return out
 
 
 def main():
@@ -466,12 +472,16 @@ def convergence_experiment(args, torch, _lib, synth, dev):
     inc = torch.empty(N, dtype=torch.int32, device=dev)
     nll = torch.empty(N, dtype=torch.float32, device=dev)
     res = {}
-    if args.counters:  # one fit per loading, no warm-up: dispatches in the order proposed, plus, gn
+    if args.counters:  # one fit each, no warm-up: dispatches proposed, plus, gn, rate (plus), time (plus)
         for load in ("proposed", "plus", "gn"):
             _lib.mpm_fit_voxelwise(shape, TR, FL, TE, X, {"mode": "ml", "n_gn": its, "init": "const",
                                                           "init_const": [0.0] * 4, "loading": load}, maps, inc, nll)
+        for basis in ("rate", "time"):
+            _lib.mpm_fit_voxelwise(shape, TR, FL, TE, X, {"mode": "ml", "n_gn": its, "init": "const",
+                                                          "init_const": [1.0, 1.0, 1.0, 0.5], "loading": "plus",
+                                                          "basis": basis}, maps, inc, nll)
         torch.cuda.synchronize()
-        log("counter workload done: three voxelwise fits")
+        log("counter workload done: five voxelwise fits")
         return
     for load in ("proposed", "plus", "gn"):
         opts = {"mode": "ml", "n_gn": its, "init": "const", "init_const": [0.0] * 4, "loading": load}
@@ -489,6 +499,14 @@ def convergence_experiment(args, torch, _lib, synth, dev):
                      "frac_nonfinite": round(rep["nonfinite_voxels"] / N, 5)}
         log(f"e1 {load}: {ms:.1f} ms, NLL rose in {100 * rose:.2f}% of voxels")
     reps = representation_comparison(args, torch, _lib, shape, TR, FL, TE, X, maps, inc, nll)
+    counts = read_valu_counts()
+    for b, key in (("log", "plus"), ("rate", "rate"), ("time", "time")):
+        if counts is not None and key in counts:
+            evals = N * (its + len(reps[b]["steps"]))  # each call evaluates its steps + 1 times
+            ach = counts[key] * evals / (reps[b]["ms"] * 1e-3) / 1e12
+            reps[b]["roofline"] = {"bound": "alu", "achieved": round(ach, 2), "peak": round(VALU_PEAK_T, 2),
+                                   "unit": "T VALU lane-instructions/s", "frac": round(ach / VALU_PEAK_T, 4),
+                                   "valu_per_voxel_iteration": counts[key]}
     cpu = None
     if not args.no_cpu_baseline:
         # the FP64 oracle on the first 32768 voxels of the same problems, 8000 steps, Proposed loading
@@ -505,7 +523,6 @@ def convergence_experiment(args, torch, _lib, synth, dev):
                "kind": "oracle", "seconds": round(dt, 2),
                "sample": f"the first {n_s} voxels of the same problems, {it_s} steps, Proposed loading, FP64"}
     roof = None
-    counts = read_valu_counts()
     if counts is not None:
         ach = counts["proposed"] * N * (its + 1) / (res["proposed"]["ms"] * 1e-3) / 1e12
         roof = {"bound": "alu", "kernel": "ml_fit_pv", "achieved": round(ach, 2), "peak": round(VALU_PEAK_T, 2),
