@@ -43,6 +43,9 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_map_brain.txt")
 VALU_SOURCES = [os.path.join(ROOT, "paper_2102_01604_amd", "csrc", f)
                 for f in ("k_voxel.hip", "mpm_voxelwise.h", "mpm_device.h")]
 VALU_FILE = os.path.join(ROOT, "profiles", "valu_ml_fit_pv_e1.txt")
+NOISE_SOURCES = [os.path.join(ROOT, "paper_2102_01604_amd", "csrc", f)
+                 for f in ("k_noise.hip", "mpm_noise.h", "mpm_device.h")]
+NOISE_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_noise_hist_brain.txt")
 # Published FP32 vector peak 157.3 TFLOP/s = 256 CUs x 2.4 GHz x 128 FMA lanes
 # per clock: 2 wave64 VALU instructions per clock per CU, 78.6 T lane-instructions/s.
 VALU_PEAK_T = 256 * 2.4e9 * 128 / 1e12
@@ -59,18 +62,18 @@ def source_hash(paths):
     return h.hexdigest()[:16]
 
 
-def read_traffic(kernel):
+def read_traffic(kernel, path=TRAFFIC_FILE, sources=KERNEL_SOURCES):
     """HBM bytes per launch measured by rocprofv3 counters (FETCH_SIZE +
     WRITE_SIZE, scaled by a copy-kernel calibration), recorded together with
     the hash of the kernel sources they were taken on; None if absent or stale."""
-    if not os.path.exists(TRAFFIC_FILE):
+    if not os.path.exists(path):
         return None
     kv = {}
-    for line in open(TRAFFIC_FILE):
+    for line in open(path):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
-    if kv.get("source_sha256_16") != source_hash(KERNEL_SOURCES) or kv.get("kernel") != kernel:
+    if kv.get("source_sha256_16") != source_hash(sources) or kv.get("kernel") != kernel:
         return None
     try:
         return float(kv["bytes_per_launch"])
@@ -610,6 +613,14 @@ def noise_estimation(args, torch, _lib, synth, dev):
     del e1, e2, truth
     torch.cuda.synchronize()
     log(f"noise workload: {dims} x {I} magnitude images in air, sigma {sigma:.3f}")
+    if args.counters:  # one estimate, then a plain 1 GiB device copy as the byte-count calibration
+        _lib.mpm_estimate_noise(c["proto"], dims, X, b1)
+        a = torch.ones(1 << 28, dtype=torch.float32, device=dev)  # 1 GiB
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log("counter workload done: one noise estimate and a 1 GiB copy")
+        return
     for _ in range(args.warmup):
         _lib.mpm_estimate_noise(c["proto"], dims, X, b1)
     torch.cuda.synchronize()
@@ -630,8 +641,9 @@ def noise_estimation(args, torch, _lib, synth, dev):
     dom = max(("image_max", "image_hist"), key=lambda k: kern[k]["avg_ms"])
     alg = float(N) * I * 4.0
     ach = alg / (kern[dom]["avg_ms"] * 1e-3) / 1e9
+    traffic = read_traffic(dom, NOISE_TRAFFIC_FILE, NOISE_SOURCES)
     roof = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": 8000.0, "unit": "GB/s",
-            "frac": round(ach / 8000.0, 4), "traffic": None, "alg_bytes_per_launch": alg,
+            "frac": round(ach / 8000.0, 4), "traffic": traffic, "alg_bytes_per_launch": alg,
             "avg_ms": kern[dom]["avg_ms"],
             "note": "the streaming pass over the echoes; the EM (rice_em) is a chain of dependent iterations, "
                     "one workgroup per image, bound by its FP64 latency on 22 CUs, not by a roofline"}

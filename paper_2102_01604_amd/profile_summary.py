@@ -17,7 +17,8 @@ last `last` dispatches, default all): FETCH_SIZE and WRITE_SIZE (KiB per
 dispatch) scaled by what the same counters read for a
 plain device-to-device copy of 1 GiB in the same run (the copy kernel whose
 name contains "copyBuffer" with the largest FETCH_SIZE), in the key: value
-format bench.py reads, tagged with the hash of the MAP kernel sources.
+format bench.py reads, tagged with the hash of the kernel's sources (the MAP
+kernels', or the noise kernels' for image_hist / image_max).
 """
 from __future__ import annotations
 
@@ -52,6 +53,11 @@ def _counter(path):
     return out
 
 
+NOISE_SOURCES = [os.path.join(HERE, "csrc", f) for f in ("k_noise.hip", "mpm_noise.h", "mpm_device.h")]
+# kernels whose summaries are tagged with the hash of other sources than the MAP kernels'
+SOURCES_BY_KERNEL = {"image_hist": NOISE_SOURCES, "image_max": NOISE_SOURCES}
+
+
 def traffic(fetch_csv, write_csv, kernel, voxels, last=0):
     f, w = _counter(fetch_csv), _counter(write_csv)
     copy = [k for k in f if "copyBuffer" in k]
@@ -64,7 +70,7 @@ def traffic(fetch_csv, write_csv, kernel, voxels, last=0):
     fk, wk = statistics.mean(fv), statistics.mean(wv)
     b = (fk * fs + wk * ws) * 1024.0
     h = hashlib.sha256()
-    for p in KERNEL_SOURCES:
+    for p in SOURCES_BY_KERNEL.get(kernel, KERNEL_SOURCES):
         h.update(open(p, "rb").read())
     src = h.hexdigest()[:16]
     print(f"kernel: {kernel}")
