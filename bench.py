@@ -19,6 +19,7 @@ Other workloads (one JSON line each; not the headline step):
                   comparison
     --noise       the noise estimation of Sec. 2.7 on the whole-brain volume in air
     --serving     the continuous-batching queue on a mix of 64 ML and MAP requests
+    --autotune    mpm_autotune's CG sweep times per workgroup count on the serving sizes
     --counters    a short workload for rocprofv3 counter runs (with --projected or
                   --e1: theirs)
 """
@@ -38,7 +39,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2102_01604_amd", "csrc", f)
-                  for f in ("k_map.hip", "mpm_map.h", "mpm_device.h", "mpm_kernels.h")]
+                  for f in ("k_map.hip", "mpm_map.h", "mpm_device.h", "mpm_kernels.h", "mpm_tune.hip")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_map_brain.txt")
 VALU_SOURCES = [os.path.join(ROOT, "paper_2102_01604_amd", "csrc", f)
                 for f in ("k_voxel.hip", "mpm_voxelwise.h", "mpm_device.h")]
@@ -133,6 +134,8 @@ def main():
     ap.add_argument("--noise", action="store_true",
                     help="the noise estimation of Sec. 2.7 (histogram + Rician mixture per image) on the "
                          "whole-brain volume placed in air")
+    ap.add_argument("--autotune", action="store_true",
+                    help="mpm_autotune on the four serving volume sizes: the CG sweep A time per workgroup count")
     ap.add_argument("--e1-voxels", type=int, default=1 << 20)
     ap.add_argument("--e1-iters", type=int, default=10000)
     ap.add_argument("--requests", type=int, default=64)
@@ -175,6 +178,15 @@ def main():
         return
     if args.noise:
         noise_estimation(args, torch, _lib, synth, dev)
+        return
+    if args.autotune:
+        out = {"metric": "CG sweep A time per workgroup count (mpm_autotune)", "sizes": {}}
+        for dims in SERVE_SIZES:
+            r = _lib.mpm_autotune(dims, reps=10)
+            out["sizes"]["x".join(str(v) for v in dims)] = r
+            log(f"autotune {dims}: chose {r['workgroups'][r['chosen']]} workgroups "
+                f"({r['planes_per_run'][r['chosen']]} planes each), {r['ms'][r['chosen']] * 1e3:.1f} us")
+        print(json.dumps(out), flush=True)
         return
     dims = tuple(int(v) for v in args.dims.split(","))
     t0 = time.time()

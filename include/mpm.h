@@ -375,6 +375,33 @@ mpm_status mpm_server_step(mpm_server *server, int32_t *pending);
 mpm_status mpm_server_poll(mpm_server *server, uint64_t ticket, int32_t *done, mpm_report *report);
 mpm_status mpm_server_destroy(mpm_server *server);
 
+/*
+ * mpm_autotune -- picks the workgroup count of the MAP fit's dominant kernel
+ * (the CG sweep that walks z-runs of 64 x 16 tiles) for one grid size by
+ * timing it; for the callers that fit many volumes of one size.  Each
+ * candidate (targets of 512 ... 16384 workgroups, i.e. z-runs of different
+ * lengths; targets that give the same launch are timed once) runs `reps`
+ * full sweeps on zeroed scratch buffers of that size (about 110 B per voxel,
+ * freed on return); the fastest is then used by every later MAP fit of exactly
+ * that grid in this process, the server's included; other sizes keep the
+ * built-in choice.  Changing the launch shape changes the order of the FP64
+ * partial sums, so a grid's results differ at rounding level from those
+ * before it was tuned.  Blocks until done.  result (host, may be NULL): the
+ * candidates, their mean sweep times and the choice.  mpm_autotune_clear
+ * forgets every choice.
+ */
+typedef struct {
+    int32_t n_candidates;
+    int32_t chosen;            /* index of the fastest candidate               */
+    int32_t target[8];         /* workgroup target                             */
+    int32_t workgroups[8];     /* workgroups launched                          */
+    int32_t planes_per_run[8]; /* z-planes each workgroup walks                */
+    double ms[8];              /* mean time of one sweep                       */
+} mpm_tune_result;
+
+mpm_status mpm_autotune(const mpm_grid *grid, int32_t reps, mpm_tune_result *result, void *stream);
+void mpm_autotune_clear(void);
+
 /* Library version string. */
 const char *mpm_version(void);
 

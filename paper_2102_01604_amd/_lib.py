@@ -80,6 +80,11 @@ class mpm_rice_fit(C.Structure):
                 ("nll", C.c_double)]
 
 
+class mpm_tune_result(C.Structure):
+    _fields_ = [("n_candidates", C.c_int32), ("chosen", C.c_int32), ("target", C.c_int32 * 8),
+                ("workgroups", C.c_int32 * 8), ("planes_per_run", C.c_int32 * 8), ("ms", C.c_double * 8)]
+
+
 class MpmError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"{STATUS.get(status, status)}: {msg}")
@@ -111,6 +116,8 @@ SIGNATURES = {
                                      C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double),
                                      C.POINTER(C.c_double), C.POINTER(mpm_rice_fit), C.POINTER(C.c_uint32),
                                      C.c_void_p]),
+    "mpm_autotune": (C.c_int, [_G, C.c_int32, C.POINTER(mpm_tune_result), C.c_void_p]),
+    "mpm_autotune_clear": (None, []),
     "mpm_last_error": (C.c_char_p, []),
     "mpm_version": (C.c_char_p, []),
     "mpm_profile_enable": (None, [C.c_int32]),
@@ -361,6 +368,21 @@ def mpm_estimate_noise(protocol: dict, dims, echoes, b1=None, nbins: int = 1024,
     if want_hist:
         out["hist"] = list(hist)
     return out
+
+
+def mpm_autotune(dims, reps: int = 5, stream=None) -> dict:
+    """Time the MAP fit's CG sweep A for each workgroup-count candidate on a
+    grid of `dims` and keep the fastest for that size (this process)."""
+    lib = load()
+    r = mpm_tune_result()
+    _check(lib.mpm_autotune(C.byref(make_grid(dims)), int(reps), C.byref(r), _stream(stream)))
+    n = r.n_candidates
+    return {"chosen": r.chosen, "target": list(r.target[:n]), "workgroups": list(r.workgroups[:n]),
+            "planes_per_run": list(r.planes_per_run[:n]), "ms": list(r.ms[:n])}
+
+
+def mpm_autotune_clear():
+    load().mpm_autotune_clear()
 
 
 def mpm_footprint_bytes(protocol: dict, dims, dtype: int, mode: int) -> int:

@@ -14,8 +14,8 @@ LIB = os.path.join(HERE, "libmpm.so")
 PROBE = os.path.join(HERE, "hbm_probe")
 VALU_PROBE = os.path.join(HERE, "valu_probe")
 OBJ_DIR = os.path.join(HERE, "_build")
-SOURCES = ["mpm_api.hip", "mpm_fit.hip", "mpm_map.hip", "mpm_serve.hip", "mpm_noise.hip", "k_voxel.hip",
-           "k_map.hip", "k_proj.hip", "k_noise.hip"]
+SOURCES = ["mpm_api.hip", "mpm_fit.hip", "mpm_map.hip", "mpm_serve.hip", "mpm_noise.hip", "mpm_tune.hip",
+           "k_voxel.hip", "k_map.hip", "k_proj.hip", "k_noise.hip"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # keep packed-FP32 instructions out of the generated code

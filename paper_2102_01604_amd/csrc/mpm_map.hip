@@ -6,6 +6,7 @@
 
 #include "mpm_api_internal.h"
 #include "mpm_proj.h"
+#include "mpm_tune.h"
 
 namespace mpm {
 
@@ -44,7 +45,7 @@ static mpm_status alloc_map(const FitArgs &a, Workspace &ws, MapArgs &m, int tra
     m.bm = a.opt->b1_receive;
     m.Y = a.maps;
     m.gp = plane_grid(m.g);
-    m.gt = make_grid3(a.nx, a.ny, a.nz, TALL_Y, tall_workgroups());
+    m.gt = make_grid3(a.nx, a.ny, a.nz, TALL_Y, tall_target(a.nx, a.ny, a.nz));
     m.gv = plane_grid(make_grid3(a.nx, a.ny, a.nz, cg_b_rows()));
     const int nblk = std::max(std::max(grid_blocks(m.g), grid_blocks(m.gp)), std::max(grid_blocks(m.gt), grid_blocks(m.gv)));
     float *big = nullptr;

@@ -29,7 +29,8 @@ import statistics
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-KERNEL_SOURCES = [os.path.join(HERE, "csrc", f) for f in ("k_map.hip", "mpm_map.h", "mpm_device.h", "mpm_kernels.h")]
+KERNEL_SOURCES = [os.path.join(HERE, "csrc", f)
+                  for f in ("k_map.hip", "mpm_map.h", "mpm_device.h", "mpm_kernels.h", "mpm_tune.hip")]
 
 
 def _short(name):

@@ -42,7 +42,8 @@ def test_struct_layouts_match_header(tmp_path):
     structs = {"mpm_protocol": _lib.mpm_protocol, "mpm_grid": _lib.mpm_grid, "mpm_options": _lib.mpm_options,
                "mpm_report": _lib.mpm_report, "mpm_kernel_stat": _lib.mpm_kernel_stat,
                "mpm_request": _lib.mpm_request, "mpm_space": _lib.mpm_space,
-               "mpm_voxel_protocols": _lib.mpm_voxel_protocols, "mpm_rice_fit": _lib.mpm_rice_fit}
+               "mpm_voxel_protocols": _lib.mpm_voxel_protocols, "mpm_rice_fit": _lib.mpm_rice_fit,
+               "mpm_tune_result": _lib.mpm_tune_result}
     rename = {"lam": "lambda"}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "mpm.h"', "int main(void){"]
     for name, cls in structs.items():
@@ -212,6 +213,12 @@ def test_noise_estimation_argument_validation(lib):
                              (dict(p=dict(proto, mt=[0, 0, 0])), 2, "MT")):
         st = run(**kw)
         assert st == status and what in lib.mpm_last_error().decode(), (kw, st, lib.mpm_last_error())
+
+
+def test_autotune_argument_validation(lib):
+    for dims, reps, what in (((0, 8, 8), 5, "axis"), ((1, 1, 1), 5, "2 voxels"), ((8, 8, 8), 0, "reps")):
+        st = lib.mpm_autotune(C.byref(_lib.make_grid(dims)), reps, None, None)
+        assert st == 1 and what in lib.mpm_last_error().decode(), (dims, reps, lib.mpm_last_error())
 
 
 def test_null_pointers_rejected(lib):
