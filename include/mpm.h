@@ -331,8 +331,9 @@ const char *mpm_last_error(void);
  * stays within `hbm_budget`.  A MAP fit of 2^21 voxels or more fills the
  * device by itself for a long time, so at most one such fit runs at a time (in
  * submission order); ML fits and smaller MAP fits may be admitted ahead of a
- * waiting large one, but never ahead of a fit that waits for memory.  Each step then enqueues the next piece of work of every
- * admitted fit (the whole ML fit, or one Newton-like step of a MAP fit) on
+ * waiting large one, but never ahead of a fit that waits for memory.  Each
+ * step then enqueues the next piece of work of every admitted fit (the whole
+ * ML fit, or one Newton-like step of a MAP fit) on
  * its stream, so fits admitted at different times run concurrently on the
  * device and new arrivals join while others are in flight.  Each fit runs
  * the same kernels with the same launch shapes as mpm_fit(), so its result is

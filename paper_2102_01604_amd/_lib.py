@@ -250,14 +250,14 @@ def mpm_fit(protocol: dict, dims, echoes, b1, options: dict, maps, stream=None):
 def mpm_uncertainty(protocol: dict, dims, echoes, b1, options: dict, maps, var, moments=None, stream=None):
     lib = load()
     _check(lib.mpm_uncertainty(C.byref(make_protocol(protocol)), C.byref(make_grid(dims)), _dtype_code(echoes),
-                               _ptr(echoes), _f32(b1, "b1"), C.byref(make_options(options)), _f32(maps, "maps"), _f32(var, "var"),
-                               _f32(moments, "moments"), _stream(stream)))
+                               _ptr(echoes), _f32(b1, "b1"), C.byref(make_options(options)), _f32(maps, "maps"),
+                               _f32(var, "var"), _f32(moments, "moments"), _stream(stream)))
 
 
 def mpm_simulate(protocol: dict, dims, maps, b1, noise, out, stream=None):
     lib = load()
-    _check(lib.mpm_simulate(C.byref(make_protocol(protocol)), C.byref(make_grid(dims)), _f32(maps, "maps"), _f32(b1, "b1"),
-                            _f32(noise, "noise"), _dtype_code(out), _ptr(out), _stream(stream)))
+    _check(lib.mpm_simulate(C.byref(make_protocol(protocol)), C.byref(make_grid(dims)), _f32(maps, "maps"),
+                            _f32(b1, "b1"), _f32(noise, "noise"), _dtype_code(out), _ptr(out), _stream(stream)))
 
 
 def make_spaces(spaces):
@@ -292,15 +292,15 @@ def mpm_uncertainty_projected(protocol: dict, dims, spaces, echoes, b1, options:
     lib = load()
     _check(lib.mpm_uncertainty_projected(C.byref(make_protocol(protocol)), C.byref(make_grid(dims)),
                                          make_spaces(spaces), _dtype_code(echoes), _ptr(echoes), _f32(b1, "b1"),
-                                         C.byref(make_options(options)), _f32(maps, "maps"), _f32(var, "var"), _f32(moments, "moments"),
-                                         _stream(stream)))
+                                         C.byref(make_options(options)), _f32(maps, "maps"), _f32(var, "var"),
+                                         _f32(moments, "moments"), _stream(stream)))
 
 
 def mpm_simulate_projected(protocol: dict, dims, spaces, maps, b1, noise, out, stream=None):
     lib = load()
-    _check(lib.mpm_simulate_projected(C.byref(make_protocol(protocol)), C.byref(make_grid(dims)), make_spaces(spaces),
-                                      _f32(maps, "maps"), _f32(b1, "b1"), _f32(noise, "noise"), _dtype_code(out), _ptr(out),
-                                      _stream(stream)))
+    _check(lib.mpm_simulate_projected(C.byref(make_protocol(protocol)), C.byref(make_grid(dims)),
+                                      make_spaces(spaces), _f32(maps, "maps"), _f32(b1, "b1"), _f32(noise, "noise"),
+                                      _dtype_code(out), _ptr(out), _stream(stream)))
 
 
 def make_voxel_protocols(shape: dict, tr=None, flip=None, te=None) -> mpm_voxel_protocols:
