@@ -10,6 +10,15 @@
  * (maximum likelihood, "SPGR-ML") or with the joint-total-variation prior
  * solved by IRLS + preconditioned conjugate gradient ("SPGR+JTV").
  *
+ * Entry points: mpm_fit, mpm_uncertainty (Laplace variance), mpm_simulate
+ * (the forward model); their projected forms for contrasts acquired on their
+ * own grids (mpm_*_projected); the fit and forward model with a protocol per
+ * voxel (mpm_fit_voxelwise, mpm_simulate_voxelwise; also in the rate and time
+ * representations); the noise level and initial maps from the echoes
+ * (mpm_estimate_noise); a serving queue with continuous batching
+ * (mpm_server_*); mpm_footprint_bytes, mpm_autotune, kernel timing
+ * (mpm_profile_*), mpm_last_error and mpm_version.
+ *
  * Conventions shared by every entry point
  *   - Voxel index n = x + nx*(y + ny*z) (x fastest); N = nx*ny*nz.
  *   - Images are numbered contrast-major: all echoes of contrast 0, then of
@@ -19,8 +28,9 @@
  *     (log A, log R1, log R2*, logit MTsat); b1: device float [N] or NULL
  *     (NULL means a transmit efficiency of 1 everywhere).
  *   - Device pointers belong to the caller and must stay valid until the call
- *     returns.  The library allocates its own workspace on the given stream
- *     and frees it before returning.  Calls block until their device work is
+ *     returns (the server's requests: until polled done).  The library
+ *     allocates its own workspace on the given stream and frees it before
+ *     returning.  Calls block until their device work is
  *     done.  `stream` is a hipStream_t (NULL: the default stream).
  *   - All arguments are validated on the host before any device work.  On an
  *     error nothing is written and mpm_last_error() describes the problem.
