@@ -143,6 +143,8 @@ def main():
     ap.add_argument("--schedule-seeds", default="4000",
                     help="serving: comma-separated seeds of the arrival schedules (request mix and gaps)")
     ap.add_argument("--budget-gib", type=float, default=16.0, help="serving: HBM budget of the server (GiB)")
+    ap.add_argument("--serve-classes", default="0,1,2,3",
+                    help="serving: the size classes requests are drawn from (indices into the four sizes)")
     ap.add_argument("--counters", action="store_true",
                     help="for hardware-counter runs: two outer loops of one Newton step each of the MAP fit "
                          "(2 x 1 x 32; the second loop has JTV weights, so its 32 CG iterations all run, as in "
@@ -693,8 +695,11 @@ def serving(args, torch, _lib, synth, dev):
     are resident in HBM before the clock starts."""
     seeds = [int(v) for v in args.schedule_seeds.split(",")]
     n = args.requests
+    classes = np.array([int(v) for v in args.serve_classes.split(",")])
     vols = {}
     for k, dims in enumerate(SERVE_SIZES):
+        if k not in classes:
+            continue
         c = synth.make_case("map_brain", dims=dims, seed=4100 + k)
         vols[k] = {"case": c, "truth": torch.from_numpy(c["truth"].astype(np.float32)).to(dev),
                    "b1": torch.from_numpy(c["b1"].astype(np.float32)).to(dev)}
@@ -703,7 +708,7 @@ def serving(args, torch, _lib, synth, dev):
 
     def make_requests(seed):
         rng = np.random.default_rng(seed)
-        cls = rng.integers(0, len(SERVE_SIZES), n)
+        cls = classes[rng.integers(0, len(classes), n)]
         is_map = rng.random(n) < 0.5
         gaps = rng.exponential(1.0 / args.rate, n)
         arrive = np.cumsum(gaps) - gaps[0]
@@ -805,7 +810,8 @@ def serving(args, torch, _lib, synth, dev):
            "value": summary["poisson"]["batched"]["p99_s"],
            "unit": "s (p99 latency, batched; median over schedules)", "n_gpus": 1, "higher_is_better": False,
            "data": "synthetic",
-           "config": {"workload": f"{n} fit requests, sizes uniform over {SERVE_SIZES}, 22 echoes, ML (20 GN) or "
+           "config": {"workload": f"{n} fit requests, sizes uniform over {[SERVE_SIZES[k] for k in classes]}, "
+                                  f"22 echoes, ML (20 GN) or "
                                   f"JTV-MAP (10x8x32) with p=0.5, Poisson arrivals {args.rate}/s; burst = all at t=0",
                       "max_active": 4, "hbm_budget_bytes": budget, "schedule_seeds": seeds,
                       "n_map": n_map},
