@@ -118,11 +118,12 @@ int    orc_pcg(const int64_t dims[3], const double *P, const double *w, const do
 /* ---- full fit and uncertainty ---- */
 int  orc_default_init(const orc_protocol *p, int64_t n, const double *x, const double *b1,
                       double y0[4]);
-/* Parity unpinned as a whole for mode ORC_MAP: the maps after a full IRLS x
- * Newton x CG schedule have no closed form and the paper prints no worked
- * example; every step of it is pinned separately (likelihood block, JTV
- * weights and L, PCG, acceptance), MAP with lambda = 0 equals ML, and the
- * objective is monotone.  Mode ORC_ML is pinned (exact recovery). */
+/* Mode ORC_MAP: the maps after a finite IRLS x Newton x CG schedule have no
+ * closed form and the paper prints no worked example; every step is pinned
+ * separately (likelihood block, JTV weights and L, PCG, acceptance), MAP with
+ * lambda = 0 equals ML, the objective is monotone, and a long schedule ends
+ * at the minimiser of NLL + smoothed JTV found by an unrelated optimiser
+ * (pinned through its end point).  Mode ORC_ML is pinned (exact recovery). */
 int  orc_fit(const orc_protocol *p, const int64_t dims[3], const double *x, const double *b1,
              const orc_options *opt, double *maps, orc_report *rep, double *trace,
              int32_t trace_len);
@@ -144,8 +145,9 @@ int orc_default_init_projected(const orc_protocol *p, const int64_t dims[3], con
 int orc_fit_voxelwise(const orc_protocol *shape, int64_t N, const double *tr, const double *flip, const double *te,
                       const double *x, const orc_options *opt, double rise_rel, double *maps, int32_t *increases,
                       double *nll, orc_report *rep);
-/* Projected fit (R-proj); as orc_fit, parity unpinned as a whole for MAP:
- * identity spaces equal orc_fit, and pull / push / pushed blocks are pinned. */
+/* Projected fit (R-proj); as orc_fit, pinned for MAP through its end point
+ * (the minimiser of the projected NLL + smoothed JTV): identity spaces equal
+ * orc_fit, and pull / push / pushed blocks are pinned. */
 int orc_fit_projected(const orc_protocol *p, const int64_t dims[3], const orc_space *spaces, const double *x,
                       const double *b1, const orc_options *opt, double *maps, orc_report *rep, double *trace,
                       int32_t trace_len);
