@@ -153,7 +153,9 @@ def test_map_whole_brain_launch_configuration(torch_cuda, orc):
     at this size with inputs of its own: the first objective value, at the
     oracle's constant initialisation, equals the oracle's NLL there; the
     objective does not rise within an outer loop; the Laplace variance at the
-    true maps equals the oracle's at every voxel."""
+    true maps equals the oracle's at every voxel; the benchmark's ML leg (its
+    default initialisation from the whole volume) starts from the oracle's
+    initial maps and equals the oracle on 2048 sampled voxels."""
     torch = torch_cuda
     c, x = _inputs(orc, "map_brain", (192, 240, 256))
     del c["eps"]
@@ -187,6 +189,27 @@ def test_map_whole_brain_launch_configuration(torch_cuda, orc):
     rv = np.abs(v[:, ok] - var_o[:, ok]) / var_o[:, ok]
     print("whole brain: variance at the truth, rel err max", rv.max(axis=1))
     assert rv.max() <= 2e-3
+    del var
+    # the benchmark's ML leg with its own options (default initialisation from
+    # the whole volume): the initial maps equal the oracle's, and the fit
+    # equals the oracle's on 2048 sampled voxels fitted one by one from them
+    ml = {"mode": "ml", "n_gn": 20, "init": "default"}
+    mm = torch.zeros((4, N), dtype=torch.float32, device="cuda")
+    _lib.mpm_fit(c["proto"], c["dims"], X, B1, dict(ml, n_gn=0), mm)
+    torch.cuda.synchronize()
+    init = mm[:, 0].cpu().numpy().astype(np.float64)
+    print("whole brain: default init gpu", init, "oracle", y0)
+    assert np.allclose(init, y0, rtol=1e-5, atol=1e-6)
+    _lib.mpm_fit(c["proto"], c["dims"], X, B1, ml, mm)
+    idx = np.sort(np.random.default_rng(106).choice(N, 2048, replace=False))
+    ym = mm[:, torch.from_numpy(idx).cuda()].cpu().numpy().astype(np.float64)
+    del mm
+    yo, _, _ = orc.fit(c["proto"], (len(idx), 1, 1), x[:, idx].astype(np.float64), c["b1"][idx],
+                       {"mode": "ml", "n_gn": 20, "init": "const", "init_const": [float(v) for v in init]})
+    good = well_posed(yo, c["truth"][:, idx])
+    rel, _, _ = map_errors(ym, yo, good)
+    print("whole brain ML on sampled voxels: well-posed", good.mean(), "rel", rel)
+    assert good.mean() > 0.8 and (rel <= TOL).all()
 
 
 @pytest.mark.parametrize("which,seed,sched", [("tol_gn", 81, (3, 8, 16)), ("tol_outer", 82, (8, 2, 12))])
