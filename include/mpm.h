@@ -120,6 +120,16 @@ typedef struct {
      * projected and per-voxel-protocol fits reject it (MPM_ERR_UNSUPPORTED). */
     const float *b1_receive;
     int32_t basis;  /* mpm_basis; other than MPM_BASIS_LOG: mpm_fit_voxelwise only */
+    /* MAP: index of the first outer loop to run, for resuming a fit (checkpoint /
+     * resume).  Loops start_outer .. n_outer-1 run; a loop t >= 1 re-weights from
+     * the current maps first, so a fit stopped after t loops (its maps saved) and
+     * resumed with init_kind = MPM_INIT_FROM_MAPS, start_outer = t and the same
+     * other options reproduces the uninterrupted fit (the IRLS state between loops
+     * is the maps and the loop index, Sec. 2.5-2.7).  0 <= start_outer < n_outer
+     * (0 when n_outer = 0); 0 for ML; tol_outer must be 0 when start_outer > 0
+     * (its gains are measured against the end of loop 0).  Trace slots of the
+     * loops before start_outer stay NaN; report counts cover the loops run. */
+    int32_t start_outer;
 } mpm_options;
 
 typedef struct {

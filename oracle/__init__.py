@@ -63,7 +63,7 @@ class Options(C.Structure):
                 ("init_kind", C.c_int32), ("basis", C.c_int32), ("lam", C.c_double * 4),
                 ("jtv_eps", C.c_double), ("cg_stop", C.c_double),
                 ("init_const", C.c_double * 4), ("tol_gn", C.c_double), ("tol_outer", C.c_double),
-                ("b1_receive", C.c_void_p)]
+                ("b1_receive", C.c_void_p), ("start_outer", C.c_int32)]
 
 
 class Report(C.Structure):
@@ -186,6 +186,7 @@ def make_options(opts: dict) -> Options:
     o.tol_gn = float(opts.get("tol_gn", 0.0))
     o.tol_outer = float(opts.get("tol_outer", 0.0))
     o.basis = BASES[opts.get("basis", "log")]
+    o.start_outer = int(opts.get("start_outer", 0))
     bm = opts.get("b1_receive")
     if bm is not None:  # the caller keeps the array alive (fit and uncertainty hold it)
         o.b1_receive = bm.ctypes.data

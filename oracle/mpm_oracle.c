@@ -880,8 +880,9 @@ static int init_from_means(const orc_protocol *p, const double *m, double b1m, d
  * Hessian of eq. precond); every step is taken, as the paper's method uses no
  * line search.
  *
- * MAP (SPGR+JTV, Sec. 2.5-2.7): IRLS.  For each outer loop t the weights are
- * refreshed (t >= 1; R-w0), then n_gn Newton-like steps solve
+ * MAP (SPGR+JTV, Sec. 2.5-2.7): IRLS.  For each outer loop t (from
+ * start_outer, for resuming) the weights are refreshed (t >= 1; R-w0), then
+ * n_gn Newton-like steps solve
  * (P~ + L) delta = g + L y by PCG (Sec. 2.6) and take y - 2^-h delta
  * (R-accept).
  *
@@ -964,7 +965,7 @@ static int fit_impl(const lik_ctx *L, const orc_options *opt, double *maps, orc_
         double F_loop0 = 0.0, obj_first = 0.0, obj_prev = 0.0;
         int n_obj = 0;
 
-        for (int t = 0; t < opt->n_outer; t++) {
+        for (int t = opt->start_outer > 0 ? opt->start_outer : 0; t < opt->n_outer; t++) {
             if (t >= 1 && lam_sum > 0.0) orc_jtv_weights(dims, maps, opt->lambda, eps, w, d);
             for (int j = 0; j < opt->n_gn; j++) {
                 double tot = lik_all(L, opt->loading, maps, nll, g, P);

@@ -73,6 +73,11 @@ typedef struct {
                                this (0: fixed count; reading R-stop)                 */
     const double *b1_receive; /* [N] net receive field b-_n multiplying every image of
                                voxel n (Sec. 2.4), or NULL; orc_fit and orc_uncertainty */
+    int32_t start_outer;    /* MAP: index of the first outer loop run (0 <= it <=
+                               n_outer); loops start_outer .. n_outer-1 run, the first
+                               of them re-weighting from the initial maps when >= 1, so
+                               a fit stopped after t loops resumes from its maps with
+                               start_outer = t (the IRLS state is the maps and t)   */
 } orc_options;
 
 typedef struct {

@@ -42,7 +42,8 @@ class mpm_options(C.Structure):
                 ("max_halvings", C.c_int32), ("loading", C.c_int32), ("init_kind", C.c_int32),
                 ("flags", C.c_int32), ("lam", C.c_double * 4), ("jtv_eps", C.c_double),
                 ("cg_stop", C.c_double), ("init_const", C.c_double * 4), ("tol_gn", C.c_double),
-                ("tol_outer", C.c_double), ("b1_receive", C.c_void_p), ("basis", C.c_int32)]
+                ("tol_outer", C.c_double), ("b1_receive", C.c_void_p), ("basis", C.c_int32),
+                ("start_outer", C.c_int32)]
 
 
 class mpm_report(C.Structure):
@@ -198,6 +199,7 @@ def make_options(opts: dict) -> mpm_options:
     bm = opts.get("b1_receive")
     o.b1_receive = None if bm is None else _f32(bm, "b1_receive").value
     o.basis = MPM_BASES[opts.get("basis", "log")]
+    o.start_outer = int(opts.get("start_outer", 0))
     return o
 
 

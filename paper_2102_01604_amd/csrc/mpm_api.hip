@@ -339,6 +339,14 @@ mpm_status check_fit_args(const mpm_protocol *protocol, const mpm_grid *grid, in
     if (!has_mt(protocol))
         return fail(MPM_ERR_UNSUPPORTED, "the four-parameter model needs at least one MT contrast");
     if (opt->mode == MPM_MAP_JTV && *N < 2) return fail(MPM_ERR_UNSUPPORTED, "MAP needs at least 2 voxels");
+    if (opt->mode == MPM_ML && opt->start_outer != 0)
+        return fail(MPM_ERR_INVALID_ARG, "start_outer is a MAP option (0 for ML)");
+    if (opt->mode == MPM_MAP_JTV &&
+        (opt->start_outer < 0 || (opt->n_outer > 0 ? opt->start_outer >= opt->n_outer : opt->start_outer != 0)))
+        return fail(MPM_ERR_INVALID_ARG, "start_outer must be in [0, n_outer) (0 when n_outer = 0)");
+    if (opt->start_outer > 0 && opt->tol_outer > 0.0)
+        return fail(MPM_ERR_UNSUPPORTED, "tol_outer measures gains from the end of outer loop 0: "
+                                         "it cannot be used with start_outer > 0");
     return MPM_OK;
 }
 

@@ -201,6 +201,7 @@ extern "C" mpm_status mpm_fit_voxelwise(const mpm_voxel_protocols *vp, int64_t n
     if (opt->loading != MPM_LOAD_PROPOSED && opt->loading != MPM_LOAD_GN && opt->loading != MPM_LOAD_PROPOSED_PLUS)
         return fail(MPM_ERR_INVALID_ARG, "unknown loading %d", opt->loading);
     if (opt->flags != 0) return fail(MPM_ERR_INVALID_ARG, "flags must be 0");
+    if (opt->start_outer != 0) return fail(MPM_ERR_INVALID_ARG, "start_outer is a MAP option (0 for ML)");
     if (opt->b1_receive) return fail(MPM_ERR_UNSUPPORTED, "b1_receive is not supported by the per-voxel-protocol fit");
     if (opt->init_kind == MPM_INIT_DEFAULT)
         return fail(MPM_ERR_UNSUPPORTED, "the default initialisation needs one protocol for all voxels");

@@ -154,9 +154,9 @@ static mpm_status alloc_proj(const FitArgs &a, Workspace &ws, ProjState &ps, Hes
 // ---------------------------------------------------------------------------
 // MAP fit as a job: piece 0 initialises (maps, control block, w = 0); then
 // one piece per Newton-like step (preceded by the weight refresh at the start
-// of each outer loop after the first); the last piece refreshes the weights
-// from the final maps, computes the final statistics and copies the control
-// block and the objective trace to pinned host memory.
+// of each outer loop t >= 1, loops running from start_outer); the last piece
+// refreshes the weights from the final maps, computes the final statistics
+// and copies the control block and the objective trace to pinned host memory.
 // ---------------------------------------------------------------------------
 struct MapJob : FitJob {
     FitArgs a;
@@ -164,7 +164,7 @@ struct MapJob : FitJob {
     Prof &prof;
     MapArgs m;
     int prior_on = 0, ntrial = 1, accept_off = 0;
-    int T = 0, J = 0, K = 0, S = 0, tl = 0;
+    int T = 0, J = 0, K = 0, S = 0, tl = 0, t0 = 0;  // t0: first outer loop run (resume)
     int nb_col = 0, nb_pl = 0, nb_cga = 0, nb_cgb = 0;
     int t = 0, j = 0;  // next Newton-like step
     bool started = false, finished = false;
@@ -198,6 +198,7 @@ struct MapJob : FitJob {
         K = o->n_cg;
         S = J + 2;
         tl = T * S;
+        t = t0 = o->start_outer;
         mpm_status st = alloc_map(a, ws, m, tl);
         if (st) return st;
         if (host.alloc(sizeof(MapCtl) + sizeof(double) * (size_t)(tl > 0 ? tl : 1)) != hipSuccess)
@@ -288,7 +289,9 @@ struct MapJob : FitJob {
         } else if (t < T && J > 0) {
             if (j == 0 && t >= 1) {
                 RUN("jtv_weights", N * 20.0, launch_weights(s, m, prior_on));
-                RUN("fin", 0.0, fin(FIN_W, (t - 1) * S + J + 1, nb_col));
+                // the end of the previous loop, if this call ran it (a resumed
+                // fit re-weights from its initial maps without ending a loop)
+                if (t > t0) RUN("fin", 0.0, fin(FIN_W, (t - 1) * S + J + 1, nb_col));
             }
             if (!proj) {
                 RUN("map_lik", N * (xb + bb + 16 + 4 + 40 + 16 + 16), launch_lik(s, m));
@@ -330,7 +333,7 @@ struct MapJob : FitJob {
             }
         } else {
             // outer loops without Newton steps only refresh the weights
-            for (int tt = (J > 0 ? T : 1); tt < T && e == hipSuccess; tt++) {
+            for (int tt = (J > 0 ? T : t0 + 1); tt < T && e == hipSuccess; tt++) {
                 RUN("jtv_weights", N * 20.0, launch_weights(s, m, prior_on));
                 RUN("fin", 0.0, fin(FIN_W, (tt - 1) * S + J + 1, nb_col));
             }

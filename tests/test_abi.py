@@ -83,6 +83,10 @@ def _fit_raw(lib, proto, dims, opts):
     (lambda p, d, o: o.update(lam=[-1.0, 0, 0, 0]), 1),
     (lambda p, d, o: o.update(flags=3), 1),
     (lambda p, d, o: o.update(basis="rate"), 2),
+    (lambda p, d, o: o.update(start_outer=1), 1),  # a MAP option
+    (lambda p, d, o: o.update(mode="map", n_outer=3, start_outer=3), 1),
+    (lambda p, d, o: o.update(mode="map", n_outer=3, start_outer=-1), 1),
+    (lambda p, d, o: o.update(mode="map", n_outer=3, start_outer=1, tol_outer=0.1), 2),
     (lambda p, d, o: (d.__setitem__(0, 1), d.__setitem__(1, 1), d.__setitem__(2, 1), o.update(mode="map")), 2),
 ])
 def test_host_validation(lib, mutate, status):
