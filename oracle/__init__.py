@@ -25,7 +25,9 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "mpm_oracle.c")
-_LIB_PATH = os.path.join(_HERE, "libmpm_oracle.so")
+# MPM_ORACLE_LIB selects another build of the same source (the sanitizer build
+# the tests make with build_sanitized)
+_LIB_PATH = os.environ.get("MPM_ORACLE_LIB") or os.path.join(_HERE, "libmpm_oracle.so")
 
 MAX_CONTRASTS = 8
 MAX_IMAGES = 64
@@ -44,6 +46,17 @@ def build(force: bool = True) -> str:
         subprocess.check_call(cmd, cwd=_HERE)
         os.replace(_LIB_PATH + ".tmp", _LIB_PATH)
     return _LIB_PATH
+
+
+def build_sanitized(path: str) -> str:
+    """Compile the oracle with AddressSanitizer and UndefinedBehaviorSanitizer
+    (every report fatal) to `path`; load it by setting MPM_ORACLE_LIB in a
+    process started with the ASan runtime preloaded."""
+    cmd = ["gcc", "-O1", "-g", "-std=c99", "-fopenmp", "-fPIC", "-shared", "-Wall",
+           "-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer",
+           "-o", path, _SRC, "-lm"]
+    subprocess.check_call(cmd, cwd=_HERE)
+    return path
 
 
 class Protocol(C.Structure):
