@@ -56,7 +56,8 @@ typedef enum {
     MPM_ERR_OUT_OF_MEMORY = 3, /* workspace allocation failed                   */
     MPM_ERR_DEVICE = 4,        /* a HIP call failed                             */
     MPM_ERR_BUSY = 5,          /* server: request not finished yet              */
-    MPM_ERR_NOT_FOUND = 6      /* server: unknown ticket                        */
+    MPM_ERR_NOT_FOUND = 6,     /* server: unknown ticket                        */
+    MPM_ERR_CANCELLED = 7      /* server: the request was cancelled             */
 } mpm_status;
 
 typedef enum { MPM_F32 = 0, MPM_F16 = 1, MPM_BF16 = 2 } mpm_dtype; /* echo storage only */
@@ -372,6 +373,12 @@ const char *mpm_last_error(void);
  * that fit's status), *done = 0 while queued or running; MPM_ERR_NOT_FOUND for
  * an unknown ticket.  A fit whose footprint exceeds the budget finishes with
  * MPM_ERR_OUT_OF_MEMORY.
+ * mpm_server_cancel: a queued request leaves the queue at once; a running one
+ * gets no further pieces and is released once its pieces in flight complete
+ * (at a later step).  Either then polls as done with MPM_ERR_CANCELLED, its
+ * maps holding whatever the completed pieces wrote (unspecified).  No effect
+ * on a finished request; MPM_ERR_NOT_FOUND for an unknown ticket.  Other
+ * requests are unaffected (each runs on its own stream and workspace).
  * mpm_server_destroy waits for running fits and frees the server.
  * Calls on one server are serialised by an internal lock.
  */
@@ -394,6 +401,7 @@ mpm_status mpm_server_create(size_t hbm_budget, int32_t max_active, int32_t flag
 mpm_status mpm_server_submit(mpm_server *server, const mpm_request *request, uint64_t *ticket);
 mpm_status mpm_server_step(mpm_server *server, int32_t *pending);
 mpm_status mpm_server_poll(mpm_server *server, uint64_t ticket, int32_t *done, mpm_report *report);
+mpm_status mpm_server_cancel(mpm_server *server, uint64_t ticket);
 mpm_status mpm_server_destroy(mpm_server *server);
 
 /*

@@ -23,7 +23,7 @@ MPM_INIT_DEFAULT, MPM_INIT_CONST, MPM_INIT_FROM_MAPS = 0, 1, 2
 MPM_LOAD_PROPOSED, MPM_LOAD_GN, MPM_LOAD_PROPOSED_PLUS = 0, 1, 2
 MPM_BASES = {"log": 0, "rate": 1, "time": 2}
 STATUS = {0: "MPM_OK", 1: "MPM_ERR_INVALID_ARG", 2: "MPM_ERR_UNSUPPORTED", 3: "MPM_ERR_OUT_OF_MEMORY",
-          4: "MPM_ERR_DEVICE", 5: "MPM_ERR_BUSY", 6: "MPM_ERR_NOT_FOUND"}
+          4: "MPM_ERR_DEVICE", 5: "MPM_ERR_BUSY", 6: "MPM_ERR_NOT_FOUND", 7: "MPM_ERR_CANCELLED"}
 
 
 class mpm_protocol(C.Structure):
@@ -128,6 +128,7 @@ SIGNATURES = {
     "mpm_server_submit": (C.c_int, [C.c_void_p, C.POINTER(mpm_request), C.POINTER(C.c_uint64)]),
     "mpm_server_step": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32)]),
     "mpm_server_poll": (C.c_int, [C.c_void_p, C.c_uint64, C.POINTER(C.c_int32), _R]),
+    "mpm_server_cancel": (C.c_int, [C.c_void_p, C.c_uint64]),
     "mpm_server_destroy": (C.c_int, [C.c_void_p]),
 }
 
@@ -457,6 +458,11 @@ class MpmServer:
             return None
         self._keep.pop(ticket, None)
         return {f[0]: getattr(rep, f[0]) for f in mpm_report._fields_}
+
+    def cancel(self, ticket: int):
+        """Cancel a queued or running request; poll then raises MPM_ERR_CANCELLED
+        (the buffers stay borrowed until it does)."""
+        _check(load().mpm_server_cancel(self._h, C.c_uint64(ticket)))
 
     def close(self):
         if self._h:

@@ -49,6 +49,7 @@ struct Entry {
     std::unique_ptr<FitJob> job;
     std::deque<hipEvent_t> inflight;
     bool all_enqueued = false;
+    bool cancel = false;  // no further pieces; released once those in flight complete
     mpm_status status = MPM_OK;
     std::string error;
     mpm_report report;
@@ -99,6 +100,14 @@ void advance(mpm_server *s, Entry &e)
     while (!e.inflight.empty() && hipEventQuery(e.inflight.front()) == hipSuccess) {
         (void)hipEventDestroy(e.inflight.front());
         e.inflight.pop_front();
+    }
+    if (e.cancel) {
+        if (!e.inflight.empty()) return;
+        release(s, e);
+        e.status = MPM_ERR_CANCELLED;
+        e.error = "cancelled while running";
+        e.state = DONE;
+        return;
     }
     if (e.all_enqueued) {
         if (!e.inflight.empty()) return;
@@ -281,6 +290,29 @@ mpm_status mpm_server_poll(mpm_server *s, uint64_t ticket, int32_t *done, mpm_re
     if (!*done) return MPM_OK;
     if (report) *report = e.report;
     if (e.status) return fail(e.status, "%s", e.error.c_str());
+    return MPM_OK;
+}
+
+mpm_status mpm_server_cancel(mpm_server *s, uint64_t ticket)
+{
+    clear_error();
+    if (!s) return fail(MPM_ERR_INVALID_ARG, "server is NULL");
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->entries.find(ticket);
+    if (it == s->entries.end()) return fail(MPM_ERR_NOT_FOUND, "unknown ticket %llu", (unsigned long long)ticket);
+    Entry &e = *it->second;
+    if (e.state == QUEUED) {
+        for (auto q = s->queue.begin(); q != s->queue.end(); ++q)
+            if (*q == ticket) {
+                s->queue.erase(q);
+                break;
+            }
+        e.status = MPM_ERR_CANCELLED;
+        e.error = "cancelled before it started";
+        e.state = DONE;
+    } else if (e.state == RUNNING) {
+        e.cancel = true;
+    }
     return MPM_OK;
 }
 

@@ -1,6 +1,7 @@
 """GPU tests of the serving loop (mpm_server_*): continuous batching gives
 every fit the same result as running it alone, admission respects the memory
-budget, and an over-budget request is rejected."""
+budget, an over-budget request is rejected, and a cancelled request (queued or
+running) leaves the others intact."""
 import time
 
 import numpy as np
@@ -118,3 +119,42 @@ def test_background_thread(torch_cuda, orc):
             assert time.time() - t0 < 120
             time.sleep(0.002)
     assert all(d["gn_done"] > 0 for d in done.values())
+
+
+def test_cancel_queued_and_running(torch_cuda, orc):
+    """mpm_server_cancel: a queued request finishes at once as cancelled, a
+    running MAP fit is released after its pieces in flight, and the request
+    behind them still equals its solo fit."""
+    torch = torch_cuda
+    reqs = [_requests(orc, torch)[i] for i in (0, 2, 5)]  # three MAP fits
+    r3 = reqs[2]
+    solo = torch.zeros((4, r3["N"]), dtype=torch.float32, device="cuda")
+    rep_solo, _ = _lib.mpm_fit(r3["case"]["proto"], r3["case"]["dims"], r3["X"], r3["b1"], r3["opts"], solo)
+    with _lib.MpmServer(hbm_budget=16 << 30, max_active=1) as srv:  # one stream: one fit runs at a time
+        outs = [torch.zeros((4, r["N"]), dtype=torch.float32, device="cuda") for r in reqs]
+        tickets = [srv.submit(r["case"]["proto"], r["case"]["dims"], r["X"], r["b1"], r["opts"], o)
+                   for r, o in zip(reqs, outs)]
+        srv.step()  # admits the first fit and enqueues its first piece; the others wait
+        srv.cancel(tickets[1])
+        with pytest.raises(_lib.MpmError) as ei:
+            srv.poll(tickets[1])
+        assert ei.value.status == 7
+        srv.cancel(tickets[0])
+        t0, cancelled = time.time(), False
+        while not cancelled:
+            srv.step()
+            try:
+                assert srv.poll(tickets[0]) is None, "a cancelled fit reported success"
+            except _lib.MpmError as e:
+                assert e.status == 7
+                cancelled = True
+            assert time.time() - t0 < 60.0
+        rep = _drive(srv, [tickets[2]])[tickets[2]]
+        srv.cancel(tickets[2])  # finished: no effect
+        assert srv.poll(tickets[2]) is not None
+        with pytest.raises(_lib.MpmError) as ei:
+            srv.cancel(10 ** 9)
+        assert ei.value.status == 6
+    torch.cuda.synchronize()
+    assert np.array_equal(outs[2].cpu().numpy(), solo.cpu().numpy())
+    assert rep["objective"] == rep_solo["objective"]
