@@ -46,9 +46,10 @@
  *              free nu converges only sublinearly along the flat nu-sigma ridge);
  *              a class's mean is its responsibility-weighted mean.
  *   R-basis  : in the rate and time representations (Sec. 3.1) the steps act
- *              on the values themselves and the signal formula is evaluated
- *              at whatever values they reach: no clamp to the physical domain
- *              (the paper states none).
+ *              on the values themselves; a step that would take A, R1 (T1) or
+ *              R2* (T2*) to <= 0, or MTsat out of (0, 1), moves that parameter
+ *              halfway to the boundary it would cross instead (the paper states
+ *              no domain handling; see step_in_domain).
  */
 #include "mpm_oracle.h"
 

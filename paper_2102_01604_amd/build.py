@@ -1,6 +1,4 @@
-"""Build libmpm.so (gfx950) in-tree with hipcc, and the hbm_probe and
-valu_probe programs (plain kernels that measure the GPU's achievable HBM
-bandwidth and VALU issue rate)."""
+"""Build libmpm.so (gfx950) in-tree with hipcc."""
 from __future__ import annotations
 
 import concurrent.futures
@@ -11,8 +9,6 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmpm.so")
-PROBE = os.path.join(HERE, "hbm_probe")
-VALU_PROBE = os.path.join(HERE, "valu_probe")
 OBJ_DIR = os.path.join(HERE, "_build")
 SOURCES = ["mpm_api.hip", "mpm_fit.hip", "mpm_map.hip", "mpm_serve.hip", "mpm_noise.hip", "mpm_tune.hip",
            "k_voxel.hip", "k_map.hip", "k_proj.hip", "k_noise.hip"]
@@ -26,7 +22,7 @@ FLAGS = [
 
 def build(verbose: bool = False) -> str:
     """Compile every source to an object (in parallel, one hipcc per file),
-    link libmpm.so, then build the two probe programs."""
+    then link libmpm.so."""
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     os.makedirs(OBJ_DIR, exist_ok=True)
     cflags = [f for f in FLAGS if f != "-shared"]
@@ -52,13 +48,6 @@ def build(verbose: bool = False) -> str:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd, cwd=CSRC)
     os.replace(LIB + ".tmp", LIB)
-    pflags = [f for f in FLAGS if f not in ("-fPIC", "-shared")]
-    for out, src in ((PROBE, "hbm_probe.hip"), (VALU_PROBE, "valu_probe.hip")):
-        cmd = [hipcc] + pflags + ["-o", out + ".tmp", os.path.join(CSRC, src)]
-        if verbose:
-            print(" ".join(cmd), flush=True)
-        subprocess.check_call(cmd, cwd=CSRC)
-        os.replace(out + ".tmp", out)
     return LIB
 
 

@@ -145,3 +145,67 @@ def test_map_uncertainty_below_ml(orc):
     v_ml = orc.uncertainty(c["proto"], c["dims"], x, c["b1"], {"mode": "ml"}, mp)
     assert (v_map <= v_ml * (1 + 1e-12)).all()
     assert (v_map < v_ml).mean() > 0.99
+
+
+def _explicit_G(dims):
+    """6N x N forward/backward differences, zero across the border (the
+    definition of the JTV operator, built independently of the oracle)."""
+    import scipy.sparse as sp
+    nx, ny, nz = dims
+    N = nx * ny * nz
+    rows, cols, vals = [], [], []
+    r = 0
+    for z in range(nz):
+        for y in range(ny):
+            for x in range(nx):
+                n = x + nx * (y + ny * z)
+                for dx, dy, dz in ((1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1)):
+                    xx, yy, zz = x + dx, y + dy, z + dz
+                    if 0 <= xx < nx and 0 <= yy < ny and 0 <= zz < nz:
+                        rows += [r, r]
+                        cols += [xx + nx * (yy + ny * zz), n]
+                        vals += [1.0, -1.0]
+                    r += 1
+    return sp.csr_matrix((vals, (rows, cols)), shape=(6 * N, N))
+
+
+@pytest.mark.parametrize("lam_scale", [1.0, 300.0])
+def test_map_laplace_variance_matches_dense_inverse(orc, lam_scale):
+    """MAP branch of the Laplace variance (Sec. 3.6): the diagonal of the dense
+    inverse of blockdiag(P~_n) + diag(G^T W G) (x) diag(lambda), assembled here
+    from an explicit difference matrix G, W = (q + eps^2)^(-1/2) computed from
+    G and the maps, and each voxel's loaded Hessian from its likelihood block.
+    The larger lambda makes the prior term dominate some blocks, so a wrong
+    factor on lambda_k d_n cannot pass."""
+    dims = (5, 4, 3)
+    c, x = _brain(dims=dims, seed=41)
+    N = int(np.prod(dims))
+    lam = np.asarray(c["lam"], dtype=np.float64) * lam_scale
+    eps = 1e-3 * math.sqrt(lam.sum())
+    opts = dict(c["opts"], lam=list(lam), jtv_eps=eps, n_outer=2, n_gn=3, n_cg=8)
+    maps, _, _ = orc.fit(c["proto"], dims, x, c["b1"], opts)
+    var = orc.uncertainty(c["proto"], dims, x, c["b1"], opts, maps)
+    G = _explicit_G(dims)
+    q = sum(lam[k] * (np.asarray(G @ maps[k]) ** 2).reshape(N, 6).sum(1) for k in range(4))
+    w = 1.0 / np.sqrt(q + eps ** 2)
+    import scipy.sparse as sp
+    dG = np.asarray((G.T @ sp.diags(np.repeat(w, 6)) @ G).diagonal()).ravel()
+    A = np.zeros((4 * N, 4 * N))
+    prior_share = 0.0
+    for n in range(N):
+        _, _, P = orc.lik_voxel(c["proto"], x[:, n], maps[:, n], c["b1"][n])
+        idx = np.arange(4) * N + n
+        A[np.ix_(idx, idx)] = P
+        for k in range(4):
+            A[k * N + n, k * N + n] += lam[k] * dG[n]
+            prior_share = max(prior_share, lam[k] * dG[n] / P[k, k])
+    ref = np.diag(np.linalg.inv(A)).reshape(4, N)
+    print("lambda x", lam_scale, "largest prior share of a diagonal entry", prior_share)
+    assert np.allclose(var, ref, rtol=1e-12, atol=0)
+    # without the prior term the variance is visibly different
+    A0 = A.copy()
+    for n in range(N):
+        for k in range(4):
+            A0[k * N + n, k * N + n] -= lam[k] * dG[n]
+    ref0 = np.diag(np.linalg.inv(A0)).reshape(4, N)
+    assert np.abs(ref0 / ref - 1).max() > (0.1 if lam_scale > 1 else 1e-4)

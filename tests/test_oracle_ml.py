@@ -136,6 +136,31 @@ def test_default_init_near_truth(orc):
     assert 1 / (1 + math.exp(-y0[3])) == pytest.approx(0.0125, rel=0.1)
 
 
+def test_default_init_scales_flips_by_mean_b1(orc):
+    """R-init applies the small-angle forms to the nominal flips times the mean
+    transmit field: noise-free data made with a constant field b1 = c gives
+    the same initial maps as the same data with every flip multiplied by c and
+    no field, and a field with the same mean but spatial variation gives that
+    init too; with the field the init lands near the truth, without it the
+    flip error biases R1 (the closed forms scale R1 with 1/alpha^2)."""
+    n = 64
+    truth = synth.encode(np.full(n, 750.0), np.full(n, 1.0), np.full(n, 25.0), np.full(n, 0.0125))
+    proto = synth.protocol()
+    proto["sigma"] = [1.0] * 22
+    cval = 1.15
+    b1 = np.full(n, cval)
+    x = orc.simulate(proto, truth, b1)
+    y_field = orc.default_init(proto, x, b1)
+    scaled = dict(proto, flip=[f * cval for f in proto["flip"]])
+    y_scaled = orc.default_init(scaled, x)
+    assert np.allclose(y_field, y_scaled, rtol=1e-12, atol=1e-12)
+    ramp = cval + 0.1 * np.linspace(-1.0, 1.0, n)  # mean cval
+    assert np.allclose(orc.default_init(proto, x, ramp), y_field, rtol=1e-12, atol=1e-12)
+    assert math.exp(y_field[1]) == pytest.approx(1.0, rel=0.05)
+    y_none = orc.default_init(proto, x)
+    assert abs(math.exp(y_none[1]) - 1.0) > 0.2
+
+
 def test_missing_echo_equals_removed_image(orc):
     """A non-finite echo is a missing observation: fitting with image 9 set to
     NaN equals fitting with image 9 removed from the protocol."""
