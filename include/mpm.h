@@ -405,6 +405,35 @@ mpm_status mpm_server_cancel(mpm_server *server, uint64_t ticket);
 mpm_status mpm_server_destroy(mpm_server *server);
 
 /*
+ * mpm_fit_noalloc --/*
+ * mpm_fit_noalloc -- mpm_fit for callers that cannot allocate memory: code
+ * under HIP graph capture, serving loops that must not allocate, harnesses
+ * that forbid it.  Same arguments, validation, results and blocking
+ * behaviour as mpm_fit (the same kernels in the same launch shapes, so the
+ * maps, report and trace are those of mpm_fit bit for bit); it calls no
+ * hipMalloc / hipFree / hipHostMalloc and no other allocating routine.  The
+ * caller still owns echoes, b1 and maps.
+ * Workspace: a fixed device array of MPM_NOALLOC_SCRATCH_BYTES (64 MiB)
+ * inside the library, one per device that runs it, held until the process
+ * ends.  That bounds the fit: a MAP fit needs about 124 bytes per voxel (up
+ * to about 530,000 voxels, e.g. a 64^3 or 80^3 volume); an ML fit needs
+ * 8 * (n_gn + 4) bytes per 256 voxels (plus 8 * (2I + 1) per 1024 voxels for
+ * the default initialisation).  A fit that does not fit is rejected with
+ * MPM_ERR_OUT_OF_MEMORY before any device work, and mpm_last_error() states
+ * the bytes it needs.
+ * Every call on a device shares that device's array, which keeps the last
+ * call's contents (each call initialises what it reads).  Calls that
+ * overlapped on one device would race on it: the library serialises them
+ * with a per-device lock held for the whole call, so concurrent host threads
+ * wait for each other.
+ */
+#define MPM_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+
+mpm_status mpm_fit_noalloc(const mpm_protocol *protocol, const mpm_grid *grid, mpm_dtype dtype,
+                           const void *echoes, const float *b1, const mpm_options *options, float *maps,
+                           mpm_report *report, double *trace, int32_t trace_len, void *stream);
+
+/*
  * mpm_autotune -- picks the workgroup count of the MAP fit's dominant kernel
  * (the CG sweep that walks z-runs of 64 x 16 tiles) for one grid size by
  * timing it; for the callers that fit many volumes of one size.  Each

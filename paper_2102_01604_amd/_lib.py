@@ -99,6 +99,8 @@ _P, _G, _O, _R = C.POINTER(mpm_protocol), C.POINTER(mpm_grid), C.POINTER(mpm_opt
 SIGNATURES = {
     "mpm_fit": (C.c_int, [_P, _G, C.c_int, C.c_void_p, C.c_void_p, _O, C.c_void_p, _R,
                           C.POINTER(C.c_double), C.c_int32, C.c_void_p]),
+    "mpm_fit_noalloc": (C.c_int, [_P, _G, C.c_int, C.c_void_p, C.c_void_p, _O, C.c_void_p, _R,
+                                  C.POINTER(C.c_double), C.c_int32, C.c_void_p]),
     "mpm_uncertainty": (C.c_int, [_P, _G, C.c_int, C.c_void_p, C.c_void_p, _O, C.c_void_p, C.c_void_p,
                                   C.c_void_p, C.c_void_p]),
     "mpm_simulate": (C.c_int, [_P, _G, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]),
@@ -246,6 +248,20 @@ def mpm_fit(protocol: dict, dims, echoes, b1, options: dict, maps, stream=None):
     _check(lib.mpm_fit(C.byref(make_protocol(protocol)), C.byref(make_grid(dims)), _dtype_code(echoes),
                        _ptr(echoes), _f32(b1, "b1"), C.byref(make_options(options)), _f32(maps, "maps"), C.byref(rep),
                        trace, tl, _stream(stream)))
+    report = {f[0]: getattr(rep, f[0]) for f in mpm_report._fields_}
+    return report, np.array(trace[:], dtype=np.float64)
+
+
+def mpm_fit_noalloc(protocol: dict, dims, echoes, b1, options: dict, maps, stream=None):
+    """mpm_fit with the library's fixed scratch as workspace (no allocation);
+    same arguments and results as mpm_fit."""
+    lib = load()
+    tl = trace_len(options)
+    trace = (C.c_double * tl)()
+    rep = mpm_report()
+    _check(lib.mpm_fit_noalloc(C.byref(make_protocol(protocol)), C.byref(make_grid(dims)), _dtype_code(echoes),
+                               _ptr(echoes), _f32(b1, "b1"), C.byref(make_options(options)), _f32(maps, "maps"),
+                               C.byref(rep), trace, tl, _stream(stream)))
     report = {f[0]: getattr(rep, f[0]) for f in mpm_report._fields_}
     return report, np.array(trace[:], dtype=np.float64)
 

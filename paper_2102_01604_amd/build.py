@@ -11,6 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmpm.so")
 OBJ_DIR = os.path.join(HERE, "_build")
 SOURCES = ["mpm_api.hip", "mpm_fit.hip", "mpm_map.hip", "mpm_serve.hip", "mpm_noise.hip", "mpm_tune.hip",
+           "mpm_noalloc.hip",
            "k_voxel.hip", "k_map.hip", "k_proj.hip", "k_noise.hip"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -354,6 +354,16 @@ mpm_status check_fit_args(const mpm_protocol *protocol, const mpm_grid *grid, in
 hipError_t Workspace::alloc(void **p, size_t bytes)
 {
     if (bytes == 0) bytes = 256;
+    if (arena) {
+        const size_t off = (used + 255) & ~(size_t)255;
+        if (off > cap || bytes > cap - off) {
+            need = off + bytes;
+            return hipErrorOutOfMemory;
+        }
+        *p = arena + off;
+        used = off + bytes;
+        return hipSuccess;
+    }
     hipError_t e = hipMallocAsync(p, bytes, stream);
     if (e == hipSuccess) bufs.push_back(*p);
     return e;
@@ -363,6 +373,26 @@ Workspace::~Workspace()
 {
     for (void *p : bufs) hipFreeAsync(p, stream);
     hipStreamSynchronize(stream);
+}
+
+mpm_status run_fit(const FitArgs &a, Workspace &ws, mpm_report *report, double *trace, int trace_len)
+{
+    mpm_status st;
+    mpm_report rep;
+    memset(&rep, 0, sizeof(rep));
+    Prof prof(a.stream);
+    std::unique_ptr<FitJob> job =
+        a.opt->mode == MPM_ML ? make_ml_job(a, ws, prof, &st) : make_map_job(a, ws, prof, &st);
+    if (st) return st;
+    bool more = true;
+    while (more)
+        if ((st = job->enqueue_next(&more))) return st;
+    hipError_t e = hipStreamSynchronize(a.stream);
+    prof.collect();
+    if (e != hipSuccess) return fail(MPM_ERR_DEVICE, "fit: %s", hipGetErrorString(e));
+    if ((st = job->collect(rep, trace, trace_len))) return st;
+    if (report) *report = rep;
+    return MPM_OK;
 }
 
 // Per-image means and the mean b1, reduced on the device in FP64.
@@ -506,24 +536,8 @@ mpm_status mpm_fit(const mpm_protocol *protocol, const mpm_grid *grid, mpm_dtype
 
     hipStream_t s = (hipStream_t)stream;
     FitArgs a{protocol, to_dev(protocol), dtype, echoes, b1, opt, maps, N, grid->nx, grid->ny, grid->nz, s};
-    mpm_report rep;
-    memset(&rep, 0, sizeof(rep));
-    {
-        Workspace ws(s);
-        Prof prof(s);
-        std::unique_ptr<FitJob> job =
-            opt->mode == MPM_ML ? make_ml_job(a, ws, prof, &st) : make_map_job(a, ws, prof, &st);
-        if (st) return st;
-        bool more = true;
-        while (more)
-            if ((st = job->enqueue_next(&more))) return st;
-        hipError_t e = hipStreamSynchronize(s);
-        prof.collect();
-        if (e != hipSuccess) return fail(MPM_ERR_DEVICE, "fit: %s", hipGetErrorString(e));
-        if ((st = job->collect(rep, trace, trace_len))) return st;
-    }
-    if (report) *report = rep;
-    return MPM_OK;
+    Workspace ws(s);
+    return run_fit(a, ws, report, trace, trace_len);
 }
 
 }  // extern "C"

@@ -43,11 +43,17 @@ struct Prof {
     void collect();
 };
 
-// Stream-ordered device allocations released (and synchronised) on scope exit.
+// Stream-ordered device allocations released (and synchronised) on scope
+// exit.  Given a fixed device region instead, alloc carves 256-byte aligned
+// pieces out of it and allocates nothing; a request beyond its end fails with
+// hipErrorOutOfMemory and records in `need` the bytes it would have taken.
 struct Workspace {
     hipStream_t stream;
     std::vector<void *> bufs;
+    char *arena = nullptr;
+    size_t cap = 0, used = 0, need = 0;
     explicit Workspace(hipStream_t s) : stream(s) {}
+    Workspace(hipStream_t s, void *region, size_t bytes) : stream(s), arena((char *)region), cap(bytes) {}
     ~Workspace();
     hipError_t alloc(void **p, size_t bytes);
 };
@@ -63,6 +69,9 @@ struct FitArgs {
     int64_t N, nx, ny, nz;
     hipStream_t stream;
     const mpm_space *spaces = nullptr;  // per-contrast acquisition spaces (projected fit) or NULL
+    // no pinned host staging: collect() reads the results from device memory
+    // with synchronous copies (the stream has completed by then)
+    bool no_pinned = false;
 };
 
 mpm_status image_means(Workspace &ws, Prof &prof, const DevProto &P, int dtype, const void *X,
@@ -82,6 +91,9 @@ struct FitJob {
 };
 std::unique_ptr<FitJob> make_ml_job(const FitArgs &a, Workspace &ws, Prof &prof, mpm_status *st);
 std::unique_ptr<FitJob> make_map_job(const FitArgs &a, Workspace &ws, Prof &prof, mpm_status *st);
+
+// Runs a whole fit on a.stream with workspace ws and blocks until it is done.
+mpm_status run_fit(const FitArgs &a, Workspace &ws, mpm_report *report, double *trace, int trace_len);
 
 // Host-side validation shared by mpm_fit and the server.
 mpm_status check_fit_args(const mpm_protocol *protocol, const mpm_grid *grid, int dtype, const void *echoes,

@@ -1,4 +1,5 @@
 // mpm_fit.hip -- the ML fit as a job, and the shared initialisation step.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 
@@ -76,7 +77,7 @@ struct MlJob : FitJob {
         nblk = ml_fit_blocks(a.N);
         if (ws.alloc((void **)&part, sizeof(double) * (size_t)rows * nblk) != hipSuccess ||
             ws.alloc((void **)&sums, sizeof(double) * rows) != hipSuccess ||
-            host.alloc(sizeof(double) * rows) != hipSuccess)
+            (!a.no_pinned && host.alloc(sizeof(double) * rows) != hipSuccess))
             return fail(MPM_ERR_OUT_OF_MEMORY, "ML workspace allocation failed");
         return MPM_OK;
     }
@@ -97,7 +98,7 @@ struct MlJob : FitJob {
             return launch_ml_fit(c, a.P, a.dtype, a.X, a.b1, bm, a.maps, a.N, n_gn, a.opt->loading, part, nblk);
         });
         if (e == hipSuccess) e = launch_reduce_rows(c, part, rows, nblk, sums);
-        if (e == hipSuccess)
+        if (e == hipSuccess && !a.no_pinned)
             e = hipMemcpyAsync(host.p, sums, sizeof(double) * rows, hipMemcpyDeviceToHost, a.stream);
         if (e != hipSuccess) return fail(MPM_ERR_DEVICE, "ML fit: %s", hipGetErrorString(e));
         return MPM_OK;
@@ -106,14 +107,24 @@ struct MlJob : FitJob {
     mpm_status collect(mpm_report &rep, double *trace, int trace_len) override
     {
         const int n_gn = a.opt->n_gn;
-        const double *h = (const double *)host.p;
-        for (int i = 0; i <= n_gn && i < trace_len; i++) trace[i] = h[i];
+        double tail[4];  // final NLL, degenerate, non-finite, increases (rows n_gn .. n_gn + 3)
+        if (a.no_pinned) {
+            // the NLL trace straight into trace
+            const int nt = std::min(n_gn + 1, trace_len);
+            hipError_t e = hipMemcpy(tail, sums + n_gn, sizeof(tail), hipMemcpyDeviceToHost);
+            if (e == hipSuccess && nt > 0) e = hipMemcpy(trace, sums, sizeof(double) * nt, hipMemcpyDeviceToHost);
+            if (e != hipSuccess) return fail(MPM_ERR_DEVICE, "ML fit: %s", hipGetErrorString(e));
+        } else {
+            const double *h = (const double *)host.p;
+            for (int i = 0; i <= n_gn && i < trace_len; i++) trace[i] = h[i];
+            for (int k = 0; k < 4; k++) tail[k] = h[n_gn + k];
+        }
         memset(&rep, 0, sizeof(rep));
-        rep.nll = rep.objective = h[n_gn];
+        rep.nll = rep.objective = tail[0];
         rep.gn_done = n_gn;
-        rep.degenerate_voxels = (int64_t)llround(h[n_gn + 1]);
-        rep.nonfinite_voxels = (int64_t)llround(h[n_gn + 2]);
-        rep.nll_increases = (int64_t)llround(h[n_gn + 3]);
+        rep.degenerate_voxels = (int64_t)llround(tail[1]);
+        rep.nonfinite_voxels = (int64_t)llround(tail[2]);
+        rep.nll_increases = (int64_t)llround(tail[3]);
         return MPM_OK;
     }
 };

@@ -1,5 +1,6 @@
 // mpm_map.hip -- host driver of the JTV-regularised (MAP) fit and of the
 // Laplace uncertainty (paper Sec. 2.5-2.7, Sec. 3.6).
+#include <algorithm>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -201,7 +202,7 @@ struct MapJob : FitJob {
         t = t0 = o->start_outer;
         mpm_status st = alloc_map(a, ws, m, tl);
         if (st) return st;
-        if (host.alloc(sizeof(MapCtl) + sizeof(double) * (size_t)(tl > 0 ? tl : 1)) != hipSuccess)
+        if (!a.no_pinned && host.alloc(sizeof(MapCtl) + sizeof(double) * (size_t)(tl > 0 ? tl : 1)) != hipSuccess)
             return fail(MPM_ERR_OUT_OF_MEMORY, "pinned host allocation failed");
         set_prior(o, m, true, prior_on);
         m.tol_gn = o->tol_gn;
@@ -348,8 +349,9 @@ struct MapJob : FitJob {
                 RUN("map_final", N * (16 + 40 + 16 + 4), launch_final_pushed(s, m, ps.pp, nullptr, nullptr));
                 RUN("fin", 0.0, fin(FIN_STATS, 0, nb_pl, ps.rows(1)));
             }
-            if (e == hipSuccess) e = hipMemcpyAsync(host.p, m.ctl, sizeof(MapCtl), hipMemcpyDeviceToHost, s);
-            if (e == hipSuccess && tl > 0)
+            if (e == hipSuccess && !a.no_pinned)
+                e = hipMemcpyAsync(host.p, m.ctl, sizeof(MapCtl), hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess && tl > 0 && !a.no_pinned)
                 e = hipMemcpyAsync((char *)host.p + sizeof(MapCtl), m.trace, sizeof(double) * tl,
                                    hipMemcpyDeviceToHost, s);
             finished = true;
@@ -363,9 +365,16 @@ struct MapJob : FitJob {
     mpm_status collect(mpm_report &rep, double *trace, int trace_len) override
     {
         MapCtl h;
-        memcpy(&h, host.p, sizeof(h));
-        const double *ht = (const double *)((const char *)host.p + sizeof(MapCtl));
-        for (int i = 0; i < tl && i < trace_len; i++) trace[i] = ht[i];
+        if (a.no_pinned) {
+            const int nt = std::min(tl, trace_len);
+            hipError_t e = hipMemcpy(&h, m.ctl, sizeof(MapCtl), hipMemcpyDeviceToHost);
+            if (e == hipSuccess && nt > 0) e = hipMemcpy(trace, m.trace, sizeof(double) * nt, hipMemcpyDeviceToHost);
+            if (e != hipSuccess) return fail(MPM_ERR_DEVICE, "MAP fit: %s", hipGetErrorString(e));
+        } else {
+            memcpy(&h, host.p, sizeof(h));
+            const double *ht = (const double *)((const char *)host.p + sizeof(MapCtl));
+            for (int i = 0; i < tl && i < trace_len; i++) trace[i] = ht[i];
+        }
         memset(&rep, 0, sizeof(rep));
         rep.nll = h.nll_final;
         rep.jtv = prior_on ? h.jtv : 0.0;
