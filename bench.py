@@ -38,6 +38,19 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
+# Per-voxel byte model of the planned hot path (compulsory HBM bytes): CG
+# sweep A reads z, the previous direction, w and the 10-entry Hessian and
+# writes p and q (16 + 16 + 4 + 40 + 16 + 16); sweep B reads the solution,
+# residual, p, q, the Hessian and the stencil diagonal and writes the solution,
+# residual and z (156).  The kernels' own byte counts differ (sweep A writes no
+# q and carries the deferred solution update; sweep B recomputes q) and are
+# reported beside these.
+MODEL_BYTES_PER_VOXEL = {"cg_a": 108.0, "cg_b": 156.0}
+# The whole step per voxel: ML fit 108 B; 80 MAP Newton steps of 8772 B
+# (likelihood pass 168, CG start 108, 32 x (108 + 156), update 48); the Laplace
+# variance pass 164 B (echoes 88, b1 4, maps 16, w 4, 20 for the weights
+# pass, variance 16, moments 16).
+STEP_MODEL_BYTES_PER_VOXEL = 108.0 + 80 * 8772.0 + 164.0
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2102_01604_amd", "csrc", f)
                   for f in ("k_map.hip", "mpm_map.h", "mpm_device.h", "mpm_kernels.h", "mpm_tune.hip")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_map_brain.txt")
@@ -115,6 +128,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--dtype", default="f32", choices=["f32", "f16", "bf16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serving-leg", dest="serving_leg", action="store_false",
+                    help="skip the serving leg (64 requests of four sizes in one burst, schedule seed 4000, "
+                         "continuous batching against serial fits)")
     ap.add_argument("--profile-every", type=int, default=7,
                     help="bracket one in this many launches of each kernel with HIP events")
     ap.add_argument("--dims", default="192,240,256")
@@ -134,6 +150,9 @@ def main():
     ap.add_argument("--noise", action="store_true",
                     help="the noise estimation of Sec. 2.7 (histogram + Rician mixture per image) on the "
                          "whole-brain volume placed in air")
+    ap.add_argument("--batch", action="store_true",
+                    help="batched JTV-MAP fits (mpm_fit_batch) against the same fits one after another: 16 volumes "
+                         "of 64^3 and 4 of 96 x 128 x 128, 10 x 8 x 32 each; one JSON line")
     ap.add_argument("--autotune", action="store_true",
                     help="mpm_autotune on the four serving volume sizes: the CG sweep A time per workgroup count")
     ap.add_argument("--e1-voxels", type=int, default=1 << 20)
@@ -143,8 +162,13 @@ def main():
     ap.add_argument("--schedule-seeds", default="4000",
                     help="serving: comma-separated seeds of the arrival schedules (request mix and gaps)")
     ap.add_argument("--budget-gib", type=float, default=16.0, help="serving: HBM budget of the server (GiB)")
+    ap.add_argument("--no-groups", action="store_true",
+                    help="serving: the server runs every fit on its own stream (no batched groups)")
     ap.add_argument("--serve-classes", default="0,1,2,3",
                     help="serving: the size classes requests are drawn from (indices into the four sizes)")
+    ap.add_argument("--ml-counters", action="store_true",
+                    help="for hardware-counter runs: the whole-brain ML fit (20 Newton steps, default "
+                         "initialisation) once, then exit")
     ap.add_argument("--counters", action="store_true",
                     help="for hardware-counter runs: two outer loops of one Newton step each of the MAP fit "
                          "(2 x 1 x 32; the second loop has JTV weights, so its 32 CG iterations all run, as in "
@@ -181,6 +205,9 @@ def main():
     if args.noise:
         noise_estimation(args, torch, _lib, synth, dev)
         return
+    if args.batch:
+        batch_bench(torch, _lib, synth, dev)
+        return
     if args.autotune:
         out = {"metric": "CG sweep A time per workgroup count (mpm_autotune)", "sizes": {}}
         for dims in SERVE_SIZES:
@@ -208,6 +235,12 @@ def main():
     log("echoes simulated on the GPU")
 
     lam = case["lam"]
+    if args.ml_counters:
+        maps = torch.empty((4, N), dtype=torch.float32, device=dev)
+        _lib.mpm_fit(case["proto"], dims, X, b1, {"mode": "ml", "n_gn": 20}, maps)
+        torch.cuda.synchronize()
+        log("counter workload done: ML 20 GN")
+        return
     if args.counters:
         maps = torch.empty((4, N), dtype=torch.float32, device=dev)
         _lib.mpm_fit(case["proto"], dims, X, b1, {"mode": "map", "n_outer": 2, "n_gn": 1, "n_cg": 32,
@@ -258,25 +291,47 @@ def main():
     t_end = time.perf_counter()
     _lib.mpm_profile_enable(0)
     stats = _lib.mpm_profile_read()
-    # the same MAP fit with FP16 echo storage (outside the timed steps)
+    # the same MAP fit with FP16 echo storage and per-image offsets (outside the timed steps)
     f16 = None
     if args.dtype == "f32":
-        X16 = X.half()
+        X16 = torch.empty(X.shape, dtype=torch.float16, device=dev)
+        off16 = _lib.mpm_pack_echoes(X, X16, stream=stream)
+        o16 = dict(map_opts, echo_offset=off16)
         m16 = torch.empty((4, N), dtype=torch.float32, device=dev)
-        _lib.mpm_fit(case["proto"], dims, X16, b1, dict(map_opts, n_outer=1, n_gn=1, n_cg=1), m16, stream=stream)
+        _lib.mpm_fit(case["proto"], dims, X16, b1, dict(o16, n_outer=1, n_gn=1, n_cg=1), m16, stream=stream)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
-        rep16 = _lib.mpm_fit(case["proto"], dims, X16, b1, map_opts, m16, stream=stream)[0]
+        rep16 = _lib.mpm_fit(case["proto"], dims, X16, b1, o16, m16, stream=stream)[0]
         e1.record(stream)
         e1.synchronize()
         ms16 = e0.elapsed_time(e1)
         d16 = (m16 - maps_map).abs().amax(dim=1) / maps_map.abs().amax(dim=1)
         f16 = {"map_fit_ms": round(ms16, 3), "map_voxel_gn_iters_per_s": round(N * 80 / (ms16 * 1e-3), 1),
+               "storage": "FP16 of each image minus its mean (mpm_pack_echoes)",
                "max_rel_diff_vs_f32_storage": [float(v) for v in d16.cpu()],
                "objective": rep16["objective"]}
         del X16, m16
         log(f"f16 storage MAP fit {ms16:.1f} ms")
+
+    # achievable copy rate of a buffer the size of CG sweep A's working set, on
+    # the same stream (reads + writes of a device-to-device copy)
+    cg_ws = int(N * 124)
+    ca = torch.empty(cg_ws // 4, dtype=torch.float32, device=dev)
+    ca.fill_(1.0)
+    cb = torch.empty_like(ca)
+    cb.copy_(ca)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(10):
+        cb.copy_(ca)
+    e1.record(stream)
+    e1.synchronize()
+    copy_gbps = 2.0 * cg_ws * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del ca, cb
+    torch.cuda.empty_cache()
+    log(f"device copy of {cg_ws / 1e9:.2f} GB: {copy_gbps:.0f} GB/s")
 
     ms_per_step = (t_end - t_start) * 1e3 / args.steps
     ml_ms, map_ms, unc_ms = (float(np.median(parts[k])) for k in ("ml", "map", "unc"))
@@ -292,7 +347,9 @@ def main():
                 best, best_t = name, tot
     roof = None
     kernels = {}
+    kernel_bytes = 0.0
     for name, s in stats.items():
+        kernel_bytes += s["bytes"]
         if s["timed"] > 0:
             avg = s["timed_ms"] / s["timed"]
             bpl = s["bytes"] / max(s["launches"], 1)
@@ -301,16 +358,46 @@ def main():
     if best is not None:
         s = stats[best]
         avg_s = s["timed_ms"] / s["timed"] * 1e-3
-        bpl = s["bytes"] / s["launches"]
+        own = s["bytes"] / s["launches"]
+        # byte model of one CG sweep A per voxel as planned: z, the previous
+        # direction, w and the 10-entry Hessian in, p and q out (108 B); the
+        # kernel itself writes no q and carries the deferred solution update
+        model = MODEL_BYTES_PER_VOXEL.get(best)
+        bpl = N * model if model else own
         achieved = bpl / avg_s / 1e9
         traffic = read_traffic(best)
         roof = {"bound": "hbm", "kernel": best, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
-                "traffic": traffic, "alg_bytes_per_launch": bpl, "avg_ms": round(avg_s * 1e3, 5)}
+                "traffic": traffic, "alg_bytes_per_launch": bpl, "bytes_per_voxel_model": model,
+                "kernel_bytes_per_launch": own, "achieved_on_kernel_bytes": round(own / avg_s / 1e9, 1),
+                "frac_on_kernel_bytes": round(own / avg_s / 1e9 / HBM_PEAK_GBPS, 4),
+                "avg_ms": round(avg_s * 1e3, 5),
+                "copy_GBps_same_size": round(copy_gbps, 1),
+                "frac_of_copy_rate": round(achieved / copy_gbps, 4)}
+    # step level: the byte model of the whole step over the measured step time
+    step_model = N * STEP_MODEL_BYTES_PER_VOXEL
+    step_hbm = {"model_bytes_per_step": step_model,
+                "model_GBps": round(step_model / (ms_per_step * 1e-3) / 1e9, 1),
+                "model_frac": round(step_model / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+                "kernel_bytes_per_step": kernel_bytes / args.steps,
+                "kernel_GBps": round(kernel_bytes / args.steps / (ms_per_step * 1e-3) / 1e9, 1),
+                "model": "per voxel: ML 108 B; each of the 80 MAP Newton steps 8772 B (likelihood pass 168, "
+                         "CG start 108, 32 CG iterations x 264, update 48); variance 164 B"}
 
-    cpu = None
+    cpu, parity = None, None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(case, dims)
+        cpu, cr = cpu_baseline(case, dims)
+        parity = crop_parity(torch, _lib, case, cr, dev)
+        log(f"crop parity vs the FP64 oracle: {parity}")
+
+    serve = None
+    if args.serving_leg:
+        classes = np.arange(len(SERVE_SIZES))
+        per_seed, n_map = serve_runs(torch, _lib, synth, dev, [4000], classes, 64, 2.0, 16 << 30,
+                                     labels=("burst",))
+        serve = {"schedule_seed": 4000, "requests": 64, "n_map": n_map[4000],
+                 "sizes": [list(v) for v in SERVE_SIZES], "arrivals": "burst (all at t = 0)",
+                 "max_active": 4, "hbm_budget_bytes": 16 << 30, **per_seed[4000]["burst"]}
 
     rm = reports["map"]
     out = {
@@ -331,7 +418,10 @@ def main():
                    "voxels": N, "echoes": I, "echo_storage": args.dtype, "ml_gn": 20,
                    "map_schedule": [10, 8, 32], "lambda": [round(v, 6) for v in lam]},
         "roofline": roof,
+        "step_hbm": step_hbm,
         "cpu_baseline": cpu,
+        "parity_vs_oracle": parity,
+        "serving_burst": serve,
         "breakdown_ms": {"ml_fit": round(ml_ms, 3), "map_fit": round(map_ms, 3), "uncertainty": round(unc_ms, 3)},
         "ml_voxel_iters_per_s": round(N * 20 / (ml_ms * 1e-3), 1),
         "map_voxel_gn_iters_per_s": round(N * 80 / (map_ms * 1e-3), 1),
@@ -688,29 +778,84 @@ def noise_estimation(args, torch, _lib, synth, dev):
 SERVE_SIZES = [(64, 64, 64), (96, 128, 128), (128, 160, 160), (192, 240, 256)]
 
 
-def serving(args, torch, _lib, synth, dev):
+def batch_bench(torch, _lib, synth, dev):
+    """JTV-MAP fits of several small volumes (the serving sizes 64^3 and
+    96 x 128 x 128, each its own seeded noise) one after another with mpm_fit
+    and together with mpm_fit_batch; the maps must be identical."""
+    res = {}
+    for dims, n in (((64, 64, 64), 16), ((96, 128, 128), 4)):
+        c = synth.make_case("map_brain", dims=dims, seed=4100)
+        del c["eps"]
+        N = int(np.prod(dims))
+        truth = torch.from_numpy(c["truth"].astype(np.float32)).to(dev)
+        b1 = torch.from_numpy(c["b1"].astype(np.float32)).to(dev)
+        opts = {"mode": "map", "n_outer": 10, "n_gn": 8, "n_cg": 32, "max_halvings": 4, "lam": c["lam"]}
+        Xs = []
+        for r in range(n):
+            g = torch.Generator(device=dev).manual_seed(9000 + r)
+            eps = torch.randn((22, N), generator=g, device=dev)
+            X = torch.empty((22, N), dtype=torch.float32, device=dev)
+            _lib.mpm_simulate(c["proto"], dims, truth, b1, eps, X)
+            Xs.append(X)
+        del eps
+        warm = torch.empty((4, N), device=dev)
+        _lib.mpm_fit(c["proto"], dims, Xs[0], b1, dict(opts, n_outer=1, n_gn=1, n_cg=2), warm)
+        _lib.mpm_fit_batch([(c["proto"], dims, X, b1, dict(opts, n_outer=1, n_gn=1, n_cg=2), torch.empty((4, N), device=dev))
+                            for X in Xs[:2]])
+        torch.cuda.synchronize()
+        serial = [torch.empty((4, N), device=dev) for _ in range(n)]
+        t0 = time.perf_counter()
+        for X, m in zip(Xs, serial):
+            _lib.mpm_fit(c["proto"], dims, X, b1, opts, m)
+        torch.cuda.synchronize()
+        t_serial = time.perf_counter() - t0
+        batched = [torch.empty((4, N), device=dev) for _ in range(n)]
+        t0 = time.perf_counter()
+        reps = _lib.mpm_fit_batch([(c["proto"], dims, X, b1, opts, m) for X, m in zip(Xs, batched)])
+        torch.cuda.synchronize()
+        t_batch = time.perf_counter() - t0
+        same = all(bool(torch.equal(a, b)) for a, b in zip(serial, batched))
+        iters = n * N * 80
+        key = "x".join(str(v) for v in dims)
+        res[key] = {"fits": n, "serial_s": round(t_serial, 4), "batched_s": round(t_batch, 4),
+                    "serial_voxel_gn_iters_per_s": round(iters / t_serial, 1),
+                    "batched_voxel_gn_iters_per_s": round(iters / t_batch, 1),
+                    "speedup": round(t_serial / t_batch, 3), "maps_identical": same,
+                    "gn_done": [r[0]["gn_done"] for r in reps]}
+        log(f"batch {key} x {n}: serial {t_serial:.3f} s, batched {t_batch:.3f} s, identical {same}")
+        del Xs, serial, batched
+        torch.cuda.empty_cache()
+    out = {"metric": "batched JTV-MAP fits vs one at a time (voxel-GN-iterations/s)",
+           "value": res["64x64x64"]["batched_voxel_gn_iters_per_s"], "unit": "voxel-GN-iterations/s",
+           "n_gpus": 1, "higher_is_better": True, "data": "synthetic",
+           "config": {"workload": "JTV-MAP 10x8x32 of 16 volumes of 64^3 and of 4 volumes of 96x128x128, 22 "
+                                  "echoes, FP32 storage, each volume its own noise"},
+           "batch": res}
+    print(json.dumps(out), flush=True)
+
+
+def serve_runs(torch, _lib, synth, dev, seeds, classes, n, rate, budget, labels=("poisson", "burst"),
+               groups=True):
     """Continuous batching against serial plain fits on the same arrival
-    schedule, for each schedule seed.  Each size class has one seeded tissue
+    schedules, for each schedule seed.  Each size class has one seeded tissue
     volume; each request draws its own noise (seeded) on the GPU; all inputs
-    are resident in HBM before the clock starts."""
-    seeds = [int(v) for v in args.schedule_seeds.split(",")]
-    n = args.requests
-    classes = np.array([int(v) for v in args.serve_classes.split(",")])
+    are resident in HBM before the clock starts.  Returns (per-seed results,
+    MAP request count per seed)."""
     vols = {}
     for k, dims in enumerate(SERVE_SIZES):
         if k not in classes:
             continue
         c = synth.make_case("map_brain", dims=dims, seed=4100 + k)
+        del c["eps"]
         vols[k] = {"case": c, "truth": torch.from_numpy(c["truth"].astype(np.float32)).to(dev),
                    "b1": torch.from_numpy(c["b1"].astype(np.float32)).to(dev)}
     log(f"serving: generated {len(vols)} volume classes")
-    budget = int(args.budget_gib * (1 << 30))
 
     def make_requests(seed):
         rng = np.random.default_rng(seed)
         cls = classes[rng.integers(0, len(classes), n)]
         is_map = rng.random(n) < 0.5
-        gaps = rng.exponential(1.0 / args.rate, n)
+        gaps = rng.exponential(1.0 / rate, n)
         arrive = np.cumsum(gaps) - gaps[0]
         reqs = []
         for r in range(n):
@@ -747,7 +892,7 @@ def serving(args, torch, _lib, synth, dev):
         outs = [torch.empty((4, r["N"]), device=dev) for r in reqs]
         done = np.full(n, np.nan)
         tickets = [None] * n
-        srv = _lib.MpmServer(hbm_budget=budget, max_active=4)
+        srv = _lib.MpmServer(hbm_budget=budget, max_active=4, groups=groups)
         t0 = time.perf_counter()
         nxt = 0
         while np.isnan(done).any():
@@ -780,7 +925,8 @@ def serving(args, torch, _lib, synth, dev):
             torch.cuda.synchronize()
         log(f"serving seed {seed}: {n} requests resident ({sum(r['N'] for r in reqs) / 1e6:.1f} M voxels)")
         res = {}
-        for label, times in (("poisson", arrive), ("burst", np.zeros(n))):
+        for label in labels:
+            times = arrive if label == "poisson" else np.zeros(n)
             so, sd = run_serial(reqs, times)
             torch.cuda.synchronize()
             bo, bd = run_batched(reqs, times)
@@ -795,6 +941,7 @@ def serving(args, torch, _lib, synth, dev):
                 "batched": {"p50_s": round(nr(lat_b, 0.5), 3), "p99_s": round(nr(lat_b, 0.99), 3),
                             "makespan_s": round(float(bd.max()), 3),
                             "voxel_iters_per_s": round(iters / float(bd.max()), 1)},
+                "throughput_batched_over_serial": round(float(sd.max()) / float(bd.max()), 3),
                 "max_abs_map_diff_batched_vs_serial": diff,
             }
             log(f"serving seed {seed} {label}: {res[label]}")
@@ -802,6 +949,17 @@ def serving(args, torch, _lib, synth, dev):
         per_seed[seed] = res
         del reqs
         torch.cuda.empty_cache()
+    return per_seed, n_map
+
+
+def serving(args, torch, _lib, synth, dev):
+    """The serving benchmark: one JSON line over every schedule seed."""
+    seeds = [int(v) for v in args.schedule_seeds.split(",")]
+    n = args.requests
+    classes = np.array([int(v) for v in args.serve_classes.split(",")])
+    budget = int(args.budget_gib * (1 << 30))
+    per_seed, n_map = serve_runs(torch, _lib, synth, dev, seeds, classes, n, args.rate, budget,
+                                 groups=not args.no_groups)
     med = lambda f: round(float(np.median([f(per_seed[s_]) for s_ in seeds])), 3)
     summary = {lab: {kind: {q: med(lambda r, lab=lab, kind=kind, q=q: r[lab][kind][q])
                             for q in ("p50_s", "p99_s", "makespan_s")} for kind in ("serial", "batched")}
@@ -814,17 +972,17 @@ def serving(args, torch, _lib, synth, dev):
                                   f"22 echoes, ML (20 GN) or "
                                   f"JTV-MAP (10x8x32) with p=0.5, Poisson arrivals {args.rate}/s; burst = all at t=0",
                       "max_active": 4, "hbm_budget_bytes": budget, "schedule_seeds": seeds,
-                      "n_map": n_map},
+                      "n_map": n_map, "batched_groups": not args.no_groups},
            "serving_median_over_schedules": summary,
            "serving": {str(k): v for k, v in per_seed.items()}}
     print(json.dumps(out), flush=True)
 
 
-def cpu_baseline(case, dims):
-    """The FP64 oracle on a bounded sample of the same workload: the central
-    crop of the volume, fitted as its own volume with the same three stages."""
+def crop(case, dims, c):
+    """The central c^3 crop of the volume as its own volume: (dims, voxel
+    indices, echoes made by the oracle's forward model plus the case's noise
+    (FP32 values, widened), b1 (FP32, widened), truth)."""
     import oracle
-    c = 40
     nx, ny, nz = dims
     cx, cy, cz = (min(c, nx), min(c, ny), min(c, nz))
     x0, y0, z0 = (nx - cx) // 2, (ny - cy) // 2, (nz - cz) // 2
@@ -835,19 +993,92 @@ def cpu_baseline(case, dims):
     b1 = case["b1"][idx].astype(np.float32).astype(np.float64)
     s = oracle.simulate(case["proto"], truth, b1)
     x = (s + case["sigma"] * case["eps"][:, idx].astype(np.float64)).astype(np.float32).astype(np.float64)
-    cd = (cx, cy, cz)
-    lam = case["lam"]
+    return (cx, cy, cz), idx, np.ascontiguousarray(x), b1, np.ascontiguousarray(truth)
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_stages(case, cd, x, b1, lam):
+    """The oracle's three stages on one volume; returns (seconds, ML maps, MAP maps)."""
+    import oracle
     t = time.perf_counter()
-    oracle.fit(case["proto"], cd, x, b1, {"mode": "ml", "n_gn": 20})
+    ml, _, _ = oracle.fit(case["proto"], cd, x, b1, {"mode": "ml", "n_gn": 20})
     maps, rep, _ = oracle.fit(case["proto"], cd, x, b1, {"mode": "map", "n_outer": 10, "n_gn": 8, "n_cg": 32,
                                                         "max_halvings": 4, "lam": lam})
     oracle.uncertainty(case["proto"], cd, x, b1, {"mode": "map", "lam": lam}, maps, moments=True)
-    dt = time.perf_counter() - t
+    return time.perf_counter() - t, ml, maps
+
+
+def cpu_baseline(case, dims):
+    """The FP64 oracle on a bounded sample of the same workload: the central
+    40^3 crop fitted as its own volume with the same three stages on every
+    host thread, and the central 20^3 crop on one thread.  Also returns the
+    40^3 crop and the oracle's maps, for the GPU's parity leg."""
+    import oracle
+    lam = case["lam"]
+    cd, idx, x, b1, truth = crop(case, dims, 40)
+    threads = oracle.num_threads()
+    dt, ml, mp = oracle_stages(case, cd, x, b1, lam)
     n = len(idx)
-    return {"value": round(n * 100 / dt, 1), "unit": "voxel-GN-iterations/s", "cores": oracle.num_threads(),
-            "kind": "oracle", "seconds": round(dt, 2),
-            "sample": f"central {cx}x{cy}x{cz} crop ({n} voxels) of the same volume, fitted as its own volume: "
-                      "ML 20 GN + MAP 10x8x32 + variance, FP64"}
+    cd1, idx1, x1, b11, _ = crop(case, dims, 20)
+    oracle.set_num_threads(1)
+    try:
+        dt1, _, _ = oracle_stages(case, cd1, x1, b11, lam)
+    finally:
+        oracle.set_num_threads(threads)
+    rec = {"value": round(n * 100 / dt, 1), "unit": "voxel-GN-iterations/s", "cores": threads,
+           "kind": "oracle", "seconds": round(dt, 2), "cpu_model": cpu_model(),
+           "sample": f"central {cd[0]}x{cd[1]}x{cd[2]} crop ({n} voxels) of the same volume, fitted as its own "
+                     "volume: ML 20 GN + MAP 10x8x32 + variance, FP64",
+           "one_thread": {"value": round(len(idx1) * 100 / dt1, 1), "unit": "voxel-GN-iterations/s", "cores": 1,
+                          "seconds": round(dt1, 2),
+                          "sample": f"central {cd1[0]}x{cd1[1]}x{cd1[2]} crop ({len(idx1)} voxels), "
+                                    "the same three stages"}}
+    return rec, {"dims": cd, "x": x, "b1": b1, "truth": truth, "ml": ml, "map": mp}
+
+
+def map_error(gpu, orc, truth):
+    """max_n |gpu - orc| / max_n |orc| per map (relative on log maps), over all
+    voxels and over the well-posed ones (oracle within 1 of the truth)."""
+    gpu = np.asarray(gpu, np.float64)
+    d = np.abs(gpu - orc)
+    sc = np.maximum(np.abs(orc).max(axis=1), 1e-30)
+    good = np.all(np.abs(orc - truth) < 1.0, axis=0)
+    return {"all_voxels": [float(v) for v in d.max(axis=1) / sc],
+            "well_posed": [float(v) for v in d[:, good].max(axis=1) / sc], "well_posed_frac": float(good.mean())}
+
+
+def crop_parity(torch, _lib, case, cr, dev):
+    """The GPU's fits of the oracle's crop (default initialisation, the
+    benchmark's options) with FP32 echoes and with FP16 echoes stored with
+    per-image offsets, against the oracle's FP64 maps of the unquantised data."""
+    cd, x, b1, truth = cr["dims"], cr["x"], cr["b1"], cr["truth"]
+    N = x.shape[1]
+    X = torch.from_numpy(x.astype(np.float32)).to(dev)
+    B1 = torch.from_numpy(b1.astype(np.float32)).to(dev)
+    Q = torch.empty(X.shape, dtype=torch.float16, device=dev)
+    off = _lib.mpm_pack_echoes(X, Q)
+    ml_opts = {"mode": "ml", "n_gn": 20}
+    map_opts = {"mode": "map", "n_outer": 10, "n_gn": 8, "n_cg": 32, "max_halvings": 4, "lam": case["lam"]}
+    out = {}
+    for name, E, extra in (("f32", X, {}), ("f16_offsets", Q, {"echo_offset": off})):
+        m = torch.empty((4, N), dtype=torch.float32, device=dev)
+        _lib.mpm_fit(case["proto"], cd, E, B1, dict(ml_opts, **extra), m)
+        ml = m.cpu().numpy()
+        _lib.mpm_fit(case["proto"], cd, E, B1, dict(map_opts, **extra), m)
+        mp = m.cpu().numpy()
+        out[name] = {"ml": map_error(ml, cr["ml"], truth), "map": map_error(mp, cr["map"], truth)}
+    out["tolerance"] = {"f32": 1e-4, "f16_offsets": 1e-3}
+    out["sample"] = f"the cpu_baseline crop {cd[0]}x{cd[1]}x{cd[2]}, default initialisation on both sides"
+    return out
 
 
 if __name__ == "__main__":

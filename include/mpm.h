@@ -15,8 +15,10 @@
  * own grids (mpm_*_projected); the fit and forward model with a protocol per
  * voxel (mpm_fit_voxelwise, mpm_simulate_voxelwise; also in the rate and time
  * representations); the noise level and initial maps from the echoes
- * (mpm_estimate_noise); a serving queue with continuous batching
- * (mpm_server_*); mpm_footprint_bytes, mpm_autotune, kernel timing
+ * (mpm_estimate_noise); batched JTV-MAP fits of several volumes
+ * (mpm_fit_batch); reduced-precision echo storage with per-image
+ * offsets (mpm_pack_echoes); a serving queue with continuous batching
+ * (mpm_server_*); mpm_footprint_bytes, mpm_autotune, mpm_autotune_set, kernel timing
  * (mpm_profile_*), mpm_last_error and mpm_version.
  *
  * Conventions shared by every entry point
@@ -131,6 +133,17 @@ typedef struct {
      * (its gains are measured against the end of loop 0).  Trace slots of the
      * loops before start_outer stay NaN; report counts cover the loops run. */
     int32_t start_outer;
+    /* Offsets of reduced-precision echo storage: host float [I] or NULL (no
+     * offsets).  With MPM_F16 / MPM_BF16 echoes, image i stores its values minus
+     * echo_offset[i], rounded to the storage type, and every kernel adds
+     * echo_offset[i] back in FP32 when it reads a value.  An offset near the
+     * image's values (mpm_pack_echoes uses the image mean) shrinks the magnitude
+     * that is rounded, and with it the rounding error: the storage type keeps a
+     * fixed number of significant bits.  Must be NULL for MPM_F32 echoes and
+     * finite.  Read by mpm_fit, mpm_fit_noalloc, mpm_uncertainty, the projected
+     * fit and uncertainty and the server (which copies it at submit);
+     * mpm_fit_voxelwise rejects it. */
+    const float *echo_offset;
 } mpm_options;
 
 typedef struct {
@@ -356,9 +369,15 @@ const char *mpm_last_error(void);
  * step then enqueues the next piece of work of every admitted fit (the whole
  * ML fit, or one Newton-like step of a MAP fit) on
  * its stream, so fits admitted at different times run concurrently on the
- * device and new arrivals join while others are in flight.  Each fit runs
- * the same kernels with the same launch shapes as mpm_fit(), so its result is
- * the same as when it is run alone.
+ * device and new arrivals join while others are in flight.  Small JTV-MAP
+ * fits (fewer than 2^21 voxels) are admitted in groups: the first waiting one
+ * takes later waiting fits that can share launches with it (mpm_fit_batch's
+ * conditions; at most 16 fits and 2^22 voxels in all, within the budget) onto
+ * its stream, and the group runs as one batched fit, every kernel launch
+ * serving all its volumes.  Each fit, alone or in a group, runs the same
+ * kernel bodies with the same per-volume launch shapes as mpm_fit(), so its
+ * result is the same as when it is run alone, bit for bit.  Flag
+ * MPM_SERVER_NO_GROUPS keeps every fit on a stream of its own.
  *
  * mpm_request: the arguments of mpm_fit() (report and trace excepted).  The
  * caller's device buffers must hold their inputs before submit and stay valid
@@ -375,10 +394,12 @@ const char *mpm_last_error(void);
  * MPM_ERR_OUT_OF_MEMORY.
  * mpm_server_cancel: a queued request leaves the queue at once; a running one
  * gets no further pieces and is released once its pieces in flight complete
- * (at a later step).  Either then polls as done with MPM_ERR_CANCELLED, its
- * maps holding whatever the completed pieces wrote (unspecified).  No effect
- * on a finished request; MPM_ERR_NOT_FOUND for an unknown ticket.  Other
- * requests are unaffected (each runs on its own stream and workspace).
+ * (at a later step); a running one in a group finishes with its group (whose
+ * launches serve every member) unless every member was cancelled.  Either then
+ * polls as done with MPM_ERR_CANCELLED, its maps holding whatever the
+ * completed pieces wrote (unspecified).  No effect on a finished request;
+ * MPM_ERR_NOT_FOUND for an unknown ticket.  Other requests are unaffected
+ * (each fit has its own workspace and control block).
  * mpm_server_destroy waits for running fits and frees the server.
  * Calls on one server are serialised by an internal lock.
  */
@@ -396,6 +417,7 @@ typedef struct {
 typedef struct mpm_server mpm_server;
 
 #define MPM_SERVER_THREAD 1
+#define MPM_SERVER_NO_GROUPS 2  /* run every fit on its own stream (no batched groups) */
 
 mpm_status mpm_server_create(size_t hbm_budget, int32_t max_active, int32_t flags, mpm_server **out);
 mpm_status mpm_server_submit(mpm_server *server, const mpm_request *request, uint64_t *ticket);
@@ -405,7 +427,43 @@ mpm_status mpm_server_cancel(mpm_server *server, uint64_t ticket);
 mpm_status mpm_server_destroy(mpm_server *server);
 
 /*
- * mpm_fit_noalloc --/*
+ * mpm_fit_batch -- several JTV-MAP fits (paper Sec. 2.5-2.7) run together on
+ * one stream, each kernel launch serving all of them: for many small volumes,
+ * whose single launches each cost about the device's dispatch latency, this
+ * spends that latency once per launch instead of once per volume.  requests:
+ * host array of n (1..64) fits as for the server (their own protocols, grids,
+ * echoes, fields, priors, initialisations and maps); all MPM_MAP_JTV, with the
+ * same schedule options (n_outer, n_gn, n_cg, max_halvings, loading,
+ * start_outer, tol_gn, tol_outer, cg_stop), echo storage dtype and register
+ * shape (at most 4 contrasts of at most 8 echoes, 4 x 16, 8 x 8, or other),
+ * else MPM_ERR_UNSUPPORTED.  Each fit's maps, report and trace are those of
+ * mpm_fit on it alone, bit for bit (each volume keeps its own workspace,
+ * launch shape, fixed-order reductions and control block).  reports: host
+ * [n] or NULL; traces: host [n][trace_len] or NULL (trace_len 0), as
+ * mpm_fit's trace per fit.  Workspace: the sum of the fits' (about 124 B per
+ * voxel).  Blocks until done.
+ */
+mpm_status mpm_fit_batch(int32_t n, const mpm_request *requests, mpm_report *reports, double *traces,
+                         int32_t trace_len, void *stream);
+
+/*
+ * mpm_pack_echoes --/*
+ * mpm_pack_echoes -- writes echoes for reduced-precision storage with per-image
+ * offsets (see mpm_options.echo_offset): offsets[i] = the mean of the finite
+ * values of image i (FP64 sum, rounded to float), then
+ * dst[i][n] = round_to_nearest_even(src[i][n] - offsets[i]) in dtype.
+ * n_images >= 1 (<= MPM_MAX_IMAGES), n_voxels in [1, 2^30); src: device float
+ * [n_images][n_voxels]; dst: device [n_images][n_voxels] of dtype (MPM_F16 or
+ * MPM_BF16; must not overlap src); offsets: host float [n_images] (written).
+ * Non-finite inputs stay non-finite (missing observations).  A finite value
+ * whose difference overflows the storage type is an error: the call returns
+ * MPM_ERR_INVALID_ARG after writing dst, with the count in mpm_last_error().
+ * Blocks until done.
+ */
+mpm_status mpm_pack_echoes(int32_t n_images, int64_t n_voxels, const float *src, mpm_dtype dtype, void *dst,
+                           float *offsets, void *stream);
+
+/*
  * mpm_fit_noalloc -- mpm_fit for callers that cannot allocate memory: code
  * under HIP graph capture, serving loops that must not allocate, harnesses
  * that forbid it.  Same arguments, validation, results and blocking
@@ -458,6 +516,20 @@ typedef struct {
 } mpm_tune_result;
 
 mpm_status mpm_autotune(const mpm_grid *grid, int32_t reps, mpm_tune_result *result, void *stream);
+
+/*
+ * mpm_autotune_set -- fixes the launch shape of MAP fits and uncertainties of
+ * exactly this grid size in this process, as mpm_autotune does after timing:
+ * cg_workgroups is the workgroup target of the CG sweep that walks z-runs
+ * (each workgroup walks ceil(tiles * nz / target) planes, at most 32), and
+ * column_workgroups that of the column walks of the stencil-only kernels (the
+ * JTV weights of Sec. 2.5 and the halved-step acceptance test); 0 keeps the
+ * built-in choice.  For callers that pin a launch shape, e.g. to reproduce a
+ * tuned run or to check every z-run length.  Results depend on the shape only
+ * through the order of FP64 partial sums.  MPM_ERR_INVALID_ARG for an invalid
+ * grid or a target outside [0, 2^20].  mpm_autotune_clear forgets it.
+ */
+mpm_status mpm_autotune_set(const mpm_grid *grid, int32_t cg_workgroups, int32_t column_workgroups);
 void mpm_autotune_clear(void);
 
 /* Library version string. */

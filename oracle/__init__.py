@@ -130,6 +130,8 @@ def _load():
                                         C.POINTER(Options), _dp, _dp, _dp]
         lib.orc_uncertainty.restype = C.c_int
         lib.orc_num_threads.restype = C.c_int
+        lib.orc_set_num_threads.argtypes = [C.c_int]
+        lib.orc_set_num_threads.restype = None
         sp = C.POINTER(Space)
         lib.orc_pull.argtypes = [C.POINTER(C.c_int64), sp, _dp, _dp]
         lib.orc_push.argtypes = [C.POINTER(C.c_int64), sp, _dp, _dp]
@@ -213,6 +215,11 @@ def _dims(dims):
 
 def num_threads() -> int:
     return int(_load().orc_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the oracle's voxel-parallel loops from now on."""
+    _load().orc_set_num_threads(int(n))
 
 
 def bessel_i01e(z):

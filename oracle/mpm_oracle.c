@@ -30,7 +30,11 @@
  *              r.z <= cg_stop * r0.z0 (cg_stop = 0 by default: the fixed
  *              iteration count of the configured schedule).
  *   R-accept : a MAP Newton step y - 2^-h * delta is accepted for the first
- *              h = 0..max_halvings that does not increase F_w; if none does,
+ *              h = 0..max_halvings that does not increase F_w by more than
+ *              ACCEPT_REL * |F_w| (1e-9: below that a single-precision
+ *              evaluation of the objective cannot tell a rise from a fall, so
+ *              the rule is the one a single-precision implementation can
+ *              follow); if none does,
  *              y is kept and the remaining Newton steps of that outer loop are
  *              skipped.
  *   R-init   : default initial maps from per-image volume means (see
@@ -61,9 +65,20 @@
 #endif
 
 #define FROZEN_REL 1e-30
+/* R-accept: the largest relative rise of F_w a step may bring and be accepted */
+#define ACCEPT_REL 1e-9
 #define PIVOT_MIN 1e-6
 /* a voxel NLL "rises" only beyond rounding level (changes near convergence are ~1e-15) */
 #define NLL_RISE_REL 1e-12
+
+void orc_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
 
 int orc_num_threads(void)
 {
@@ -988,7 +1003,7 @@ static int fit_impl(const lik_ctx *L, const orc_options *opt, double *maps, orc_
                     for (int h = 0; h <= opt->max_halvings; h++) {
                         for (int64_t i = 0; i < V; i++) trial[i] = maps[i] - step * delta[i];
                         double Ft = objective_w(L, opt->loading, w, opt->lambda, trial, nll, Ly);
-                        if (Ft <= F) {
+                        if (Ft <= F + ACCEPT_REL * fabs(F)) {
                             memcpy(maps, trial, sizeof(double) * (size_t)V);
                             Fnew = Ft;
                             accepted = 1;

@@ -136,6 +136,8 @@ int  orc_uncertainty(const orc_protocol *p, const int64_t dims[3], const double 
                      const double *b1, const orc_options *opt, const double *maps,
                      double *var, double *moments);
 int  orc_num_threads(void);
+/* Threads of the voxel-parallel loops from now on (results do not depend on it). */
+void orc_set_num_threads(int n);
 
 /* Spatial projection (R-proj): trilinear pull Psi and its adjoint push. */
 void orc_pull(const int64_t dims[3], const orc_space *sp, const double *vol, double *out);

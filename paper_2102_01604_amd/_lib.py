@@ -43,7 +43,7 @@ class mpm_options(C.Structure):
                 ("flags", C.c_int32), ("lam", C.c_double * 4), ("jtv_eps", C.c_double),
                 ("cg_stop", C.c_double), ("init_const", C.c_double * 4), ("tol_gn", C.c_double),
                 ("tol_outer", C.c_double), ("b1_receive", C.c_void_p), ("basis", C.c_int32),
-                ("start_outer", C.c_int32)]
+                ("start_outer", C.c_int32), ("echo_offset", C.POINTER(C.c_float))]
 
 
 class mpm_report(C.Structure):
@@ -64,6 +64,7 @@ class mpm_request(C.Structure):
 
 
 MPM_SERVER_THREAD = 1
+MPM_SERVER_NO_GROUPS = 2
 
 
 class mpm_space(C.Structure):
@@ -99,6 +100,10 @@ _P, _G, _O, _R = C.POINTER(mpm_protocol), C.POINTER(mpm_grid), C.POINTER(mpm_opt
 SIGNATURES = {
     "mpm_fit": (C.c_int, [_P, _G, C.c_int, C.c_void_p, C.c_void_p, _O, C.c_void_p, _R,
                           C.POINTER(C.c_double), C.c_int32, C.c_void_p]),
+    "mpm_fit_batch": (C.c_int, [C.c_int32, C.c_void_p, C.c_void_p, C.POINTER(C.c_double), C.c_int32,
+                                C.c_void_p]),
+    "mpm_pack_echoes": (C.c_int, [C.c_int32, C.c_int64, C.c_void_p, C.c_int, C.c_void_p, C.POINTER(C.c_float),
+                                  C.c_void_p]),
     "mpm_fit_noalloc": (C.c_int, [_P, _G, C.c_int, C.c_void_p, C.c_void_p, _O, C.c_void_p, _R,
                                   C.POINTER(C.c_double), C.c_int32, C.c_void_p]),
     "mpm_uncertainty": (C.c_int, [_P, _G, C.c_int, C.c_void_p, C.c_void_p, _O, C.c_void_p, C.c_void_p,
@@ -120,6 +125,7 @@ SIGNATURES = {
                                      C.POINTER(C.c_double), C.POINTER(mpm_rice_fit), C.POINTER(C.c_uint32),
                                      C.c_void_p]),
     "mpm_autotune": (C.c_int, [_G, C.c_int32, C.POINTER(mpm_tune_result), C.c_void_p]),
+    "mpm_autotune_set": (C.c_int, [_G, C.c_int32, C.c_int32]),
     "mpm_autotune_clear": (None, []),
     "mpm_last_error": (C.c_char_p, []),
     "mpm_version": (C.c_char_p, []),
@@ -203,6 +209,11 @@ def make_options(opts: dict) -> mpm_options:
     o.b1_receive = None if bm is None else _f32(bm, "b1_receive").value
     o.basis = MPM_BASES[opts.get("basis", "log")]
     o.start_outer = int(opts.get("start_outer", 0))
+    off = opts.get("echo_offset")
+    if off is not None:
+        arr = (C.c_float * len(off))(*[float(v) for v in off])
+        o._echo_offset_keep = arr  # the struct holds a raw pointer into it
+        o.echo_offset = C.cast(arr, C.POINTER(C.c_float))
     return o
 
 
@@ -250,6 +261,56 @@ def mpm_fit(protocol: dict, dims, echoes, b1, options: dict, maps, stream=None):
                        trace, tl, _stream(stream)))
     report = {f[0]: getattr(rep, f[0]) for f in mpm_report._fields_}
     return report, np.array(trace[:], dtype=np.float64)
+
+
+def make_request(protocol: dict, dims, echoes, b1, options: dict, maps):
+    """An mpm_request for device tensors (the struct keeps raw pointers: keep
+    the tensors and the returned object alive while it is in use)."""
+    r = mpm_request()
+    r.protocol = make_protocol(protocol)
+    r.grid = make_grid(dims)
+    r.dtype = _dtype_code(echoes)
+    r.echoes = echoes.data_ptr()
+    r.b1 = None if b1 is None else _f32(b1, "b1").value
+    o = make_options(options)
+    r.options = o
+    r._options_keep = o
+    r.maps = _f32(maps, "maps").value
+    return r
+
+
+def mpm_fit_batch(fits, stream=None):
+    """Fit several JTV-MAP volumes together (batched launches).  fits: list of
+    (protocol, dims, echoes, b1, options, maps) with device tensors; maps are
+    updated in place.  Returns a list of (report dict, trace array)."""
+    lib = load()
+    n = len(fits)
+    reqs = (mpm_request * n)()
+    keep = []
+    for i, (protocol, dims, echoes, b1, options, maps) in enumerate(fits):
+        r = make_request(protocol, dims, echoes, b1, options, maps)
+        keep.append(r)
+        reqs[i] = r
+    tl = max(trace_len(f[4]) for f in fits)
+    traces = (C.c_double * (n * tl))()
+    reps = (mpm_report * n)()
+    _check(lib.mpm_fit_batch(n, reqs, reps, traces, tl, _stream(stream)))
+    out = []
+    for i in range(n):
+        rep = {f[0]: getattr(reps[i], f[0]) for f in mpm_report._fields_}
+        out.append((rep, np.array(traces[i * tl:(i + 1) * tl], dtype=np.float64)[:trace_len(fits[i][4])]))
+    return out
+
+
+def mpm_pack_echoes(src, dst, stream=None):
+    """Pack float32 echoes src [I][N] into dst (float16 / bfloat16 [I][N]) with
+    per-image offsets; returns the offsets (list of I floats) for the options'
+    "echo_offset"."""
+    lib = load()
+    I, N = int(src.shape[0]), int(src.shape[1])
+    off = (C.c_float * I)()
+    _check(lib.mpm_pack_echoes(I, N, _f32(src, "src"), _dtype_code(dst), _ptr(dst), off, _stream(stream)))
+    return [float(v) for v in off]
 
 
 def mpm_fit_noalloc(protocol: dict, dims, echoes, b1, options: dict, maps, stream=None):
@@ -400,6 +461,12 @@ def mpm_autotune(dims, reps: int = 5, stream=None) -> dict:
             "planes_per_run": list(r.planes_per_run[:n]), "ms": list(r.ms[:n])}
 
 
+def mpm_autotune_set(dims, cg_workgroups: int, column_workgroups: int = 0):
+    """Fix the CG sweep A and column-walk workgroup targets of MAP fits on a
+    grid of `dims` (this process); 0 keeps the built-in choice."""
+    _check(load().mpm_autotune_set(C.byref(make_grid(dims)), int(cg_workgroups), int(column_workgroups)))
+
+
 def mpm_autotune_clear():
     load().mpm_autotune_clear()
 
@@ -432,11 +499,11 @@ def mpm_profile_read():
 class MpmServer:
     """Thin wrapper of the mpm_server_* calls (continuous batching of fits)."""
 
-    def __init__(self, hbm_budget: int, max_active: int = 4, thread: bool = False):
+    def __init__(self, hbm_budget: int, max_active: int = 4, thread: bool = False, groups: bool = True):
         lib = load()
         h = C.c_void_p()
-        _check(lib.mpm_server_create(int(hbm_budget), int(max_active), MPM_SERVER_THREAD if thread else 0,
-                                     C.byref(h)))
+        flags = (MPM_SERVER_THREAD if thread else 0) | (0 if groups else MPM_SERVER_NO_GROUPS)
+        _check(lib.mpm_server_create(int(hbm_budget), int(max_active), flags, C.byref(h)))
         self._h = h
         self._keep = {}
 
@@ -449,11 +516,12 @@ class MpmServer:
         r.dtype = _dtype_code(echoes)
         r.echoes = echoes.data_ptr()
         r.b1 = None if b1 is None else b1.data_ptr()
-        r.options = make_options(options)
+        o = make_options(options)
+        r.options = o
         r.maps = maps.data_ptr()
         t = C.c_uint64()
         _check(load().mpm_server_submit(self._h, C.byref(r), C.byref(t)))
-        self._keep[t.value] = (echoes, b1, maps, options.get("b1_receive"))
+        self._keep[t.value] = (echoes, b1, maps, options.get("b1_receive"), o)
         return t.value
 
     def step(self) -> int:

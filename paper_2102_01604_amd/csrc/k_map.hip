@@ -12,6 +12,7 @@
 // index is remapped so that each of the 8 XCDs receives a contiguous run of
 // tiles (neighbouring tiles and planes share stencil halos in that XCD's L2).
 #include <cstdlib>
+#include <cstring>
 
 #include "mpm_proj.h"
 
@@ -100,12 +101,13 @@ __device__ __forceinline__ void lik_body(const Grid3 &g, const typename VoxelEch
                                          const float *__restrict__ Y, const float *__restrict__ w, float l0, float l1,
                                          float l2, float l3, int loading, const HessArrays &Hs,
                                          float4 *__restrict__ R, float4 *__restrict__ Z,
-                                         const MapCtl *__restrict__ ctl, double *__restrict__ partials)
+                                         const MapCtl *__restrict__ ctl, double *__restrict__ partials, int L,
+                                         int T_)
 {
     if (ctl->gn_stop) return;
     const int64_t N = g.N;
     const float lam[4] = {l0, l1, l2, l3};
-    const Col c = locate_col(g);
+    const Col c = locate_col(g, L, T_);
     const auto K = VoxelEchoes<T, CM, EM>::stage(P);
     double part[3] = {0.0, 0.0, 0.0};
     if (c.act) {
@@ -139,7 +141,7 @@ __device__ __forceinline__ void lik_body(const Grid3 &g, const typename VoxelEch
         part[1] = dot4(y0, acc);
         part[2] = dot4(r, zz);
     }
-    write_partials<3>(part, partials);
+    write_partials<3>(part, partials, L, T_);
 }
 
 #define LIK_PARAMS                                                                                           \
@@ -151,9 +153,15 @@ __device__ __forceinline__ void lik_body(const Grid3 &g, const typename VoxelEch
 #define LIK_ARGS g, P, X, b1, bm, Y, w, l0, l1, l2, l3, loading, Hs, R, Z, ctl, partials
 
 template <typename T, int CM, int EM>
-__global__ __launch_bounds__(BLOCK) void k_lik(LIK_PARAMS) { lik_body<false, T, CM, EM>(LIK_ARGS); }
+__global__ __launch_bounds__(BLOCK) void k_lik(LIK_PARAMS)
+{
+    lik_body<false, T, CM, EM>(LIK_ARGS, blockIdx.x, gridDim.x);
+}
 template <typename T, int CM, int EM>  // Proposed+ loading
-__global__ __launch_bounds__(BLOCK) void k_lik_plus(LIK_PARAMS) { lik_body<true, T, CM, EM>(LIK_ARGS); }
+__global__ __launch_bounds__(BLOCK) void k_lik_plus(LIK_PARAMS)
+{
+    lik_body<true, T, CM, EM>(LIK_ARGS, blockIdx.x, gridDim.x);
+}
 
 // ---------------------------------------------------------------------------
 // CG sweeps (paper Sec. 2.6, preconditioned CG on (H + L) delta = g + L y).
@@ -210,19 +218,18 @@ __device__ __forceinline__ void tall_neighbours(const Col &c, const Grid3 &g, in
     }
 }
 
-__global__ __launch_bounds__(TALL_THREADS) void k_cg_a(Grid3 g, int it, HessArrays Hs,
-                                                            const float *__restrict__ w, float l0, float l1, float l2,
-                                                            float l3, const float4 *__restrict__ Z,
-                                                            const float4 *__restrict__ Pold, float4 *__restrict__ Pnew,
-                                                            float4 *__restrict__ D, const MapCtl *__restrict__ ctl,
-                                                            double *__restrict__ partials)
+__device__ __forceinline__ void cg_a_body(const Grid3 &g, int it, const HessArrays &Hs, const float *__restrict__ w,
+                                          float l0, float l1, float l2, float l3, const float4 *__restrict__ Z,
+                                          const float4 *__restrict__ Pold, float4 *__restrict__ Pnew,
+                                          float4 *__restrict__ D, const MapCtl *__restrict__ ctl,
+                                          double *__restrict__ partials, int Lb, int Tb)
 {
     if (ctl->gn_stop || ctl->cg_stop) return;
     __shared__ TallLds L;
     const float lam[4] = {l0, l1, l2, l3};
     const float beta = it > 0 ? (float)ctl->beta : 0.0f;
     const float alpha_prev = (float)ctl->alpha_pend;
-    const Col c = locate_col(g);
+    const Col c = locate_col(g, Lb, Tb);
     const int tx = threadIdx.x & (TILE_X - 1), ty = threadIdx.x / TILE_X;
     auto getp = [&](int64_t m, float p[4], float po[4]) {
         vload(Z, m, p);
@@ -300,9 +307,19 @@ __global__ __launch_bounds__(TALL_THREADS) void k_cg_a(Grid3 g, int it, HessArra
         if (threadIdx.x == 0) {
             double t = 0.0;
             for (int i = 0; i < TALL_THREADS / 64; i++) t += lds_part[0][i];
-            partials[blockIdx.x] = t;
+            partials[Lb] = t;
         }
     }
+}
+
+__global__ __launch_bounds__(TALL_THREADS) void k_cg_a(Grid3 g, int it, HessArrays Hs,
+                                                            const float *__restrict__ w, float l0, float l1, float l2,
+                                                            float l3, const float4 *__restrict__ Z,
+                                                            const float4 *__restrict__ Pold, float4 *__restrict__ Pnew,
+                                                            float4 *__restrict__ D, const MapCtl *__restrict__ ctl,
+                                                            double *__restrict__ partials)
+{
+    cg_a_body(g, it, Hs, w, l0, l1, l2, l3, Z, Pold, Pnew, D, ctl, partials, blockIdx.x, gridDim.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -317,7 +334,7 @@ constexpr int CGB_Y = 16;
 constexpr int CGB_THREADS = TILE_X * CGB_Y;
 
 template <int THREADS>
-__device__ __forceinline__ void write_partial1(double v, double *__restrict__ partials)
+__device__ __forceinline__ void write_partial1(double v, double *__restrict__ partials, int L)
 {
     __shared__ double lds[THREADS / 64];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -327,19 +344,19 @@ __device__ __forceinline__ void write_partial1(double v, double *__restrict__ pa
     if (threadIdx.x == 0) {
         double t = 0.0;
         for (int i = 0; i < THREADS / 64; i++) t += lds[i];
-        partials[blockIdx.x] = t;
+        partials[L] = t;
     }
 }
 
-__global__ __launch_bounds__(CGB_THREADS) void k_cg_b(Grid3 g, HessArrays Hs, const float *__restrict__ w, float l0,
-                                                         float l1, float l2, float l3, const float4 *__restrict__ Pc,
-                                                         float4 *__restrict__ R, float4 *__restrict__ Z,
-                                                         const MapCtl *__restrict__ ctl, double *__restrict__ partials)
+__device__ __forceinline__ void cg_b_body(const Grid3 &g, const HessArrays &Hs, const float *__restrict__ w, float l0,
+                                          float l1, float l2, float l3, const float4 *__restrict__ Pc,
+                                          float4 *__restrict__ R, float4 *__restrict__ Z,
+                                          const MapCtl *__restrict__ ctl, double *__restrict__ partials, int L, int T)
 {
     if (ctl->gn_stop || ctl->cg_stop) return;
     const float lam[4] = {l0, l1, l2, l3};
     const float alpha = (float)ctl->alpha_pend;
-    const Col c = locate_col(g);
+    const Col c = locate_col(g, L, T);
     double part = 0.0;
     if (c.act) {
         const int64_t n = c.base + (int64_t)c.z0 * c.sxy;
@@ -366,7 +383,15 @@ __global__ __launch_bounds__(CGB_THREADS) void k_cg_b(Grid3 g, HessArrays Hs, co
         vstore_nt(Z, n, zz);
         part = dot4(r, zz);
     }
-    write_partial1<CGB_THREADS>(part, partials);
+    write_partial1<CGB_THREADS>(part, partials, L);
+}
+
+__global__ __launch_bounds__(CGB_THREADS) void k_cg_b(Grid3 g, HessArrays Hs, const float *__restrict__ w, float l0,
+                                                         float l1, float l2, float l3, const float4 *__restrict__ Pc,
+                                                         float4 *__restrict__ R, float4 *__restrict__ Z,
+                                                         const MapCtl *__restrict__ ctl, double *__restrict__ partials)
+{
+    cg_b_body(g, Hs, w, l0, l1, l2, l3, Pc, R, Z, ctl, partials, blockIdx.x, gridDim.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -375,20 +400,21 @@ __global__ __launch_bounds__(CGB_THREADS) void k_cg_b(Grid3 g, HessArrays Hs, co
 // F_w(y - t delta_f) = NLL(y - t delta_f) + (y.Ly - 2 t c1 + t^2 c2) / 2.
 // One voxel per thread.  Partials: NLL_0, c1, c2
 // ---------------------------------------------------------------------------
+#define ACCEPT_PARAMS                                                                                        \
+    Grid3 g, typename VoxelEchoes<T, CM, EM>::Proto P, const T *__restrict__ X, const float *__restrict__ b1, \
+        const float *__restrict__ bm, const float *__restrict__ Y, const float *__restrict__ w, float l0,       \
+        float l1, float l2, float l3, const float4 *__restrict__ D, const float4 *__restrict__ P0,              \
+        const float4 *__restrict__ P1, const MapCtl *__restrict__ ctl, double *__restrict__ partials
+#define ACCEPT_ARGS g, P, X, b1, bm, Y, w, l0, l1, l2, l3, D, P0, P1, ctl, partials
+
 template <typename T, int CM, int EM>
-__global__ __launch_bounds__(BLOCK) void k_accept(Grid3 g, typename VoxelEchoes<T, CM, EM>::Proto P,
-                                                  const T *__restrict__ X, const float *__restrict__ b1,
-                                                  const float *__restrict__ bm,
-                                                  const float *__restrict__ Y, const float *__restrict__ w, float l0,
-                                                  float l1, float l2, float l3, const float4 *__restrict__ D,
-                                                  const float4 *__restrict__ P0, const float4 *__restrict__ P1,
-                                                  const MapCtl *__restrict__ ctl, double *__restrict__ partials)
+__device__ __forceinline__ void accept_body(ACCEPT_PARAMS, int L, int T_)
 {
     if (ctl->gn_stop) return;
     const int64_t N = g.N;
     const float lam[4] = {l0, l1, l2, l3};
     const DeltaF getd{D, ctl->p_buf ? P1 : P0, (float)ctl->alpha_pend, ctl->delta_valid != 0};
-    const Col c = locate_col(g);
+    const Col c = locate_col(g, L, T_);
     const auto K = VoxelEchoes<T, CM, EM>::stage(P);
     double part[3] = {0.0, 0.0, 0.0};
     if (c.act) {
@@ -422,25 +448,32 @@ __global__ __launch_bounds__(BLOCK) void k_accept(Grid3 g, typename VoxelEchoes<
         part[1] = dot4(d0, ay);
         part[2] = dot4(d0, ad);
     }
-    write_partials<3>(part, partials);
+    write_partials<3>(part, partials, L, T_);
+}
+
+template <typename T, int CM, int EM>
+__global__ __launch_bounds__(BLOCK) void k_accept(ACCEPT_PARAMS)
+{
+    accept_body<T, CM, EM>(ACCEPT_ARGS, blockIdx.x, gridDim.x);
 }
 
 // accept, pass 2 (only after the full step was rejected): the NLL at the
 // halved steps y - 2^-h delta_f, h = 1 .. ntrial-1.  Column grid (returns at
 // once in the common case, so few workgroups).  Partial row h.
+#define ACCEPT2_PARAMS                                                                                       \
+    Grid3 g, typename VoxelEchoes<T, CM, EM>::Proto P, const T *__restrict__ X, const float *__restrict__ b1, \
+        const float *__restrict__ bm, const float *__restrict__ Y, const float4 *__restrict__ D,               \
+        const float4 *__restrict__ P0, const float4 *__restrict__ P1, int ntrial, const MapCtl *__restrict__ ctl, \
+        double *__restrict__ partials
+#define ACCEPT2_ARGS g, P, X, b1, bm, Y, D, P0, P1, ntrial, ctl, partials
+
 template <typename T, int CM, int EM>
-__global__ __launch_bounds__(BLOCK) void k_accept2(Grid3 g, typename VoxelEchoes<T, CM, EM>::Proto P,
-                                                   const T *__restrict__ X, const float *__restrict__ b1,
-                                                   const float *__restrict__ bm,
-                                                   const float *__restrict__ Y, const float4 *__restrict__ D,
-                                                   const float4 *__restrict__ P0, const float4 *__restrict__ P1,
-                                                   int ntrial, const MapCtl *__restrict__ ctl,
-                                                   double *__restrict__ partials)
+__device__ __forceinline__ void accept2_body(ACCEPT2_PARAMS, int L, int T_)
 {
     if (ctl->gn_stop || !ctl->accept_more) return;
     const int64_t N = g.N;
     const DeltaF getd{D, ctl->p_buf ? P1 : P0, (float)ctl->alpha_pend, ctl->delta_valid != 0};
-    const Col c = locate_col(g);
+    const Col c = locate_col(g, L, T_);
     const auto K = VoxelEchoes<T, CM, EM>::stage(P);
     double part[MAX_TRIALS];
 #pragma unroll
@@ -467,18 +500,24 @@ __global__ __launch_bounds__(BLOCK) void k_accept2(Grid3 g, typename VoxelEchoes
             }
         }
     }
-    write_partials<MAX_TRIALS>(part, partials);
+    write_partials<MAX_TRIALS>(part, partials, L, T_);
 }
 
-// y -= step * delta_f
-__global__ __launch_bounds__(BLOCK) void k_update(int64_t N, float *__restrict__ Y, const float4 *__restrict__ D,
-                                                  const float4 *__restrict__ P0, const float4 *__restrict__ P1,
-                                                  const MapCtl *__restrict__ ctl)
+template <typename T, int CM, int EM>
+__global__ __launch_bounds__(BLOCK) void k_accept2(ACCEPT2_PARAMS)
+{
+    accept2_body<T, CM, EM>(ACCEPT2_ARGS, blockIdx.x, gridDim.x);
+}
+
+// y -= step * delta_f (voxels L * BLOCK + thread)
+__device__ __forceinline__ void update_body(int64_t N, float *__restrict__ Y, const float4 *__restrict__ D,
+                                            const float4 *__restrict__ P0, const float4 *__restrict__ P1,
+                                            const MapCtl *__restrict__ ctl, int L)
 {
     if (ctl->gn_stop || ctl->step == 0.0) return;
     const float step = (float)ctl->step;
     const DeltaF getd{D, ctl->p_buf ? P1 : P0, (float)ctl->alpha_pend, ctl->delta_valid != 0};
-    int64_t n = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    int64_t n = (int64_t)L * BLOCK + threadIdx.x;
     if (n >= N) return;
     float df[4];
     getd(n, df);
@@ -486,17 +525,24 @@ __global__ __launch_bounds__(BLOCK) void k_update(int64_t N, float *__restrict__
     for (int k = 0; k < 4; k++) Y[k * N + n] -= step * df[k];
 }
 
+__global__ __launch_bounds__(BLOCK) void k_update(int64_t N, float *__restrict__ Y, const float4 *__restrict__ D,
+                                                  const float4 *__restrict__ P0, const float4 *__restrict__ P1,
+                                                  const MapCtl *__restrict__ ctl)
+{
+    update_body(N, Y, D, P0, P1, ctl, blockIdx.x);
+}
+
 // ---------------------------------------------------------------------------
 // JTV weights (paper Sec. 2.5, eq. bound): q_n = sum_k lam_k ||G_n y_k||^2,
 // w_n = (q_n + eps^2)^(-1/2).  Partial: sum_n sqrt(q_n + eps^2)
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(BLOCK) void k_weights(Grid3 g, const float *__restrict__ Y, float l0, float l1,
-                                                   float l2, float l3, float eps, int prior_on,
-                                                   float *__restrict__ w, double *__restrict__ partials)
+__device__ __forceinline__ void weights_body(const Grid3 &g, const float *__restrict__ Y, float l0, float l1,
+                                             float l2, float l3, float eps, int prior_on, float *__restrict__ w,
+                                             double *__restrict__ partials, int L, int T)
 {
     const int64_t N = g.N;
     const float lam[4] = {l0, l1, l2, l3};
-    const Col c = locate_col(g);
+    const Col c = locate_col(g, L, T);
     double part[1] = {0.0};
     if (c.act) {
         int64_t n = c.base + (int64_t)c.z0 * c.sxy;
@@ -535,7 +581,14 @@ __global__ __launch_bounds__(BLOCK) void k_weights(Grid3 g, const float *__restr
             }
         }
     }
-    write_partials<1>(part, partials);
+    write_partials<1>(part, partials, L, T);
+}
+
+__global__ __launch_bounds__(BLOCK) void k_weights(Grid3 g, const float *__restrict__ Y, float l0, float l1,
+                                                   float l2, float l3, float eps, int prior_on,
+                                                   float *__restrict__ w, double *__restrict__ partials)
+{
+    weights_body(g, Y, l0, l1, l2, l3, eps, prior_on, w, partials, blockIdx.x, gridDim.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -549,11 +602,11 @@ __device__ __forceinline__ void final_body(const Grid3 &g, const typename VoxelE
                                            const float *__restrict__ bm,
                                            const float *__restrict__ Y, const float *__restrict__ w, float l0,
                                            float l1, float l2, float l3, int loading, float *__restrict__ var,
-                                           float *__restrict__ mom, double *__restrict__ partials)
+                                           float *__restrict__ mom, double *__restrict__ partials, int L, int T_)
 {
     const int64_t N = g.N;
     const float lam[4] = {l0, l1, l2, l3};
-    const Col c = locate_col(g);
+    const Col c = locate_col(g, L, T_);
     const auto K = VoxelEchoes<T, CM, EM>::stage(P);
     double part[3] = {0.0, 0.0, 0.0};
     if (c.act) {
@@ -607,7 +660,7 @@ __device__ __forceinline__ void final_body(const Grid3 &g, const typename VoxelE
             }
         }
     }
-    write_partials<3>(part, partials);
+    write_partials<3>(part, partials, L, T_);
 }
 
 #define FINAL_PARAMS                                                                                         \
@@ -618,9 +671,15 @@ __device__ __forceinline__ void final_body(const Grid3 &g, const typename VoxelE
 #define FINAL_ARGS g, P, X, b1, bm, Y, w, l0, l1, l2, l3, loading, var, mom, partials
 
 template <typename T, int CM, int EM>
-__global__ __launch_bounds__(BLOCK) void k_final(FINAL_PARAMS) { final_body<false, T, CM, EM>(FINAL_ARGS); }
+__global__ __launch_bounds__(BLOCK) void k_final(FINAL_PARAMS)
+{
+    final_body<false, T, CM, EM>(FINAL_ARGS, blockIdx.x, gridDim.x);
+}
 template <typename T, int CM, int EM>  // Proposed+ loading
-__global__ __launch_bounds__(BLOCK) void k_final_plus(FINAL_PARAMS) { final_body<true, T, CM, EM>(FINAL_ARGS); }
+__global__ __launch_bounds__(BLOCK) void k_final_plus(FINAL_PARAMS)
+{
+    final_body<true, T, CM, EM>(FINAL_ARGS, blockIdx.x, gridDim.x);
+}
 
 // ---------------------------------------------------------------------------
 // one-workgroup finalisers: fixed-order reduction of the partials, then the
@@ -662,10 +721,10 @@ __device__ __forceinline__ void stop_on_gain(MapCtl &c, double F, double Fn, dou
     if (!(den > 0.0) || F - Fn < tol * den) c.tol_stop = 1;
 }
 
-__global__ __launch_bounds__(FIN_THREADS) void k_fin(int stage, int arg, int nblk,
-                                                     const double *__restrict__ partials, MapCtl *__restrict__ ctl,
-                                                     double *__restrict__ trace, double cg_stop_rel, int ntrial,
-                                                     int accept_off, ExtRows ext, double tol_gn, double tol_outer)
+__device__ __forceinline__ void fin_body(int stage, int arg, int nblk, const double *__restrict__ partials,
+                                         MapCtl *__restrict__ ctl, double *__restrict__ trace, double cg_stop_rel,
+                                         int ntrial, int accept_off, const ExtRows &ext, double tol_gn,
+                                         double tol_outer)
 {
     __shared__ double lds[FIN_THREADS / 64];
     const bool gated = (stage == FIN_W || stage == FIN_STATS) ? false : (ctl->gn_stop != 0);
@@ -723,7 +782,7 @@ __global__ __launch_bounds__(FIN_THREADS) void k_fin(int stage, int arg, int nbl
         c.c1 = s[1];
         c.c2 = s[2];
         const double F0 = s[0] + 0.5 * (c.yLy - 2.0 * c.c1 + c.c2);
-        if (accept_off || F0 <= c.F) {
+        if (accept_off || F0 <= c.F + ACCEPT_REL * fabs(c.F)) {
             stop_on_gain(c, c.F, F0, tol_gn);
             c.step = 1.0;
             c.nll_cur = s[0];
@@ -745,7 +804,7 @@ __global__ __launch_bounds__(FIN_THREADS) void k_fin(int stage, int arg, int nbl
         double Fc = 0.0;
         for (int h = 1; h < ntrial; h++) {
             const double Fh = s[h] + 0.5 * (c.yLy - 2.0 * t * c.c1 + t * t * c.c2);
-            if (Fh <= c.F) {
+            if (Fh <= c.F + ACCEPT_REL * fabs(c.F)) {
                 chosen = h;
                 Fc = Fh;
                 break;
@@ -799,6 +858,14 @@ __global__ __launch_bounds__(FIN_THREADS) void k_fin(int stage, int arg, int nbl
         c.nonfinite = s[2];
         break;
     }
+}
+
+__global__ __launch_bounds__(FIN_THREADS) void k_fin(int stage, int arg, int nblk,
+                                                     const double *__restrict__ partials, MapCtl *__restrict__ ctl,
+                                                     double *__restrict__ trace, double cg_stop_rel, int ntrial,
+                                                     int accept_off, ExtRows ext, double tol_gn, double tol_outer)
+{
+    fin_body(stage, arg, nblk, partials, ctl, trace, cg_stop_rel, ntrial, accept_off, ext, tol_gn, tol_outer);
 }
 
 // ---------------------------------------------------------------------------
@@ -950,6 +1017,338 @@ hipError_t launch_final_pushed(hipStream_t s, const MapArgs &a, const PushedProt
     hipLaunchKernelGGL((k_final<Pushed, 0, 0>), cols(a.gp), dim3(BLOCK), 0, s, a.gp, pp, (const Pushed *)nullptr,
                        (const float *)nullptr, (const float *)nullptr,
                        a.Y, a.w, l[0], l[1], l[2], l[3], a.loading, var, mom, a.partials);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// batched launches (several volumes per launch; see BatchTab)
+// ---------------------------------------------------------------------------
+template <typename Proto>
+struct VolDesc {
+    MapArgs m;
+    int prior_on;
+    Proto proto;
+};
+
+// Volume of workgroup b in a launch over grid kind k, and the workgroup's
+// index L and count T within that volume; -1 for the alignment padding.
+__device__ __forceinline__ int batch_volume(const BatchTab *__restrict__ tab, int k, int b, int &L, int &T)
+{
+    int lo = 0, hi = tab->n;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (tab->start[k][mid] <= b) lo = mid;
+        else hi = mid;
+    }
+    L = b - tab->start[k][lo];
+    T = tab->count[k][lo];
+    return L < T ? lo : -1;
+}
+
+__global__ void k_ctl_init_batch(const VolDesc<DevProto> *__restrict__ vols, size_t stride, int trace_len)
+{
+    const MapArgs &m = ((const VolDesc<DevProto> *)((const char *)vols + stride * blockIdx.x))->m;
+    if (threadIdx.x == 0) {
+        MapCtl c = {};
+        *m.ctl = c;
+    }
+    for (int i = threadIdx.x; i < trace_len; i += blockDim.x) m.trace[i] = __builtin_nan("");
+}
+
+// The descriptor of volume v: element v of an array of VolDesc<Proto>.
+template <typename Proto>
+__device__ __forceinline__ const VolDesc<Proto> &vol_at(const void *vols, int v)
+{
+    return ((const VolDesc<Proto> *)vols)[v];
+}
+
+template <bool PLUS, typename T, int CM, int EM>
+__global__ __launch_bounds__(BLOCK) void k_lik_batch(const BatchTab *__restrict__ tab, const void *__restrict__ vols)
+{
+    int L, Tn;
+    const int v = batch_volume(tab, BK_PLANE, blockIdx.x, L, Tn);
+    if (v < 0) return;
+    const auto &d = vol_at<typename VoxelEchoes<T, CM, EM>::Proto>(vols, v);
+    const MapArgs &m = d.m;
+    lik_body<PLUS, T, CM, EM>(m.gp, d.proto, (const T *)m.X, m.b1, m.bm, m.Y, m.w, m.lam[0], m.lam[1], m.lam[2],
+                              m.lam[3], m.loading, m.H, m.R, m.Z, m.ctl, m.partials, L, Tn);
+}
+
+__global__ __launch_bounds__(TALL_THREADS) void k_cg_a_batch(const BatchTab *__restrict__ tab,
+                                                                const void *__restrict__ vols, size_t stride, int it)
+{
+    int L, Tn;
+    const int v = batch_volume(tab, BK_TALL, blockIdx.x, L, Tn);
+    if (v < 0) return;
+    const MapArgs &m = ((const VolDesc<DevProto> *)((const char *)vols + stride * v))->m;
+    const float4 *pold = (it & 1) ? m.P0 : m.P1;
+    float4 *pnew = (it & 1) ? m.P1 : m.P0;
+    cg_a_body(m.gt, it, m.H, m.w, m.lam[0], m.lam[1], m.lam[2], m.lam[3], m.Z, pold, pnew, m.D, m.ctl, m.partials, L,
+              Tn);
+}
+
+__global__ __launch_bounds__(CGB_THREADS) void k_cg_b_batch(const BatchTab *__restrict__ tab,
+                                                               const void *__restrict__ vols, size_t stride, int it)
+{
+    int L, Tn;
+    const int v = batch_volume(tab, BK_CGB, blockIdx.x, L, Tn);
+    if (v < 0) return;
+    const MapArgs &m = ((const VolDesc<DevProto> *)((const char *)vols + stride * v))->m;
+    const float4 *pc = (it & 1) ? m.P1 : m.P0;
+    cg_b_body(m.gv, m.H, m.w, m.lam[0], m.lam[1], m.lam[2], m.lam[3], pc, m.R, m.Z, m.ctl, m.partials, L, Tn);
+}
+
+template <typename T, int CM, int EM>
+__global__ __launch_bounds__(BLOCK) void k_accept_batch(const BatchTab *__restrict__ tab,
+                                                        const void *__restrict__ vols)
+{
+    int L, Tn;
+    const int v = batch_volume(tab, BK_PLANE, blockIdx.x, L, Tn);
+    if (v < 0) return;
+    const auto &d = vol_at<typename VoxelEchoes<T, CM, EM>::Proto>(vols, v);
+    const MapArgs &m = d.m;
+    accept_body<T, CM, EM>(m.gp, d.proto, (const T *)m.X, m.b1, m.bm, m.Y, m.w, m.lam[0], m.lam[1], m.lam[2],
+                           m.lam[3], m.D, m.P0, m.P1, m.ctl, m.partials, L, Tn);
+}
+
+template <typename T, int CM, int EM>
+__global__ __launch_bounds__(BLOCK) void k_accept2_batch(const BatchTab *__restrict__ tab,
+                                                         const void *__restrict__ vols, int ntrial)
+{
+    int L, Tn;
+    const int v = batch_volume(tab, BK_COL, blockIdx.x, L, Tn);
+    if (v < 0) return;
+    const auto &d = vol_at<typename VoxelEchoes<T, CM, EM>::Proto>(vols, v);
+    const MapArgs &m = d.m;
+    accept2_body<T, CM, EM>(m.g, d.proto, (const T *)m.X, m.b1, m.bm, m.Y, m.D, m.P0, m.P1, ntrial, m.ctl,
+                            m.partials, L, Tn);
+}
+
+__global__ __launch_bounds__(BLOCK) void k_update_batch(const BatchTab *__restrict__ tab,
+                                                        const void *__restrict__ vols, size_t stride)
+{
+    int L, Tn;
+    const int v = batch_volume(tab, BK_UPD, blockIdx.x, L, Tn);
+    if (v < 0) return;
+    const MapArgs &m = ((const VolDesc<DevProto> *)((const char *)vols + stride * v))->m;
+    update_body(m.g.N, m.Y, m.D, m.P0, m.P1, m.ctl, L);
+}
+
+__global__ __launch_bounds__(BLOCK) void k_weights_batch(const BatchTab *__restrict__ tab,
+                                                         const void *__restrict__ vols, size_t stride)
+{
+    int L, Tn;
+    const int v = batch_volume(tab, BK_COL, blockIdx.x, L, Tn);
+    if (v < 0) return;
+    const VolDesc<DevProto> &d = *(const VolDesc<DevProto> *)((const char *)vols + stride * v);
+    const MapArgs &m = d.m;
+    weights_body(m.g, m.Y, m.lam[0], m.lam[1], m.lam[2], m.lam[3], m.eps, d.prior_on, m.w, m.partials, L, Tn);
+}
+
+template <bool PLUS, typename T, int CM, int EM>
+__global__ __launch_bounds__(BLOCK) void k_final_batch(const BatchTab *__restrict__ tab,
+                                                       const void *__restrict__ vols)
+{
+    int L, Tn;
+    const int v = batch_volume(tab, BK_PLANE, blockIdx.x, L, Tn);
+    if (v < 0) return;
+    const auto &d = vol_at<typename VoxelEchoes<T, CM, EM>::Proto>(vols, v);
+    const MapArgs &m = d.m;
+    final_body<PLUS, T, CM, EM>(m.gp, d.proto, (const T *)m.X, m.b1, m.bm, m.Y, m.w, m.lam[0], m.lam[1], m.lam[2],
+                                m.lam[3], m.loading, nullptr, nullptr, m.partials, L, Tn);
+}
+
+// one workgroup per volume
+__global__ __launch_bounds__(FIN_THREADS) void k_fin_batch(const BatchTab *__restrict__ tab,
+                                                           const void *__restrict__ vols, size_t stride, int stage,
+                                                           int arg, int kind, double cg_stop_rel, int ntrial,
+                                                           int accept_off, double tol_gn, double tol_outer)
+{
+    const int v = blockIdx.x;
+    const MapArgs &m = ((const VolDesc<DevProto> *)((const char *)vols + stride * v))->m;
+    const int nblk = kind >= 0 ? tab->count[kind][v] : 0;
+    fin_body(stage, arg, nblk, m.partials, m.ctl, m.trace, cg_stop_rel, ntrial, accept_off, ExtRows(), tol_gn,
+             tol_outer);
+}
+
+// --- host side of the batched launches ---
+template <typename T, int CM, int EM>
+static size_t desc_bytes_of()
+{
+    return sizeof(VolDesc<typename VoxelEchoes<T, CM, EM>::Proto>);
+}
+
+template <typename T, int CM, int EM>
+static void fill_desc_of(void *host, int v, const MapArgs &m, int prior_on)
+{
+    using Proto = typename VoxelEchoes<T, CM, EM>::Proto;
+    VolDesc<Proto> *d = (VolDesc<Proto> *)host + v;
+    memset((void *)d, 0, sizeof(*d));
+    d->m = m;
+    d->prior_on = prior_on;
+    d->proto = ProtoArg<T, CM, EM>::make(m.P, (const T *)m.X, m.g.N);
+}
+
+#define BATCH_SHAPED(FN, T, ...)                                  \
+    do {                                                          \
+        switch (shape) {                                          \
+        case 1: FN<T, 4, 8>(__VA_ARGS__); break;                  \
+        case 2: FN<T, 4, 16>(__VA_ARGS__); break;                 \
+        case 3: FN<T, 8, 8>(__VA_ARGS__); break;                  \
+        default: FN<T, 0, 0>(__VA_ARGS__); break;                 \
+        }                                                         \
+    } while (0)
+#define BATCH_TYPED(FN, ...)                                      \
+    do {                                                          \
+        if (dtype == DT_F32) BATCH_SHAPED(FN, float, __VA_ARGS__); \
+        else if (dtype == DT_F16) BATCH_SHAPED(FN, F16, __VA_ARGS__); \
+        else BATCH_SHAPED(FN, BF16, __VA_ARGS__);                 \
+    } while (0)
+
+template <typename T, int CM, int EM>
+static void desc_bytes_into(size_t *out)
+{
+    *out = desc_bytes_of<T, CM, EM>();
+}
+
+size_t batch_desc_bytes(int dtype, int shape)
+{
+    size_t b = 0;
+    BATCH_TYPED(desc_bytes_into, &b);
+    return b;
+}
+
+void fill_batch_desc(void *host, int v, const MapArgs &m, int prior_on, int dtype, int shape)
+{
+    BATCH_TYPED(fill_desc_of, host, v, m, prior_on);
+}
+
+void fill_batch_tab(BatchTab &t, const MapArgs *m, int n, int total[BK_N])
+{
+    memset(&t, 0, sizeof(t));
+    t.n = n;
+    for (int k = 0; k < BK_N; k++) {
+        int at = 0;
+        for (int v = 0; v < n; v++) {
+            const MapArgs &a = m[v];
+            const int c = k == BK_PLANE ? grid_blocks(a.gp)
+                          : k == BK_TALL ? grid_blocks(a.gt)
+                          : k == BK_CGB  ? grid_blocks(a.gv)
+                          : k == BK_COL  ? grid_blocks(a.g)
+                                         : (int)((a.g.N + BLOCK - 1) / BLOCK);
+            t.start[k][v] = at;
+            t.count[k][v] = c;
+            at += (c + 7) & ~7;  // the next volume starts on an XCD boundary
+        }
+        t.start[k][n] = at;
+        total[k] = at;
+    }
+}
+
+hipError_t launch_ctl_init_batch(hipStream_t s, const BatchLaunch &b, int trace_len)
+{
+    const size_t stride = batch_desc_bytes(b.dtype, b.shape);
+    hipLaunchKernelGGL(k_ctl_init_batch, dim3(b.n), dim3(BLOCK), 0, s, (const VolDesc<DevProto> *)b.vols, stride,
+                       trace_len);
+    return hipGetLastError();
+}
+
+template <typename T, int CM, int EM>
+static void lik_batch_of(hipStream_t s, const BatchLaunch &b)
+{
+    if (b.loading == 2)
+        hipLaunchKernelGGL((k_lik_batch<true, T, CM, EM>), dim3(b.total[BK_PLANE]), dim3(BLOCK), 0, s, b.tab, b.vols);
+    else
+        hipLaunchKernelGGL((k_lik_batch<false, T, CM, EM>), dim3(b.total[BK_PLANE]), dim3(BLOCK), 0, s, b.tab,
+                           b.vols);
+}
+
+hipError_t launch_lik_batch(hipStream_t s, const BatchLaunch &b)
+{
+    const int dtype = b.dtype, shape = b.shape;
+    BATCH_TYPED(lik_batch_of, s, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_a_batch(hipStream_t s, const BatchLaunch &b, int it)
+{
+    hipLaunchKernelGGL(k_cg_a_batch, dim3(b.total[BK_TALL]), dim3(TALL_THREADS), 0, s, b.tab, b.vols,
+                       batch_desc_bytes(b.dtype, b.shape), it);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_b_batch(hipStream_t s, const BatchLaunch &b, int it)
+{
+    hipLaunchKernelGGL(k_cg_b_batch, dim3(b.total[BK_CGB]), dim3(CGB_THREADS), 0, s, b.tab, b.vols,
+                       batch_desc_bytes(b.dtype, b.shape), it);
+    return hipGetLastError();
+}
+
+template <typename T, int CM, int EM>
+static void accept_batch_of(hipStream_t s, const BatchLaunch &b)
+{
+    hipLaunchKernelGGL((k_accept_batch<T, CM, EM>), dim3(b.total[BK_PLANE]), dim3(BLOCK), 0, s, b.tab, b.vols);
+}
+
+hipError_t launch_accept_batch(hipStream_t s, const BatchLaunch &b)
+{
+    const int dtype = b.dtype, shape = b.shape;
+    BATCH_TYPED(accept_batch_of, s, b);
+    return hipGetLastError();
+}
+
+template <typename T, int CM, int EM>
+static void accept2_batch_of(hipStream_t s, const BatchLaunch &b, int ntrial)
+{
+    hipLaunchKernelGGL((k_accept2_batch<T, CM, EM>), dim3(b.total[BK_COL]), dim3(BLOCK), 0, s, b.tab, b.vols,
+                       ntrial);
+}
+
+hipError_t launch_accept2_batch(hipStream_t s, const BatchLaunch &b, int ntrial)
+{
+    const int dtype = b.dtype, shape = b.shape;
+    BATCH_TYPED(accept2_batch_of, s, b, ntrial);
+    return hipGetLastError();
+}
+
+hipError_t launch_update_batch(hipStream_t s, const BatchLaunch &b)
+{
+    hipLaunchKernelGGL(k_update_batch, dim3(b.total[BK_UPD]), dim3(BLOCK), 0, s, b.tab, b.vols,
+                       batch_desc_bytes(b.dtype, b.shape));
+    return hipGetLastError();
+}
+
+hipError_t launch_weights_batch(hipStream_t s, const BatchLaunch &b)
+{
+    hipLaunchKernelGGL(k_weights_batch, dim3(b.total[BK_COL]), dim3(BLOCK), 0, s, b.tab, b.vols,
+                       batch_desc_bytes(b.dtype, b.shape));
+    return hipGetLastError();
+}
+
+template <typename T, int CM, int EM>
+static void final_batch_of(hipStream_t s, const BatchLaunch &b)
+{
+    if (b.loading == 2)
+        hipLaunchKernelGGL((k_final_batch<true, T, CM, EM>), dim3(b.total[BK_PLANE]), dim3(BLOCK), 0, s, b.tab,
+                           b.vols);
+    else
+        hipLaunchKernelGGL((k_final_batch<false, T, CM, EM>), dim3(b.total[BK_PLANE]), dim3(BLOCK), 0, s, b.tab,
+                           b.vols);
+}
+
+hipError_t launch_final_batch(hipStream_t s, const BatchLaunch &b)
+{
+    const int dtype = b.dtype, shape = b.shape;
+    BATCH_TYPED(final_batch_of, s, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_fin_batch(hipStream_t s, const BatchLaunch &b, int stage, int arg, int kind, double cg_stop_rel,
+                            int ntrial, int accept_off, double tol_gn, double tol_outer)
+{
+    hipLaunchKernelGGL(k_fin_batch, dim3(b.n), dim3(FIN_THREADS), 0, s, b.tab, b.vols,
+                       batch_desc_bytes(b.dtype, b.shape), stage, arg, kind, cg_stop_rel, ntrial, accept_off, tol_gn,
+                       tol_outer);
     return hipGetLastError();
 }
 

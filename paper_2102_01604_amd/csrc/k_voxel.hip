@@ -2,6 +2,7 @@
 // the maximum-likelihood fit (SPGR-ML) and a fixed-order row reduction.
 #include <algorithm>
 
+#include "mpm_stream.h"
 #include "mpm_voxelwise.h"
 
 namespace mpm {
@@ -125,16 +126,16 @@ hipError_t launch_simulate_pv(const LaunchCtx &c, const DevProto &P, const PVArr
 }
 
 // ---------------------------------------------------------------------------
-// per-image sums (for the default initialisation): grid (nblk, 2I + 1).
-// Row i < I: sum of the finite values of image i; row I + i: their count;
-// row 2I: sum of b1.  Non-finite echoes are missing observations.
+// per-image sums (for the default initialisation) in one streaming pass over
+// the echoes: grid (nblk, I + 1).  Workgroup row i < I reads image i once and
+// writes partial row i (sum of its finite values) and row I + i (their count);
+// row I reads b1 and writes row 2I (its sum).  Non-finite echoes are missing
+// observations.  Every partial is an FP64 sum in a fixed order.
 // ---------------------------------------------------------------------------
-constexpr int SUM_ITEMS = 16;  // voxels per thread
-
 int echo_sums_blocks(int64_t N)
 {
-    int64_t per = (int64_t)BLOCK * SUM_ITEMS;
-    return (int)((N + per - 1) / per);
+    const int64_t per = (int64_t)BLOCK * 64;  // values per workgroup and pass
+    return (int)std::min<int64_t>(std::max<int64_t>((N + per - 1) / per, 1), 128);
 }
 
 template <typename T>
@@ -142,28 +143,37 @@ __global__ __launch_bounds__(BLOCK) void k_echo_sums(int I, const T *__restrict_
                                                      const float *__restrict__ b1, int64_t N,
                                                      double *__restrict__ partials)
 {
-    __shared__ double lds[1][NWAVE];
-    int row = blockIdx.y;
-    int64_t base = (int64_t)blockIdx.x * BLOCK * SUM_ITEMS + threadIdx.x;
-    double v[1] = {0.0};
-    for (int j = 0; j < SUM_ITEMS; j++) {
-        int64_t n = base + (int64_t)j * BLOCK;
-        if (n >= N) break;
-        if (row < 2 * I) {
-            const float x = load_echo(X + (int64_t)(row < I ? row : row - I) * N + n);
-            if (fabsf(x) < INFINITY) v[0] += row < I ? (double)x : 1.0;
+    __shared__ double lds[2][NWAVE];
+    const int row = blockIdx.y;
+    double v[2] = {0.0, 0.0};
+    if (row < I) {
+        for_each_value(X + (int64_t)row * N, N, [&](float x) {
+            if (fabsf(x) < INFINITY) {
+                v[0] += (double)x;
+                v[1] += 1.0;
+            }
+        });
+    } else if (b1) {
+        for_each_value(b1, N, [&](float x) { v[0] += (double)x; });
+    } else if (blockIdx.x == 0 && threadIdx.x == 0) {
+        v[0] = (double)N;  // b1 = 1 everywhere
+    }
+    block_sum<2>(v, lds);
+    if (threadIdx.x == 0) {
+        const int64_t nb = gridDim.x;
+        if (row < I) {
+            partials[(int64_t)row * nb + blockIdx.x] = v[0];
+            partials[(int64_t)(I + row) * nb + blockIdx.x] = v[1];
         } else {
-            v[0] += b1 ? (double)b1[n] : 1.0;
+            partials[(int64_t)2 * I * nb + blockIdx.x] = v[0];
         }
     }
-    block_sum<1>(v, lds);
-    if (threadIdx.x == 0) partials[(int64_t)row * gridDim.x + blockIdx.x] = v[0];
 }
 
 hipError_t launch_echo_sums(const LaunchCtx &c, const DevProto &P, int dtype, const void *X,
                             const float *b1, int64_t N, double *partials, int nblk)
 {
-    dim3 g(nblk, 2 * P.I + 1);
+    dim3 g(nblk, P.I + 1);
     if (dtype == DT_F32)
         hipLaunchKernelGGL(k_echo_sums<float>, g, dim3(BLOCK), 0, c.stream, P.I, (const float *)X, b1, N,
                            partials);
@@ -173,6 +183,40 @@ hipError_t launch_echo_sums(const LaunchCtx &c, const DevProto &P, int dtype, co
     else
         hipLaunchKernelGGL(k_echo_sums<BF16>, g, dim3(BLOCK), 0, c.stream, P.I, (const BF16 *)X, b1, N,
                            partials);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// reduced-precision storage with per-image offsets: dst = round(src - off_i);
+// counts finite inputs whose stored difference is not finite (overflow)
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_pack_echoes(const float *__restrict__ src, T *__restrict__ dst, int64_t N,
+                                                       EchoOffsets off, unsigned int *__restrict__ overflow)
+{
+    const int i = blockIdx.y;
+    const float o = off.v[i];
+    const float *s = src + (int64_t)i * N;
+    T *d = dst + (int64_t)i * N;
+    unsigned int bad = 0;
+    for (int64_t n = (int64_t)blockIdx.x * BLOCK + threadIdx.x; n < N; n += (int64_t)gridDim.x * BLOCK) {
+        const float x = s[n];
+        store_echo(d + n, x - o);
+        const float back = load_echo(d + n);
+        bad += (fabsf(x) < INFINITY && !(fabsf(back) < INFINITY)) ? 1u : 0u;
+    }
+    if (bad) atomicAdd(overflow, bad);
+}
+
+hipError_t launch_pack_echoes(const LaunchCtx &c, int I, int64_t N, const float *src, int dtype, void *dst,
+                              const EchoOffsets &off, unsigned int *overflow)
+{
+    const int64_t want = (N + BLOCK - 1) / BLOCK;
+    dim3 g((unsigned)(want < 1024 ? want : 1024), (unsigned)I);
+    if (dtype == DT_F16)
+        hipLaunchKernelGGL(k_pack_echoes<F16>, g, dim3(BLOCK), 0, c.stream, src, (F16 *)dst, N, off, overflow);
+    else
+        hipLaunchKernelGGL(k_pack_echoes<BF16>, g, dim3(BLOCK), 0, c.stream, src, (BF16 *)dst, N, off, overflow);
     return hipGetLastError();
 }
 

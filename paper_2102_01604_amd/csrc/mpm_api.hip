@@ -201,6 +201,7 @@ DevProto sub_proto(const DevProto &P, int c)
     for (int e = 0; e < ne; e++) {
         q.te[e] = P.te[i0 + e];
         q.wgt[e] = P.wgt[i0 + e];
+        q.off[e] = P.off[i0 + e];
     }
     return q;
 }
@@ -212,7 +213,17 @@ bool has_mt(const mpm_protocol *p)
     return false;
 }
 
-DevProto to_dev(const mpm_protocol *p)
+mpm_status check_echo_offset(const mpm_protocol *p, int dtype, const float *echo_offset)
+{
+    if (!echo_offset) return MPM_OK;
+    if (dtype == MPM_F32) return fail(MPM_ERR_INVALID_ARG, "echo_offset applies to MPM_F16 / MPM_BF16 echoes only");
+    const int I = n_images(p);
+    for (int i = 0; i < I; i++)
+        if (!std::isfinite(echo_offset[i])) return fail(MPM_ERR_INVALID_ARG, "echo_offset[%d] is not finite", i);
+    return MPM_OK;
+}
+
+DevProto to_dev(const mpm_protocol *p, const float *echo_offset)
 {
     DevProto d;
     memset(&d, 0, sizeof(d));
@@ -230,6 +241,7 @@ DevProto to_dev(const mpm_protocol *p)
     for (int k = 0; k < i; k++) {
         d.te[k] = (float)p->te_s[k];
         d.wgt[k] = (float)(1.0 / (p->sigma[k] * p->sigma[k]));
+        d.off[k] = echo_offset ? echo_offset[k] : 0.0f;
     }
     return d;
 }
@@ -344,6 +356,7 @@ mpm_status check_fit_args(const mpm_protocol *protocol, const mpm_grid *grid, in
     if (opt->mode == MPM_MAP_JTV &&
         (opt->start_outer < 0 || (opt->n_outer > 0 ? opt->start_outer >= opt->n_outer : opt->start_outer != 0)))
         return fail(MPM_ERR_INVALID_ARG, "start_outer must be in [0, n_outer) (0 when n_outer = 0)");
+    if ((st = check_echo_offset(protocol, dtype, opt->echo_offset))) return st;
     if (opt->start_outer > 0 && opt->tol_outer > 0.0)
         return fail(MPM_ERR_UNSUPPORTED, "tol_outer measures gains from the end of outer loop 0: "
                                          "it cannot be used with start_outer > 0");
@@ -414,7 +427,7 @@ mpm_status image_means(Workspace &ws, Prof &prof, const DevProto &P, int dtype, 
     if (e == hipSuccess) e = hipStreamSynchronize(ws.stream);
     if (e != hipSuccess) return fail(MPM_ERR_DEVICE, "image means: %s", hipGetErrorString(e));
     mean.resize(P.I);
-    for (int i = 0; i < P.I; i++) mean[i] = host[P.I + i] > 0.0 ? host[i] / host[P.I + i] : NAN;
+    for (int i = 0; i < P.I; i++) mean[i] = host[P.I + i] > 0.0 ? P.off[i] + host[i] / host[P.I + i] : NAN;
     b1m = host[2 * P.I] / (double)N;
     return MPM_OK;
 }
@@ -468,6 +481,53 @@ mpm_status mpm_simulate(const mpm_protocol *protocol, const mpm_grid *grid, cons
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     prof.collect();
     if (e != hipSuccess) return fail(MPM_ERR_DEVICE, "simulate: %s", hipGetErrorString(e));
+    return MPM_OK;
+}
+
+mpm_status mpm_pack_echoes(int32_t n_images, int64_t n_voxels, const float *src, mpm_dtype dtype, void *dst,
+                           float *offsets, void *stream)
+{
+    clear_error();
+    if (n_images < 1 || n_images > MPM_MAX_IMAGES)
+        return fail(MPM_ERR_INVALID_ARG, "n_images=%d outside [1, %d]", n_images, MPM_MAX_IMAGES);
+    if (n_voxels < 1 || n_voxels > ((int64_t)1 << 30) - 1)
+        return fail(MPM_ERR_INVALID_ARG, "n_voxels=%lld outside [1, 2^30)", (long long)n_voxels);
+    if (dtype != MPM_F16 && dtype != MPM_BF16) return fail(MPM_ERR_INVALID_ARG, "dtype must be MPM_F16 or MPM_BF16");
+    if (!src || !dst || !offsets) return fail(MPM_ERR_INVALID_ARG, "src, dst and offsets must be non-NULL");
+    const int64_t N = n_voxels;
+    const char *s0 = (const char *)src, *s1 = s0 + (size_t)n_images * N * 4;
+    const char *d0 = (const char *)dst, *d1 = d0 + (size_t)n_images * N * 2;
+    if (d0 < s1 && s0 < d1) return fail(MPM_ERR_INVALID_ARG, "dst overlaps src");
+    hipStream_t s = (hipStream_t)stream;
+    DevProto P;
+    memset(&P, 0, sizeof(P));
+    P.I = n_images;
+    unsigned int bad = 0;
+    {
+        Workspace ws(s);
+        Prof prof(s);
+        std::vector<double> mean;
+        double unused;
+        mpm_status st = image_means(ws, prof, P, MPM_F32, src, nullptr, N, mean, unused);
+        if (st) return st;
+        EchoOffsets off;
+        memset(&off, 0, sizeof(off));
+        for (int i = 0; i < n_images; i++) off.v[i] = std::isfinite(mean[i]) ? (float)mean[i] : 0.0f;
+        unsigned int *cnt = nullptr;
+        if (ws.alloc((void **)&cnt, sizeof(unsigned int)) != hipSuccess)
+            return fail(MPM_ERR_OUT_OF_MEMORY, "pack: workspace allocation failed");
+        LaunchCtx c{s};
+        hipError_t e = hipMemsetAsync(cnt, 0, sizeof(unsigned int), s);
+        if (e == hipSuccess)
+            e = prof.launch("pack_echoes", (double)n_images * N * 6.0,
+                            [&] { return launch_pack_echoes(c, n_images, N, src, dtype, dst, off, cnt); });
+        if (e == hipSuccess) e = hipMemcpyAsync(&bad, cnt, sizeof(bad), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        prof.collect();
+        if (e != hipSuccess) return fail(MPM_ERR_DEVICE, "pack: %s", hipGetErrorString(e));
+        for (int i = 0; i < n_images; i++) offsets[i] = off.v[i];
+    }
+    if (bad) return fail(MPM_ERR_INVALID_ARG, "pack: %u finite values overflow the storage type", bad);
     return MPM_OK;
 }
 
@@ -535,7 +595,8 @@ mpm_status mpm_fit(const mpm_protocol *protocol, const mpm_grid *grid, mpm_dtype
     for (int i = 0; i < trace_len; i++) trace[i] = NAN;
 
     hipStream_t s = (hipStream_t)stream;
-    FitArgs a{protocol, to_dev(protocol), dtype, echoes, b1, opt, maps, N, grid->nx, grid->ny, grid->nz, s};
+    FitArgs a{protocol, to_dev(protocol, opt->echo_offset), dtype, echoes, b1, opt, maps, N,
+              grid->nx, grid->ny, grid->nz, s};
     Workspace ws(s);
     return run_fit(a, ws, report, trace, trace_len);
 }

@@ -19,7 +19,10 @@ mpm_status check_protocol(const mpm_protocol *p);
 mpm_status check_grid(const mpm_grid *g, int64_t *N);
 mpm_status check_dtype(int dtype);
 bool has_mt(const mpm_protocol *p);
-DevProto to_dev(const mpm_protocol *p);
+// Device form of a protocol; echo_offset: host float [I] or NULL (zeros).
+DevProto to_dev(const mpm_protocol *p, const float *echo_offset = nullptr);
+// echo_offset of the options: only with reduced-precision storage, finite.
+mpm_status check_echo_offset(const mpm_protocol *p, int dtype, const float *echo_offset);
 size_t dtype_size(int dtype);
 mpm_status default_init_from_means(const mpm_protocol *p, const double *mean, double b1_mean, float y0[4]);
 // Spatial projection: validation of the spaces, the device protocol restricted
@@ -91,6 +94,20 @@ struct FitJob {
 };
 std::unique_ptr<FitJob> make_ml_job(const FitArgs &a, Workspace &ws, Prof &prof, mpm_status *st);
 std::unique_ptr<FitJob> make_map_job(const FitArgs &a, Workspace &ws, Prof &prof, mpm_status *st);
+
+// Several JTV-MAP fits of one schedule enqueued together, every kernel launch
+// serving all of them (batched launches); collect_item reads fit i's results
+// once all enqueued work has completed.
+struct BatchJob {
+    virtual ~BatchJob() {}
+    virtual mpm_status enqueue_next(bool *more) = 0;
+    virtual mpm_status collect_item(int i, mpm_report &rep, double *trace, int trace_len) = 0;
+};
+std::unique_ptr<BatchJob> make_batch_job(const std::vector<FitArgs> &a, Workspace &ws, Prof &prof,
+                                         mpm_status *st);
+// Whether MAP fit b can share batched launches with fit a (same schedule,
+// echo storage and register shape; no spatial projection).
+bool batch_compatible(const FitArgs &a, const FitArgs &b);
 
 // Runs a whole fit on a.stream with workspace ws and blocks until it is done.
 mpm_status run_fit(const FitArgs &a, Workspace &ws, mpm_report *report, double *trace, int trace_len);

@@ -30,6 +30,7 @@ struct DevProto {
     int mt[MAXC];
     float te[MAXI];
     float wgt[MAXI];          // 1 / sigma_i^2
+    float off[MAXI];          // offset added to each stored value (reduced-precision storage)
 };
 
 // ---------------------------------------------------------------------------
@@ -52,6 +53,19 @@ __device__ __forceinline__ float load_echo(const BF16 *p)
     float f;
     __builtin_memcpy(&f, &b, 4);
     return f;
+}
+
+// A stored value plus its image's offset (reduced-precision storage only: FP32
+// echoes carry no offsets, so their path has no extra instruction).
+template <typename T>
+__device__ __forceinline__ float decode_echo(const T *p, float off)
+{
+    return load_echo(p) + off;
+}
+template <>
+__device__ __forceinline__ float decode_echo(const float *p, float)
+{
+    return load_echo(p);
 }
 
 __device__ __forceinline__ void store_echo(float *p, float v) { *p = v; }
@@ -276,6 +290,7 @@ struct ShapedProto {
     float tr[CM], flip[CM];
     int mt[CM];
     float te[CM][EM], te2[CM][EM], wgt[CM][EM];
+    float off[CM][EM];        // offset added to each stored value (FP16 / BF16 storage)
 };
 
 // Host: the slot table of protocol P for echoes X [I][N] (N < 2^30).  Needs
@@ -299,6 +314,7 @@ inline ShapedProto<T, CM, EM> make_shaped(const DevProto &P, const T *X, int64_t
             s.te[c][e] = P.te[i];
             s.te2[c][e] = P.te[i] * P.te[i];
             s.wgt[c][e] = on && e < ne ? P.wgt[i] : 0.0f;
+            s.off[c][e] = P.off[i];
         }
     }
     return s;
@@ -346,7 +362,7 @@ struct VoxelEchoes {
 #pragma unroll
                 for (int e = 0; e < EM; e++) {
                     const uint64_t k = (uint64_t)(e < P.last[c] ? e : P.last[c]);  // slots past the last echo
-                    x[c][e] = load_echo((const T *)(img0 + k * P.stride));
+                    x[c][e] = decode_echo((const T *)(img0 + k * P.stride), P.off[c][e]);
                 }
             }
         }
@@ -444,8 +460,8 @@ struct VoxelEchoes<T, 0, 0> {
             EchoAcc acc;
             for (int i = P.first[c]; i < P.first[c + 1]; i++) {
                 const float te = P.te[i];
-                acc.add(K.s0 * __builtin_amdgcn_exp2f(k2 * te), load_echo(X + (int64_t)i * N + n), te, te * te,
-                        P.wgt[i], p.r2);
+                acc.add(K.s0 * __builtin_amdgcn_exp2f(k2 * te), decode_echo(X + (int64_t)i * N + n, P.off[i]), te,
+                        te * te, P.wgt[i], p.r2);
             }
             nll += 0.5f * acc.L;
             if (grad) accumulate_contrast<PLUS>(acc, K, p.r2, loading, g, H);
@@ -463,7 +479,8 @@ struct VoxelEchoes<T, 0, 0> {
             const float s0 = contrast_factors(p, P.tr[c], make_angle(P.flip[c] * b), P.mt[c]).s0;
             float L = 0.f;
             for (int i = P.first[c]; i < P.first[c + 1]; i++)
-                L = nll_add(s0 * __builtin_amdgcn_exp2f(k2 * P.te[i]), load_echo(X + (int64_t)i * N + n), P.wgt[i], L);
+                L = nll_add(s0 * __builtin_amdgcn_exp2f(k2 * P.te[i]), decode_echo(X + (int64_t)i * N + n, P.off[i]),
+                            P.wgt[i], L);
             v += 0.5f * L;
         }
         return v;

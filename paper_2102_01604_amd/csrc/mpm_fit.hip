@@ -214,6 +214,7 @@ extern "C" mpm_status mpm_fit_voxelwise(const mpm_voxel_protocols *vp, int64_t n
     if (opt->flags != 0) return fail(MPM_ERR_INVALID_ARG, "flags must be 0");
     if (opt->start_outer != 0) return fail(MPM_ERR_INVALID_ARG, "start_outer is a MAP option (0 for ML)");
     if (opt->b1_receive) return fail(MPM_ERR_UNSUPPORTED, "b1_receive is not supported by the per-voxel-protocol fit");
+    if (opt->echo_offset) return fail(MPM_ERR_UNSUPPORTED, "echo_offset is not supported by the per-voxel-protocol fit");
     if (opt->init_kind == MPM_INIT_DEFAULT)
         return fail(MPM_ERR_UNSUPPORTED, "the default initialisation needs one protocol for all voxels");
     if (opt->init_kind != MPM_INIT_CONST && opt->init_kind != MPM_INIT_FROM_MAPS)

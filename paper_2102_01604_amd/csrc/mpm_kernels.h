@@ -31,6 +31,14 @@ hipError_t launch_ml_fit(const LaunchCtx &c, const DevProto &P, int dtype, const
                          const float *b1, const float *bm, float *maps, int64_t N, int n_gn, int loading,
                          double *partials, int nblk);
 int ml_fit_blocks(int64_t N);
+// per-image offsets of reduced-precision storage
+struct EchoOffsets {
+    float v[MAXI];
+};
+// dst[i][n] = round(src[i][n] - off.v[i]) in dtype (F16 / BF16); *overflow +=
+// the finite inputs whose stored value is not finite
+hipError_t launch_pack_echoes(const LaunchCtx &c, int I, int64_t N, const float *src, int dtype, void *dst,
+                              const EchoOffsets &off, unsigned int *overflow);
 // out[r] = sum over b < ncols of in[r*ncols + b] (fixed order)
 hipError_t launch_reduce_rows(const LaunchCtx &c, const double *in, int nrows, int ncols, double *out);
 

@@ -10,6 +10,10 @@ namespace mpm {
 constexpr int TILE_X = 64;   // voxels along x per workgroup (one wavefront)
 constexpr int TILE_Y = 4;    // rows along y per workgroup (256 threads)
 constexpr int MAX_TRIALS = 8;  // step sizes 1, 1/2, ..., 1/128 of the acceptance test
+// A step is accepted when F_w rises by at most ACCEPT_REL |F_w|: the objective
+// is a sum of single-precision voxel terms, whose rounding makes differences
+// below about 1e-11 |F_w| (larger for small volumes) indistinguishable from 0.
+constexpr double ACCEPT_REL = 1e-9;
 constexpr int TALL_Y = 16;            // rows of a CG-sweep tile (1024 threads)
 constexpr int TALL_WORKGROUPS = 2048; // 4 rounds of 2 workgroups per CU
 
@@ -109,9 +113,10 @@ struct Col {
     int64_t sxy;          // plane stride
 };
 
-__device__ __forceinline__ Col locate_col(const Grid3 &g)
+// L: the workgroup's index among the T workgroups that walk grid g (its
+// blockIdx.x and gridDim.x, unless one launch serves several volumes).
+__device__ __forceinline__ Col locate_col(const Grid3 &g, int L, int T)
 {
-    const int L = blockIdx.x, T = gridDim.x;
     const int q = T >> 3, r = T & 7, j = L & 7;
     const int lid = j * q + min(j, r) + (L >> 3);  // XCD-contiguous workgroup index
     const int bx = lid % g.gx;
@@ -133,6 +138,8 @@ __device__ __forceinline__ Col locate_col(const Grid3 &g)
     return c;
 }
 
+__device__ __forceinline__ Col locate_col(const Grid3 &g) { return locate_col(g, blockIdx.x, gridDim.x); }
+
 template <class Visit>
 __device__ __forceinline__ void for_inplane(const Col &c, int64_t n, int nx, Visit visit)
 {
@@ -145,15 +152,22 @@ __device__ __forceinline__ void for_inplane(const Col &c, int64_t n, int nx, Vis
 // ---------------------------------------------------------------------------
 // device helpers shared by the MAP kernels
 // ---------------------------------------------------------------------------
+// Block sums of v written to partials[k * T + L] (workgroup L of T).
 template <int NV>
-__device__ __forceinline__ void write_partials(double (&v)[NV], double *__restrict__ partials)
+__device__ __forceinline__ void write_partials(double (&v)[NV], double *__restrict__ partials, int L, int T)
 {
     __shared__ double lds[NV][NWAVE];
     block_sum<NV>(v, lds);
     if (threadIdx.x == 0) {
 #pragma unroll
-        for (int k = 0; k < NV; k++) partials[(int64_t)k * gridDim.x + blockIdx.x] = v[k];
+        for (int k = 0; k < NV; k++) partials[(int64_t)k * T + L] = v[k];
     }
+}
+
+template <int NV>
+__device__ __forceinline__ void write_partials(double (&v)[NV], double *__restrict__ partials)
+{
+    write_partials<NV>(v, partials, blockIdx.x, gridDim.x);
 }
 
 // Non-temporal access for arrays that a kernel streams exactly once (no
@@ -299,5 +313,54 @@ struct ExtRows {
 };
 hipError_t launch_fin(hipStream_t s, const MapArgs &a, int stage, int arg, int nblk, double cg_stop_rel,
                       int ntrial, int accept_off, const ExtRows &ext = ExtRows());
+
+// ---------------------------------------------------------------------------
+// Batched launches: one launch of a MAP kernel serves several volumes (their
+// own grids, buffers, priors and control blocks) that run the same schedule
+// in lockstep.  Volume v owns the workgroups [start[k][v], start[k][v] +
+// count[k][v]) of a launch over grid kind k; each start is a multiple of 8,
+// so a volume's workgroups meet the XCDs exactly as in a launch of its own,
+// and each workgroup runs the single-volume kernel body with its index L and
+// count T within its volume: every partial sum, and so every result, is the
+// one of the volume fitted alone.
+// ---------------------------------------------------------------------------
+constexpr int MAX_BATCH = 64;
+enum BatchKind { BK_PLANE = 0, BK_TALL = 1, BK_CGB = 2, BK_COL = 3, BK_UPD = 4, BK_N = 5, BK_NONE = -1 };
+
+struct BatchTab {
+    int n;
+    int start[BK_N][MAX_BATCH + 1];  // start[k][n]: workgroups of the whole launch
+    int count[BK_N][MAX_BATCH];
+};
+
+// Host-side description of one batched fit's device tables.
+struct BatchLaunch {
+    int n = 0;
+    int dtype = 0, shape = 0, loading = 0;
+    int total[BK_N] = {};
+    const BatchTab *tab = nullptr;  // device
+    const void *vols = nullptr;     // device array of per-volume descriptors (batch_desc_bytes each)
+};
+
+// Bytes of one per-volume descriptor for echo storage dtype and register
+// shape (echo_shape), and writing descriptor v of a host array of them.
+size_t batch_desc_bytes(int dtype, int shape);
+void fill_batch_desc(void *host, int v, const MapArgs &m, int prior_on, int dtype, int shape);
+// Fills the workgroup table of the batch from the volumes' grids.
+void fill_batch_tab(BatchTab &t, const MapArgs *m, int n, int total[BK_N]);
+
+hipError_t launch_ctl_init_batch(hipStream_t s, const BatchLaunch &b, int trace_len);
+hipError_t launch_lik_batch(hipStream_t s, const BatchLaunch &b);
+hipError_t launch_cg_a_batch(hipStream_t s, const BatchLaunch &b, int it);
+hipError_t launch_cg_b_batch(hipStream_t s, const BatchLaunch &b, int it);
+hipError_t launch_accept_batch(hipStream_t s, const BatchLaunch &b);
+hipError_t launch_accept2_batch(hipStream_t s, const BatchLaunch &b, int ntrial);
+hipError_t launch_update_batch(hipStream_t s, const BatchLaunch &b);
+hipError_t launch_weights_batch(hipStream_t s, const BatchLaunch &b);
+hipError_t launch_final_batch(hipStream_t s, const BatchLaunch &b);
+// kind: the grid whose per-volume workgroup count is the partial count
+// (BK_NONE: no partials)
+hipError_t launch_fin_batch(hipStream_t s, const BatchLaunch &b, int stage, int arg, int kind, double cg_stop_rel,
+                            int ntrial, int accept_off, double tol_gn, double tol_outer);
 
 }  // namespace mpm

@@ -38,7 +38,7 @@ size_t map_workspace_floats_per_voxel() { return 31; }
 static mpm_status alloc_map(const FitArgs &a, Workspace &ws, MapArgs &m, int trace_len)
 {
     const int64_t N = a.N;
-    m.g = make_grid3(a.nx, a.ny, a.nz);
+    m.g = make_grid3(a.nx, a.ny, a.nz, TILE_Y, column_target(a.nx, a.ny, a.nz));
     m.P = a.P;
     m.dtype = a.dtype;
     m.X = a.X;
@@ -397,6 +397,196 @@ std::unique_ptr<FitJob> make_map_job(const FitArgs &a, Workspace &ws, Prof &prof
     return std::unique_ptr<FitJob>(j.release());
 }
 
+// ---------------------------------------------------------------------------
+// Batched MAP fits: the sequence of MapJob (without spatial projection), each
+// launch a batched one over every volume; each volume keeps its own
+// workspace, control block and trace, so its results are those of its fit
+// alone.
+// ---------------------------------------------------------------------------
+static bool same_schedule(const mpm_options &a, const mpm_options &b)
+{
+    return a.mode == b.mode && a.n_outer == b.n_outer && a.n_gn == b.n_gn && a.n_cg == b.n_cg &&
+           a.max_halvings == b.max_halvings && a.loading == b.loading && a.start_outer == b.start_outer &&
+           a.tol_gn == b.tol_gn && a.tol_outer == b.tol_outer && a.cg_stop == b.cg_stop;
+}
+
+bool batch_compatible(const FitArgs &a, const FitArgs &b)
+{
+    return !a.spaces && !b.spaces && a.opt->mode == MPM_MAP_JTV && same_schedule(*a.opt, *b.opt) &&
+           a.dtype == b.dtype && echo_shape(a.P) == echo_shape(b.P);
+}
+
+struct BatchMapJob : BatchJob {
+    std::vector<FitArgs> a;
+    Workspace &ws;
+    Prof &prof;
+    hipStream_t s = nullptr;
+    int n = 0;
+    std::vector<MapArgs> m;
+    std::vector<int> prior_on;
+    int ntrial = 1, accept_off = 0, T = 0, J = 0, K = 0, S = 0, tl = 0, t0 = 0;
+    int t = 0, j = 0;
+    bool started = false;
+    double cg_stop = 0.0, tol_gn = 0.0, tol_outer = 0.0;
+    BatchLaunch b;
+    double vox = 0.0, xvox = 0.0, bvox = 0.0;  // sums over volumes: N, N * echo bytes, N * field bytes
+
+    BatchMapJob(const std::vector<FitArgs> &a_, Workspace &ws_, Prof &prof_) : a(a_), ws(ws_), prof(prof_) {}
+
+    mpm_status setup()
+    {
+        n = (int)a.size();
+        if (n < 1 || n > MAX_BATCH) return fail(MPM_ERR_INVALID_ARG, "a batch holds 1 to %d fits", MAX_BATCH);
+        s = a[0].stream;
+        const mpm_options *o = a[0].opt;
+        for (int v = 1; v < n; v++)
+            if (!batch_compatible(a[0], a[v]))
+                return fail(MPM_ERR_UNSUPPORTED, "fit %d cannot share launches with fit 0 (batched fits need the same "
+                                                 "schedule options, echo storage and register shape)", v);
+        if (a[0].spaces || o->mode != MPM_MAP_JTV)
+            return fail(MPM_ERR_UNSUPPORTED, "batched fits are JTV-MAP fits without spatial projection");
+        T = o->n_outer;
+        J = o->n_gn;
+        K = o->n_cg;
+        S = J + 2;
+        tl = T * S;
+        t = t0 = o->start_outer;
+        ntrial = o->max_halvings < 0 ? 1 : o->max_halvings + 1;
+        accept_off = o->max_halvings < 0;
+        cg_stop = o->cg_stop;
+        tol_gn = o->tol_gn;
+        tol_outer = o->tol_outer;
+        m.resize(n);
+        prior_on.resize(n);
+        for (int v = 0; v < n; v++) {
+            memset(&m[v], 0, sizeof(MapArgs));
+            mpm_status st = alloc_map(a[v], ws, m[v], tl);
+            if (st) return st;
+            set_prior(a[v].opt, m[v], true, prior_on[v]);
+            m[v].tol_gn = tol_gn;
+            m[v].tol_outer = tol_outer;
+            const double N = (double)a[v].N;
+            vox += N;
+            xvox += N * a[v].P.I * dtype_size(a[v].dtype);
+            bvox += N * ((a[v].b1 ? 4.0 : 0.0) + (a[v].opt->b1_receive ? 4.0 : 0.0));
+        }
+        b.n = n;
+        b.dtype = a[0].dtype;
+        b.shape = echo_shape(a[0].P);
+        b.loading = o->loading;
+        // device tables: the workgroup ranges and one descriptor per volume
+        BatchTab tab;
+        fill_batch_tab(tab, m.data(), n, b.total);
+        const size_t db = batch_desc_bytes(b.dtype, b.shape);
+        std::vector<char> desc(db * (size_t)n);
+        for (int v = 0; v < n; v++) fill_batch_desc(desc.data(), v, m[v], prior_on[v], b.dtype, b.shape);
+        void *dtab = nullptr, *dvols = nullptr;
+        if (ws.alloc(&dtab, sizeof(BatchTab)) != hipSuccess || ws.alloc(&dvols, desc.size()) != hipSuccess)
+            return fail(MPM_ERR_OUT_OF_MEMORY, "batch table allocation failed");
+        hipError_t e = hipMemcpyAsync(dtab, &tab, sizeof(BatchTab), hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(dvols, desc.data(), desc.size(), hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);  // the host copies are local
+        if (e != hipSuccess) return fail(MPM_ERR_DEVICE, "batch tables: %s", hipGetErrorString(e));
+        b.tab = (const BatchTab *)dtab;
+        b.vols = dvols;
+        return MPM_OK;
+    }
+
+    hipError_t fin(int stage, int arg, int kind)
+    {
+        return launch_fin_batch(s, b, stage, arg, kind, cg_stop, ntrial, accept_off, tol_gn, tol_outer);
+    }
+
+    mpm_status enqueue_next(bool *more) override
+    {
+        hipError_t e = hipSuccess;
+        const double V = vox;
+#define RUNB(name, bytes, call)                                                   \
+    do {                                                                          \
+        if (e == hipSuccess) e = prof.launch(name, bytes, [&] { return call; }); \
+    } while (0)
+        *more = true;
+        if (!started) {
+            started = true;
+            for (int v = 0; v < n; v++) {
+                mpm_status st = enqueue_init(a[v], ws, prof);
+                if (st) return st;
+            }
+            e = launch_ctl_init_batch(s, b, tl);
+            LaunchCtx c{s};
+            for (int v = 0; v < n && e == hipSuccess; v++) e = launch_fill(c, m[v].w, a[v].N, 0.0f);
+        } else if (t < T && J > 0) {
+            if (j == 0 && t >= 1) {
+                RUNB("jtv_weights", V * 20.0, launch_weights_batch(s, b));
+                if (t > t0) RUNB("fin", 0.0, fin(FIN_W, (t - 1) * S + J + 1, BK_COL));
+            }
+            RUNB("map_lik", xvox + bvox + V * (16 + 4 + 40 + 16 + 16), launch_lik_batch(s, b));
+            RUNB("fin", 0.0, fin(FIN_LIK, j == 0 ? t * S : -1, BK_PLANE));
+            for (int i = 0; i < K && e == hipSuccess; i++) {
+                double ab = 16 + (i > 0 ? 16 : 0) + 40 + 4 + 16 + (i == 1 ? 16 : i >= 2 ? 32 : 0);
+                RUNB("cg_a", V * ab, launch_cg_a_batch(s, b, i));
+                RUNB("fin", 0.0, fin(FIN_A, i, BK_TALL));
+                RUNB("cg_b", V * (16 + 4 + 40 + 32 + 16), launch_cg_b_batch(s, b, i));
+                RUNB("fin", 0.0, fin(FIN_B, i, BK_CGB));
+            }
+            RUNB("map_accept", xvox + bvox + V * (16 + 16 + 16 + 4), launch_accept_batch(s, b));
+            RUNB("fin", 0.0, fin(FIN_ACCEPT, t * S + j + 1, BK_PLANE));
+            if (ntrial > 1) {
+                RUNB("map_accept2", 0.0, launch_accept2_batch(s, b, ntrial));
+                RUNB("fin", 0.0, fin(FIN_ACCEPT2, t * S + j + 1, BK_COL));
+            }
+            RUNB("map_update", V * 64.0, launch_update_batch(s, b));
+            if (tol_gn > 0.0) RUNB("fin", 0.0, fin(FIN_STOP, -1, BK_NONE));
+            if (++j == J) {
+                j = 0;
+                t++;
+            }
+        } else {
+            for (int tt = (J > 0 ? T : t0 + 1); tt < T && e == hipSuccess; tt++) {
+                RUNB("jtv_weights", V * 20.0, launch_weights_batch(s, b));
+                RUNB("fin", 0.0, fin(FIN_W, (tt - 1) * S + J + 1, BK_COL));
+            }
+            RUNB("jtv_weights", V * 20.0, launch_weights_batch(s, b));
+            RUNB("fin", 0.0, fin(FIN_W, T >= 1 ? (T - 1) * S + J + 1 : -1, BK_COL));
+            RUNB("map_final", xvox + bvox + V * (16 + 4), launch_final_batch(s, b));
+            RUNB("fin", 0.0, fin(FIN_STATS, 0, BK_PLANE));
+            *more = false;
+        }
+#undef RUNB
+        if (e != hipSuccess) return fail(MPM_ERR_DEVICE, "batched MAP fit: %s", hipGetErrorString(e));
+        return MPM_OK;
+    }
+
+    mpm_status collect_item(int i, mpm_report &rep, double *trace, int trace_len) override
+    {
+        if (i < 0 || i >= n) return fail(MPM_ERR_INVALID_ARG, "no fit %d in this batch", i);
+        MapCtl h;
+        const int nt = std::min(tl, trace_len);
+        hipError_t e = hipMemcpy(&h, m[i].ctl, sizeof(MapCtl), hipMemcpyDeviceToHost);
+        if (e == hipSuccess && nt > 0) e = hipMemcpy(trace, m[i].trace, sizeof(double) * nt, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return fail(MPM_ERR_DEVICE, "batched MAP fit: %s", hipGetErrorString(e));
+        memset(&rep, 0, sizeof(rep));
+        rep.nll = h.nll_final;
+        rep.jtv = prior_on[i] ? h.jtv : 0.0;
+        rep.objective = rep.nll + rep.jtv;
+        rep.outer_done = h.outer_done;
+        rep.gn_done = h.gn_done;
+        rep.cg_done = h.cg_done;
+        rep.rejected = h.rejected;
+        rep.degenerate_voxels = (int64_t)llround(h.degenerate);
+        rep.nonfinite_voxels = (int64_t)llround(h.nonfinite);
+        return MPM_OK;
+    }
+};
+
+std::unique_ptr<BatchJob> make_batch_job(const std::vector<FitArgs> &a, Workspace &ws, Prof &prof, mpm_status *st)
+{
+    std::unique_ptr<BatchMapJob> j(new BatchMapJob(a, ws, prof));
+    *st = j->setup();
+    if (*st) return nullptr;
+    return std::unique_ptr<BatchJob>(j.release());
+}
+
 }  // namespace mpm
 
 using namespace mpm;
@@ -424,15 +614,16 @@ static mpm_status uncertainty_impl(const mpm_protocol *protocol, const mpm_grid 
             return fail(MPM_ERR_INVALID_ARG, "lambda[%d] must be finite and >= 0", k);
     if (!(opt->jtv_eps >= 0.0)) return fail(MPM_ERR_INVALID_ARG, "jtv_eps must be >= 0");
     if (!has_mt(protocol)) return fail(MPM_ERR_UNSUPPORTED, "the four-parameter model needs at least one MT contrast");
+    if ((st = check_echo_offset(protocol, dtype, opt->echo_offset))) return st;
     hipStream_t s = (hipStream_t)stream;
-    FitArgs a{protocol, to_dev(protocol), dtype, echoes, b1, opt, const_cast<float *>(maps), N,
+    FitArgs a{protocol, to_dev(protocol, opt->echo_offset), dtype, echoes, b1, opt, const_cast<float *>(maps), N,
               grid->nx, grid->ny, grid->nz, s, spaces};
     {
         Workspace ws(s);
         Prof prof(s);
         MapArgs m;
         memset(&m, 0, sizeof(m));
-        m.g = make_grid3(a.nx, a.ny, a.nz);
+        m.g = make_grid3(a.nx, a.ny, a.nz, TILE_Y, column_target(a.nx, a.ny, a.nz));
         m.P = a.P;
         m.dtype = dtype;
         m.X = echoes;
@@ -509,7 +700,8 @@ extern "C" mpm_status mpm_fit_projected(const mpm_protocol *protocol, const mpm_
     if (trace_len < 0 || (trace_len > 0 && !trace)) return fail(MPM_ERR_INVALID_ARG, "trace is NULL");
     for (int i = 0; i < trace_len; i++) trace[i] = NAN;
     hipStream_t s = (hipStream_t)stream;
-    FitArgs a{protocol, to_dev(protocol), dtype, echoes, b1, opt, maps, N, grid->nx, grid->ny, grid->nz, s, spaces};
+    FitArgs a{protocol, to_dev(protocol, opt->echo_offset), dtype, echoes, b1, opt, maps, N,
+              grid->nx, grid->ny, grid->nz, s, spaces};
     mpm_report rep;
     memset(&rep, 0, sizeof(rep));
     {
@@ -526,5 +718,46 @@ extern "C" mpm_status mpm_fit_projected(const mpm_protocol *protocol, const mpm_
         if ((st = job->collect(rep, trace, trace_len))) return st;
     }
     if (report) *report = rep;
+    return MPM_OK;
+}
+
+extern "C" mpm_status mpm_fit_batch(int32_t n, const mpm_request *requests, mpm_report *reports, double *traces,
+                                    int32_t trace_len, void *stream)
+{
+    clear_error();
+    if (n < 1 || n > MAX_BATCH) return fail(MPM_ERR_INVALID_ARG, "n=%d outside [1, %d]", n, MAX_BATCH);
+    if (!requests) return fail(MPM_ERR_INVALID_ARG, "requests is NULL");
+    if (trace_len < 0 || (trace_len > 0 && !traces)) return fail(MPM_ERR_INVALID_ARG, "traces is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<FitArgs> a;
+    for (int v = 0; v < n; v++) {
+        const mpm_request &r = requests[v];
+        int64_t N;
+        mpm_status st = check_fit_args(&r.protocol, &r.grid, r.dtype, r.echoes, &r.options, r.maps, &N);
+        if (st) return fail(st, "fit %d: %s", v, mpm_last_error());
+        if (r.reserved != 0) return fail(MPM_ERR_INVALID_ARG, "fit %d: reserved must be 0", v);
+        if (r.options.mode != MPM_MAP_JTV)
+            return fail(MPM_ERR_UNSUPPORTED, "fit %d: mpm_fit_batch fits JTV-MAP volumes (an ML fit is one launch: "
+                                             "use mpm_fit)", v);
+        a.push_back(FitArgs{&r.protocol, to_dev(&r.protocol, r.options.echo_offset), r.dtype, r.echoes, r.b1,
+                            &r.options, r.maps, N, r.grid.nx, r.grid.ny, r.grid.nz, s});
+    }
+    for (int i = 0; i < n * trace_len; i++) traces[i] = NAN;
+    Workspace ws(s);
+    Prof prof(s);
+    mpm_status st;
+    std::unique_ptr<BatchJob> job = make_batch_job(a, ws, prof, &st);
+    if (st) return st;
+    bool more = true;
+    while (more)
+        if ((st = job->enqueue_next(&more))) return st;
+    hipError_t e = hipStreamSynchronize(s);
+    prof.collect();
+    if (e != hipSuccess) return fail(MPM_ERR_DEVICE, "batched fit: %s", hipGetErrorString(e));
+    for (int v = 0; v < n; v++) {
+        mpm_report rep;
+        if ((st = job->collect_item(v, rep, traces ? traces + (size_t)v * trace_len : nullptr, trace_len))) return st;
+        if (reports) reports[v] = rep;
+    }
     return MPM_OK;
 }

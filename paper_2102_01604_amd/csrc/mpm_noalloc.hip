@@ -58,7 +58,8 @@ extern "C" mpm_status mpm_fit_noalloc(const mpm_protocol *protocol, const mpm_gr
     if ((st = scratch_address(dev, &base))) return st;
     std::lock_guard<std::mutex> lk(g_call_mu[dev]);  // held until the workspace's stream has drained
     hipStream_t s = (hipStream_t)stream;
-    FitArgs a{protocol, to_dev(protocol), dtype, echoes, b1, opt, maps, N, grid->nx, grid->ny, grid->nz, s};
+    FitArgs a{protocol, to_dev(protocol, opt->echo_offset), dtype, echoes, b1, opt, maps, N,
+              grid->nx, grid->ny, grid->nz, s};
     a.no_pinned = true;
     Workspace ws(s, base, MPM_NOALLOC_SCRATCH_BYTES);
     st = run_fit(a, ws, report, trace, trace_len);

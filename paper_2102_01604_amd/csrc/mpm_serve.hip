@@ -1,10 +1,14 @@
 // mpm_serve.hip -- request queue with continuous batching (mpm_server_* in
 // include/mpm.h).
 //
-// Admitted fits each own one of the server's streams; every step enqueues the
-// next piece of every admitted fit (at most DEPTH pieces in flight per fit),
-// so fits of different sizes and modes overlap on the device and a new
-// arrival starts as soon as a stream and enough of the memory budget are free.
+// Admitted work runs on the server's streams: a fit alone, or a group of small
+// JTV-MAP fits of one schedule fitted together with batched launches (every
+// kernel launch serves all of them: a small volume's launches each cost about
+// the device's dispatch latency, which the group then pays once).  Every step
+// enqueues the next piece of every running unit (at most DEPTH pieces in
+// flight per unit), so fits of different sizes and modes overlap on the
+// device and a new arrival starts as soon as a stream and enough of the
+// memory budget are free.
 #include <hip/hip_runtime.h>
 
 #include <atomic>
@@ -25,16 +29,38 @@ using namespace mpm;
 
 namespace {
 
-constexpr int DEPTH = 2;  // pieces of one fit in flight at a time
+constexpr int DEPTH = 2;  // pieces of one unit in flight at a time
 
 // A MAP fit of at least this many voxels fills the device by itself for a long
-// time (each of its ~13,000 kernels runs several rounds of workgroups on every
+// time (each of its ~11,000 kernels runs several rounds of workgroups on every
 // CU): two such fits side by side only share the bandwidth and both finish
 // later.  At most one of them runs at a time (FIFO among them); ML fits (one
 // short launch) and smaller MAP fits fill the gaps around it.
 constexpr int64_t LARGE_FIT_VOXELS = (int64_t)1 << 21;
 
+// Groups of small MAP fits: at most this many fits and this many voxels in
+// all (about what fills the device in one launch of the CG sweeps).
+constexpr int GROUP_MAX_FITS = 16;
+constexpr int64_t GROUP_MAX_VOXELS = (int64_t)1 << 22;
+
 enum State { QUEUED = 0, RUNNING = 1, DONE = 2 };
+
+struct Entry;
+
+// What runs on one stream: one fit (job) or a group of fits (batch).
+struct Unit {
+    int stream = -1;
+    std::vector<Entry *> members;
+    std::vector<FitArgs> args;
+    std::unique_ptr<Workspace> ws;
+    std::unique_ptr<Prof> prof;
+    std::unique_ptr<FitJob> job;
+    std::unique_ptr<BatchJob> batch;
+    std::deque<hipEvent_t> inflight;
+    bool all_enqueued = false;
+    bool cancel = false;  // no further pieces; released once those in flight complete
+    size_t footprint = 0;
+};
 
 struct Entry {
     uint64_t ticket;
@@ -42,30 +68,28 @@ struct Entry {
     int64_t N = 0;
     size_t footprint = 0;
     State state = QUEUED;
-    int stream = -1;
-    FitArgs args;
-    std::unique_ptr<Workspace> ws;
-    std::unique_ptr<Prof> prof;
-    std::unique_ptr<FitJob> job;
-    std::deque<hipEvent_t> inflight;
-    bool all_enqueued = false;
-    bool cancel = false;  // no further pieces; released once those in flight complete
+    std::shared_ptr<Unit> unit;
+    bool cancelled = false;  // cancelled while running in a group: finishes as cancelled
     mpm_status status = MPM_OK;
     std::string error;
     mpm_report report;
+    float echo_offset[MPM_MAX_IMAGES];  // copy of the request's echo offsets (if any)
 };
 
 bool is_large(const Entry &e) { return e.req.options.mode == MPM_MAP_JTV && e.N >= LARGE_FIT_VOXELS; }
+bool groupable(const Entry &e) { return e.req.options.mode == MPM_MAP_JTV && e.N < LARGE_FIT_VOXELS; }
 
 }  // namespace
 
 struct mpm_server {
     size_t budget = 0, used = 0;
     int device = 0;
+    int32_t flags = 0;
     std::vector<hipStream_t> streams;
-    std::vector<uint64_t> owner;  // ticket running on each stream, 0 = free
+    std::vector<bool> busy;  // stream in use
     std::deque<uint64_t> queue;
     std::map<uint64_t, std::unique_ptr<Entry>> entries;
+    std::vector<std::shared_ptr<Unit>> units;
     uint64_t next_ticket = 1;
     std::mutex mu;
     std::thread worker;
@@ -74,104 +98,140 @@ struct mpm_server {
 
 namespace {
 
-void release(mpm_server *s, Entry &e)
+FitArgs args_of(Entry &e, hipStream_t hs)
 {
-    for (hipEvent_t ev : e.inflight) (void)hipEventDestroy(ev);
-    e.inflight.clear();
-    e.job.reset();
-    e.ws.reset();  // frees the workspace on the fit's stream and waits for it
-    e.prof.reset();
-    if (e.stream >= 0) s->owner[e.stream] = 0;
-    e.stream = -1;
-    s->used -= e.footprint;
+    return FitArgs{&e.req.protocol, to_dev(&e.req.protocol, e.req.options.echo_offset), e.req.dtype, e.req.echoes,
+                   e.req.b1, &e.req.options, e.req.maps, e.N, e.req.grid.nx, e.req.grid.ny, e.req.grid.nz, hs};
 }
 
-void finish_failed(mpm_server *s, Entry &e, mpm_status st)
+void release(mpm_server *s, Unit &u)
+{
+    for (hipEvent_t ev : u.inflight) (void)hipEventDestroy(ev);
+    u.inflight.clear();
+    u.job.reset();
+    u.batch.reset();
+    u.ws.reset();  // frees the workspace on the unit's stream and waits for it
+    u.prof.reset();
+    if (u.stream >= 0) s->busy[u.stream] = false;
+    u.stream = -1;
+    s->used -= u.footprint;
+    u.footprint = 0;
+}
+
+void finish(Entry &e, mpm_status st, const std::string &msg)
 {
     e.status = st;
-    e.error = mpm_last_error();
-    if (e.state == RUNNING) release(s, e);
+    e.error = msg;
     e.state = DONE;
+    e.unit.reset();
 }
 
-// Enqueue the next piece of a running fit if fewer than DEPTH are in flight.
-void advance(mpm_server *s, Entry &e)
+void finish_unit(mpm_server *s, Unit &u, mpm_status st)
 {
-    while (!e.inflight.empty() && hipEventQuery(e.inflight.front()) == hipSuccess) {
-        (void)hipEventDestroy(e.inflight.front());
-        e.inflight.pop_front();
+    const std::string msg = mpm_last_error();
+    release(s, u);
+    for (Entry *e : u.members) finish(*e, st, msg);
+}
+
+// Enqueue the next piece of a running unit if fewer than DEPTH are in flight;
+// finish its fits once every piece has completed.  Returns false once done.
+bool advance(mpm_server *s, Unit &u)
+{
+    while (!u.inflight.empty() && hipEventQuery(u.inflight.front()) == hipSuccess) {
+        (void)hipEventDestroy(u.inflight.front());
+        u.inflight.pop_front();
     }
-    if (e.cancel) {
-        if (!e.inflight.empty()) return;
-        release(s, e);
-        e.status = MPM_ERR_CANCELLED;
-        e.error = "cancelled while running";
-        e.state = DONE;
-        return;
+    if (u.cancel) {
+        if (!u.inflight.empty()) return true;
+        release(s, u);
+        for (Entry *e : u.members) finish(*e, MPM_ERR_CANCELLED, "cancelled while running");
+        return false;
     }
-    if (e.all_enqueued) {
-        if (!e.inflight.empty()) return;
+    if (u.all_enqueued) {
+        if (!u.inflight.empty()) return true;
         // every piece has completed
-        e.prof->collect();
-        e.status = e.job->collect(e.report, nullptr, 0);
-        if (e.status) e.error = mpm_last_error();
-        release(s, e);
-        e.state = DONE;
-        return;
+        u.prof->collect();
+        for (size_t i = 0; i < u.members.size(); i++) {
+            Entry &e = *u.members[i];
+            mpm_status st = u.batch ? u.batch->collect_item((int)i, e.report, nullptr, 0)
+                                    : u.job->collect(e.report, nullptr, 0);
+            if (e.cancelled) finish(e, MPM_ERR_CANCELLED, "cancelled while running");
+            else finish(e, st, st ? mpm_last_error() : "");
+        }
+        release(s, u);
+        return false;
     }
-    if ((int)e.inflight.size() >= DEPTH) return;
+    if ((int)u.inflight.size() >= DEPTH) return true;
     bool more = true;
-    mpm_status st = e.job->enqueue_next(&more);
+    mpm_status st = u.batch ? u.batch->enqueue_next(&more) : u.job->enqueue_next(&more);
     if (st) {
-        finish_failed(s, e, st);
-        return;
+        finish_unit(s, u, st);
+        return false;
     }
     hipEvent_t ev;
     if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess ||
-        hipEventRecord(ev, s->streams[e.stream]) != hipSuccess) {
-        finish_failed(s, e, fail(MPM_ERR_DEVICE, "server: event record failed"));
-        return;
+        hipEventRecord(ev, s->streams[u.stream]) != hipSuccess) {
+        fail(MPM_ERR_DEVICE, "server: event record failed");
+        finish_unit(s, u, MPM_ERR_DEVICE);
+        return false;
     }
-    e.inflight.push_back(ev);
-    e.all_enqueued = !more;
+    u.inflight.push_back(ev);
+    u.all_enqueued = !more;
+    return true;
 }
 
-mpm_status admit(mpm_server *s, Entry &e, int stream)
+// Start a unit of fits on a free stream.
+void start_unit(mpm_server *s, std::vector<Entry *> members, int stream)
 {
+    std::shared_ptr<Unit> u(new Unit);
     hipStream_t hs = s->streams[stream];
-    e.stream = stream;
-    s->owner[stream] = e.ticket;
-    s->used += e.footprint;
-    e.state = RUNNING;
-    e.args = FitArgs{&e.req.protocol, to_dev(&e.req.protocol), e.req.dtype, e.req.echoes, e.req.b1,
-                     &e.req.options, e.req.maps, e.N, e.req.grid.nx, e.req.grid.ny, e.req.grid.nz, hs};
-    e.ws.reset(new Workspace(hs));
-    e.prof.reset(new Prof(hs));
+    u->stream = stream;
+    u->members = members;
+    s->busy[stream] = true;
+    for (Entry *e : members) {
+        u->footprint += e->footprint;
+        e->state = RUNNING;
+        e->unit = u;
+        u->args.push_back(args_of(*e, hs));
+    }
+    s->used += u->footprint;
+    u->ws.reset(new Workspace(hs));
+    u->prof.reset(new Prof(hs));
     mpm_status st = MPM_OK;
-    e.job = e.req.options.mode == MPM_ML ? make_ml_job(e.args, *e.ws, *e.prof, &st)
-                                         : make_map_job(e.args, *e.ws, *e.prof, &st);
-    return st;
+    if (members.size() > 1)
+        u->batch = make_batch_job(u->args, *u->ws, *u->prof, &st);
+    else
+        u->job = members[0]->req.options.mode == MPM_ML ? make_ml_job(u->args[0], *u->ws, *u->prof, &st)
+                                                         : make_map_job(u->args[0], *u->ws, *u->prof, &st);
+    if (st) {
+        finish_unit(s, *u, st);
+        return;
+    }
+    s->units.push_back(u);
+    advance(s, *u);
 }
 
 void step_locked(mpm_server *s)
 {
-    // progress the running fits
-    for (auto &kv : s->entries) {
-        Entry &e = *kv.second;
-        if (e.state == RUNNING) advance(s, e);
+    // progress the running units
+    for (size_t i = 0; i < s->units.size();) {
+        if (advance(s, *s->units[i])) i++;
+        else s->units.erase(s->units.begin() + (long)i);
     }
     // admit in submission order; a large fit waits while another large one
     // runs and smaller ones may pass it, but none passes a fit that waits for
     // memory (so a large request cannot starve)
     int large_running = 0;
-    for (auto &kv : s->entries)
-        if (kv.second->state == RUNNING && is_large(*kv.second)) large_running++;
+    for (auto &u : s->units)
+        for (Entry *e : u->members)
+            if (is_large(*e)) large_running++;
     for (auto it = s->queue.begin(); it != s->queue.end();) {
         Entry &e = *s->entries[*it];
         if (e.footprint > s->budget) {
             it = s->queue.erase(it);
-            finish_failed(s, e, fail(MPM_ERR_OUT_OF_MEMORY, "request needs %zu bytes, server budget is %zu",
-                                     e.footprint, s->budget));
+            const mpm_status st = fail(MPM_ERR_OUT_OF_MEMORY, "request needs %zu bytes, server budget is %zu",
+                                       e.footprint, s->budget);
+            finish(e, st, mpm_last_error());
             continue;
         }
         const bool large = is_large(e);
@@ -180,20 +240,36 @@ void step_locked(mpm_server *s)
             continue;
         }
         int free_stream = -1;
-        for (size_t i = 0; i < s->owner.size(); i++)
-            if (!s->owner[i]) {
+        for (size_t i = 0; i < s->busy.size(); i++)
+            if (!s->busy[i]) {
                 free_stream = (int)i;
                 break;
             }
         if (free_stream < 0 || s->used + e.footprint > s->budget) break;
+        std::vector<Entry *> group{&e};
         it = s->queue.erase(it);
-        mpm_status st = admit(s, e, free_stream);
-        if (st) {
-            finish_failed(s, e, st);
-            continue;
+        if (groupable(e) && !(s->flags & MPM_SERVER_NO_GROUPS)) {
+            // (erasing from the queue invalidates its iterators: the scan restarts below)
+            // later small MAP fits that can share launches with this one join it
+            FitArgs a0 = args_of(e, nullptr);
+            int64_t vox = e.N;
+            size_t mem = s->used + e.footprint;
+            for (auto jt = it; jt != s->queue.end() && (int)group.size() < GROUP_MAX_FITS;) {
+                Entry &f = *s->entries[*jt];
+                if (groupable(f) && vox + f.N <= GROUP_MAX_VOXELS && mem + f.footprint <= s->budget &&
+                    batch_compatible(a0, args_of(f, nullptr))) {
+                    group.push_back(&f);
+                    vox += f.N;
+                    mem += f.footprint;
+                    jt = s->queue.erase(jt);
+                } else {
+                    ++jt;
+                }
+            }
+            it = s->queue.begin();  // the queue changed: restart the scan
         }
         if (large) large_running++;
-        advance(s, e);
+        start_unit(s, group, free_stream);
     }
 }
 
@@ -228,10 +304,12 @@ mpm_status mpm_server_create(size_t hbm_budget, int32_t max_active, int32_t flag
     clear_error();
     if (!out) return fail(MPM_ERR_INVALID_ARG, "out is NULL");
     if (max_active < 1 || max_active > 64) return fail(MPM_ERR_INVALID_ARG, "max_active must be in [1, 64]");
-    if (flags & ~MPM_SERVER_THREAD) return fail(MPM_ERR_INVALID_ARG, "unknown flags 0x%x", flags);
+    if (flags & ~(MPM_SERVER_THREAD | MPM_SERVER_NO_GROUPS))
+        return fail(MPM_ERR_INVALID_ARG, "unknown flags 0x%x", flags);
     if (hbm_budget == 0) return fail(MPM_ERR_INVALID_ARG, "hbm_budget must be > 0");
     std::unique_ptr<mpm_server> s(new mpm_server);
     s->budget = hbm_budget;
+    s->flags = flags;
     if (hipGetDevice(&s->device) != hipSuccess) return fail(MPM_ERR_DEVICE, "no HIP device");
     for (int i = 0; i < max_active; i++) {
         hipStream_t hs;
@@ -241,7 +319,7 @@ mpm_status mpm_server_create(size_t hbm_budget, int32_t max_active, int32_t flag
         }
         s->streams.push_back(hs);
     }
-    s->owner.assign(max_active, 0);
+    s->busy.assign(max_active, false);
     if (flags & MPM_SERVER_THREAD) s->worker = std::thread(worker_loop, s.get());
     *out = s.release();
     return MPM_OK;
@@ -257,6 +335,10 @@ mpm_status mpm_server_submit(mpm_server *s, const mpm_request *r, uint64_t *tick
     if (r->reserved != 0) return fail(MPM_ERR_INVALID_ARG, "reserved must be 0");
     std::unique_ptr<Entry> e(new Entry);
     e->req = *r;
+    if (r->options.echo_offset) {  // the request keeps its own copy
+        memcpy(e->echo_offset, r->options.echo_offset, sizeof(float) * (size_t)n_images(&r->protocol));
+        e->req.options.echo_offset = e->echo_offset;
+    }
     e->N = N;
     e->footprint = mpm_footprint_bytes(&r->protocol, &r->grid, (mpm_dtype)r->dtype, r->options.mode);
     memset(&e->report, 0, sizeof(e->report));
@@ -307,11 +389,12 @@ mpm_status mpm_server_cancel(mpm_server *s, uint64_t ticket)
                 s->queue.erase(q);
                 break;
             }
-        e.status = MPM_ERR_CANCELLED;
-        e.error = "cancelled before it started";
-        e.state = DONE;
+        finish(e, MPM_ERR_CANCELLED, "cancelled before it started");
     } else if (e.state == RUNNING) {
-        e.cancel = true;
+        e.cancelled = true;
+        bool all = true;  // a unit whose fits are all cancelled stops
+        for (Entry *m : e.unit->members) all = all && m->cancelled;
+        if (all) e.unit->cancel = true;
     }
     return MPM_OK;
 }
@@ -326,14 +409,12 @@ mpm_status mpm_server_destroy(mpm_server *s)
     }
     {
         std::lock_guard<std::mutex> lk(s->mu);
-        for (auto &kv : s->entries) {
-            Entry &e = *kv.second;
-            if (e.state == RUNNING) {
-                (void)hipStreamSynchronize(s->streams[e.stream]);
-                release(s, e);
-                e.state = DONE;
-            }
+        for (auto &u : s->units) {
+            (void)hipStreamSynchronize(s->streams[u->stream]);
+            release(s, *u);
+            for (Entry *e : u->members) finish(*e, MPM_ERR_CANCELLED, "server destroyed");
         }
+        s->units.clear();
         for (hipStream_t x : s->streams) (void)hipStreamDestroy(x);
     }
     delete s;

@@ -10,4 +10,8 @@ namespace mpm {
 // built-in choice.
 int tall_target(int64_t nx, int64_t ny, int64_t nz);
 
+// Workgroup target of the column walks (JTV weights, halved-step acceptance)
+// for that grid: the one set by mpm_autotune_set, else the built-in choice.
+int column_target(int64_t nx, int64_t ny, int64_t nz);
+
 }  // namespace mpm

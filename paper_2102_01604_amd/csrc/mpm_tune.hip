@@ -20,8 +20,14 @@
 namespace mpm {
 
 namespace {
+// Launch shape chosen for one grid size: the workgroup target of CG sweep A
+// and of the column walks of the stencil-only kernels (0: built-in choice).
+struct Shape {
+    int tall = 0;
+    int col = 0;
+};
 std::mutex g_mu;
-std::map<std::tuple<int64_t, int64_t, int64_t>, int> g_tuned;
+std::map<std::tuple<int64_t, int64_t, int64_t>, Shape> g_tuned;
 }  // namespace
 
 // Built-in choice: grids beyond the last-level cache (about 4 M voxels at the
@@ -36,12 +42,20 @@ int tall_target(int64_t nx, int64_t ny, int64_t nz)
     {
         std::lock_guard<std::mutex> lock(g_mu);
         auto it = g_tuned.find(std::make_tuple(nx, ny, nz));
-        if (it != g_tuned.end()) return it->second;
+        if (it != g_tuned.end() && it->second.tall > 0) return it->second.tall;
     }
     if (std::getenv("MPM_TALL_WORKGROUPS")) return tall_workgroups();
     const int64_t tiles = ((nx + TILE_X - 1) / TILE_X) * ((ny + TALL_Y - 1) / TALL_Y);
     if (nx * ny * nz >= ((int64_t)1 << 22)) return (int)std::min<int64_t>((tiles * nz + 1) / 2, 1 << 20);
     return tall_workgroups();
+}
+
+int column_target(int64_t nx, int64_t ny, int64_t nz)
+{
+    std::lock_guard<std::mutex> lock(g_mu);
+    auto it = g_tuned.find(std::make_tuple(nx, ny, nz));
+    if (it != g_tuned.end() && it->second.col > 0) return it->second.col;
+    return stencil_workgroups();
 }
 
 }  // namespace mpm
@@ -120,9 +134,26 @@ extern "C" mpm_status mpm_autotune(const mpm_grid *grid, int32_t reps, mpm_tune_
         if (r.ms[c] < r.ms[r.chosen]) r.chosen = c;
     {
         std::lock_guard<std::mutex> lock(g_mu);
-        g_tuned[std::make_tuple(grid->nx, grid->ny, grid->nz)] = r.target[r.chosen];
+        g_tuned[std::make_tuple(grid->nx, grid->ny, grid->nz)].tall = r.target[r.chosen];
     }
     if (result) *result = r;
+    return MPM_OK;
+}
+
+extern "C" mpm_status mpm_autotune_set(const mpm_grid *grid, int32_t cg_workgroups, int32_t column_workgroups)
+{
+    clear_error();
+    int64_t N;
+    mpm_status st;
+    if ((st = check_grid(grid, &N))) return st;
+    if (cg_workgroups < 0 || cg_workgroups > (1 << 20))
+        return fail(MPM_ERR_INVALID_ARG, "cg_workgroups must be in [0, 2^20]");
+    if (column_workgroups < 0 || column_workgroups > (1 << 20))
+        return fail(MPM_ERR_INVALID_ARG, "column_workgroups must be in [0, 2^20]");
+    std::lock_guard<std::mutex> lock(g_mu);
+    Shape &sh = g_tuned[std::make_tuple(grid->nx, grid->ny, grid->nz)];
+    sh.tall = cg_workgroups;
+    sh.col = column_workgroups;
     return MPM_OK;
 }
 

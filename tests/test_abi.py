@@ -225,6 +225,16 @@ def test_autotune_argument_validation(lib):
         assert st == 1 and what in lib.mpm_last_error().decode(), (dims, reps, lib.mpm_last_error())
 
 
+def test_autotune_set_validation(lib):
+    g = C.byref(_lib.make_grid((8, 8, 8)))
+    for cg, col, what in ((-1, 0, "cg_workgroups"), (1 << 21, 0, "cg_workgroups"), (0, -5, "column_workgroups")):
+        st = lib.mpm_autotune_set(g, cg, col)
+        assert st == 1 and what in lib.mpm_last_error().decode(), (cg, col, lib.mpm_last_error())
+    assert lib.mpm_autotune_set(C.byref(_lib.make_grid((0, 8, 8))), 16, 16) == 1
+    assert lib.mpm_autotune_set(g, 16, 64) == 0  # host bookkeeping only
+    lib.mpm_autotune_clear()
+
+
 def test_null_pointers_rejected(lib):
     proto = synth.protocol()
     proto["sigma"] = [1.0] * 22

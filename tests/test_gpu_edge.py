@@ -162,4 +162,4 @@ def test_uncertainty_reduced_precision(torch_cuda, orc):
     v = var.cpu().numpy().astype(np.float64)
     ok = np.isfinite(var_o)
     assert np.array_equal(np.isfinite(v), ok)
-    assert (np.abs(v[ok] - var_o[ok]) / var_o[ok]).max() <= 2e-3
+    assert (np.abs(v[ok] - var_o[ok]) / var_o[ok]).max() <= 1e-4

@@ -8,6 +8,9 @@ from paper_2102_01604_amd import _lib, synth
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-4
+# Laplace variance and moments, relative per voxel (FP32 assembly of the
+# 4 x 4 block and its inverse; measured at a few 1e-6)
+VAR_TOL = 1e-4
 
 
 @pytest.fixture(scope="module")
@@ -53,7 +56,7 @@ def _compare(orc, torch, c, x, opts, tol=TOL, trace_rtol=1e-5):
     print(c["dims"], "well-posed", good.mean(), "rel", rel, "abs", ab, "rms", rms, "| all voxels rel", rel_all)
     print("gpu report", rep)
     print("orc report", rep_o)
-    assert (rel <= tol).all()
+    assert (rel <= tol).all() and (rel_all <= tol).all()
     fin = np.isfinite(tr_o)
     assert np.array_equal(np.isfinite(tr), fin)
     assert np.allclose(tr[fin], tr_o[fin], rtol=trace_rtol)
@@ -81,6 +84,59 @@ def test_map_parity_crop_full_schedule(torch_cuda, orc):
     _compare(orc, torch_cuda, c, x, opts)
 
 
+# Launch shapes whose workgroups walk z-runs of several planes on a ragged
+# 70 x 37 x 41 grid (nz not a multiple of the run length): CG sweep A tiles
+# are 64 x 16 (2 x 3 = 6 per plane), column-walk tiles 64 x 4 (2 x 10 = 20).
+# (sweep A target, column target) -> planes per run: (123, 410) -> 2 / 2,
+# (50, 164) -> 5 / 5, (1, 1) -> 32 / 32 (the longest run the sweeps take).
+SHAPE_DIMS = (70, 37, 41)
+
+
+def _runs(tiles, nz, target):
+    zc = min(32, nz, max(1, -(-tiles * nz // target)))
+    return zc, -(-nz // zc)
+
+
+@pytest.fixture(scope="module")
+def shape_case(orc):
+    c, x = _inputs(orc, "map_brain", SHAPE_DIMS, seed=37)
+    opts = _const_opts(orc, c, x)  # the full 10 x 8 x 32 schedule
+    y_orc, rep_o, tr_o = orc.fit(c["proto"], c["dims"], x.astype(np.float64), c["b1"], opts)
+    return c, x, opts, y_orc, rep_o, tr_o
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("cg_wg,col_wg", [(123, 410), (50, 164), (1, 1)])
+def test_map_parity_multi_plane_runs(torch_cuda, shape_case, cg_wg, col_wg):
+    """CG sweep A's cross-plane register rotation and double-buffered LDS
+    planes, and the column walks of the JTV weights and of the halved-step
+    acceptance, compared with the oracle voxel by voxel over the full
+    schedule."""
+    c, x, opts, y_orc, rep_o, tr_o = shape_case
+    nx, ny, nz = SHAPE_DIMS
+    za = _runs(2 * 3, nz, cg_wg)
+    zw = _runs(2 * 10, nz, col_wg)
+    assert za[0] >= 2 and zw[0] >= 2 and nz % za[0] and nz % zw[0]
+    _lib.mpm_autotune_set(SHAPE_DIMS, cg_wg, col_wg)
+    try:
+        y_gpu, rep, tr = _gpu(torch_cuda, c, x, opts)
+    finally:
+        _lib.mpm_autotune_clear()
+    good = well_posed(y_orc, c["truth"])
+    rel, ab, rms = map_errors(y_gpu, y_orc, good)
+    rel_all, _, _ = map_errors(y_gpu, y_orc)
+    print("sweep A runs", za, "column runs", zw, "well-posed", good.mean(), "rel", rel, "all", rel_all)
+    print("gpu report", rep, "| oracle report", rep_o)
+    assert (rel <= TOL).all() and (rel_all <= TOL).all()
+    fin = np.isfinite(tr_o)
+    assert np.array_equal(np.isfinite(tr), fin)
+    assert np.allclose(tr[fin], tr_o[fin], rtol=1e-6)
+    # (CG counts differ in the first outer loop, where one iteration solves each
+    # system and the FP64 residual vanishes while the FP32 one does not)
+    assert rep["gn_done"] == rep_o["gn_done"] and rep["rejected"] == rep_o["rejected"]
+    assert rep["objective"] == pytest.approx(rep_o["objective"], rel=1e-6)
+
+
 def test_map_without_prior_equals_ml_on_gpu(torch_cuda, orc):
     c, x = _inputs(orc, "map_brain", (40, 24, 8), seed=32)
     ml = _const_opts(orc, c, x, mode="ml", n_gn=9)
@@ -100,26 +156,98 @@ def test_map_objective_monotone_on_gpu(torch_cuda, orc):
     t = tr.reshape(5, 6)
     for row in t:
         fw = row[:5][np.isfinite(row[:5])]
-        assert np.all(np.diff(fw) <= 0)
+        assert np.all(np.diff(fw) <= 1e-9 * np.abs(fw[:-1]))  # the acceptance test's slack
     assert np.all(np.diff(t[:, -1]) <= 1e-9 * np.abs(t[:-1, -1]))
 
 
-@pytest.mark.parametrize("dtype", ["f16", "bf16"])
-def test_map_reduced_precision_storage(torch_cuda, orc, dtype):
-    torch = torch_cuda
+def _pack(torch, x, dtype, offsets):
+    """(device echoes in dtype, offsets or None, dequantised values): FP16 /
+    BF16 of x - per-image offsets (mpm_pack_echoes) or of x itself."""
     dt = {"f16": torch.float16, "bf16": torch.bfloat16}[dtype]
+    X = cuda(x.astype(np.float32))
+    if offsets:
+        Q = torch.empty(X.shape, dtype=dt, device="cuda")
+        off = _lib.mpm_pack_echoes(X, Q)
+        o = np.asarray(off, np.float64)[:, None]
+    else:
+        Q, off, o = X.to(dt), None, 0.0
+    torch.cuda.synchronize()
+    return Q, off, Q.float().cpu().numpy().astype(np.float64) + o
+
+
+def _fit_packed(torch, c, Q, opts, off):
+    maps = torch.zeros((4, Q.shape[1]), dtype=torch.float32, device="cuda")
+    b1 = None if c["b1"] is None else cuda(c["b1"].astype(np.float32))
+    rep, tr = _lib.mpm_fit(c["proto"], c["dims"], Q, b1, dict(opts, echo_offset=off), maps)
+    torch.cuda.synchronize()
+    return maps.cpu().numpy().astype(np.float64), rep, tr
+
+
+@pytest.mark.parametrize("offsets", [True, False], ids=["offsets", "plain"])
+@pytest.mark.parametrize("dtype", ["f16", "bf16"])
+def test_map_reduced_precision_storage(torch_cuda, orc, dtype, offsets):
+    """As the ML test: arithmetic parity with the oracle on the dequantised
+    values (1e-4, all voxels); against the unquantised data FP16 with
+    per-image offsets meets 1e-3, the other forms stay within the oracle's own
+    storage floor plus the FP32 bound."""
+    torch = torch_cuda
     c, x = _inputs(orc, "map_brain", (32, 24, 16), seed=34)
     opts = _const_opts(orc, c, x, n_outer=4, n_gn=4, n_cg=16)
-    xq = torch.from_numpy(x).to(dt).float().numpy()
-    y_gpu, rep, tr = _gpu(torch, c, x, opts, dtype=dt)
-    y_orc, _, tr_o = orc.fit(c["proto"], c["dims"], xq.astype(np.float64), c["b1"], opts)
-    rel, ab, rms = map_errors(y_gpu, y_orc, well_posed(y_orc, c["truth"]))
-    print(dtype, "vs dequantised oracle", rel, ab, rms)
+    Q, off, xq = _pack(torch, x, dtype, offsets)
+    y_gpu, rep, tr = _fit_packed(torch, c, Q, opts, off)
+    y_orc_q, rep_q, tr_q = orc.fit(c["proto"], c["dims"], xq, c["b1"], opts)
+    rel, ab, rms = map_errors(y_gpu, y_orc_q)
+    print(dtype, offsets, "vs dequantised oracle (all voxels)", rel, ab, rms)
     assert (rel <= TOL).all()
-    y_orc_u, _, _ = orc.fit(c["proto"], c["dims"], x.astype(np.float64), c["b1"], opts)
-    good = well_posed(y_orc_u, c["truth"])
-    rel_u, ab_u, rms_u = map_errors(y_gpu, y_orc_u, good)
-    print(dtype, "vs unquantised oracle", rel_u, ab_u, rms_u / np.abs(y_orc_u[:, good]).max(axis=1))
+    fin = np.isfinite(tr_q)
+    assert np.allclose(tr[fin], tr_q[fin], rtol=1e-6)
+    y_orc, _, _ = orc.fit(c["proto"], c["dims"], x.astype(np.float64), c["b1"], opts)
+    rel_u, _, _ = map_errors(y_gpu, y_orc)
+    good = well_posed(y_orc, c["truth"])
+    floor = map_errors(y_orc_q, y_orc)[0]
+    print(dtype, offsets, "vs unquantised oracle (all voxels)", rel_u, "well-posed",
+          map_errors(y_gpu, y_orc, good)[0], "| oracle's own storage floor", floor)
+    if dtype == "f16" and offsets:
+        assert (rel_u <= 1e-3).all()
+    else:
+        assert (rel_u <= floor + TOL).all()
+
+
+@pytest.mark.timeout(600)
+def test_map_high_resolution_crop_fp16(torch_cuda, orc):
+    """The high-resolution recipe's parity case: a 64^3 volume drawn with it
+    (B1 0.7-1.3, sigma 2% of mean PD), FP16 echo storage with per-image
+    offsets, the full 10 x 8 x 32 schedule, then the Laplace variance, against
+    the oracle on the unquantised data: maps within 1e-3 (all voxels), the
+    objective trace within 1e-5, the variance at the oracle's maps within
+    1e-3."""
+    torch = torch_cuda
+    c, x = _inputs(orc, "map_hires", (64, 64, 64))
+    opts = _const_opts(orc, c, x)
+    Q, off, xq = _pack(torch, x, "f16", True)
+    y_gpu, rep, tr = _fit_packed(torch, c, Q, opts, off)
+    print("hires crop: fitting the oracle", flush=True)
+    y_orc, rep_o, tr_o = orc.fit(c["proto"], c["dims"], x.astype(np.float64), c["b1"], opts)
+    rel, ab, rms = map_errors(y_gpu, y_orc)
+    good = well_posed(y_orc, c["truth"])
+    print("hires crop FP16: rel (all voxels)", rel, "well-posed", map_errors(y_gpu, y_orc, good)[0], "rms", rms)
+    print("gpu report", rep, "| oracle", rep_o)
+    assert (rel <= 1e-3).all()
+    fin = np.isfinite(tr_o)
+    assert np.array_equal(np.isfinite(tr), fin) and np.allclose(tr[fin], tr_o[fin], rtol=1e-5)
+    assert rep["gn_done"] == rep_o["gn_done"] and rep["rejected"] == rep_o["rejected"]
+    maps = f32(y_orc)
+    var_o = orc.uncertainty(c["proto"], c["dims"], x.astype(np.float64), c["b1"], opts, maps)
+    N = x.shape[1]
+    var = torch.empty((4, N), dtype=torch.float32, device="cuda")
+    _lib.mpm_uncertainty(c["proto"], c["dims"], Q, cuda(c["b1"].astype(np.float32)), dict(opts, echo_offset=off),
+                         cuda(maps.astype(np.float32)), var)
+    v = var.cpu().numpy().astype(np.float64)
+    ok = np.all(np.isfinite(var_o), axis=0)
+    assert np.array_equal(np.isfinite(v), np.isfinite(var_o))
+    rv = np.abs(v[:, ok] - var_o[:, ok]) / var_o[:, ok]
+    print("hires crop FP16: variance rel err max", rv.max(axis=1))
+    assert rv.max() <= 1e-3
 
 
 @pytest.mark.parametrize("mode", ["ml", "map"])
@@ -144,18 +272,21 @@ def test_uncertainty_parity(torch_cuda, orc, mode):
     rv = np.abs(v[:, good] - var_o[:, good]) / var_o[:, good]
     rm = np.abs(m[:, good] - mom_o[:, good]) / np.abs(mom_o[:, good])
     print(mode, "variance rel err max", rv.max(axis=1), "moments", rm.max(axis=1))
-    assert rv.max() <= 2e-3 and rm.max() <= 2e-3
+    assert rv.max() <= VAR_TOL and rm.max() <= VAR_TOL
 
 
+@pytest.mark.timeout(900)
 def test_map_whole_brain_launch_configuration(torch_cuda, orc):
     """The whole-brain workload (192 x 240 x 256, 22 echoes, B1 0.8-1.2) in the
-    launch configuration the benchmark times, checked where the oracle follows
-    at this size with inputs of its own: the first objective value, at the
-    oracle's constant initialisation, equals the oracle's NLL there; the
-    objective does not rise within an outer loop; the Laplace variance at the
-    true maps equals the oracle's at every voxel; the benchmark's ML leg (its
-    default initialisation from the whole volume) starts from the oracle's
-    initial maps and equals the oracle on 2048 sampled voxels."""
+    launch configuration the benchmark times (CG sweep A walks 2-plane z-runs,
+    the column walks 6-plane runs), against the oracle run on the same volume:
+    a 2 x 3 x 16 MAP fit equals the oracle's at every voxel, with the same
+    objective trace, no rejected step and a strictly decreasing objective
+    within each outer loop; the first objective value equals the oracle's NLL
+    at the constant start; the Laplace variance at the true maps equals the
+    oracle's at every voxel; the benchmark's ML leg (its default
+    initialisation from the whole volume) starts from the oracle's initial
+    maps and equals the oracle on 2048 sampled voxels."""
     torch = torch_cuda
     c, x = _inputs(orc, "map_brain", (192, 240, 256))
     del c["eps"]
@@ -167,6 +298,7 @@ def test_map_whole_brain_launch_configuration(torch_cuda, orc):
     maps = torch.zeros((4, N), dtype=torch.float32, device="cuda")
     rep, tr = _lib.mpm_fit(c["proto"], c["dims"], X, B1, opts, maps)
     torch.cuda.synchronize()
+    y_gpu = maps.cpu().numpy().astype(np.float64)
     del maps
     _, rep0, _ = orc.fit(c["proto"], c["dims"], x, c["b1"], {"mode": "ml", "n_gn": 0, "init": "const",
                                                               "init_const": y0})
@@ -175,9 +307,23 @@ def test_map_whole_brain_launch_configuration(torch_cuda, orc):
     S = opts["n_gn"] + 2
     for t in range(opts["n_outer"]):
         f = tr[t * S:t * S + opts["n_gn"] + 1]
-        f = f[np.isfinite(f)]
-        assert np.all(np.diff(f) <= 0.0), (t, f)
-    assert rep["nonfinite_voxels"] == 0
+        assert np.isfinite(f).all() and np.all(np.diff(f) < 0.0), (t, f)
+    assert rep["nonfinite_voxels"] == 0 and rep["rejected"] == 0
+    print("whole brain: oracle MAP fit of the whole volume", flush=True)
+    y_orc, rep_o, tr_o = orc.fit(c["proto"], c["dims"], x.astype(np.float64), c["b1"], opts)
+    good = well_posed(y_orc, c["truth"])
+    rel, ab, rms = map_errors(y_gpu, y_orc, good)
+    rel_all, ab_all, _ = map_errors(y_gpu, y_orc)
+    print("whole brain MAP 2x3x16 vs oracle: well-posed", good.mean(), "rel", rel, "all voxels rel", rel_all,
+          "abs", ab_all)
+    del y_gpu, y_orc
+    assert (rel <= TOL).all() and (rel_all <= TOL).all()
+    fin = np.isfinite(tr_o)
+    assert np.array_equal(np.isfinite(tr), fin) and np.allclose(tr[fin], tr_o[fin], rtol=1e-6)
+    # (CG iteration counts may differ: in the first outer loop, without JTV
+    # weights, one iteration solves each system and the FP64 residual then
+    # vanishes, the FP32 one does not)
+    assert rep["gn_done"] == rep_o["gn_done"] and rep_o["rejected"] == 0
     # Laplace variance at the true maps (JTV weights from them)
     truth = f32(c["truth"])
     var = torch.empty((4, N), dtype=torch.float32, device="cuda")
@@ -188,7 +334,7 @@ def test_map_whole_brain_launch_configuration(torch_cuda, orc):
     assert ok.mean() > 0.99 and np.array_equal(np.isfinite(v), np.isfinite(var_o))
     rv = np.abs(v[:, ok] - var_o[:, ok]) / var_o[:, ok]
     print("whole brain: variance at the truth, rel err max", rv.max(axis=1))
-    assert rv.max() <= 2e-3
+    assert rv.max() <= VAR_TOL
     del var
     # the benchmark's ML leg with its own options (default initialisation from
     # the whole volume): the initial maps equal the oracle's, and the fit
@@ -268,7 +414,7 @@ def test_map_high_resolution_launch_configuration(torch_cuda, orc):
     for t in range(opts["n_outer"]):
         f = tr[t * S:t * S + opts["n_gn"] + 1]
         f = f[np.isfinite(f)]
-        assert np.all(np.diff(f) <= 0.0), (t, f)
+        assert np.all(np.diff(f) <= 1e-9 * np.abs(f[:-1])), (t, f)
     assert rep["nonfinite_voxels"] == 0
     rng = np.random.default_rng(105)
     # ML on sampled voxels
@@ -301,4 +447,4 @@ def test_map_high_resolution_launch_configuration(torch_cuda, orc):
         v = vo[:, 62]  # the centre of the crop
         worst = max(worst, float(np.max(np.abs(vg[:, k] - v) / v)))
     print("high resolution: variance at the truth on sampled voxels, rel err max", worst)
-    assert worst <= 2e-3
+    assert worst <= VAR_TOL

@@ -75,45 +75,93 @@ def test_ml_parity(torch_cuda, orc, dims):
     good = well_posed(y_orc, c["truth"])
     rel, ab, rms = map_errors(y_gpu, y_orc, good)
     print(dims, "well-posed", good.mean(), "rel", rel, "abs", ab, "rms", rms)
-    print("all voxels", map_errors(y_gpu, y_orc))
-    assert (rel <= TOL["f32"]).all()
+    rel_all = map_errors(y_gpu, y_orc)[0]
+    print("all voxels", rel_all)
+    assert (rel <= TOL["f32"]).all() and (rel_all <= TOL["f32"]).all()
     assert np.allclose(trace, trace_o, rtol=2e-5)
     assert rep["degenerate_voxels"] == rep_o["degenerate_voxels"]
     assert rep["nonfinite_voxels"] == 0
 
 
-def _quantise(torch, x, dtype):
+def _pack(torch, x, dtype, offsets):
+    """Echoes as the library stores them: FP16 / BF16 of x - offset (offsets
+    from mpm_pack_echoes, or none).  Returns (device tensor, offsets or None,
+    the dequantised values as float64)."""
     dt = {"f16": torch.float16, "bf16": torch.bfloat16}[dtype]
-    return torch.from_numpy(x).to(dt).float().numpy()
+    X = cuda(x.astype(np.float32))
+    if offsets:
+        Q = torch.empty(X.shape, dtype=dt, device="cuda")
+        off = _lib.mpm_pack_echoes(X, Q)
+        o = np.asarray(off, np.float64)[:, None]
+    else:
+        Q = X.to(dt)
+        off, o = None, 0.0
+    torch.cuda.synchronize()
+    return Q, off, Q.float().cpu().numpy().astype(np.float64) + o
 
 
+@pytest.mark.parametrize("offsets", [True, False], ids=["offsets", "plain"])
 @pytest.mark.parametrize("dtype", ["f16", "bf16"])
-def test_ml_reduced_precision_storage(torch_cuda, orc, dtype):
-    """Arithmetic parity: the oracle fits the dequantised FP16/BF16 values the
-    GPU reads, so the bound is the FP32 one.  The error against the
-    unquantised data (storage quantisation included) is printed and bounded
-    separately: FP16 keeps 11 significant bits, BF16 8."""
+def test_ml_reduced_precision_storage(torch_cuda, orc, dtype, offsets):
+    """Arithmetic parity: the oracle fitting the dequantised values the GPU
+    reads agrees to the FP32 bound.  Against the unquantised data the
+    storage rounding adds its own error: FP16 with per-image offsets meets the
+    1e-3 target; plain FP16 and BF16 cannot (the oracle itself moves by more
+    than 1e-3 on rounded data), so there the GPU's error must stay within the
+    oracle's own storage floor plus the FP32 bound."""
+    torch = torch_cuda
     c = synth.make_case("ml32", dims=(32, 32, 16))
     x = observations(orc, c)
     y0 = f32(orc.default_init(c["proto"], x.astype(np.float64)))
     opts = {"mode": "ml", "n_gn": 20, "init": "const", "init_const": y0}
-    y_gpu, _, _ = _gpu_fit(torch_cuda, c, x, opts, dtype=dtype)
-    xq = _quantise(torch_cuda, x, dtype).astype(np.float64)
+    Q, off, xq = _pack(torch, x, dtype, offsets)
+    maps = torch.zeros((4, x.shape[1]), dtype=torch.float32, device="cuda")
+    _lib.mpm_fit(c["proto"], c["dims"], Q, None, dict(opts, echo_offset=off), maps)
+    y_gpu = maps.cpu().numpy().astype(np.float64)
     y_orc_q, _, _ = orc.fit(c["proto"], c["dims"], xq, None, opts)
     good = well_posed(y_orc_q, c["truth"])
     rel, ab, rms = map_errors(y_gpu, y_orc_q, good)
-    print(dtype, "vs dequantised oracle: rel", rel, "abs", ab, "rms", rms)
+    print(dtype, offsets, "vs dequantised oracle: rel", rel, "abs", ab, "rms", rms)
     assert (rel <= TOL["f32"]).all()
     y_orc, _, _ = orc.fit(c["proto"], c["dims"], x.astype(np.float64), None, opts)
     good = well_posed(y_orc, c["truth"])
     rel, ab, rms = map_errors(y_gpu, y_orc, good)
-    scale = np.abs(y_orc[:, good]).max(axis=1)
-    print(dtype, "vs unquantised oracle: rel", rel, "abs", ab, "rms/scale", rms / scale)
-    # storage quantisation bounds (FP16: 11 significant bits, BF16: 8)
-    max_limit = {"f16": 3e-3, "bf16": 3e-2}[dtype]
-    rms_limit = {"f16": 1e-3, "bf16": 3e-3}[dtype]
-    assert (rel <= max_limit).all()
-    assert (rms / scale <= rms_limit).all()
+    floor = map_errors(y_orc_q, y_orc, good)[0]
+    print(dtype, offsets, "vs unquantised oracle: rel", rel, "| oracle's own storage floor", floor)
+    if dtype == "f16" and offsets:
+        assert (rel <= TOL["f16"]).all()
+    else:
+        assert (rel <= floor + TOL["f32"]).all()
+
+
+def test_pack_echoes(torch_cuda):
+    """mpm_pack_echoes: offsets = each image's mean of its finite values, and
+    every stored value = the FP32 difference rounded to nearest even, bit for
+    bit; missing values stay missing; an overflow is an error."""
+    torch = torch_cuda
+    rng = np.random.default_rng(71)
+    I, N = 5, 100003  # a ragged length: images start off 16-byte boundaries
+    x = (rng.uniform(20.0, 300.0, (I, N)) * rng.uniform(0.5, 2.0, (I, 1))).astype(np.float32)
+    x[2, 17] = np.nan
+    x[3, 5] = np.inf
+    X = cuda(x)
+    for dt, name in ((torch.float16, "f16"), (torch.bfloat16, "bf16")):
+        Q = torch.empty((I, N), dtype=dt, device="cuda")
+        off = np.asarray(_lib.mpm_pack_echoes(X, Q), np.float64)
+        fin = np.isfinite(x)
+        ref_off = np.array([x[i][fin[i]].astype(np.float64).mean() for i in range(I)])
+        assert np.allclose(off, ref_off, rtol=1e-6) and np.array_equal(off.astype(np.float32), off)
+        diff = x - off.astype(np.float32)[:, None]  # FP32 arithmetic
+        ref = torch.from_numpy(diff).to(dt)
+        got = Q.cpu()
+        same = (got.view(torch.int16) == ref.view(torch.int16)).numpy() | (np.isnan(diff) & np.isnan(got.float().numpy()))
+        assert same.all(), name
+        assert np.isnan(got[2, 17].float().item()) and np.isinf(got[3, 5].float().item())
+    big = X.clone()
+    big[1, 9] = 1e6  # 1e6 - mean overflows FP16
+    with pytest.raises(_lib.MpmError) as err:
+        _lib.mpm_pack_echoes(big, torch.empty((I, N), dtype=torch.float16, device="cuda"))
+    assert "overflow" in str(err.value)
 
 
 def test_ml_whole_brain_sampled(torch_cuda, orc):
@@ -144,8 +192,9 @@ def test_ml_whole_brain_sampled(torch_cuda, orc):
     y_orc, _, _ = orc.fit(c["proto"], (len(idx), 1, 1), x[:, idx].astype(np.float64), f32(c["b1"][idx]), opts)
     good = well_posed(y_orc, c["truth"][:, idx])
     rel, ab, rms = map_errors(y_gpu[:, idx], y_orc, good)
-    print("whole brain sampled: well-posed", good.mean(), "rel", rel, "abs", ab, "rms", rms, rep)
-    assert (rel <= TOL["f32"]).all()
+    rel_all = map_errors(y_gpu[:, idx], y_orc)[0]
+    print("whole brain sampled: well-posed", good.mean(), "rel", rel, "abs", ab, "rms", rms, "all", rel_all, rep)
+    assert (rel <= TOL["f32"]).all() and (rel_all <= TOL["f32"]).all()
     assert rep["nonfinite_voxels"] == 0
 
 

@@ -182,7 +182,7 @@ def test_projected_uncertainty_parity(torch_cuda, orc):
     assert np.array_equal(np.isfinite(v), ok)
     rel = np.abs(v[ok] - var_o[ok]) / var_o[ok]
     print("projected variance rel max", rel.max())
-    assert rel.max() <= 1e-3
+    assert rel.max() <= 1e-4
 
 
 def test_space_outside_the_field_of_view(torch_cuda, orc):

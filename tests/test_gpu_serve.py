@@ -1,7 +1,8 @@
 """GPU tests of the serving loop (mpm_server_*): continuous batching gives
-every fit the same result as running it alone, admission respects the memory
-budget, an over-budget request is rejected, and a cancelled request (queued or
-running) leaves the others intact."""
+every fit the same result as running it alone (small JTV-MAP fits in batched
+groups included), admission respects the memory budget, an over-budget
+request is rejected, and a cancelled request (queued, running, or running in a
+group) leaves the others intact."""
 import time
 
 import numpy as np
@@ -130,7 +131,8 @@ def test_cancel_queued_and_running(torch_cuda, orc):
     r3 = reqs[2]
     solo = torch.zeros((4, r3["N"]), dtype=torch.float32, device="cuda")
     rep_solo, _ = _lib.mpm_fit(r3["case"]["proto"], r3["case"]["dims"], r3["X"], r3["b1"], r3["opts"], solo)
-    with _lib.MpmServer(hbm_budget=16 << 30, max_active=1) as srv:  # one stream: one fit runs at a time
+    # one stream, no groups: one fit runs at a time
+    with _lib.MpmServer(hbm_budget=16 << 30, max_active=1, groups=False) as srv:
         outs = [torch.zeros((4, r["N"]), dtype=torch.float32, device="cuda") for r in reqs]
         tickets = [srv.submit(r["case"]["proto"], r["case"]["dims"], r["X"], r["b1"], r["opts"], o)
                    for r, o in zip(reqs, outs)]
@@ -158,3 +160,36 @@ def test_cancel_queued_and_running(torch_cuda, orc):
     torch.cuda.synchronize()
     assert np.array_equal(outs[2].cpu().numpy(), solo.cpu().numpy())
     assert rep["objective"] == rep_solo["objective"]
+
+
+def test_group_runs_batched_and_cancel_in_group(torch_cuda, orc):
+    """Small MAP fits waiting together run as one batched group: with one
+    stream, all four are running after the first step and each equals its fit
+    alone bit for bit; a member cancelled while running finishes with its
+    group as cancelled, the others are unaffected."""
+    torch = torch_cuda
+    reqs = [r for r in _requests(orc, torch) if r["opts"]["mode"] == "map"]
+    assert len(reqs) == 4
+    solo = []
+    for r in reqs:
+        m = torch.zeros((4, r["N"]), dtype=torch.float32, device="cuda")
+        rep, _ = _lib.mpm_fit(r["case"]["proto"], r["case"]["dims"], r["X"], r["b1"], r["opts"], m)
+        solo.append((m.cpu().numpy(), rep))
+    with _lib.MpmServer(hbm_budget=64 << 30, max_active=1) as srv:
+        outs = [torch.zeros((4, r["N"]), dtype=torch.float32, device="cuda") for r in reqs]
+        tickets = [srv.submit(r["case"]["proto"], r["case"]["dims"], r["X"], r["b1"], r["opts"], o)
+                   for r, o in zip(reqs, outs)]
+        assert srv.step() == 4
+        srv.cancel(tickets[1])  # running in the group
+        assert srv.poll(tickets[1]) is None  # finishes with its group
+        live = [t for i, t in enumerate(tickets) if i != 1]
+        reports = _drive(srv, live)
+        with pytest.raises(_lib.MpmError) as ei:
+            srv.poll(tickets[1])
+        assert ei.value.status == 7
+    torch.cuda.synchronize()
+    for i, ((ref, rep_a), o, t) in enumerate(zip(solo, outs, tickets)):
+        if i == 1:
+            continue
+        assert np.array_equal(o.cpu().numpy(), ref), i
+        assert reports[t] == rep_a
