@@ -57,6 +57,7 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_map_brain.txt")
 VALU_SOURCES = [os.path.join(ROOT, "paper_2102_01604_amd", "csrc", f)
                 for f in ("k_voxel.hip", "mpm_voxelwise.h", "mpm_device.h")]
 VALU_FILE = os.path.join(ROOT, "profiles", "valu_ml_fit_pv_e1.txt")
+ML_VALU_FILE = os.path.join(ROOT, "profiles", "valu_ml_fit_brain.txt")
 NOISE_SOURCES = [os.path.join(ROOT, "paper_2102_01604_amd", "csrc", f)
                  for f in ("k_noise.hip", "mpm_noise.h", "mpm_device.h")]
 NOISE_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_noise_hist_brain.txt")
@@ -92,6 +93,24 @@ def read_traffic(kernel, path=TRAFFIC_FILE, sources=KERNEL_SOURCES):
     try:
         return float(kv["bytes_per_launch"])
     except (KeyError, ValueError):
+        return None
+
+
+def read_ml_valu():
+    """VALU lane-instructions per voxel evaluation of the whole-brain ML kernel
+    from the committed counter summary; None if absent or taken on other sources."""
+    if not os.path.exists(ML_VALU_FILE):
+        return None
+    kv = {}
+    for line in open(ML_VALU_FILE):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("source_sha256_16") != source_hash(VALU_SOURCES):
+        return None
+    try:
+        return float(kv["SQ_INSTS_VALU_dispatch0_lanes_per_voxel_eval"])
+    except KeyError:
         return None
 
 
@@ -374,6 +393,18 @@ def main():
                 "avg_ms": round(avg_s * 1e3, 5),
                 "copy_GBps_same_size": round(copy_gbps, 1),
                 "frac_of_copy_rate": round(achieved / copy_gbps, 4)}
+    # the ML kernel against the VALU roofline: executed lane-instructions (from
+    # the committed counter summary) over its measured launch time
+    ml_valu = None
+    lanes = read_ml_valu()
+    if lanes is not None and "ml_fit" in stats and stats["ml_fit"]["timed"] > 0:
+        s_ = stats["ml_fit"]
+        t_ml = s_["timed_ms"] / s_["timed"] * 1e-3
+        evals = N * (ml_opts["n_gn"] + 1)
+        ach = lanes * evals / t_ml / 1e12
+        ml_valu = {"bound": "alu", "kernel": "ml_fit", "lanes_per_voxel_eval": lanes,
+                   "achieved": round(ach, 2), "peak": round(VALU_PEAK_T, 2), "unit": "T lane-instructions/s",
+                   "frac": round(ach / VALU_PEAK_T, 4), "avg_ms": round(t_ml * 1e3, 4)}
     # step level: the byte model of the whole step over the measured step time
     step_model = N * STEP_MODEL_BYTES_PER_VOXEL
     step_hbm = {"model_bytes_per_step": step_model,
@@ -419,6 +450,7 @@ def main():
                    "map_schedule": [10, 8, 32], "lambda": [round(v, 6) for v in lam]},
         "roofline": roof,
         "step_hbm": step_hbm,
+        "ml_valu_roofline": ml_valu,
         "cpu_baseline": cpu,
         "parity_vs_oracle": parity,
         "serving_burst": serve,

@@ -370,11 +370,12 @@ const char *mpm_last_error(void);
  * ML fit, or one Newton-like step of a MAP fit) on
  * its stream, so fits admitted at different times run concurrently on the
  * device and new arrivals join while others are in flight.  Small JTV-MAP
- * fits (fewer than 2^21 voxels) are admitted in groups: the first waiting one
- * takes later waiting fits that can share launches with it (mpm_fit_batch's
- * conditions; at most 16 fits and 2^22 voxels in all, within the budget) onto
- * its stream, and the group runs as one batched fit, every kernel launch
- * serving all its volumes.  Each fit, alone or in a group, runs the same
+ * fits (at most 2^19 voxels, whose launches are short enough that the
+ * device's dispatch latency dominates them) are admitted in groups: the first
+ * waiting one takes later waiting fits of at most twice or half its size that
+ * can share launches with it (mpm_fit_batch's conditions; at most 16 fits and
+ * 2^22 voxels in all, within the budget) onto its stream, and the group runs
+ * as one batched fit, every kernel launch serving all its volumes.  Each fit, alone or in a group, runs the same
  * kernel bodies with the same per-volume launch shapes as mpm_fit(), so its
  * result is the same as when it is run alone, bit for bit.  Flag
  * MPM_SERVER_NO_GROUPS keeps every fit on a stream of its own.

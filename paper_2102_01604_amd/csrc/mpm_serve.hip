@@ -38,8 +38,15 @@ constexpr int DEPTH = 2;  // pieces of one unit in flight at a time
 // short launch) and smaller MAP fits fill the gaps around it.
 constexpr int64_t LARGE_FIT_VOXELS = (int64_t)1 << 21;
 
-// Groups of small MAP fits: at most this many fits and this many voxels in
-// all (about what fills the device in one launch of the CG sweeps).
+// Groups of small MAP fits.  Only fits of at most GROUP_FIT_VOXELS join groups:
+// their CG sweeps last about as long as a launch's dispatch latency, which a
+// group pays once for all its members; a fit of 96 x 128 x 128 voxels already
+// streams its sweeps at nearly the bandwidth of the part (measured: 4 of them
+// batched 1.05x faster than one after another, 16 of 64^3 1.81x).  A group
+// holds fits whose sizes differ by at most 2x (it finishes with its largest
+// member), at most GROUP_MAX_FITS fits and GROUP_MAX_VOXELS voxels in all
+// (about what fills the device in one launch of the CG sweeps).
+constexpr int64_t GROUP_FIT_VOXELS = (int64_t)1 << 19;
 constexpr int GROUP_MAX_FITS = 16;
 constexpr int64_t GROUP_MAX_VOXELS = (int64_t)1 << 22;
 
@@ -77,7 +84,7 @@ struct Entry {
 };
 
 bool is_large(const Entry &e) { return e.req.options.mode == MPM_MAP_JTV && e.N >= LARGE_FIT_VOXELS; }
-bool groupable(const Entry &e) { return e.req.options.mode == MPM_MAP_JTV && e.N < LARGE_FIT_VOXELS; }
+bool groupable(const Entry &e) { return e.req.options.mode == MPM_MAP_JTV && e.N <= GROUP_FIT_VOXELS; }
 
 }  // namespace
 
@@ -256,7 +263,8 @@ void step_locked(mpm_server *s)
             size_t mem = s->used + e.footprint;
             for (auto jt = it; jt != s->queue.end() && (int)group.size() < GROUP_MAX_FITS;) {
                 Entry &f = *s->entries[*jt];
-                if (groupable(f) && vox + f.N <= GROUP_MAX_VOXELS && mem + f.footprint <= s->budget &&
+                const bool similar = f.N <= 2 * e.N && e.N <= 2 * f.N;
+                if (groupable(f) && similar && vox + f.N <= GROUP_MAX_VOXELS && mem + f.footprint <= s->budget &&
                     batch_compatible(a0, args_of(f, nullptr))) {
                     group.push_back(&f);
                     vox += f.N;

@@ -5,6 +5,7 @@
                                                    <WRITE run_counter_collection.csv> <kernel> <voxels> [last]
 
     python -m paper_2102_01604_amd.profile_summary valu <run_counter_collection.csv> <kernel> <voxels> <steps>
+    python -m paper_2102_01604_amd.profile_summary counters <run_counter_collection.csv> <kernel> [last]
 
 `trace` prints a markdown table of per-kernel call counts and durations.
 `valu` prints the executed VALU instructions (SQ_INSTS_VALU, per wavefront,
@@ -12,6 +13,8 @@ so x 64 lanes) and transcendental ones (SQ_INSTS_VALU_TRANS_F32) per voxel
 and evaluation, for each dispatch of a voxelwise kernel that evaluates the
 likelihood steps + 1 times per voxel, tagged with the hash of the voxel
 kernel sources.
+`counters` prints the mean per dispatch of every counter a run collected for
+one kernel.
 `traffic` prints the HBM bytes per dispatch of one kernel (averaged over its
 last `last` dispatches, default all): FETCH_SIZE and WRITE_SIZE (KiB per
 dispatch) scaled by what the same counters read for a
@@ -110,10 +113,26 @@ def valu(csv_path, kernel, voxels, steps):
     print(f"source_sha256_16: {h.hexdigest()[:16]}")
 
 
+def counters(csv_path, kernel, last=0):
+    """Mean value per dispatch of every counter of one kernel (its last `last`
+    dispatches, default all)."""
+    per = {}
+    for r in csv.DictReader(open(csv_path)):
+        if _short(r["Kernel_Name"]).split("<")[0].endswith(kernel):
+            per.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    print(f"kernel: {kernel}")
+    for c in sorted(per):
+        v = per[c][-last:] if last else per[c]
+        print(f"{c}_dispatches: {len(v)}")
+        print(f"{c}_per_dispatch: {statistics.mean(v):.6g}")
+
+
 if __name__ == "__main__":
     if sys.argv[1] == "trace":
         trace(sys.argv[2])
     elif sys.argv[1] == "valu":
         valu(sys.argv[2], sys.argv[3], int(sys.argv[4]), int(sys.argv[5]))
+    elif sys.argv[1] == "counters":
+        counters(sys.argv[2], sys.argv[3], int(sys.argv[4]) if len(sys.argv) > 4 else 0)
     else:
         traffic(sys.argv[2], sys.argv[3], sys.argv[4], int(sys.argv[5]), int(sys.argv[6]) if len(sys.argv) > 6 else 0)

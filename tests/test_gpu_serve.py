@@ -168,8 +168,13 @@ def test_group_runs_batched_and_cancel_in_group(torch_cuda, orc):
     alone bit for bit; a member cancelled while running finishes with its
     group as cancelled, the others are unaffected."""
     torch = torch_cuda
-    reqs = [r for r in _requests(orc, torch) if r["opts"]["mode"] == "map"]
-    assert len(reqs) == 4
+    reqs = []
+    for dims, seed in (((40, 33, 12), 11), ((24, 20, 30), 12), ((31, 31, 9), 13), ((30, 25, 20), 14)):
+        c = synth.make_case("map_brain", dims=dims, seed=seed)  # sizes within 2x of each other
+        c["b1"] = f32(c["b1"])
+        x = observations(orc, c)
+        reqs.append({"case": c, "opts": dict(c["opts"], n_outer=3, n_gn=3, n_cg=12), "X": cuda(x),
+                     "b1": cuda(c["b1"].astype(np.float32)), "N": x.shape[1]})
     solo = []
     for r in reqs:
         m = torch.zeros((4, r["N"]), dtype=torch.float32, device="cuda")
@@ -180,16 +185,19 @@ def test_group_runs_batched_and_cancel_in_group(torch_cuda, orc):
         tickets = [srv.submit(r["case"]["proto"], r["case"]["dims"], r["X"], r["b1"], r["opts"], o)
                    for r, o in zip(reqs, outs)]
         assert srv.step() == 4
+        srv.cancel(tickets[3])  # running in the group: with one stream, only as a member of it
+        assert srv.poll(tickets[3]) is None
         srv.cancel(tickets[1])  # running in the group
         assert srv.poll(tickets[1]) is None  # finishes with its group
-        live = [t for i, t in enumerate(tickets) if i != 1]
+        live = [t for i, t in enumerate(tickets) if i not in (1, 3)]
         reports = _drive(srv, live)
-        with pytest.raises(_lib.MpmError) as ei:
-            srv.poll(tickets[1])
-        assert ei.value.status == 7
+        for i in (1, 3):
+            with pytest.raises(_lib.MpmError) as ei:
+                srv.poll(tickets[i])
+            assert ei.value.status == 7
     torch.cuda.synchronize()
     for i, ((ref, rep_a), o, t) in enumerate(zip(solo, outs, tickets)):
-        if i == 1:
+        if i in (1, 3):
             continue
         assert np.array_equal(o.cpu().numpy(), ref), i
         assert reports[t] == rep_a
