@@ -172,6 +172,9 @@ def main():
     ap.add_argument("--batch", action="store_true",
                     help="batched JTV-MAP fits (mpm_fit_batch) against the same fits one after another: 16 volumes "
                          "of 64^3 and 4 of 96 x 128 x 128, 10 x 8 x 32 each; one JSON line")
+    ap.add_argument("--oracle-full", action="store_true",
+                    help="CPU only: the FP64 oracle on the whole benchmark volume (ML 20 GN, MAP 10 x 8 x 32, "
+                         "variance), each stage timed; one JSON line (tens of minutes)")
     ap.add_argument("--autotune", action="store_true",
                     help="mpm_autotune on the four serving volume sizes: the CG sweep A time per workgroup count")
     ap.add_argument("--e1-voxels", type=int, default=1 << 20)
@@ -198,6 +201,10 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the fits are single-GPU; "
               "a z-slab decomposition across GPUs is not built.", file=sys.stderr)
         sys.exit(2)
+
+    if args.oracle_full:
+        oracle_full(args)
+        return
 
     import torch
 
@@ -1075,6 +1082,48 @@ def cpu_baseline(case, dims):
                           "sample": f"central {cd1[0]}x{cd1[1]}x{cd1[2]} crop ({len(idx1)} voxels), "
                                     "the same three stages"}}
     return rec, {"dims": cd, "x": x, "b1": b1, "truth": truth, "ml": ml, "map": mp}
+
+
+def oracle_full(args):
+    """The FP64 oracle on the whole benchmark volume (the timed step's three
+    stages, default initialisation), each stage timed: the CPU baseline at full
+    size.  Runs on the host only."""
+    import oracle
+    from paper_2102_01604_amd import synth
+    dims = tuple(int(v) for v in args.dims.split(","))
+    case = synth.make_case("map_brain", dims=dims)
+    N = int(np.prod(dims))
+    log(f"oracle at full size: {dims}, {oracle.num_threads()} threads")
+    b1 = case["b1"].astype(np.float32).astype(np.float64)
+    x = np.empty((len(case["proto"]["te"]), N))
+    step = 1 << 21
+    for s0 in range(0, N, step):
+        sl = slice(s0, min(N, s0 + step))
+        sim = oracle.simulate(case["proto"], case["truth"][:, sl], b1[sl])
+        x[:, sl] = (sim + case["sigma"] * case["eps"][:, sl].astype(np.float64)).astype(np.float32)
+    del case["eps"]
+    lam = case["lam"]
+    t = {}
+    t0 = time.perf_counter()
+    oracle.fit(case["proto"], dims, x, b1, {"mode": "ml", "n_gn": 20})
+    t["ml_s"] = time.perf_counter() - t0
+    log(f"ML {t['ml_s']:.1f} s")
+    t0 = time.perf_counter()
+    maps, rep, _ = oracle.fit(case["proto"], dims, x, b1, {"mode": "map", "n_outer": 10, "n_gn": 8, "n_cg": 32,
+                                                          "max_halvings": 4, "lam": lam})
+    t["map_s"] = time.perf_counter() - t0
+    log(f"MAP {t['map_s']:.1f} s")
+    t0 = time.perf_counter()
+    oracle.uncertainty(case["proto"], dims, x, b1, {"mode": "map", "lam": lam}, maps, moments=True)
+    t["var_s"] = time.perf_counter() - t0
+    total = t["ml_s"] + t["map_s"] + t["var_s"]
+    out = {"metric": "voxel-iters/s (GN+JTV-CG), FP64 oracle at full size", "value": round(N * 100 / total, 1),
+           "unit": "voxel-GN-iterations/s", "cores": oracle.num_threads(), "cpu_model": cpu_model(),
+           "kind": "oracle", "seconds": {k: round(v, 1) for k, v in t.items()}, "total_s": round(total, 1),
+           "map_voxel_cg_iters_per_s": round(N * rep["cg_done"] / t["map_s"], 1), "map_report": rep,
+           "config": {"workload": f"SPGR-ML 20 GN + SPGR+JTV-MAP 10x8x32 + Laplace variance, "
+                                  f"{dims[0]}x{dims[1]}x{dims[2]} grid, 8/8/6 echoes, B1 0.8-1.2", "voxels": N}}
+    print(json.dumps(out), flush=True)
 
 
 def map_error(gpu, orc, truth):

@@ -77,6 +77,31 @@ __device__ __forceinline__ bool precond(const float H[10], const float lam[4], f
     return solve_sym4(M, r, z);
 }
 
+constexpr int FIN_THREADS = 1024;
+
+// Sum of row[0..ncols) in a fixed order; four independent accumulators per
+// thread keep several loads in flight.  The result is valid in every thread.
+__device__ __forceinline__ double reduce_row(const double *__restrict__ row, int ncols, double *lds)
+{
+    const int t = threadIdx.x;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int b = t;
+    for (; b + 3 * FIN_THREADS < ncols; b += 4 * FIN_THREADS) {
+        a0 += row[b];
+        a1 += row[b + FIN_THREADS];
+        a2 += row[b + 2 * FIN_THREADS];
+        a3 += row[b + 3 * FIN_THREADS];
+    }
+    for (; b < ncols; b += FIN_THREADS) a0 += row[b];
+    double v = wave_sum((a0 + a1) + (a2 + a3));
+    if ((t & 63) == 0) lds[t >> 6] = v;
+    __syncthreads();
+    double r = 0.0;
+    for (int i = 0; i < FIN_THREADS / 64; i++) r += lds[i];
+    __syncthreads();
+    return r;
+}
+
 // ---------------------------------------------------------------------------
 // control block
 // ---------------------------------------------------------------------------
@@ -218,16 +243,46 @@ __device__ __forceinline__ void tall_neighbours(const Col &c, const Grid3 &g, in
     }
 }
 
+// Folded finalising of the CG sweeps (MapArgs::fold): the partials of the
+// previous sweep, their count, and CG's relative stop level.
+struct CgFold {
+    int on;
+    int nblk_prev;
+    const double *prev;
+    double cg_stop_rel;
+};
+
+template <bool FOLD>
 __device__ __forceinline__ void cg_a_body(const Grid3 &g, int it, const HessArrays &Hs, const float *__restrict__ w,
                                           float l0, float l1, float l2, float l3, const float4 *__restrict__ Z,
                                           const float4 *__restrict__ Pold, float4 *__restrict__ Pnew,
-                                          float4 *__restrict__ D, const MapCtl *__restrict__ ctl,
-                                          double *__restrict__ partials, int Lb, int Tb)
+                                          float4 *__restrict__ D, MapCtl *ctl, double *__restrict__ partials,
+                                          const CgFold &fold, int Lb, int Tb)
 {
     if (ctl->gn_stop || ctl->cg_stop) return;
     __shared__ TallLds L;
     const float lam[4] = {l0, l1, l2, l3};
-    const float beta = it > 0 ? (float)ctl->beta : 0.0f;
+    float beta = 0.0f;
+    if (FOLD && it > 0) {
+        // the finaliser of the previous sweep B, in every workgroup (same
+        // fixed order, so every workgroup gets the same value); the first
+        // workgroup records it for the kernels after this one
+        __shared__ double red[FIN_THREADS / 64];
+        const double gn = reduce_row(fold.prev, fold.nblk_prev, red);
+        const double gold = ctl->gam[(it - 1) & 1];
+        const bool stop = !(gn > fold.cg_stop_rel * ctl->gamma0) || !(gn > 0.0);
+        if (Lb == 0 && threadIdx.x == 0) {
+            ctl->cg_done++;
+            if (stop) ctl->cg_stop = 1;
+            ctl->beta = gn / gold;
+            ctl->gamma = gn;
+            ctl->gam[it & 1] = gn;
+        }
+        if (stop) return;
+        beta = (float)(gn / gold);
+    } else if (it > 0) {
+        beta = (float)ctl->beta;
+    }
     const float alpha_prev = (float)ctl->alpha_pend;
     const Col c = locate_col(g, Lb, Tb);
     const int tx = threadIdx.x & (TILE_X - 1), ty = threadIdx.x / TILE_X;
@@ -312,14 +367,15 @@ __device__ __forceinline__ void cg_a_body(const Grid3 &g, int it, const HessArra
     }
 }
 
+template <bool FOLD>
 __global__ __launch_bounds__(TALL_THREADS) void k_cg_a(Grid3 g, int it, HessArrays Hs,
                                                             const float *__restrict__ w, float l0, float l1, float l2,
                                                             float l3, const float4 *__restrict__ Z,
                                                             const float4 *__restrict__ Pold, float4 *__restrict__ Pnew,
-                                                            float4 *__restrict__ D, const MapCtl *__restrict__ ctl,
-                                                            double *__restrict__ partials)
+                                                            float4 *__restrict__ D, MapCtl *ctl,
+                                                            double *__restrict__ partials, CgFold fold)
 {
-    cg_a_body(g, it, Hs, w, l0, l1, l2, l3, Z, Pold, Pnew, D, ctl, partials, blockIdx.x, gridDim.x);
+    cg_a_body<FOLD>(g, it, Hs, w, l0, l1, l2, l3, Z, Pold, Pnew, D, ctl, partials, fold, blockIdx.x, gridDim.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -332,6 +388,8 @@ __global__ __launch_bounds__(TALL_THREADS) void k_cg_a(Grid3 g, int it, HessArra
 // ---------------------------------------------------------------------------
 constexpr int CGB_Y = 16;
 constexpr int CGB_THREADS = TILE_X * CGB_Y;
+// the folded finalising reduces in the finaliser's own order (reduce_row)
+static_assert(TALL_THREADS == FIN_THREADS && CGB_THREADS == FIN_THREADS, "CG sweeps run FIN_THREADS threads");
 
 template <int THREADS>
 __device__ __forceinline__ void write_partial1(double v, double *__restrict__ partials, int L)
@@ -348,14 +406,32 @@ __device__ __forceinline__ void write_partial1(double v, double *__restrict__ pa
     }
 }
 
-__device__ __forceinline__ void cg_b_body(const Grid3 &g, const HessArrays &Hs, const float *__restrict__ w, float l0,
-                                          float l1, float l2, float l3, const float4 *__restrict__ Pc,
-                                          float4 *__restrict__ R, float4 *__restrict__ Z,
-                                          const MapCtl *__restrict__ ctl, double *__restrict__ partials, int L, int T)
+template <bool FOLD>
+__device__ __forceinline__ void cg_b_body(const Grid3 &g, int it, const HessArrays &Hs, const float *__restrict__ w,
+                                          float l0, float l1, float l2, float l3, const float4 *__restrict__ Pc,
+                                          float4 *__restrict__ R, float4 *__restrict__ Z, MapCtl *ctl,
+                                          double *__restrict__ partials, const CgFold &fold, int L, int T)
 {
     if (ctl->gn_stop || ctl->cg_stop) return;
     const float lam[4] = {l0, l1, l2, l3};
-    const float alpha = (float)ctl->alpha_pend;
+    float alpha;
+    if (FOLD) {
+        // the finaliser of sweep A of this iteration, in every workgroup
+        __shared__ double red[FIN_THREADS / 64];
+        const double pq = reduce_row(fold.prev, fold.nblk_prev, red);
+        const bool stop = !(pq > 0.0);
+        const double a = stop ? 0.0 : ctl->gam[it & 1] / pq;
+        if (L == 0 && threadIdx.x == 0) {
+            if (it >= 1) ctl->delta_valid = 1;
+            ctl->p_buf = it & 1;
+            ctl->alpha_pend = a;
+            if (stop) ctl->cg_stop = 1;
+        }
+        if (stop) return;
+        alpha = (float)a;
+    } else {
+        alpha = (float)ctl->alpha_pend;
+    }
     const Col c = locate_col(g, L, T);
     double part = 0.0;
     if (c.act) {
@@ -386,12 +462,14 @@ __device__ __forceinline__ void cg_b_body(const Grid3 &g, const HessArrays &Hs, 
     write_partial1<CGB_THREADS>(part, partials, L);
 }
 
-__global__ __launch_bounds__(CGB_THREADS) void k_cg_b(Grid3 g, HessArrays Hs, const float *__restrict__ w, float l0,
-                                                         float l1, float l2, float l3, const float4 *__restrict__ Pc,
-                                                         float4 *__restrict__ R, float4 *__restrict__ Z,
-                                                         const MapCtl *__restrict__ ctl, double *__restrict__ partials)
+template <bool FOLD>
+__global__ __launch_bounds__(CGB_THREADS) void k_cg_b(Grid3 g, int it, HessArrays Hs, const float *__restrict__ w,
+                                                         float l0, float l1, float l2, float l3,
+                                                         const float4 *__restrict__ Pc, float4 *__restrict__ R,
+                                                         float4 *__restrict__ Z, MapCtl *ctl,
+                                                         double *__restrict__ partials, CgFold fold)
 {
-    cg_b_body(g, Hs, w, l0, l1, l2, l3, Pc, R, Z, ctl, partials, blockIdx.x, gridDim.x);
+    cg_b_body<FOLD>(g, it, Hs, w, l0, l1, l2, l3, Pc, R, Z, ctl, partials, fold, blockIdx.x, gridDim.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -685,31 +763,6 @@ __global__ __launch_bounds__(BLOCK) void k_final_plus(FINAL_PARAMS)
 // one-workgroup finalisers: fixed-order reduction of the partials, then the
 // scalar logic of the step
 // ---------------------------------------------------------------------------
-constexpr int FIN_THREADS = 1024;
-
-// Sum of row[0..ncols) in a fixed order; four independent accumulators per
-// thread keep several loads in flight.  The result is valid in every thread.
-__device__ __forceinline__ double reduce_row(const double *__restrict__ row, int ncols, double *lds)
-{
-    const int t = threadIdx.x;
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-    int b = t;
-    for (; b + 3 * FIN_THREADS < ncols; b += 4 * FIN_THREADS) {
-        a0 += row[b];
-        a1 += row[b + FIN_THREADS];
-        a2 += row[b + 2 * FIN_THREADS];
-        a3 += row[b + 3 * FIN_THREADS];
-    }
-    for (; b < ncols; b += FIN_THREADS) a0 += row[b];
-    double v = wave_sum((a0 + a1) + (a2 + a3));
-    if ((t & 63) == 0) lds[t >> 6] = v;
-    __syncthreads();
-    double r = 0.0;
-    for (int i = 0; i < FIN_THREADS / 64; i++) r += lds[i];
-    __syncthreads();
-    return r;
-}
-
 // Early stopping (reading of the gain in Sec. 2.7): a step from F to Fn ends
 // its outer loop when its decrease is below tol times the decrease since the
 // loop's first F_w (or there was none); the flag takes effect after the
@@ -746,6 +799,7 @@ __device__ __forceinline__ void fin_body(int stage, int arg, int nblk, const dou
         c.yLy = s[1];
         c.F = s[0] + 0.5 * s[1];
         c.gamma = c.gamma0 = s[2];
+        c.gam[0] = s[2];
         c.alpha_pend = 0.0;
         c.beta = 0.0;
         c.step = 0.0;
@@ -921,13 +975,29 @@ hipError_t launch_lik(hipStream_t s, const MapArgs &a)
     return hipGetLastError();
 }
 
+// With folded finalising sweep A writes partial row 0 and reads sweep B's
+// row 1; sweep B the other way round.
+static CgFold fold_a(const MapArgs &a)
+{
+    return CgFold{a.fold, a.nb_b, a.partials + a.pstride, a.cg_stop_rel};
+}
+
+static CgFold fold_b(const MapArgs &a)
+{
+    return CgFold{a.fold, a.nb_a, a.partials, a.cg_stop_rel};
+}
+
 hipError_t launch_cg_a(hipStream_t s, const MapArgs &a, int it)
 {
     const float *l = a.lam;
     const float4 *pold = (it & 1) ? a.P0 : a.P1;
     float4 *pnew = (it & 1) ? a.P1 : a.P0;
-    hipLaunchKernelGGL(k_cg_a, cols(a.gt), dim3(TALL_THREADS), 0, s, a.gt, it, a.H, a.w, l[0], l[1], l[2], l[3], a.Z,
-                       pold, pnew, a.D, a.ctl, a.partials);
+    if (a.fold)
+        hipLaunchKernelGGL(k_cg_a<true>, cols(a.gt), dim3(TALL_THREADS), 0, s, a.gt, it, a.H, a.w, l[0], l[1], l[2],
+                           l[3], a.Z, pold, pnew, a.D, a.ctl, a.partials, fold_a(a));
+    else
+        hipLaunchKernelGGL(k_cg_a<false>, cols(a.gt), dim3(TALL_THREADS), 0, s, a.gt, it, a.H, a.w, l[0], l[1], l[2],
+                           l[3], a.Z, pold, pnew, a.D, a.ctl, a.partials, fold_a(a));
     return hipGetLastError();
 }
 
@@ -935,8 +1005,12 @@ hipError_t launch_cg_b(hipStream_t s, const MapArgs &a, int it)
 {
     const float *l = a.lam;
     const float4 *pc = (it & 1) ? a.P1 : a.P0;
-    hipLaunchKernelGGL(k_cg_b, cols(a.gv), dim3(CGB_THREADS), 0, s, a.gv, a.H, a.w, l[0], l[1], l[2], l[3], pc, a.R,
-                       a.Z, a.ctl, a.partials);
+    if (a.fold)
+        hipLaunchKernelGGL(k_cg_b<true>, cols(a.gv), dim3(CGB_THREADS), 0, s, a.gv, it, a.H, a.w, l[0], l[1], l[2],
+                           l[3], pc, a.R, a.Z, a.ctl, a.partials + a.pstride, fold_b(a));
+    else
+        hipLaunchKernelGGL(k_cg_b<false>, cols(a.gv), dim3(CGB_THREADS), 0, s, a.gv, it, a.H, a.w, l[0], l[1], l[2],
+                           l[3], pc, a.R, a.Z, a.ctl, a.partials, fold_b(a));
     return hipGetLastError();
 }
 
@@ -984,10 +1058,10 @@ hipError_t launch_final(hipStream_t s, const MapArgs &a, float *var, float *mom)
 }
 
 hipError_t launch_fin(hipStream_t s, const MapArgs &a, int stage, int arg, int nblk, double cg_stop_rel,
-                      int ntrial, int accept_off, const ExtRows &ext)
+                      int ntrial, int accept_off, const ExtRows &ext, int row)
 {
-    hipLaunchKernelGGL(k_fin, dim3(1), dim3(FIN_THREADS), 0, s, stage, arg, nblk, a.partials, a.ctl, a.trace,
-                       cg_stop_rel, ntrial, accept_off, ext, a.tol_gn, a.tol_outer);
+    hipLaunchKernelGGL(k_fin, dim3(1), dim3(FIN_THREADS), 0, s, stage, arg, nblk, a.partials + (int64_t)row * a.pstride,
+                       a.ctl, a.trace, cg_stop_rel, ntrial, accept_off, ext, a.tol_gn, a.tol_outer);
     return hipGetLastError();
 }
 
@@ -1083,8 +1157,8 @@ __global__ __launch_bounds__(TALL_THREADS) void k_cg_a_batch(const BatchTab *__r
     const MapArgs &m = ((const VolDesc<DevProto> *)((const char *)vols + stride * v))->m;
     const float4 *pold = (it & 1) ? m.P0 : m.P1;
     float4 *pnew = (it & 1) ? m.P1 : m.P0;
-    cg_a_body(m.gt, it, m.H, m.w, m.lam[0], m.lam[1], m.lam[2], m.lam[3], m.Z, pold, pnew, m.D, m.ctl, m.partials, L,
-              Tn);
+    cg_a_body<false>(m.gt, it, m.H, m.w, m.lam[0], m.lam[1], m.lam[2], m.lam[3], m.Z, pold, pnew, m.D, m.ctl,
+                     m.partials, CgFold{0, 0, nullptr, 0.0}, L, Tn);
 }
 
 __global__ __launch_bounds__(CGB_THREADS) void k_cg_b_batch(const BatchTab *__restrict__ tab,
@@ -1095,7 +1169,8 @@ __global__ __launch_bounds__(CGB_THREADS) void k_cg_b_batch(const BatchTab *__re
     if (v < 0) return;
     const MapArgs &m = ((const VolDesc<DevProto> *)((const char *)vols + stride * v))->m;
     const float4 *pc = (it & 1) ? m.P1 : m.P0;
-    cg_b_body(m.gv, m.H, m.w, m.lam[0], m.lam[1], m.lam[2], m.lam[3], pc, m.R, m.Z, m.ctl, m.partials, L, Tn);
+    cg_b_body<false>(m.gv, it, m.H, m.w, m.lam[0], m.lam[1], m.lam[2], m.lam[3], pc, m.R, m.Z, m.ctl, m.partials,
+                     CgFold{0, 0, nullptr, 0.0}, L, Tn);
 }
 
 template <typename T, int CM, int EM>
@@ -1161,14 +1236,15 @@ __global__ __launch_bounds__(BLOCK) void k_final_batch(const BatchTab *__restric
 // one workgroup per volume
 __global__ __launch_bounds__(FIN_THREADS) void k_fin_batch(const BatchTab *__restrict__ tab,
                                                            const void *__restrict__ vols, size_t stride, int stage,
-                                                           int arg, int kind, double cg_stop_rel, int ntrial,
-                                                           int accept_off, double tol_gn, double tol_outer)
+                                                           int arg, int kind, int row, double cg_stop_rel,
+                                                           int ntrial, int accept_off, double tol_gn,
+                                                           double tol_outer)
 {
     const int v = blockIdx.x;
     const MapArgs &m = ((const VolDesc<DevProto> *)((const char *)vols + stride * v))->m;
     const int nblk = kind >= 0 ? tab->count[kind][v] : 0;
-    fin_body(stage, arg, nblk, m.partials, m.ctl, m.trace, cg_stop_rel, ntrial, accept_off, ExtRows(), tol_gn,
-             tol_outer);
+    fin_body(stage, arg, nblk, m.partials + (int64_t)row * m.pstride, m.ctl, m.trace, cg_stop_rel, ntrial,
+             accept_off, ExtRows(), tol_gn, tol_outer);
 }
 
 // --- host side of the batched launches ---
@@ -1344,11 +1420,11 @@ hipError_t launch_final_batch(hipStream_t s, const BatchLaunch &b)
 }
 
 hipError_t launch_fin_batch(hipStream_t s, const BatchLaunch &b, int stage, int arg, int kind, double cg_stop_rel,
-                            int ntrial, int accept_off, double tol_gn, double tol_outer)
+                            int ntrial, int accept_off, double tol_gn, double tol_outer, int row)
 {
     hipLaunchKernelGGL(k_fin_batch, dim3(b.n), dim3(FIN_THREADS), 0, s, b.tab, b.vols,
-                       batch_desc_bytes(b.dtype, b.shape), stage, arg, kind, cg_stop_rel, ntrial, accept_off, tol_gn,
-                       tol_outer);
+                       batch_desc_bytes(b.dtype, b.shape), stage, arg, kind, row, cg_stop_rel, ntrial, accept_off,
+                       tol_gn, tol_outer);
     return hipGetLastError();
 }
 

@@ -78,6 +78,7 @@ struct MapCtl {
     double F;           // F_w at the current maps
     double yLy;         // y^T L y at the current maps
     double gamma, gamma0, alpha_pend, beta;
+    double gam[2];      // r.z of CG iteration k in slot k & 1 (the sweeps' own finalising)
     double step;        // accepted step length of this Newton step (0: none)
     double nll_cur;     // NLL at the current maps
     double jtv;         // smoothed JTV at the last weight refresh
@@ -287,7 +288,15 @@ struct MapArgs {
     float eps;
     int loading;
     MapCtl *ctl;
-    double *partials;   // [MAX_TRIALS + 2][nblk]
+    double *partials;   // [MAX_TRIALS + 2][pstride]
+    int pstride;        // row stride of partials (the largest workgroup count of any grid)
+    int nb_a, nb_b;     // workgroups (partials) of CG sweeps A and B
+    // The CG sweeps finalise each other: sweep B reduces sweep A's partials
+    // (row 0) and sweep A the previous sweep B's (row 1) itself, in every
+    // workgroup and in the finaliser's order, instead of a one-workgroup
+    // finaliser launch between them.  Used where the partials are few.
+    int fold;
+    double cg_stop_rel;
     double *trace;      // device copy of the objective trace
     double tol_gn, tol_outer;  // early-stopping tolerances (0: fixed counts)
 };
@@ -312,7 +321,16 @@ struct ExtRows {
     int stride = 0, cols = 0, rows = 0;
 };
 hipError_t launch_fin(hipStream_t s, const MapArgs &a, int stage, int arg, int nblk, double cg_stop_rel,
-                      int ntrial, int accept_off, const ExtRows &ext = ExtRows());
+                      int ntrial, int accept_off, const ExtRows &ext = ExtRows(), int row = 0);
+// Folded CG finalising is used when both sweeps have at most this many
+// workgroups: about one round of resident workgroups, so the reduction at the
+// start of a sweep adds its latency once (≈2 us) against the ≈5.6 us of a
+// finaliser launch saved.  Measured on 64^3 MAP fits (256 partials per sweep):
+// 53 vs 61 ms; with 2048 partials (96 x 128 x 128) the reduction in every
+// workgroup of four rounds cost more than the launch (271 vs 254 ms), and in
+// batched launches, which share one finaliser launch among their volumes, it
+// did not pay either (16 x 64^3: 0.56 vs 0.54 s), so batches do not fold.
+constexpr int FOLD_MAX_PARTIALS = 512;
 
 // ---------------------------------------------------------------------------
 // Batched launches: one launch of a MAP kernel serves several volumes (their
@@ -361,6 +379,6 @@ hipError_t launch_final_batch(hipStream_t s, const BatchLaunch &b);
 // kind: the grid whose per-volume workgroup count is the partial count
 // (BK_NONE: no partials)
 hipError_t launch_fin_batch(hipStream_t s, const BatchLaunch &b, int stage, int arg, int kind, double cg_stop_rel,
-                            int ntrial, int accept_off, double tol_gn, double tol_outer);
+                            int ntrial, int accept_off, double tol_gn, double tol_outer, int row = 0);
 
 }  // namespace mpm

@@ -56,6 +56,11 @@ static mpm_status alloc_map(const FitArgs &a, Workspace &ws, MapArgs &m, int tra
         ws.alloc((void **)&m.ctl, sizeof(MapCtl)) != hipSuccess ||
         ws.alloc((void **)&m.trace, sizeof(double) * (size_t)(trace_len > 0 ? trace_len : 1)) != hipSuccess)
         return fail(MPM_ERR_OUT_OF_MEMORY, "MAP workspace allocation failed (%zu bytes)", nf * sizeof(float));
+    m.pstride = nblk;
+    m.nb_a = grid_blocks(m.gt);
+    m.nb_b = grid_blocks(m.gv);
+    m.fold = m.nb_a <= FOLD_MAX_PARTIALS && m.nb_b <= FOLD_MAX_PARTIALS;
+    m.cg_stop_rel = a.opt->cg_stop;
     float4 *v4 = (float4 *)big;  // 16-byte aligned (hipMallocAsync)
     m.H.d = v4;
     m.H.o = v4 + N;
@@ -217,9 +222,9 @@ struct MapJob : FitJob {
         return MPM_OK;
     }
 
-    hipError_t fin(int stage, int arg, int nblk, const ExtRows &ext = ExtRows())
+    hipError_t fin(int stage, int arg, int nblk, const ExtRows &ext = ExtRows(), int row = 0)
     {
-        return launch_fin(a.stream, m, stage, arg, nblk, a.opt->cg_stop, ntrial, accept_off, ext);
+        return launch_fin(a.stream, m, stage, arg, nblk, a.opt->cg_stop, ntrial, accept_off, ext, row);
     }
 
     // acquisition-space likelihood of every contrast, then the push
@@ -305,9 +310,12 @@ struct MapJob : FitJob {
             for (int i = 0; i < K && e == hipSuccess; i++) {
                 double ab = 16 + (i > 0 ? 16 : 0) + 40 + 4 + 16 + (i == 1 ? 16 : i >= 2 ? 32 : 0);
                 RUN("cg_a", N * ab, launch_cg_a(s, m, i));
-                RUN("fin", 0.0, fin(FIN_A, i, nb_cga));
+                if (!m.fold) RUN("fin", 0.0, fin(FIN_A, i, nb_cga));
                 RUN("cg_b", N * (16 + 4 + 40 + 32 + 16), launch_cg_b(s, m, i));
-                RUN("fin", 0.0, fin(FIN_B, i, nb_cgb));
+                // folded: each sweep finalises the one before it; the last sweep B
+                // is finalised by a launch of its own (its partials are in row 1)
+                if (!m.fold) RUN("fin", 0.0, fin(FIN_B, i, nb_cgb));
+                else if (i == K - 1) RUN("fin", 0.0, fin(FIN_B, i, nb_cgb, ExtRows(), 1));
             }
             if (!proj) {
                 RUN("map_accept", N * (xb + bb + 16 + 16 + 16 + 4), launch_accept(s, m));
@@ -470,6 +478,8 @@ struct BatchMapJob : BatchJob {
             xvox += N * a[v].P.I * dtype_size(a[v].dtype);
             bvox += N * ((a[v].b1 ? 4.0 : 0.0) + (a[v].opt->b1_receive ? 4.0 : 0.0));
         }
+        // batched launches share one finaliser launch among their volumes: no folding
+        for (int v = 0; v < n; v++) m[v].fold = 0;
         b.n = n;
         b.dtype = a[0].dtype;
         b.shape = echo_shape(a[0].P);
