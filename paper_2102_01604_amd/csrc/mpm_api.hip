@@ -408,27 +408,44 @@ mpm_status run_fit(const FitArgs &a, Workspace &ws, mpm_report *report, double *
     return MPM_OK;
 }
 
-// Per-image means and the mean b1, reduced on the device in FP64.
-mpm_status image_means(Workspace &ws, Prof &prof, const DevProto &P, int dtype, const void *X,
-                       const float *b1, int64_t N, std::vector<double> &mean, double &b1m)
+int image_sum_rows(const DevProto &P) { return 2 * P.I + 1; }
+
+mpm_status enqueue_image_sums(Workspace &ws, Prof &prof, const DevProto &P, int dtype, const void *X,
+                              const float *b1, int64_t N, double **sums)
 {
     LaunchCtx c{ws.stream};
     int nblk = echo_sums_blocks(N);
-    const int rows = 2 * P.I + 1;
-    double *part = nullptr, *sums = nullptr;
+    const int rows = image_sum_rows(P);
+    double *part = nullptr;
     if (ws.alloc((void **)&part, sizeof(double) * (size_t)nblk * rows) != hipSuccess ||
-        ws.alloc((void **)&sums, sizeof(double) * rows) != hipSuccess)
+        ws.alloc((void **)sums, sizeof(double) * rows) != hipSuccess)
         return fail(MPM_ERR_OUT_OF_MEMORY, "workspace allocation failed");
     hipError_t e = prof.launch("echo_sums", (double)N * ((double)P.I * dtype_size(dtype) + (b1 ? 4 : 0)),
                                [&] { return launch_echo_sums(c, P, dtype, X, b1, N, part, nblk); });
-    if (e == hipSuccess) e = launch_reduce_rows(c, part, rows, nblk, sums);
-    std::vector<double> host(rows);
-    if (e == hipSuccess) e = hipMemcpyAsync(host.data(), sums, sizeof(double) * rows, hipMemcpyDeviceToHost, ws.stream);
+    if (e == hipSuccess) e = launch_reduce_rows(c, part, rows, nblk, *sums);
+    if (e != hipSuccess) return fail(MPM_ERR_DEVICE, "image sums: %s", hipGetErrorString(e));
+    return MPM_OK;
+}
+
+void image_means_from_sums(const DevProto &P, int64_t N, const double *sums, std::vector<double> &mean,
+                           double &b1m)
+{
+    mean.resize(P.I);
+    for (int i = 0; i < P.I; i++) mean[i] = sums[P.I + i] > 0.0 ? P.off[i] + sums[i] / sums[P.I + i] : NAN;
+    b1m = sums[2 * P.I] / (double)N;
+}
+
+mpm_status image_means(Workspace &ws, Prof &prof, const DevProto &P, int dtype, const void *X,
+                       const float *b1, int64_t N, std::vector<double> &mean, double &b1m)
+{
+    double *sums = nullptr;
+    mpm_status st = enqueue_image_sums(ws, prof, P, dtype, X, b1, N, &sums);
+    if (st) return st;
+    std::vector<double> host(image_sum_rows(P));
+    hipError_t e = hipMemcpyAsync(host.data(), sums, sizeof(double) * host.size(), hipMemcpyDeviceToHost, ws.stream);
     if (e == hipSuccess) e = hipStreamSynchronize(ws.stream);
     if (e != hipSuccess) return fail(MPM_ERR_DEVICE, "image means: %s", hipGetErrorString(e));
-    mean.resize(P.I);
-    for (int i = 0; i < P.I; i++) mean[i] = host[P.I + i] > 0.0 ? P.off[i] + host[i] / host[P.I + i] : NAN;
-    b1m = host[2 * P.I] / (double)N;
+    image_means_from_sums(P, N, host.data(), mean, b1m);
     return MPM_OK;
 }
 

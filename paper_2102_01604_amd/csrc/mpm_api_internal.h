@@ -77,11 +77,56 @@ struct FitArgs {
     bool no_pinned = false;
 };
 
+// Pinned host buffer (freed with the owner).
+struct PinnedBuf {
+    void *p = nullptr;
+    ~PinnedBuf();
+    hipError_t alloc(size_t bytes);
+};
+
+// Per-image sums reduced on the device in FP64 (fixed order): rows 0..I-1 the
+// sums of each image's finite values, I..2I-1 their counts, 2I the sum of b1
+// (N without b1).  enqueue_image_sums leaves them in a workspace buffer of
+// image_sum_rows(P) doubles; image_means_from_sums turns a host copy into the
+// per-image means (each image's storage offset added) and the mean b1.
+int image_sum_rows(const DevProto &P);
+mpm_status enqueue_image_sums(Workspace &ws, Prof &prof, const DevProto &P, int dtype, const void *X,
+                              const float *b1, int64_t N, double **sums);
+void image_means_from_sums(const DevProto &P, int64_t N, const double *sums, std::vector<double> &mean,
+                           double &b1m);
+// Both, with one stream synchronisation.
 mpm_status image_means(Workspace &ws, Prof &prof, const DevProto &P, int dtype, const void *X,
                        const float *b1, int64_t N, std::vector<double> &mean, double &b1m);
-// Writes the initial maps (constant, or the default initialisation from the
-// image means, which synchronises the stream once) unless they are given.
-mpm_status enqueue_init(const FitArgs &a, Workspace &ws, Prof &prof);
+
+// The initial maps of a fit, in two halves so that a caller driving several
+// fits never waits for the device: start() writes constant maps at once or,
+// for the default initialisation, enqueues the image sums and their copy to
+// pinned host memory (to device memory only, when the fit has no pinned
+// staging); ready() says whether that copy has landed; finish() waits for it
+// if it has not, computes the starting point on the host and enqueues the fill
+// of the maps.  Given maps need neither half.
+struct InitStage {
+    InitStage() = default;
+    InitStage(const InitStage &) = delete;
+    InitStage &operator=(const InitStage &) = delete;
+    ~InitStage();
+    mpm_status start(const FitArgs &a, Workspace &ws, Prof &prof);
+    bool ready() const;
+    mpm_status finish(const FitArgs &a);
+    bool pending = false;
+
+  private:
+    struct Seg {
+        DevProto P;
+        int64_t N;
+        double *dev;  // workspace rows
+        size_t at;    // first row in the host copy
+    };
+    std::vector<Seg> segs;
+    size_t rows = 0;
+    PinnedBuf host;
+    hipEvent_t ev = nullptr;
+};
 size_t map_workspace_floats_per_voxel();
 
 // A fit enqueued piece by piece on one stream (a piece is the whole ML fit,
@@ -89,6 +134,9 @@ size_t map_workspace_floats_per_voxel();
 // fit).  collect() reads the results once all enqueued work has completed.
 struct FitJob {
     virtual ~FitJob() {}
+    // false while the next piece waits for host data still in flight (the
+    // default initialisation); enqueue_next would then block until it lands
+    virtual bool ready() const { return true; }
     virtual mpm_status enqueue_next(bool *more) = 0;
     virtual mpm_status collect(mpm_report &rep, double *trace, int trace_len) = 0;
 };
@@ -100,6 +148,7 @@ std::unique_ptr<FitJob> make_map_job(const FitArgs &a, Workspace &ws, Prof &prof
 // once all enqueued work has completed.
 struct BatchJob {
     virtual ~BatchJob() {}
+    virtual bool ready() const { return true; }
     virtual mpm_status enqueue_next(bool *more) = 0;
     virtual mpm_status collect_item(int i, mpm_report &rep, double *trace, int trace_len) = 0;
 };
@@ -115,12 +164,5 @@ mpm_status run_fit(const FitArgs &a, Workspace &ws, mpm_report *report, double *
 // Host-side validation shared by mpm_fit and the server.
 mpm_status check_fit_args(const mpm_protocol *protocol, const mpm_grid *grid, int dtype, const void *echoes,
                           const mpm_options *opt, const float *maps, int64_t *N);
-
-// Pinned host buffer (freed with the owner).
-struct PinnedBuf {
-    void *p = nullptr;
-    ~PinnedBuf();
-    hipError_t alloc(size_t bytes);
-};
 
 }  // namespace mpm

@@ -15,45 +15,103 @@ PinnedBuf::~PinnedBuf()
 
 hipError_t PinnedBuf::alloc(size_t bytes) { return hipHostMalloc(&p, bytes ? bytes : 8, hipHostMallocDefault); }
 
-mpm_status enqueue_init(const FitArgs &a, Workspace &ws, Prof &prof)
+InitStage::~InitStage()
 {
-    const mpm_options *opt = a.opt;
-    if (opt->init_kind == MPM_INIT_FROM_MAPS) return MPM_OK;
-    float y0[4];
-    if (opt->init_kind == MPM_INIT_CONST) {
-        for (int k = 0; k < 4; k++) y0[k] = (float)opt->init_const[k];
-    } else {
-        std::vector<double> mean;
-        double b1m;
-        mpm_status st;
-        if (!a.spaces) {
-            if ((st = image_means(ws, prof, a.P, a.dtype, a.X, a.b1, a.N, mean, b1m))) return st;
-        } else {
-            // projected: each image's mean over its own space; b1 over the reconstruction grid
-            const char *X = (const char *)a.X;
-            double unused;
-            for (int c = 0; c < a.P.C; c++) {
-                const DevProto Pc = sub_proto(a.P, c);
-                const int64_t M = space_voxels(a.spaces[c]);
-                std::vector<double> mc;
-                if ((st = image_means(ws, prof, Pc, a.dtype, X, nullptr, M, mc, unused))) return st;
-                mean.insert(mean.end(), mc.begin(), mc.end());
-                X += (int64_t)Pc.I * M * (int64_t)dtype_size(a.dtype);
-            }
-            b1m = 1.0;
-            if (a.b1) {
-                DevProto none;
-                memset(&none, 0, sizeof(none));
-                std::vector<double> m0;
-                if ((st = image_means(ws, prof, none, a.dtype, nullptr, a.b1, a.N, m0, b1m))) return st;
-            }
-        }
-        if ((st = default_init_from_means(a.proto, mean.data(), b1m, y0))) return st;
-    }
+    if (ev) (void)hipEventDestroy(ev);
+}
+
+static mpm_status fill_maps(const FitArgs &a, const float y0[4])
+{
     LaunchCtx c{a.stream};
     hipError_t e = launch_fill_maps(c, a.maps, a.N, y0);
     if (e != hipSuccess) return fail(MPM_ERR_DEVICE, "init: %s", hipGetErrorString(e));
     return MPM_OK;
+}
+
+mpm_status InitStage::start(const FitArgs &a, Workspace &ws, Prof &prof)
+{
+    const mpm_options *opt = a.opt;
+    if (opt->init_kind == MPM_INIT_FROM_MAPS) return MPM_OK;
+    if (opt->init_kind == MPM_INIT_CONST) {
+        float y0[4];
+        for (int k = 0; k < 4; k++) y0[k] = (float)opt->init_const[k];
+        return fill_maps(a, y0);
+    }
+    // default: the sums of every image (projected: each over its own space)
+    // and of b1 over the reconstruction grid
+    auto add = [&](const DevProto &P, const void *X, const float *b1, int64_t N) -> mpm_status {
+        Seg sg{P, N, nullptr, rows};
+        mpm_status st = enqueue_image_sums(ws, prof, P, a.dtype, X, b1, N, &sg.dev);
+        if (st) return st;
+        segs.push_back(sg);
+        rows += image_sum_rows(P);
+        return MPM_OK;
+    };
+    mpm_status st;
+    if (!a.spaces) {
+        if ((st = add(a.P, a.X, a.b1, a.N))) return st;
+    } else {
+        const char *X = (const char *)a.X;
+        for (int c = 0; c < a.P.C; c++) {
+            const DevProto Pc = sub_proto(a.P, c);
+            const int64_t M = space_voxels(a.spaces[c]);
+            if ((st = add(Pc, X, nullptr, M))) return st;
+            X += (int64_t)Pc.I * M * (int64_t)dtype_size(a.dtype);
+        }
+        if (a.b1) {
+            DevProto none;
+            memset(&none, 0, sizeof(none));
+            if ((st = add(none, nullptr, a.b1, a.N))) return st;
+        }
+    }
+    pending = true;
+    if (a.no_pinned) return MPM_OK;
+    hipError_t e = host.alloc(sizeof(double) * rows);
+    for (size_t k = 0; k < segs.size() && e == hipSuccess; k++)
+        e = hipMemcpyAsync((double *)host.p + segs[k].at, segs[k].dev, sizeof(double) * image_sum_rows(segs[k].P),
+                           hipMemcpyDeviceToHost, a.stream);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(ev, a.stream);
+    if (e != hipSuccess) return fail(MPM_ERR_DEVICE, "init: %s", hipGetErrorString(e));
+    return MPM_OK;
+}
+
+bool InitStage::ready() const { return !pending || !ev || hipEventQuery(ev) != hipErrorNotReady; }
+
+mpm_status InitStage::finish(const FitArgs &a)
+{
+    if (!pending) return MPM_OK;
+    pending = false;
+    std::vector<double> local;
+    const double *h;
+    hipError_t e = hipSuccess;
+    if (ev) {
+        e = hipEventSynchronize(ev);
+        h = (const double *)host.p;
+    } else {
+        // no pinned staging: copies on the fit's stream, then wait for them
+        local.resize(rows);
+        for (size_t k = 0; k < segs.size() && e == hipSuccess; k++)
+            e = hipMemcpyAsync(local.data() + segs[k].at, segs[k].dev, sizeof(double) * image_sum_rows(segs[k].P),
+                               hipMemcpyDeviceToHost, a.stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(a.stream);
+        h = local.data();
+    }
+    if (e != hipSuccess) return fail(MPM_ERR_DEVICE, "init: %s", hipGetErrorString(e));
+    std::vector<double> mean;
+    double b1m = 1.0;
+    for (const Seg &sg : segs) {
+        std::vector<double> m;
+        double b;
+        image_means_from_sums(sg.P, sg.N, h + sg.at, m, b);
+        mean.insert(mean.end(), m.begin(), m.end());
+        // b1 comes with the images on one grid; projected fits sum it on its own
+        if (!a.spaces || sg.P.I == 0) b1m = b;
+    }
+    float y0[4];
+    mpm_status st = default_init_from_means(a.proto, mean.data(), b1m, y0);
+    if (st) return st;
+    return fill_maps(a, y0);
 }
 
 // ---------------------------------------------------------------------------
@@ -68,6 +126,9 @@ struct MlJob : FitJob {
     int piece = 0, rows = 0, nblk = 0;
     double *part = nullptr, *sums = nullptr;
     PinnedBuf host;
+    InitStage init;
+
+    bool ready() const override { return init.ready(); }
 
     MlJob(const FitArgs &a_, Workspace &ws_, Prof &prof_) : a(a_), ws(ws_), prof(prof_) {}
 
@@ -86,8 +147,10 @@ struct MlJob : FitJob {
     {
         if (piece++ == 0) {
             *more = true;
-            return enqueue_init(a, ws, prof);
+            return init.start(a, ws, prof);
         }
+        mpm_status st = init.finish(a);
+        if (st) return st;
         *more = false;
         LaunchCtx c{a.stream};
         const int n_gn = a.opt->n_gn;

@@ -175,12 +175,15 @@ struct MapJob : FitJob {
     int t = 0, j = 0;  // next Newton-like step
     bool started = false, finished = false;
     PinnedBuf host;    // MapCtl followed by the trace
+    InitStage init;
     bool proj = false;      // spatial projection
     bool ml_as_map = false; // projected ML: one outer loop, no prior, one CG iteration, every step taken
     mpm_options opt_local;
     ProjState ps;
 
     MapJob(const FitArgs &a_, Workspace &ws_, Prof &prof_) : a(a_), ws(ws_), prof(prof_) { memset(&m, 0, sizeof(m)); }
+
+    bool ready() const override { return init.ready(); }
 
     mpm_status setup()
     {
@@ -284,9 +287,13 @@ struct MapJob : FitJob {
         if (e == hipSuccess) e = prof.launch(name, bytes, [&] { return call; }); \
     } while (0)
         *more = true;
+        if (started && init.pending) {
+            mpm_status st = init.finish(a);
+            if (st) return st;
+        }
         if (!started) {
             started = true;
-            mpm_status st = enqueue_init(a, ws, prof);
+            mpm_status st = init.start(a, ws, prof);
             if (st) return st;
             e = launch_ctl_init(s, m.ctl, m.trace, tl);
             LaunchCtx c{s};
@@ -437,6 +444,15 @@ struct BatchMapJob : BatchJob {
     bool started = false;
     double cg_stop = 0.0, tol_gn = 0.0, tol_outer = 0.0;
     BatchLaunch b;
+    std::unique_ptr<InitStage[]> init;
+
+    bool ready() const override
+    {
+        if (init)
+            for (int v = 0; v < n; v++)
+                if (!init[v].ready()) return false;
+        return true;
+    }
     double vox = 0.0, xvox = 0.0, bvox = 0.0;  // sums over volumes: N, N * echo bytes, N * field bytes
 
     BatchMapJob(const std::vector<FitArgs> &a_, Workspace &ws_, Prof &prof_) : a(a_), ws(ws_), prof(prof_) {}
@@ -516,10 +532,17 @@ struct BatchMapJob : BatchJob {
         if (e == hipSuccess) e = prof.launch(name, bytes, [&] { return call; }); \
     } while (0)
         *more = true;
+        if (started)
+            for (int v = 0; v < n; v++)
+                if (init[v].pending) {
+                    mpm_status st = init[v].finish(a[v]);
+                    if (st) return st;
+                }
         if (!started) {
             started = true;
+            init.reset(new InitStage[n]);
             for (int v = 0; v < n; v++) {
-                mpm_status st = enqueue_init(a[v], ws, prof);
+                mpm_status st = init[v].start(a[v], ws, prof);
                 if (st) return st;
             }
             e = launch_ctl_init_batch(s, b, tl);

@@ -169,6 +169,9 @@ bool advance(mpm_server *s, Unit &u)
         return false;
     }
     if ((int)u.inflight.size() >= DEPTH) return true;
+    // the default initialisation's image means are still on their way to the
+    // host: come back on a later step instead of waiting under the lock
+    if (!(u.batch ? u.batch->ready() : u.job->ready())) return true;
     bool more = true;
     mpm_status st = u.batch ? u.batch->enqueue_next(&more) : u.job->enqueue_next(&more);
     if (st) {
