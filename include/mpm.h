@@ -448,7 +448,6 @@ mpm_status mpm_fit_batch(int32_t n, const mpm_request *requests, mpm_report *rep
                          int32_t trace_len, void *stream);
 
 /*
- * mpm_pack_echoes --/*
  * mpm_pack_echoes -- writes echoes for reduced-precision storage with per-image
  * offsets (see mpm_options.echo_offset): offsets[i] = the mean of the finite
  * values of image i (FP64 sum, rounded to float), then

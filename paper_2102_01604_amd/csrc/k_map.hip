@@ -129,7 +129,9 @@ __device__ __forceinline__ void lik_body(const Grid3 &g, const typename VoxelEch
                                          const MapCtl *__restrict__ ctl, double *__restrict__ partials, int L,
                                          int T_)
 {
-    if (ctl->gn_stop) return;
+    // (spec_ready: the previous step's accept pass already computed all of
+    // this at the maps now current, see accept_spec_body)
+    if (ctl->gn_stop || ctl->spec_ready) return;
     const int64_t N = g.N;
     const float lam[4] = {l0, l1, l2, l3};
     const Col c = locate_col(g, L, T_);
@@ -535,6 +537,95 @@ __global__ __launch_bounds__(BLOCK) void k_accept(ACCEPT_PARAMS)
     accept_body<T, CM, EM>(ACCEPT_ARGS, blockIdx.x, gridDim.x);
 }
 
+// accept, pass 1, when the next Newton step follows in the same outer loop:
+// besides the partials of k_accept it evaluates that step's likelihood pass
+// (k_lik) at the full step.  If the full step is taken the maps become
+// y - delta_f exactly (the update subtracts 1 * delta_f) and the weights stay,
+// so H, r and z written here, and the partial rows 3 (y.Ly) and 4 (r.z) beside
+// the NLL in row 0, are what k_lik would compute after the update, bit for bit
+// (the same operations in the same order: the neighbours' maps are formed as
+// y_m - delta_m like the update forms them, the NLL of the likelihood
+// evaluation equals that of the NLL-only one).  The finaliser then marks them
+// valid and the next k_lik returns at once.  H, r and z are dead at this point
+// of a step (the halved trials and the update read y, delta_f and the echoes).
+// Partials: NLL, c1, c2, y.Ly and r.z at the full step.
+#define ACCEPT_SPEC_PARAMS                                                                                   \
+    Grid3 g, typename VoxelEchoes<T, CM, EM>::Proto P, const T *__restrict__ X, const float *__restrict__ b1, \
+        const float *__restrict__ bm, const float *__restrict__ Y, const float *__restrict__ w, float l0,       \
+        float l1, float l2, float l3, const float4 *__restrict__ D, const float4 *__restrict__ P0,              \
+        const float4 *__restrict__ P1, int loading, HessArrays Hs, float4 *__restrict__ R,                      \
+        float4 *__restrict__ Z, const MapCtl *__restrict__ ctl, double *__restrict__ partials
+#define ACCEPT_SPEC_ARGS g, P, X, b1, bm, Y, w, l0, l1, l2, l3, D, P0, P1, loading, Hs, R, Z, ctl, partials
+
+template <bool PLUS, typename T, int CM, int EM>
+__device__ __forceinline__ void accept_spec_body(ACCEPT_SPEC_PARAMS, int L, int T_)
+{
+    if (ctl->gn_stop) return;
+    const int64_t N = g.N;
+    const float lam[4] = {l0, l1, l2, l3};
+    const DeltaF getd{D, ctl->p_buf ? P1 : P0, (float)ctl->alpha_pend, ctl->delta_valid != 0};
+    const Col c = locate_col(g, L, T_);
+    const auto K = VoxelEchoes<T, CM, EM>::stage(P);
+    double part[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    if (c.act) {
+        const int64_t n = c.base + (int64_t)c.z0 * c.sxy;
+        VoxelEchoes<T, CM, EM> ve;
+        ve.load(P, X, N, n, b1 ? b1[n] : 1.0f, bm ? bm[n] : 1.0f);
+        float y0[4], d0[4], yt[4];
+        load4(Y, N, n, y0);
+        getd(n, d0);
+#pragma unroll
+        for (int k = 0; k < 4; k++) yt[k] = y0[k] - d0[k];
+        const float w0 = w[n];
+        float ay[4] = {0.f, 0.f, 0.f, 0.f}, ad[4] = {0.f, 0.f, 0.f, 0.f}, at[4] = {0.f, 0.f, 0.f, 0.f};
+        float d = 0.f, d2 = 0.f, d3 = 0.f;
+        const auto nb = [&](int64_t m) {
+            float vm[4], um[4], tm[4];
+            load4(Y, N, m, vm);
+            getd(m, um);
+#pragma unroll
+            for (int k = 0; k < 4; k++) tm[k] = vm[k] - um[k];
+            const float wmm = w[m];
+            edge(w0, wmm, y0, vm, ay, d);
+            edge(w0, wmm, d0, um, ad, d2);
+            edge(w0, wmm, yt, tm, at, d3);
+        };
+        for_inplane(c, n, g.nx, nb);
+        if (c.z0 > 0) nb(n - c.sxy);
+        if (c.z0 < g.nz - 1) nb(n + c.sxy);
+        float gr[4], H[10], r[4], zz[4];
+        const float nll = ve.template lik<PLUS>(P, K, yt, loading, true, gr, H);
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            ay[k] *= lam[k];
+            ad[k] *= lam[k];
+            at[k] *= lam[k];  // (L y) at the full step
+            r[k] = gr[k] + at[k];
+        }
+        precond(H, lam, d, r, zz);
+        store_H(Hs, n, H);
+        vstore_nt(R, n, r);
+        vstore_nt(Z, n, zz);
+        part[0] = nll;
+        part[1] = dot4(d0, ay);
+        part[2] = dot4(d0, ad);
+        part[3] = dot4(yt, at);
+        part[4] = dot4(r, zz);
+    }
+    write_partials<5>(part, partials, L, T_);
+}
+
+template <typename T, int CM, int EM>
+__global__ __launch_bounds__(BLOCK) void k_accept_spec(ACCEPT_SPEC_PARAMS)
+{
+    accept_spec_body<false, T, CM, EM>(ACCEPT_SPEC_ARGS, blockIdx.x, gridDim.x);
+}
+template <typename T, int CM, int EM>  // Proposed+ loading
+__global__ __launch_bounds__(BLOCK) void k_accept_spec_plus(ACCEPT_SPEC_PARAMS)
+{
+    accept_spec_body<true, T, CM, EM>(ACCEPT_SPEC_ARGS, blockIdx.x, gridDim.x);
+}
+
 // accept, pass 2 (only after the full step was rejected): the NLL at the
 // halved steps y - 2^-h delta_f, h = 1 .. ntrial-1.  Column grid (returns at
 // once in the common case, so few workgroups).  Partial row h.
@@ -785,11 +876,14 @@ __device__ __forceinline__ void fin_body(int stage, int arg, int nblk, const dou
     if ((stage == FIN_A || stage == FIN_B) && ctl->cg_stop) return;
     if (stage == FIN_ACCEPT2 && !ctl->accept_more) return;
     double s[MAX_TRIALS];
-    const int rows = (stage == FIN_LIK || stage == FIN_ACCEPT || stage == FIN_STATS) ? 3
+    const int rows = (stage == FIN_LIK || stage == FIN_ACCEPT || stage == FIN_ACCEPT_SPEC || stage == FIN_STATS) ? 3
                      : stage == FIN_ACCEPT2                                          ? MAX_TRIALS
                      : stage == FIN_STOP                                             ? 0
                                                                                      : 1;
-    for (int k = 0; k < rows; k++) s[k] = reduce_row(partials + (int64_t)k * nblk, nblk, lds);
+    // the likelihood pass evaluated by the accept pass: rows 0, 3, 4
+    const bool spec = stage == FIN_LIK && ctl->spec_ready;
+    for (int k = 0; k < rows; k++)
+        s[k] = reduce_row(partials + (int64_t)(spec && k > 0 ? k + 2 : k) * nblk, nblk, lds);
     for (int k = 0; k < rows && k < ext.rows; k++) s[k] += reduce_row(ext.p + (int64_t)k * ext.stride, ext.cols, lds);
     if (threadIdx.x != 0) return;
     MapCtl &c = *ctl;
@@ -807,6 +901,7 @@ __device__ __forceinline__ void fin_body(int stage, int arg, int nblk, const dou
         c.p_buf = 0;
         c.accept_more = 0;
         c.cg_stop = !(s[2] > 0.0);
+        c.spec_ready = 0;
         if (arg >= 0) {  // the first Newton step of an outer loop
             trace[arg] = c.F;
             c.F_loop0 = c.F;
@@ -832,13 +927,15 @@ __device__ __forceinline__ void fin_body(int stage, int arg, int nblk, const dou
         c.gamma = gn;
         break;
     }
-    case FIN_ACCEPT: {  // full step; arg: trace slot for "F after this step"
+    case FIN_ACCEPT:         // full step; arg: trace slot for "F after this step"
+    case FIN_ACCEPT_SPEC: {  // the same, after k_accept_spec
         c.c1 = s[1];
         c.c2 = s[2];
         const double F0 = s[0] + 0.5 * (c.yLy - 2.0 * c.c1 + c.c2);
         if (accept_off || F0 <= c.F + ACCEPT_REL * fabs(c.F)) {
             stop_on_gain(c, c.F, F0, tol_gn);
             c.step = 1.0;
+            c.spec_ready = stage == FIN_ACCEPT_SPEC;
             c.nll_cur = s[0];
             c.F = F0;
             c.gn_done++;
@@ -898,6 +995,7 @@ __device__ __forceinline__ void fin_body(int stage, int arg, int nblk, const dou
         }
         c.gn_stop = c.outer_stop;
         c.tol_stop = 0;
+        c.spec_ready = 0;  // the weights changed (or the loop stopped before using it)
         break;
     }
     case FIN_STOP:  // after the update of a step that ended its outer loop
@@ -1023,6 +1121,18 @@ hipError_t launch_accept(hipStream_t s, const MapArgs &a)
     const float *l = a.lam;
     DISPATCH_T(k_accept, a.gp, a.b1, a.bm, a.Y, a.w, l[0], l[1], l[2], l[3], a.D, a.P0, a.P1, a.ctl,
                a.partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_accept_spec(hipStream_t s, const MapArgs &a)
+{
+    const float *l = a.lam;
+    if (a.loading == 2)
+        DISPATCH_T(k_accept_spec_plus, a.gp, a.b1, a.bm, a.Y, a.w, l[0], l[1], l[2], l[3], a.D, a.P0, a.P1,
+                   a.loading, a.H, a.R, a.Z, a.ctl, a.partials);
+    else
+        DISPATCH_T(k_accept_spec, a.gp, a.b1, a.bm, a.Y, a.w, l[0], l[1], l[2], l[3], a.D, a.P0, a.P1, a.loading,
+                   a.H, a.R, a.Z, a.ctl, a.partials);
     return hipGetLastError();
 }
 

@@ -97,6 +97,7 @@ struct MapCtl {
     int outer_done;     // outer loops run
     int outer_stop;     // the remaining outer loops are skipped
     int tol_stop;       // the accepted step ends this outer loop (set after its update)
+    int spec_ready;     // the accept pass evaluated the next likelihood pass at the taken full step
 };
 
 // ---------------------------------------------------------------------------
@@ -268,7 +269,10 @@ struct DeltaF {
     }
 };
 
-enum { FIN_LIK = 0, FIN_A = 1, FIN_B = 2, FIN_ACCEPT = 3, FIN_W = 4, FIN_STATS = 5, FIN_ACCEPT2 = 6, FIN_STOP = 7 };
+enum {
+    FIN_LIK = 0, FIN_A = 1, FIN_B = 2, FIN_ACCEPT = 3, FIN_W = 4, FIN_STATS = 5, FIN_ACCEPT2 = 6, FIN_STOP = 7,
+    FIN_ACCEPT_SPEC = 8
+};
 
 struct MapArgs {
     Grid3 g;
@@ -306,6 +310,9 @@ hipError_t launch_lik(hipStream_t s, const MapArgs &a);
 hipError_t launch_cg_a(hipStream_t s, const MapArgs &a, int it);
 hipError_t launch_cg_b(hipStream_t s, const MapArgs &a, int it);
 hipError_t launch_accept(hipStream_t s, const MapArgs &a);
+// k_accept that also evaluates the next Newton step's likelihood pass at the
+// full step (that step must follow in the same outer loop)
+hipError_t launch_accept_spec(hipStream_t s, const MapArgs &a);
 hipError_t launch_accept2(hipStream_t s, const MapArgs &a, int ntrial);
 hipError_t launch_update(hipStream_t s, const MapArgs &a);
 hipError_t launch_weights(hipStream_t s, const MapArgs &a, int prior_on);

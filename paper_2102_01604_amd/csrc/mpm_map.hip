@@ -307,7 +307,10 @@ struct MapJob : FitJob {
                 if (t > t0) RUN("fin", 0.0, fin(FIN_W, (t - 1) * S + J + 1, nb_col));
             }
             if (!proj) {
-                RUN("map_lik", N * (xb + bb + 16 + 4 + 40 + 16 + 16), launch_lik(s, m));
+                // after a step whose accept pass evaluated this pass (j >= 1),
+                // k_lik only checks that the full step was taken
+                if (j == 0) RUN("map_lik", N * (xb + bb + 16 + 4 + 40 + 16 + 16), launch_lik(s, m));
+                else RUN("map_lik_check", 0.0, launch_lik(s, m));
                 RUN("fin", 0.0, fin(FIN_LIK, j == 0 ? t * S : -1, nb_pl));
             } else {
                 if (e == hipSuccess) e = proj_lik_push(1);
@@ -325,8 +328,15 @@ struct MapJob : FitJob {
                 else if (i == K - 1) RUN("fin", 0.0, fin(FIN_B, i, nb_cgb, ExtRows(), 1));
             }
             if (!proj) {
-                RUN("map_accept", N * (xb + bb + 16 + 16 + 16 + 4), launch_accept(s, m));
-                RUN("fin", 0.0, fin(FIN_ACCEPT, t * S + j + 1, nb_pl));
+                if (j + 1 < J) {
+                    // the next step of this outer loop: its likelihood pass is
+                    // evaluated here, at the full step
+                    RUN("map_accept_lik", N * (xb + bb + 16 + 16 + 16 + 4 + 40 + 16 + 16), launch_accept_spec(s, m));
+                    RUN("fin", 0.0, fin(FIN_ACCEPT_SPEC, t * S + j + 1, nb_pl));
+                } else {
+                    RUN("map_accept", N * (xb + bb + 16 + 16 + 16 + 4), launch_accept(s, m));
+                    RUN("fin", 0.0, fin(FIN_ACCEPT, t * S + j + 1, nb_pl));
+                }
                 if (ntrial > 1) {
                     // runs only when the full step was rejected (device flag)
                     RUN("map_accept2", 0.0, launch_accept2(s, m, ntrial));
