@@ -248,8 +248,15 @@ hipError_t launch_reduce_rows(const LaunchCtx &c, const double *in, int nrows, i
 // ---------------------------------------------------------------------------
 int ml_fit_blocks(int64_t N) { return (int)((N + BLOCK - 1) / BLOCK); }
 
+// Waves per SIMD asked of the compiler: with up to 32 echo slots the kernel
+// fits in 168 registers (3 waves) with 6 spilled (measured on the whole-brain
+// volume, 4 x 8 slots: 6.0 ms at 2 waves, 5.0 ms at 3); the larger register
+// shapes would spill 46-101 and keep the compiler's choice.
+template <int CM, int EM>
+constexpr int ml_min_waves() { return CM * EM > 0 && CM * EM <= 32 ? 3 : 1; }
+
 template <typename T, int CM, int EM, bool PLUS>
-__global__ __launch_bounds__(BLOCK) void k_ml_fit(typename VoxelEchoes<T, CM, EM>::Proto P, const T *__restrict__ X,
+__global__ __launch_bounds__(BLOCK, (ml_min_waves<CM, EM>())) void k_ml_fit(typename VoxelEchoes<T, CM, EM>::Proto P, const T *__restrict__ X,
                                                   const float *__restrict__ b1, const float *__restrict__ bm,
                                                   float *__restrict__ maps,
                                                   int64_t N, int n_gn, int loading,

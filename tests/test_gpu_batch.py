@@ -68,6 +68,49 @@ def test_batch_equals_fits_alone(torch_cuda, orc):
     assert np.allclose(out[0][1][fin], tr_o[fin], rtol=1e-6)
 
 
+def test_batch_equals_fits_alone_with_halved_steps(torch_cuda, orc):
+    """Plain Gauss-Newton loading, whose full steps the acceptance test of
+    Sec. 2.7 sometimes rejects: inside an outer loop a halved step is then
+    taken.  A fit alone lets its full-step acceptance pass evaluate the next
+    likelihood pass in advance and discards it after a halved step; a batched
+    fit evaluates every pass in turn.  Both give the same bits, and the oracle's
+    maps and trace."""
+    torch = torch_cuda
+    vols = []
+    for dims, seed in [((24, 20, 12), 101), ((16, 12, 10), 102)]:
+        c = synth.make_case("map_brain", dims=dims, seed=seed)
+        c["b1"] = f32(c["b1"])
+        x = observations(orc, c)
+        y0 = f32(orc.default_init(c["proto"], x.astype(np.float64), c["b1"]))
+        opts = dict(c["opts"], n_outer=3, n_gn=4, n_cg=16, loading="gn", max_halvings=4, init="const",
+                    init_const=[float(v) for v in y0])
+        # without halvings the oracle rejects some full steps: the case takes halved ones
+        _, rep0, _ = orc.fit(c["proto"], dims, x.astype(np.float64), c["b1"], dict(opts, max_halvings=0))
+        assert rep0["rejected"] > 0, dims
+        vols.append((c, x, opts))
+    fits, solo = [], []
+    for c, x, opts in vols:
+        X, B1, M = _tensors(torch, c, x)
+        fits.append((c["proto"], c["dims"], X, B1, opts, M))
+        M2 = torch.zeros_like(M)
+        rep, tr = _lib.mpm_fit(c["proto"], c["dims"], X, B1, opts, M2)
+        solo.append((M2.cpu().numpy(), rep, tr))
+    out = _lib.mpm_fit_batch(fits)
+    torch.cuda.synchronize()
+    for (c, x, opts), f, (y_solo, rep_solo, tr_solo), (rep, tr) in zip(vols, fits, solo, out):
+        y = f[5].cpu().numpy()
+        print(c["dims"], rep)
+        assert np.array_equal(y, y_solo), c["dims"]
+        assert rep == rep_solo
+        assert np.array_equal(tr, tr_solo, equal_nan=True)
+        y_orc, rep_o, tr_o = orc.fit(c["proto"], c["dims"], x.astype(np.float64), c["b1"], opts)
+        rel = map_errors(y.astype(np.float64), y_orc)[0]
+        print("halved steps: gpu vs oracle", rel, rep_o)
+        assert (rel <= TOL).all() and rep["gn_done"] == rep_o["gn_done"] == 12
+        fin = np.isfinite(tr_o)
+        assert np.array_equal(np.isfinite(tr), fin) and np.allclose(tr[fin], tr_o[fin], rtol=1e-5)
+
+
 def test_batch_fp16_offsets_and_incompatible_schedule(torch_cuda, orc):
     torch = torch_cuda
     vols = [_volume(orc, (32, 24, 16), 96), _volume(orc, (40, 27, 19), 97)]
