@@ -1,5 +1,8 @@
 """GPU parity of the JTV-MAP fit (SPGR+JTV) and of the Laplace uncertainty
 against the FP64 oracle, through the C ABI."""
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -356,6 +359,72 @@ def test_map_whole_brain_launch_configuration(torch_cuda, orc):
     rel, _, _ = map_errors(ym, yo, good)
     print("whole brain ML on sampled voxels: well-posed", good.mean(), "rel", rel)
     assert good.mean() > 0.8 and (rel <= TOL).all()
+
+
+GOLDEN_WHOLE_BRAIN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                                  "whole_brain_map_10x8x32.json")
+
+
+def test_map_whole_brain_full_schedule_against_stored_oracle(torch_cuda, orc):
+    """The benchmarked MAP fit itself: the whole-brain workload with the full
+    10 x 8 x 32 schedule, in the benchmark's launch configuration, against the
+    oracle's fit of the same volume (an hour of FP64 CPU time, stored by
+    tests/golden/make_whole_brain_map.py): the objective trace, the report,
+    the maps at 1024 seeded voxels and the per-map means over the whole volume;
+    the Laplace variance at the GPU's maps at those voxels equals the oracle's
+    computed at the same maps on the 5 x 5 x 5 crop around each voxel (clipped
+    at the volume's faces; the JTV weights of a voxel and its neighbours depend
+    on nothing farther), and the stored variance at the oracle's maps."""
+    torch = torch_cuda
+    g = json.load(open(GOLDEN_WHOLE_BRAIN))
+    c, x = _inputs(orc, g["case"], tuple(g["dims"]))
+    assert c["seed"] == g["seed"]
+    del c["eps"]
+    opts = g["options"]
+    assert opts["lam"] == [float(v) for v in c["lam"]]
+    N = x.shape[1]
+    X = cuda(x)
+    B1 = cuda(c["b1"].astype(np.float32))
+    maps = torch.zeros((4, N), dtype=torch.float32, device="cuda")
+    rep, tr = _lib.mpm_fit(c["proto"], c["dims"], X, B1, opts, maps)
+    torch.cuda.synchronize()
+    tr_o = np.array([np.nan if v is None else v for v in g["trace"]])
+    fin = np.isfinite(tr_o)
+    print("whole brain 10x8x32: gpu objective", rep["objective"], "oracle", g["report"]["objective"], flush=True)
+    assert np.array_equal(np.isfinite(tr), fin) and np.allclose(tr[fin], tr_o[fin], rtol=1e-6)
+    assert rep["objective"] == pytest.approx(g["report"]["objective"], rel=1e-6)
+    assert rep["gn_done"] == g["report"]["gn_done"] == 80
+    assert rep["rejected"] == g["report"]["rejected"] == 0 and rep["nonfinite_voxels"] == 0
+    idx = torch.tensor(g["sample_index"], dtype=torch.int64, device="cuda")
+    ys = maps[:, idx].cpu().numpy().astype(np.float64)
+    scale = np.array(g["map_max_abs"])
+    rel = np.abs(ys - np.array(g["sample_maps"])).max(axis=1) / scale
+    mean = maps.double().mean(dim=1).cpu().numpy()
+    rel_mean = np.abs(mean - np.array(g["map_mean"])) / scale
+    print("whole brain 10x8x32: sampled maps rel", rel, "means rel", rel_mean, flush=True)
+    assert (rel <= TOL).all() and (rel_mean <= TOL).all()
+    var = torch.empty((4, N), dtype=torch.float32, device="cuda")
+    _lib.mpm_uncertainty(c["proto"], c["dims"], X, B1, opts, maps, var)
+    vg = var[:, idx].cpu().numpy().astype(np.float64)
+    del var, X, B1
+    y = maps.cpu().numpy().astype(np.float64)
+    del maps
+    nx, ny, nz = c["dims"]
+    worst = 0.0
+    for k, n in enumerate(g["sample_index"]):
+        p = (n % nx, (n // nx) % ny, n // (nx * ny))
+        rx, ry, rz = (range(max(0, q - 2), min(m, q + 3)) for q, m in zip(p, (nx, ny, nz)))
+        cr = np.array([i + nx * (j + ny * l) for l in rz for j in ry for i in rx])
+        cen = (p[0] - rx.start) + len(rx) * ((p[1] - ry.start) + len(ry) * (p[2] - rz.start))
+        vo = orc.uncertainty(c["proto"], (len(rx), len(ry), len(rz)), x[:, cr].astype(np.float64), c["b1"][cr],
+                             opts, y[:, cr])[:, cen]
+        worst = max(worst, float(np.max(np.abs(vg[:, k] - vo) / vo)))
+    # and against the oracle's at its own maps (those differ from the GPU's by
+    # the map errors above)
+    v_o = np.array(g["sample_var"])
+    rv = (np.abs(vg - v_o) / v_o).max(axis=1)
+    print("whole brain 10x8x32: sampled variance rel err max", worst, "| against the oracle's at its own maps", rv)
+    assert worst <= VAR_TOL and (rv <= VAR_TOL).all()
 
 
 @pytest.mark.parametrize("which,seed,sched", [("tol_gn", 81, (3, 8, 16)), ("tol_outer", 82, (8, 2, 12))])
