@@ -399,7 +399,11 @@ mpm_status run_fit(const FitArgs &a, Workspace &ws, mpm_report *report, double *
     if (st) return st;
     bool more = true;
     while (more)
-        if ((st = job->enqueue_next(&more))) return st;
+        if ((st = job->enqueue_next(&more))) {
+            // the work already enqueued ends before the job and its staging go
+            (void)hipStreamSynchronize(a.stream);
+            return st;
+        }
     hipError_t e = hipStreamSynchronize(a.stream);
     prof.collect();
     if (e != hipSuccess) return fail(MPM_ERR_DEVICE, "fit: %s", hipGetErrorString(e));

@@ -754,7 +754,11 @@ extern "C" mpm_status mpm_fit_projected(const mpm_protocol *protocol, const mpm_
         if (st) return st;
         bool more = true;
         while (more)
-            if ((st = job->enqueue_next(&more))) return st;
+            if ((st = job->enqueue_next(&more))) {
+                // the work already enqueued ends before the job and its staging go
+                (void)hipStreamSynchronize(s);
+                return st;
+            }
         hipError_t e = hipStreamSynchronize(s);
         prof.collect();
         if (e != hipSuccess) return fail(MPM_ERR_DEVICE, "fit: %s", hipGetErrorString(e));
@@ -793,7 +797,11 @@ extern "C" mpm_status mpm_fit_batch(int32_t n, const mpm_request *requests, mpm_
     if (st) return st;
     bool more = true;
     while (more)
-        if ((st = job->enqueue_next(&more))) return st;
+        if ((st = job->enqueue_next(&more))) {
+            // the work already enqueued ends before the job and its staging go
+            (void)hipStreamSynchronize(s);
+            return st;
+        }
     hipError_t e = hipStreamSynchronize(s);
     prof.collect();
     if (e != hipSuccess) return fail(MPM_ERR_DEVICE, "batched fit: %s", hipGetErrorString(e));

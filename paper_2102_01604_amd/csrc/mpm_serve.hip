@@ -115,9 +115,12 @@ void release(mpm_server *s, Unit &u)
 {
     for (hipEvent_t ev : u.inflight) (void)hipEventDestroy(ev);
     u.inflight.clear();
+    // the workspace first: freeing it waits for the unit's stream, so pieces
+    // still in flight after an error have ended before the jobs' pinned
+    // staging buffers go
+    u.ws.reset();
     u.job.reset();
     u.batch.reset();
-    u.ws.reset();  // frees the workspace on the unit's stream and waits for it
     u.prof.reset();
     if (u.stream >= 0) s->busy[u.stream] = false;
     u.stream = -1;
