@@ -42,7 +42,7 @@ constexpr int64_t LARGE_FIT_VOXELS = (int64_t)1 << 21;
 // their CG sweeps last about as long as a launch's dispatch latency, which a
 // group pays once for all its members; a fit of 96 x 128 x 128 voxels already
 // streams its sweeps at nearly the bandwidth of the part (measured: 4 of them
-// batched 1.05x faster than one after another, 16 of 64^3 1.81x).  A group
+// batched 1.03x faster than one after another, 16 of 64^3 1.50x).  A group
 // holds fits whose sizes differ by at most 2x (it finishes with its largest
 // member), at most GROUP_MAX_FITS fits and GROUP_MAX_VOXELS voxels in all
 // (about what fills the device in one launch of the CG sweeps).
