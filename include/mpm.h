@@ -386,8 +386,10 @@ const char *mpm_last_error(void);
  * flags: MPM_SERVER_THREAD starts a host thread that calls mpm_server_step()
  * continuously; otherwise the caller drives it.
  * mpm_server_submit validates like mpm_fit (same errors) and returns a ticket.
- * mpm_server_step: non-blocking apart from the brief synchronisation of a
- * default initialisation; *pending (may be NULL) receives the number of fits
+ * mpm_server_step: does not wait for the device (a fit whose default
+ * initialisation still awaits its image means on the host gets its next
+ * piece at a later step; only after an error does a step wait for the work
+ * that fit had enqueued); *pending (may be NULL) receives the number of fits
  * queued or running.
  * mpm_server_poll: *done = 1 and the report once the fit finished (returning
  * that fit's status), *done = 0 while queued or running; MPM_ERR_NOT_FOUND for
