@@ -455,6 +455,7 @@ struct BatchMapJob : BatchJob {
     double cg_stop = 0.0, tol_gn = 0.0, tol_outer = 0.0;
     BatchLaunch b;
     std::unique_ptr<InitStage[]> init;
+    PinnedBuf staging;  // the device tables' host copy
 
     bool ready() const override
     {
@@ -517,11 +518,16 @@ struct BatchMapJob : BatchJob {
         std::vector<char> desc(db * (size_t)n);
         for (int v = 0; v < n; v++) fill_batch_desc(desc.data(), v, m[v], prior_on[v], b.dtype, b.shape);
         void *dtab = nullptr, *dvols = nullptr;
-        if (ws.alloc(&dtab, sizeof(BatchTab)) != hipSuccess || ws.alloc(&dvols, desc.size()) != hipSuccess)
+        if (ws.alloc(&dtab, sizeof(BatchTab)) != hipSuccess || ws.alloc(&dvols, desc.size()) != hipSuccess ||
+            staging.alloc(sizeof(BatchTab) + desc.size()) != hipSuccess)
             return fail(MPM_ERR_OUT_OF_MEMORY, "batch table allocation failed");
-        hipError_t e = hipMemcpyAsync(dtab, &tab, sizeof(BatchTab), hipMemcpyHostToDevice, s);
-        if (e == hipSuccess) e = hipMemcpyAsync(dvols, desc.data(), desc.size(), hipMemcpyHostToDevice, s);
-        if (e == hipSuccess) e = hipStreamSynchronize(s);  // the host copies are local
+        // staged in pinned memory owned by the job, so the copies are
+        // asynchronous (the job outlives the work on its stream)
+        char *h = (char *)staging.p;
+        memcpy(h, &tab, sizeof(BatchTab));
+        memcpy(h + sizeof(BatchTab), desc.data(), desc.size());
+        hipError_t e = hipMemcpyAsync(dtab, h, sizeof(BatchTab), hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(dvols, h + sizeof(BatchTab), desc.size(), hipMemcpyHostToDevice, s);
         if (e != hipSuccess) return fail(MPM_ERR_DEVICE, "batch tables: %s", hipGetErrorString(e));
         b.tab = (const BatchTab *)dtab;
         b.vols = dvols;
