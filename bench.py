@@ -54,6 +54,9 @@ STEP_MODEL_BYTES_PER_VOXEL = 108.0 + 80 * 8772.0 + 164.0
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2102_01604_amd", "csrc", f)
                   for f in ("k_map.hip", "mpm_map.h", "mpm_device.h", "mpm_kernels.h", "mpm_tune.hip")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_map_brain.txt")
+# the oracle's full 10 x 8 x 32 MAP fit of the whole-brain volume, stored once
+# with its wall time by tests/golden/make_whole_brain_map.py
+ORACLE_FULL_FIT = os.path.join(ROOT, "tests", "golden", "whole_brain_map_10x8x32.json")
 VALU_SOURCES = [os.path.join(ROOT, "paper_2102_01604_amd", "csrc", f)
                 for f in ("k_voxel.hip", "mpm_voxelwise.h", "mpm_device.h")]
 VALU_FILE = os.path.join(ROOT, "profiles", "valu_ml_fit_pv_e1.txt")
@@ -1081,6 +1084,16 @@ def cpu_baseline(case, dims):
                           "seconds": round(dt1, 2),
                           "sample": f"central {cd1[0]}x{cd1[1]}x{cd1[2]} crop ({len(idx1)} voxels), "
                                     "the same three stages"}}
+    if os.path.exists(ORACLE_FULL_FIT):
+        g = json.load(open(ORACLE_FULL_FIT))
+        if tuple(g["dims"]) == tuple(dims):
+            nv = int(np.prod(dims))
+            o = g["options"]
+            rec["full_size_map_fit"] = {
+                "value": round(nv * o["n_outer"] * o["n_gn"] / g["oracle_fit_seconds"], 1),
+                "unit": "voxel-GN-iterations/s", "cores": g["oracle_threads"], "seconds": g["oracle_fit_seconds"],
+                "sample": "the whole volume, MAP 10x8x32 alone, FP64, timed once on the host that wrote "
+                          "tests/golden/whole_brain_map_10x8x32.json (not this one)"}
     return rec, {"dims": cd, "x": x, "b1": b1, "truth": truth, "ml": ml, "map": mp}
 
 
