@@ -370,7 +370,9 @@ def test_map_whole_brain_full_schedule_against_stored_oracle(torch_cuda, orc):
     10 x 8 x 32 schedule, in the benchmark's launch configuration, against the
     oracle's fit of the same volume (an hour of FP64 CPU time, stored by
     tests/golden/make_whole_brain_map.py): the objective trace, the report,
-    the maps at 1024 seeded voxels and the per-map means over the whole volume;
+    the maps at 1024 seeded voxels and the per-map means over the whole volume
+    (and, for the same fit of FP16 echoes stored with per-image offsets, the
+    maps and means within the 1e-3 of reduced-precision storage);
     the Laplace variance at the GPU's maps at those voxels equals the oracle's
     computed at the same maps on the 5 x 5 x 5 crop around each voxel (clipped
     at the volume's faces; the JTV weights of a voxel and its neighbours depend
@@ -406,9 +408,25 @@ def test_map_whole_brain_full_schedule_against_stored_oracle(torch_cuda, orc):
     var = torch.empty((4, N), dtype=torch.float32, device="cuda")
     _lib.mpm_uncertainty(c["proto"], c["dims"], X, B1, opts, maps, var)
     vg = var[:, idx].cpu().numpy().astype(np.float64)
-    del var, X, B1
+    del var
     y = maps.cpu().numpy().astype(np.float64)
+    # the benchmark's FP16 leg: echoes stored as FP16 of each image minus its
+    # mean (mpm_pack_echoes); against the oracle's fit of the unquantised data,
+    # within the 1e-3 of reduced-precision storage
+    Q = torch.empty(X.shape, dtype=torch.float16, device="cuda")
+    off = _lib.mpm_pack_echoes(X, Q)
+    del X
+    maps.zero_()
+    rep16, _ = _lib.mpm_fit(c["proto"], c["dims"], Q, B1, dict(opts, echo_offset=off), maps)
+    torch.cuda.synchronize()
+    del Q, B1
+    rel16 = np.abs(maps[:, idx].cpu().numpy().astype(np.float64) - np.array(g["sample_maps"])).max(axis=1) / scale
+    mean16 = np.abs(maps.double().mean(dim=1).cpu().numpy() - np.array(g["map_mean"])) / scale
     del maps
+    print("whole brain 10x8x32, FP16 echoes with offsets: sampled maps rel", rel16, "means rel", mean16, rep16,
+          flush=True)
+    assert (rel16 <= 1e-3).all() and (mean16 <= 1e-3).all()
+    assert rep16["gn_done"] == 80 and rep16["nonfinite_voxels"] == 0
     nx, ny, nz = c["dims"]
     worst = 0.0
     for k, n in enumerate(g["sample_index"]):
