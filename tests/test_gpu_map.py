@@ -445,6 +445,82 @@ def test_map_whole_brain_full_schedule_against_stored_oracle(torch_cuda, orc):
     assert worst <= VAR_TOL and (rv <= VAR_TOL).all()
 
 
+GOLDEN_HIRES = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "hires_map_10x8x32.json")
+
+
+def _fp16_echoes(orc, c, b1, planes=16):
+    """s(truth) + sigma * eps in FP64, rounded to FP32 and then to FP16, a few
+    z-planes at a time (as the stored oracle fit's generator builds them)."""
+    nx, ny, nz = c["dims"]
+    x16 = np.empty((c["eps"].shape[0], nx * ny * nz), np.float16)
+    for z0 in range(0, nz, planes):
+        sl = slice(z0 * nx * ny, min(nz, z0 + planes) * nx * ny)
+        s = orc.simulate(c["proto"], c["truth"][:, sl], b1[sl])
+        x16[:, sl] = (s + c["sigma"] * c["eps"][:, sl].astype(np.float64)).astype(np.float32).astype(np.float16)
+    return x16
+
+
+def test_map_high_resolution_full_schedule_against_stored_oracle(torch_cuda, orc):
+    """The high-resolution workload (416 x 384 x 320 = 51 M voxels, FP16
+    echoes, B1 0.7-1.3, noise 2% of the mean PD) with the full 10 x 8 x 32
+    schedule, in the benchmark's launch configuration, against the oracle's
+    fit of the same FP16 echoes (about three hours of FP64 CPU time, stored by
+    tests/golden/make_hires_map.py): the objective trace, the report, the maps
+    at 1024 seeded voxels and the per-map means over the whole volume; the
+    Laplace variance at the GPU's maps at those voxels against the oracle's at
+    the same maps on the 5 x 5 x 5 crop around each voxel (clipped at the
+    volume's faces), and against the stored variance at the oracle's maps."""
+    torch = torch_cuda
+    g = json.load(open(GOLDEN_HIRES))
+    c = synth.make_case(g["case"])
+    assert c["seed"] == g["seed"] and list(c["dims"]) == g["dims"]
+    opts = g["options"]
+    assert opts["lam"] == [float(v) for v in c["lam"]]
+    b1 = f32(c["b1"])
+    x16 = _fp16_echoes(orc, c, b1)
+    del c["eps"]
+    N = x16.shape[1]
+    X = torch.from_numpy(x16).cuda()
+    B1 = cuda(b1.astype(np.float32))
+    maps = torch.zeros((4, N), dtype=torch.float32, device="cuda")
+    print("high resolution 10x8x32: GPU fit", flush=True)
+    rep, tr = _lib.mpm_fit(c["proto"], c["dims"], X, B1, opts, maps)
+    torch.cuda.synchronize()
+    tr_o = np.array([np.nan if v is None else v for v in g["trace"]])
+    fin = np.isfinite(tr_o)
+    print("high resolution 10x8x32: gpu objective", rep["objective"], "oracle", g["report"]["objective"], flush=True)
+    assert np.array_equal(np.isfinite(tr), fin) and np.allclose(tr[fin], tr_o[fin], rtol=1e-6)
+    assert rep["objective"] == pytest.approx(g["report"]["objective"], rel=1e-6)
+    assert rep["gn_done"] == g["report"]["gn_done"] == 80
+    assert rep["rejected"] == g["report"]["rejected"] == 0 and rep["nonfinite_voxels"] == 0
+    idx = torch.tensor(g["sample_index"], dtype=torch.int64, device="cuda")
+    scale = np.array(g["map_max_abs"])
+    rel = np.abs(maps[:, idx].cpu().numpy().astype(np.float64) - np.array(g["sample_maps"])).max(axis=1) / scale
+    rel_mean = np.abs(maps.double().mean(dim=1).cpu().numpy() - np.array(g["map_mean"])) / scale
+    print("high resolution 10x8x32: sampled maps rel", rel, "means rel", rel_mean, flush=True)
+    assert (rel <= TOL).all() and (rel_mean <= TOL).all()
+    var = torch.empty((4, N), dtype=torch.float32, device="cuda")
+    _lib.mpm_uncertainty(c["proto"], c["dims"], X, B1, opts, maps, var)
+    vg = var[:, idx].cpu().numpy().astype(np.float64)
+    del var, X, B1
+    y = maps.cpu().numpy().astype(np.float64)
+    del maps
+    nx, ny, nz = c["dims"]
+    worst = 0.0
+    for k, n in enumerate(g["sample_index"]):
+        p = (n % nx, (n // nx) % ny, n // (nx * ny))
+        rx, ry, rz = (range(max(0, q - 2), min(m, q + 3)) for q, m in zip(p, (nx, ny, nz)))
+        cr = np.array([i + nx * (j + ny * l) for l in rz for j in ry for i in rx])
+        cen = (p[0] - rx.start) + len(rx) * ((p[1] - ry.start) + len(ry) * (p[2] - rz.start))
+        vo = orc.uncertainty(c["proto"], (len(rx), len(ry), len(rz)), x16[:, cr].astype(np.float64), b1[cr],
+                             opts, y[:, cr])[:, cen]
+        worst = max(worst, float(np.max(np.abs(vg[:, k] - vo) / vo)))
+    v_o = np.array(g["sample_var"])
+    rv = (np.abs(vg - v_o) / v_o).max(axis=1)
+    print("high resolution 10x8x32: sampled variance rel err max", worst, "| against the oracle's at its own maps", rv)
+    assert worst <= VAR_TOL and (rv <= VAR_TOL).all()
+
+
 @pytest.mark.parametrize("which,seed,sched", [("tol_gn", 81, (3, 8, 16)), ("tol_outer", 82, (8, 2, 12))])
 def test_map_early_stopping_parity(torch_cuda, orc, which, seed, sched):
     """Gain-based early stopping (Sec. 2.7): the same steps and loops are cut
