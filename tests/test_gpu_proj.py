@@ -3,6 +3,10 @@ mpm_simulate_projected, mpm_fit_projected (ML, MAP, Proposed+ loading, FP32
 and FP16 echo storage) and mpm_uncertainty_projected against the oracle, on
 three contrasts of which two are acquired on moved and resized grids; and the
 projected path with identity spaces against the plain GPU fit."""
+import json
+import os
+import sys
+
 import numpy as np
 import pytest
 
@@ -213,3 +217,62 @@ def test_space_outside_the_field_of_view(torch_cuda, orc):
     assert (rel <= TOL).all()
     assert np.abs(y_gpu[3] - np.float32(y0[3])).max() <= 1e-6
 
+
+GOLDEN_PROJECTED = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "projected_map_10x8x32.json")
+
+
+def test_projected_whole_brain_full_schedule_against_stored_oracle(torch_cuda, orc):
+    """The benchmark's projected workload (maps on the 192 x 240 x 256 grid,
+    T1w and MTw acquired on grids moved by its seeded rigid motions, MTw with 8
+    slices fewer) with the full 10 x 8 x 32 schedule, against the oracle's fit
+    of the same echoes (stored by tests/golden/make_projected_map.py, which
+    builds them as this test does): the objective trace, the report, the maps
+    at 1024 seeded voxels (those whose oracle maps lie within 1 of the truth)
+    and at all 1024, the per-map means, and the Laplace variance at the GPU's
+    maps against the stored variance at the oracle's maps (well-posed voxels)."""
+    torch = torch_cuda
+    sys.path.insert(0, os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden"))
+    from make_projected_map import projected_echoes, spaces_of
+    g = json.load(open(GOLDEN_PROJECTED))
+    c = synth.make_case(g["case"])
+    del c["eps"]
+    assert c["seed"] == g["seed"] and list(c["dims"]) == g["dims"]
+    opts = g["options"]
+    assert opts["lam"] == [float(v) for v in c["lam"]]
+    b1 = f32(c["b1"])
+    spaces = spaces_of(c["dims"])
+    x = projected_echoes(orc, c, spaces, b1)
+    N = int(np.prod(c["dims"]))
+    X = cuda(x)
+    del x
+    B1 = cuda(b1.astype(np.float32))
+    maps = torch.zeros((4, N), dtype=torch.float32, device="cuda")
+    print("projected whole brain 10x8x32: GPU fit", flush=True)
+    rep, tr = _lib.mpm_fit_projected(c["proto"], c["dims"], spaces, X, B1, opts, maps)
+    torch.cuda.synchronize()
+    tr_o = np.array([np.nan if v is None else v for v in g["trace"]])
+    fin = np.isfinite(tr_o)
+    print("projected whole brain 10x8x32: gpu objective", rep["objective"], "oracle", g["report"]["objective"],
+          "| gpu", rep, flush=True)
+    assert np.array_equal(np.isfinite(tr), fin) and np.allclose(tr[fin], tr_o[fin], rtol=1e-6)
+    assert rep["objective"] == pytest.approx(g["report"]["objective"], rel=1e-6)
+    assert rep["gn_done"] == g["report"]["gn_done"] == 80 and rep["nonfinite_voxels"] == 0
+    idx = np.array(g["sample_index"])
+    ys = maps[:, torch.from_numpy(idx).cuda()].cpu().numpy().astype(np.float64)
+    yo = np.array(g["sample_maps"])
+    good = well_posed(yo, c["truth"][:, idx])
+    scale = np.array(g["map_max_abs"])
+    rel = np.abs(ys - yo)[:, good].max(axis=1) / scale
+    rel_all = np.abs(ys - yo).max(axis=1) / scale
+    rel_mean = np.abs(maps.double().mean(dim=1).cpu().numpy() - np.array(g["map_mean"])) / scale
+    print("projected whole brain 10x8x32: well-posed", good.mean(), "sampled maps rel", rel, "all sampled",
+          rel_all, "means rel", rel_mean, flush=True)
+    assert good.mean() > 0.8 and (rel <= TOL).all() and (rel_all <= TOL).all() and (rel_mean <= TOL).all()
+    var = torch.empty((4, N), dtype=torch.float32, device="cuda")
+    _lib.mpm_uncertainty_projected(c["proto"], c["dims"], spaces, X, B1, opts, maps, var)
+    vg = var[:, torch.from_numpy(idx).cuda()].cpu().numpy().astype(np.float64)
+    v_o = np.array(g["sample_var"])
+    ok = np.isfinite(v_o).all(axis=0) & good
+    rv = (np.abs(vg - v_o)[:, ok] / v_o[:, ok]).max(axis=1)
+    print("projected whole brain 10x8x32: sampled variance rel (well-posed voxels)", rv)
+    assert (rv <= 1e-4).all()
