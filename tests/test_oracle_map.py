@@ -209,3 +209,26 @@ def test_map_laplace_variance_matches_dense_inverse(orc, lam_scale):
             A0[k * N + n, k * N + n] -= lam[k] * dG[n]
     ref0 = np.diag(np.linalg.inv(A0)).reshape(4, N)
     assert np.abs(ref0 / ref - 1).max() > (0.1 if lam_scale > 1 else 1e-4)
+
+
+def test_results_do_not_depend_on_thread_count(orc):
+    """Every sum over voxels in the oracle is a serial loop in index order and
+    the threads only split independent voxel work, so a MAP fit, its trace and
+    its Laplace variance are the same bits on 1 thread as on all of them (the
+    stored full-size fits were written on 8 threads and are read on hosts with
+    other counts)."""
+    c, x = _brain(dims=(14, 12, 10), seed=21)
+    opts = dict(c["opts"], n_outer=3, n_gn=3, n_cg=12)
+    n0 = orc.num_threads()
+    out = []
+    try:
+        for n in (1, max(n0, 2)):
+            orc.set_num_threads(n)
+            y, rep, tr = orc.fit(c["proto"], c["dims"], x, c["b1"], opts)
+            v = orc.uncertainty(c["proto"], c["dims"], x, c["b1"], opts, y)
+            out.append((y, rep, tr, v))
+    finally:
+        orc.set_num_threads(n0)
+    (y1, r1, t1, v1), (y2, r2, t2, v2) = out
+    assert np.array_equal(y1, y2) and np.array_equal(v1, v2) and r1 == r2
+    assert np.array_equal(t1, t2, equal_nan=True)
